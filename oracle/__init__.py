@@ -1,0 +1,200 @@
+"""FP64 CPU oracle for the grid integrals (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU
+library: it has its own spline, spherical harmonics, image search and loops
+(``gint_oracle.c``), compiled with gcc into ``liboracle.so``.
+
+Functions follow Sec. 3.3.1 ("Uniform Grid Integration for Usual
+Quantities") of the paper: the rho(r_g) equation, the H^loc equation and the
+F^{loc,Pulay} equation, at the Gamma point, on the basis of Sec. 2.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "gint_oracle.c")
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           SRC_PATH, "-o", LIB_PATH + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lp = ctypes.POINTER(ctypes.c_long)
+    lib.oracle_create.restype = P
+    lib.oracle_create.argtypes = [dp, ip, ctypes.c_int, ip, ip, dp, dp, dp, dp,
+                                  ctypes.c_int, ip, ctypes.c_int, ip, dp]
+    lib.oracle_destroy.argtypes = [P]
+    lib.oracle_norb.argtypes = [P]
+    lib.oracle_atom_orb0.argtypes = [P, ctypes.c_int]
+    lib.oracle_dV.argtypes = [P]
+    lib.oracle_dV.restype = ctypes.c_double
+    lib.oracle_radial.argtypes = [P, ctypes.c_int, ctypes.c_double, dp]
+    lib.oracle_radial.restype = ctypes.c_double
+    lib.oracle_ylm.argtypes = [ctypes.c_int, dp, dp]
+    lib.oracle_phi.argtypes = [P, dp, dp, dp]
+    lib.oracle_H_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
+    lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, dp]
+    lib.oracle_set_positions.argtypes = [P, dp]
+    lib.oracle_support_stats.argtypes = [P, dp, dp]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def ylm(l: int, u) -> np.ndarray:
+    """Real Y_lm(u), m = -l..l, at a unit vector (closed forms)."""
+    lib = _load()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(2 * l + 1)
+    lib.oracle_ylm(l, _dp(u), _dp(out))
+    return out
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+class Oracle:
+    """Oracle context for one cell (geometry, basis, mesh)."""
+
+    def __init__(self, lattice, grid, species, species_of_atom, positions):
+        lib = _load()
+        self._lib = lib
+        rad_l, rad_nr, rad_dr, rad_d0, rad_drc, fs, begin = [], [], [], [], [], [], [0]
+        for sp in species:
+            for r in sp.radials:
+                rad_l.append(r.l)
+                rad_nr.append(r.nr)
+                rad_dr.append(r.dr)
+                rad_d0.append(r.dfdr0)
+                rad_drc.append(r.dfdrc)
+                fs.append(np.asarray(r.f, dtype=np.float64))
+            begin.append(len(rad_l))
+        self._keep = [
+            np.ascontiguousarray(lattice, dtype=np.float64).reshape(9),
+            np.asarray(grid, dtype=np.int32),
+            np.asarray(rad_l, dtype=np.int32),
+            np.asarray(rad_nr, dtype=np.int32),
+            np.asarray(rad_dr, dtype=np.float64),
+            np.concatenate(fs),
+            np.asarray(rad_d0, dtype=np.float64),
+            np.asarray(rad_drc, dtype=np.float64),
+            np.asarray(begin, dtype=np.int32),
+            np.asarray(species_of_atom, dtype=np.int32),
+            np.ascontiguousarray(positions, dtype=np.float64).reshape(-1),
+        ]
+        k = self._keep
+        self.natom = int(len(k[9]))
+        self.grid = tuple(int(g) for g in grid)
+        self.ngrid = int(np.prod(self.grid))
+        self._ctx = lib.oracle_create(_dp(k[0]), _ip(k[1]), len(rad_l), _ip(k[2]), _ip(k[3]), _dp(k[4]),
+                                      _dp(k[5]), _dp(k[6]), _dp(k[7]), len(species), _ip(k[8]),
+                                      self.natom, _ip(k[9]), _dp(k[10]))
+        self.norb = int(lib.oracle_norb(self._ctx))
+        self.dV = float(lib.oracle_dV(self._ctx))
+        self.atom_orb0 = np.array([lib.oracle_atom_orb0(self._ctx, i) for i in range(self.natom)] + [self.norb])
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.lattice, w.grid, w.species, w.species_of_atom, w.positions)
+
+    def __del__(self):
+        if getattr(self, "_ctx", None):
+            self._lib.oracle_destroy(self._ctx)
+            self._ctx = None
+
+    # -- pointwise -----------------------------------------------------------
+    def radial(self, k: int, r: float):
+        d = ctypes.c_double(0.0)
+        v = self._lib.oracle_radial(self._ctx, k, float(r), ctypes.byref(d))
+        return v, d.value
+
+    def phi(self, r, grad: bool = False):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        phi = np.zeros(self.norb)
+        g = np.zeros((self.norb, 3)) if grad else None
+        self._lib.oracle_phi(self._ctx, _dp(r), _dp(phi), _dp(g) if grad else None)
+        return (phi, g) if grad else phi
+
+    def set_positions(self, positions):
+        p = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
+        self._keep[10] = p
+        self._lib.oracle_set_positions(self._ctx, _dp(p))
+
+    def support_stats(self):
+        a, b = ctypes.c_double(0), ctypes.c_double(0)
+        self._lib.oracle_support_stats(self._ctx, ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
+    # -- integrals -------------------------------------------------------------
+    def H_rows(self, V, I0: int, I1: int) -> np.ndarray:
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        assert V.size == self.ngrid
+        n = int(self.atom_orb0[I1] - self.atom_orb0[I0])
+        out = np.zeros((n, self.norb))
+        self._lib.oracle_H_rows(self._ctx, _dp(V), int(I0), int(I1), _dp(out))
+        return out
+
+    def H(self, V) -> np.ndarray:
+        return self.H_rows(V, 0, self.natom)
+
+    def rho(self, D, idx: Optional[Sequence[int]] = None) -> np.ndarray:
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        assert D.shape == (self.norb, self.norb)
+        if idx is None:
+            out = np.zeros(self.ngrid)
+            self._lib.oracle_rho(self._ctx, _dp(D), self.ngrid, None, _dp(out))
+        else:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            out = np.zeros(idx.size)
+            self._lib.oracle_rho(self._ctx, _dp(D), idx.size,
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))
+        return out
+
+    def force(self, V, D, atoms: Optional[Sequence[int]] = None) -> np.ndarray:
+        """dE/dR_I (not the force) for the chosen atoms, E = dV sum V rho."""
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        sel = np.arange(self.natom, dtype=np.int32) if atoms is None else np.asarray(atoms, dtype=np.int32)
+        out = np.zeros((sel.size, 3))
+        self._lib.oracle_force(self._ctx, _dp(V), _dp(D), int(sel.size), _ip(sel), _dp(out))
+        return out
+
+    def energy(self, V, D) -> float:
+        return float(self.dV * np.dot(np.asarray(V, dtype=np.float64), self.rho(D)))
