@@ -25,13 +25,22 @@ def _two_atom_dzp(rc=5.0):
                          n_waves=6, nocc=3, seed=7)
 
 
+def _tiny_long_range():
+    # rc = 5.5 > L = 4: images two cells away still carry weight (slow decay)
+    sp = gi.Species([gi.nao_like_radial(0, 0.08, 5.5, 0.01), gi.nao_like_radial(1, 0.1, 5.5, 0.01),
+                     gi.nao_like_radial(2, 0.12, 5.5, 0.01)])
+    lat = np.array([[4.0, 0.0, 0.0], [0.0, 4.4, 0.0], [0.5, 0.0, 4.2]])
+    pos = np.array([[0.2, 0.3, 0.1], [2.1, 2.4, 1.9]])
+    return gi.small_cell(pos, lat, (7, 8, 8), [sp], n_waves=5, nocc=4, seed=9)
+
+
 def _si8_coarse():
     w = gi.si8_sz()
     w2 = gi.small_cell(w.positions, w.lattice, (12, 12, 12), w.species, n_waves=8, nocc=8, seed=11)
     return w2
 
 
-@pytest.mark.parametrize("make", [_two_atom_dzp, _si8_coarse])
+@pytest.mark.parametrize("make", [_two_atom_dzp, _tiny_long_range, _si8_coarse])
 def test_bruteforce_H_rho(oracle_mod, make):
     w = make()
     o = oracle_mod.Oracle.from_workload(w)
@@ -45,9 +54,10 @@ def test_bruteforce_H_rho(oracle_mod, make):
     assert np.max(np.abs(rho - rho_bf)) <= 1e-13 * max(1.0, np.max(np.abs(rho_bf)))
 
 
-def test_bruteforce_force_by_differences(oracle_mod):
+@pytest.mark.parametrize("make", [_two_atom_dzp, _tiny_long_range])
+def test_bruteforce_force_by_differences(oracle_mod, make):
     # the brute force has no analytic gradient: differentiate its energy
-    w = _two_atom_dzp()
+    w = make()
     o = oracle_mod.Oracle.from_workload(w)
     bf = BruteCell(w)
     F = o.force(w.V, w.D)

@@ -70,3 +70,28 @@ def test_translation_sum_rule(oracle_mod):
     gradV = -(np.sin(phase) * w.pw_amp) @ G
     rhs = o.dV * (rho[:, None] * gradV).sum(0)
     assert np.max(np.abs(F.sum(0) - rhs)) <= 1e-3 * np.max(np.abs(F))
+
+
+def test_nonsymmetric_D_force(oracle_mod):
+    # E depends on D only through D + D^T; the gradient must use both
+    sp = gi.dzp_species(rc=5.0)
+    lat = np.eye(3) * 8.0
+    pos = np.array([[0.5, 0.7, 1.1], [3.9, 4.4, 3.6]])
+    w = gi.small_cell(pos, lat, (14, 14, 14), [sp], n_waves=6, nocc=5, seed=4)
+    rng = np.random.default_rng(8)
+    D = rng.standard_normal((w.norb, w.norb)) * 0.1
+    o = oracle_mod.Oracle.from_workload(w)
+    F = o.force(w.V, D)
+    np.testing.assert_allclose(F, o.force(w.V, 0.5 * (D + D.T)), rtol=0, atol=1e-12 * np.abs(F).max())
+    h = 1e-4
+    for I in range(2):
+        for k in range(3):
+            p = w.positions.copy()
+            p[I, k] += h
+            o.set_positions(p)
+            Ep = o.energy(w.V, D)
+            p[I, k] -= 2 * h
+            o.set_positions(p)
+            Em = o.energy(w.V, D)
+            o.set_positions(w.positions)
+            assert abs(F[I, k] - (Ep - Em) / (2 * h)) <= 1e-6 * np.abs(F).max()
