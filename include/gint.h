@@ -1,0 +1,186 @@
+/*
+ * gint.h -- C ABI of the MI355X (gfx950) real-space grid-integration library.
+ *
+ * The library evaluates, on one GPU, the three uniform-mesh integrals of
+ * NAO-based DFT / RT-TDDFT described in Sec. 3.3.1 ("Uniform Grid
+ * Integration for Usual Quantities") of arXiv:2603.21835, at the Gamma point:
+ *
+ *   H_mu,nu   = dV sum_g phit_mu(r_g) V(r_g) phit_nu(r_g)        (H^loc equation)
+ *   rho(r_g)  = sum_{mu,nu} D_mu,nu phit_mu(r_g) phit_nu(r_g)     (rho(r_g) equation)
+ *   dE/dR_I   for E = dV sum_g W(r_g) rho(r_g)                   (F^{loc,Pulay} equation,
+ *                                                                 returned as the gradient,
+ *                                                                 i.e. minus the force)
+ *
+ * where phit_mu is the numerical atomic orbital f_{l zeta}(r) Y_lm(r^) of
+ * Sec. 2.1 folded over all lattice images (the k = 0 case of the lattice sums
+ * of the rho(r_g) and H(k) equations), f is the clamped cubic spline through
+ * the caller's radial table, Y_lm are real spherical harmonics (no
+ * Condon-Shortley phase), r_g = sum_i (n_i/N_i) a_i and dV = |det A|/(N1 N2 N3).
+ *
+ * Units: Hartree atomic units (bohr, Ha).  All caller-visible floating-point
+ * data is FP64 in every precision mode.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Orbital order: atoms in input order; within an atom the species' radials
+ *    sorted by l (stable, so radials of equal l keep their order = zeta),
+ *    then m = -l..l.  gint_norb() gives the total.
+ *  - Mesh arrays (V, W, rho) are N1*N2*N3 doubles, C order (index
+ *    (n1*N2 + n2)*N3 + n3, n3 fastest).  Matrices (H, D) are norb*norb
+ *    doubles, row-major.
+ *  - Ownership: pointers marked "device" are caller-owned device memory
+ *    (e.g. torch.Tensor.data_ptr()); the library never frees or keeps them
+ *    beyond the call.  Host pointers are read during the call only.  The
+ *    plan owns its spline tables, binning lists and work buffers.
+ *  - Streams: every call enqueues its kernels on the plan's HIP stream and
+ *    returns without waiting, except where stated (plan creation and
+ *    gint_plan_set_positions read back list sizes and synchronise the stream).
+ *  - Errors: invalid arguments are detected on the host before anything is
+ *    enqueued and return GINT_EINVAL with outputs untouched.  A failed HIP
+ *    call returns GINT_EDEVICE; asynchronous device errors surface on the
+ *    next call or on gint_plan_sync.  No C++ exception crosses this ABI.
+ *    gint_last_error() returns a message for the calling thread's last
+ *    failure.
+ *  - Outputs are overwritten, not accumulated.
+ *  - A plan is not thread-safe; distinct plans may be used concurrently on
+ *    distinct streams.
+ *  - Limits: l <= 2, at most 16 orbitals per atom, 1 <= natom <= 16384,
+ *    radial tables with nr >= 4 knots, N1*N2*N3 < 2^31.
+ */
+#ifndef GINT_H
+#define GINT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GINT_OK = 0,
+    GINT_EINVAL = 1,       /* invalid argument (nothing enqueued)          */
+    GINT_ENOMEM = 2,       /* device or host allocation failed             */
+    GINT_EDEVICE = 3,      /* no usable gfx950 device, or a HIP call failed */
+    GINT_EUNSUPPORTED = 4, /* valid but not supported (e.g. l > 2)         */
+    GINT_ESTATE = 5        /* plan destroyed, corrupted or not ready       */
+} gint_status;
+
+/* Arithmetic of the contractions.  Inputs/outputs stay FP64 in all modes;
+   the cross-batch reductions are FP64 in all modes. */
+typedef enum {
+    GINT_FP64 = 0, /* FP64 orbitals, FP64 MFMA                                 */
+    GINT_FP32 = 1, /* FP32 orbitals and FP32 accumulation                      */
+    GINT_BF16 = 2, /* BF16 MFMA operands, FP32 accumulation                    */
+    GINT_FP16 = 3  /* FP16 MFMA operands, FP32 accumulation                    */
+} gint_precision;
+
+/* One radial function, tabulated on the host at r_i = i*dr, i < nr; its
+ * cutoff is rc = (nr-1)*dr and f = 0 for r >= rc.  dfdr_0 and dfdr_rc are the
+ * end slopes of the clamped cubic spline (Sec. 2.1 NAO radial; the radial
+ * derivative is taken from the spline, Sec. 2.3 Pulay-force remark). */
+typedef struct {
+    int l;
+    int nr;
+    double dr;
+    const double *f; /* host, nr doubles */
+    double dfdr_0;
+    double dfdr_rc;
+} gint_radial;
+
+typedef struct {
+    int nradial;
+    const gint_radial *radial; /* host, nradial entries */
+} gint_species;
+
+/* Work counts of the current geometry, for throughput reporting. */
+typedef struct {
+    long long ngrid;       /* N1*N2*N3                                           */
+    long long nbatch;      /* mesh batches                                       */
+    long long nentry;      /* (batch, atom) pairs after binning                  */
+    long long npair;       /* active atom-group pairs                            */
+    double sum_ng;         /* sum over mesh points of supported orbitals n_g     */
+    double sum_ng2;        /* sum over mesh points of n_g^2                      */
+    int batch[3];          /* batch shape in mesh points                         */
+    int nchunk;            /* batch-list chunks per group pair                   */
+} gint_work;
+
+typedef struct gint_plan_s *gint_plan;
+
+/* Create a plan: geometry, mesh and basis (the GintInfo role of Fig. 2:
+ * mesh division into batches and batch/atom neighbour lists).
+ *   lattice          host, 9 doubles, rows a1, a2, a3 (bohr), det != 0
+ *   grid             host, 3 ints N1, N2, N3 >= 1
+ *   species          host, nspecies entries (see limits above)
+ *   species_of_atom  host, natom ints in [0, nspecies)
+ *   positions        host, natom*3 doubles, cartesian (any image)
+ *   prec             arithmetic of the contractions
+ *   hip_stream       hipStream_t to enqueue on (NULL = default stream)
+ *   out              receives the plan (unchanged on error)
+ * Synchronises the stream once (list sizes are read back). */
+gint_status gint_plan_create(const double lattice[9], const int grid[3], int nspecies,
+                             const gint_species *species, int natom, const int *species_of_atom,
+                             const double *positions, gint_precision prec, void *hip_stream,
+                             gint_plan *out);
+
+/* Move the atoms (host, natom*3 doubles) and rebuild the binning lists on
+ * the GPU.  Synchronises the stream once. */
+gint_status gint_plan_set_positions(gint_plan plan, const double *positions);
+
+/* Batch shape (mesh points per batch along each axis; product 16 or 32) and
+ * the number of chunks each group pair's batch list is split into (0 =
+ * automatic).  Rebuilds the lists; synchronises the stream. */
+gint_status gint_plan_tune(gint_plan plan, const int batch[3], int nchunk);
+
+/* Change the stream subsequent calls enqueue on. */
+gint_status gint_plan_set_stream(gint_plan plan, void *hip_stream);
+
+/* H^loc of Sec. 3.3.1 (Gamma point, images folded):
+ *   V_dev  device, N1*N2*N3 doubles (Ha)
+ *   H_dev  device, norb*norb doubles, row-major, overwritten; exactly
+ *          symmetric (each pair is computed once and mirrored). */
+gint_status gint_build_H(gint_plan plan, const double *V_dev, double *H_dev);
+
+/* As gint_build_H with the per-point weight given directly:
+ * H_mu,nu = sum_g w_g phit_mu phit_nu (no dV factor).  This is the
+ * derivative of sum_g w_g rho_g with respect to D. */
+gint_status gint_build_H_weighted(gint_plan plan, const double *w_dev, double *H_dev);
+
+/* rho(r_g) of Sec. 3.3.1 (Gamma point, images folded):
+ *   D_dev    device, norb*norb doubles, row-major, used as given (a
+ *            non-symmetric D acts through its symmetric part)
+ *   rho_dev  device, N1*N2*N3 doubles, overwritten. */
+gint_status gint_build_rho(gint_plan plan, const double *D_dev, double *rho_dev);
+
+/* Gradient of E = dV sum_g W_g rho_g with respect to the atom positions
+ * (minus F^{loc,Pulay} of Sec. 3.3.1; W does not move with the atoms):
+ *   dE/dR_I = -dV sum_g W_g sum_{mu in I} grad phit_mu(r_g) . [(D + D^T) phit(r_g)]_mu
+ *   W_dev     device, N1*N2*N3 doubles
+ *   D_dev     device, norb*norb doubles
+ *   dEdR_dev  device, natom*3 doubles (input atom order), overwritten. */
+gint_status gint_force(gint_plan plan, const double *W_dev, const double *D_dev, double *dEdR_dev);
+
+/* As gint_force with the per-point weight w_g given directly (no dV):
+ * the gradient of sum_g w_g rho_g. */
+gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const double *D_dev,
+                                double *dEdR_dev);
+
+/* Wait for the plan's stream and report any asynchronous device error. */
+gint_status gint_plan_sync(gint_plan plan);
+
+/* Work counts of the current geometry (computes the exact sum_g n_g^2 on
+ * the GPU; synchronises the stream). */
+gint_status gint_plan_work(gint_plan plan, gint_work *out);
+
+int gint_norb(gint_plan plan);   /* total orbitals, or -1 for an invalid plan */
+int gint_natom(gint_plan plan);  /* atoms, or -1                               */
+double gint_dV(gint_plan plan);  /* mesh volume element, or -1                 */
+const char *gint_status_string(gint_status s);
+const char *gint_last_error(void);
+
+/* Release the plan and everything it owns (waits for its stream).  NULL is
+ * accepted. */
+void gint_plan_destroy(gint_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GINT_H */

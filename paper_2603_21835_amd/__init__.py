@@ -1,0 +1,271 @@
+"""MI355X (gfx950) grid integration: Python binding over ``libgint.so``.
+
+Argument marshalling only: every step of the computation (splines, binning,
+orbital tiles, contractions, reductions) runs in the HIP kernels of the C
+library declared in ``include/gint.h``.  PyTorch supplies device memory and
+the current stream.  There is no CPU fallback: if the library is missing or
+no gfx950 GPU is present, the calls raise.
+
+The computed quantities are those of Sec. 3.3.1 ("Uniform Grid Integration
+for Usual Quantities") of arXiv:2603.21835 at the Gamma point: H^loc, rho(r_g)
+and the local Pulay force (returned as the gradient dE/dR).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgint.so")
+
+GINT_OK, GINT_EINVAL, GINT_ENOMEM, GINT_EDEVICE, GINT_EUNSUPPORTED, GINT_ESTATE = range(6)
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+
+# Every symbol include/gint.h declares.
+EXPORTS = (
+    "gint_plan_create", "gint_plan_set_positions", "gint_plan_tune", "gint_plan_set_stream",
+    "gint_build_H", "gint_build_H_weighted", "gint_build_rho", "gint_force",
+    "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
+    "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
+)
+
+
+class GintError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class _Radial(ctypes.Structure):
+    _fields_ = [("l", ctypes.c_int), ("nr", ctypes.c_int), ("dr", ctypes.c_double),
+                ("f", ctypes.POINTER(ctypes.c_double)), ("dfdr_0", ctypes.c_double),
+                ("dfdr_rc", ctypes.c_double)]
+
+
+class _Species(ctypes.Structure):
+    _fields_ = [("nradial", ctypes.c_int), ("radial", ctypes.POINTER(_Radial))]
+
+
+class Work(ctypes.Structure):
+    _fields_ = [("ngrid", ctypes.c_longlong), ("nbatch", ctypes.c_longlong),
+                ("nentry", ctypes.c_longlong), ("npair", ctypes.c_longlong),
+                ("sum_ng", ctypes.c_double), ("sum_ng2", ctypes.c_double),
+                ("batch", ctypes.c_int * 3), ("nchunk", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgint.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    st = ctypes.c_int
+    lib.gint_plan_create.restype = st
+    lib.gint_plan_create.argtypes = [dp, ip, ctypes.c_int, ctypes.POINTER(_Species), ctypes.c_int, ip, dp,
+                                     ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.gint_plan_set_positions.restype = st
+    lib.gint_plan_set_positions.argtypes = [P, dp]
+    lib.gint_plan_tune.restype = st
+    lib.gint_plan_tune.argtypes = [P, ip, ctypes.c_int]
+    lib.gint_plan_set_stream.restype = st
+    lib.gint_plan_set_stream.argtypes = [P, P]
+    for name in ("gint_build_H", "gint_build_H_weighted", "gint_build_rho"):
+        getattr(lib, name).restype = st
+        getattr(lib, name).argtypes = [P, P, P]
+    for name in ("gint_force", "gint_force_weighted"):
+        getattr(lib, name).restype = st
+        getattr(lib, name).argtypes = [P, P, P, P]
+    lib.gint_plan_sync.restype = st
+    lib.gint_plan_sync.argtypes = [P]
+    lib.gint_plan_work.restype = st
+    lib.gint_plan_work.argtypes = [P, ctypes.POINTER(Work)]
+    lib.gint_norb.restype = ctypes.c_int
+    lib.gint_norb.argtypes = [P]
+    lib.gint_natom.restype = ctypes.c_int
+    lib.gint_natom.argtypes = [P]
+    lib.gint_dV.restype = ctypes.c_double
+    lib.gint_dV.argtypes = [P]
+    lib.gint_status_string.restype = ctypes.c_char_p
+    lib.gint_status_string.argtypes = [ctypes.c_int]
+    lib.gint_last_error.restype = ctypes.c_char_p
+    lib.gint_last_error.argtypes = []
+    lib.gint_plan_destroy.restype = None
+    lib.gint_plan_destroy.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != GINT_OK:
+        lib = load_library()
+        raise GintError(status, f"{lib.gint_status_string(status).decode()}: {lib.gint_last_error().decode()}")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _dev_ptr(t, numel: int, what: str):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{what} must be contiguous float64")
+    if t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class GintPlan:
+    """Geometry + mesh + basis of one periodic cell (the GintInfo of Fig. 2).
+
+    ``species`` is a list of objects with ``.radials``, each radial having
+    ``l, dr, f (knot values), dfdr0, dfdrc`` (see ``gint_inputs``).
+    """
+
+    def __init__(self, lattice, grid, species, species_of_atom, positions, precision: str = "fp64",
+                 stream=None):
+        lib = load_library()
+        self._lib = lib
+        self._lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+        self._grid = np.ascontiguousarray(grid, dtype=np.int32).reshape(3)
+        self._keep = []
+        sp_arr = (_Species * len(species))()
+        for s, spc in enumerate(species):
+            rads = (_Radial * len(spc.radials))()
+            for k, r in enumerate(spc.radials):
+                f = np.ascontiguousarray(r.f, dtype=np.float64)
+                self._keep.append(f)
+                rads[k] = _Radial(int(r.l), int(f.size), float(r.dr), _dptr(f), float(r.dfdr0), float(r.dfdrc))
+            self._keep.append(rads)
+            sp_arr[s] = _Species(len(spc.radials), rads)
+        self._keep.append(sp_arr)
+        self._soa = np.ascontiguousarray(species_of_atom, dtype=np.int32)
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
+        self.natom = int(self._soa.size)
+        self.ngrid = int(np.prod(self._grid))
+        self.grid = tuple(int(x) for x in self._grid)
+        handle = ctypes.c_void_p()
+        _check(lib.gint_plan_create(_dptr(self._lat), _iptr(self._grid), len(species), sp_arr, self.natom,
+                                    _iptr(self._soa), _dptr(pos), PRECISIONS[precision],
+                                    _stream_handle(stream), ctypes.byref(handle)))
+        self._h = handle
+        self.norb = int(lib.gint_norb(handle))
+        self.dV = float(lib.gint_dV(handle))
+        self.precision = precision
+
+    @classmethod
+    def from_workload(cls, w, precision: str = "fp64", stream=None):
+        return cls(w.lattice, w.grid, w.species, w.species_of_atom, w.positions, precision, stream)
+
+    # -- lifecycle -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.gint_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if self._h is None:
+            raise GintError(GINT_ESTATE, "plan is closed")
+        return self._h
+
+    # -- geometry ---------------------------------------------------------------
+    def set_positions(self, positions):
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
+        if pos.size != 3 * self.natom:
+            raise ValueError("positions must have natom*3 entries")
+        _check(self._lib.gint_plan_set_positions(self._handle(), _dptr(pos)))
+
+    def tune(self, batch: Sequence[int], nchunk: int = 0):
+        b = np.ascontiguousarray(batch, dtype=np.int32)
+        _check(self._lib.gint_plan_tune(self._handle(), _iptr(b), int(nchunk)))
+
+    def set_stream(self, stream=None):
+        _check(self._lib.gint_plan_set_stream(self._handle(), _stream_handle(stream)))
+
+    def sync(self):
+        _check(self._lib.gint_plan_sync(self._handle()))
+
+    def work(self) -> dict:
+        w = Work()
+        _check(self._lib.gint_plan_work(self._handle(), ctypes.byref(w)))
+        return {"ngrid": w.ngrid, "nbatch": w.nbatch, "nentry": w.nentry, "npair": w.npair,
+                "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nchunk": w.nchunk}
+
+    # -- the three grid integrals ----------------------------------------------------
+    def build_H(self, V, out=None, weighted: bool = False):
+        """H^loc (norb x norb). With weighted=True the input is the per-point weight w_g (no dV)."""
+        import torch
+
+        vp = _dev_ptr(V, self.ngrid, "V")
+        if out is None:
+            out = torch.empty((self.norb, self.norb), dtype=torch.float64, device=V.device)
+        op = _dev_ptr(out, self.norb * self.norb, "H")
+        fn = self._lib.gint_build_H_weighted if weighted else self._lib.gint_build_H
+        _check(fn(self._handle(), vp, op))
+        return out
+
+    def build_rho(self, D, out=None):
+        import torch
+
+        dp = _dev_ptr(D, self.norb * self.norb, "D")
+        if out is None:
+            out = torch.empty(self.ngrid, dtype=torch.float64, device=D.device)
+        op = _dev_ptr(out, self.ngrid, "rho")
+        _check(self._lib.gint_build_rho(self._handle(), dp, op))
+        return out
+
+    def force(self, W, D, out=None, weighted: bool = False):
+        """dE/dR (natom x 3) for E = dV sum W rho (or sum w rho with weighted=True)."""
+        import torch
+
+        wp = _dev_ptr(W, self.ngrid, "W")
+        dp = _dev_ptr(D, self.norb * self.norb, "D")
+        if out is None:
+            out = torch.empty((self.natom, 3), dtype=torch.float64, device=W.device)
+        op = _dev_ptr(out, self.natom * 3, "dEdR")
+        fn = self._lib.gint_force_weighted if weighted else self._lib.gint_force
+        _check(fn(self._handle(), wp, dp, op))
+        return out
+
+
+def build_H(plan: GintPlan, V, out=None):
+    return plan.build_H(V, out)
+
+
+def build_rho(plan: GintPlan, D, out=None):
+    return plan.build_rho(D, out)
+
+
+def force(plan: GintPlan, W, D, out=None):
+    return plan.force(W, D, out)

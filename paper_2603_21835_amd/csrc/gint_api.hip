@@ -1,0 +1,715 @@
+// gint_api.hip -- host side of the C ABI declared in include/gint.h:
+// argument validation, the plan (GintInfo role: geometry, basis tables and
+// the batch/atom lists), and dispatch of the kernels in gint_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gint.h"
+#include "gint_internal.h"
+
+using namespace gint;
+
+namespace {
+
+constexpr unsigned kMagic = 0x47494e54u;  // "GINT"
+thread_local std::string g_last_error;
+
+gint_status fail(gint_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? GINT_ENOMEM : GINT_EDEVICE, "%s failed: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                             \
+    } while (0)
+
+#define STCHK(call)                 \
+    do {                            \
+        gint_status s_ = (call);    \
+        if (s_ != GINT_OK)          \
+            return s_;              \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+    gint_status ensure(size_t need)
+    {
+        if (need == 0)
+            need = 256;
+        if (need <= bytes)
+            return GINT_OK;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(GINT_ENOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+        }
+        bytes = need;
+        return GINT_OK;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+}  // namespace
+
+struct gint_plan_s {
+    unsigned magic = kMagic;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    gint_precision prec = GINT_FP64;
+    Geo geo{};
+    int natom = 0, norb = 0, nrad = 0, nspecies = 0;
+    double dV = 0.0;
+    double rc_max = 0.0;
+    int nchunk_req = 0;  // 0 = automatic
+    int nchunk = 1;
+    long long nent = 0, nimg = 0, nslot = 0, ngb = 0, npair = 0, ngbatch = 0;
+
+    // basis and atoms
+    DevBuf rad, sp, knots, s0, sn, coef, scratch;
+    DevBuf spc_in, spc, pos_in, xw_in, xw, keys, perm, inv_perm, orb0, orb_atom;
+    // binning lists
+    DevBuf cnt_e, cnt_i, cnt_g, cnt_s, bptr, iptr, bgptr, soff;
+    DevBuf ent_atom, ent_img, img, bgrp;
+    DevBuf gcnt, gptr, gbatch;
+    DevBuf mark, mscan, pair_index, pairA, pairB;
+    // work buffers
+    DevBuf Hblk, rho_part, Fpart, sums, readback;
+
+    Basis basis() const
+    {
+        Basis b;
+        b.rad = rad.as<DevRadial>();
+        b.sp = sp.as<DevSpecies>();
+        b.coef = coef.as<double>();
+        b.spc = spc.as<int>();
+        b.xw = xw.as<double>();
+        b.perm = perm.as<int>();
+        b.inv_perm = inv_perm.as<int>();
+        b.orb0 = orb0.as<int>();
+        b.orb_atom = orb_atom.as<int>();
+        return b;
+    }
+    Bins bins() const
+    {
+        Bins b;
+        b.bptr = bptr.as<int>();
+        b.ent_atom = ent_atom.as<int>();
+        b.ent_img = ent_img.as<int>();
+        b.img = img.as<int>();
+        b.bgptr = bgptr.as<int>();
+        b.bgrp = bgrp.as<int>();
+        b.soff = soff.as<long long>();
+        b.gptr = gptr.as<int>();
+        b.gbatch = gbatch.as<int>();
+        b.pairA = pairA.as<int>();
+        b.pairB = pairB.as<int>();
+        b.pair_index = pair_index.as<int>();
+        return b;
+    }
+};
+
+namespace {
+
+bool finite3(const double *p, long long n)
+{
+    for (long long i = 0; i < n; ++i)
+        if (!std::isfinite(p[i]))
+            return false;
+    return true;
+}
+
+gint_status check_plan(gint_plan p)
+{
+    if (!p)
+        return fail(GINT_EINVAL, "plan is NULL");
+    if (p->magic != kMagic)
+        return fail(GINT_ESTATE, "plan is destroyed or corrupted");
+    return GINT_OK;
+}
+
+// Select the device the plan lives on; refuse anything that is not gfx950.
+gint_status device_ok(int *dev)
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0)
+        return fail(GINT_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    HIPCHK(hipGetDevice(dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, *dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GINT_EDEVICE, "device %d is %s; this library is built for gfx950 only", *dev, prop.gcnArchName);
+    return GINT_OK;
+}
+
+void set_batch(Geo &g, const int bs[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        g.bs[k] = bs[k];
+        g.nb[k] = (g.N[k] + bs[k] - 1) / bs[k];
+    }
+    g.P = bs[0] * bs[1] * bs[2];
+    g.nbatch = g.nb[0] * g.nb[1] * g.nb[2];
+}
+
+// Largest lattice multiple any batch can need, given the batch shape.
+double max_image_index(const Geo &g, double rc)
+{
+    double m = 0.0;
+    double sd[3] = {(double)g.bs[0] / g.N[0], (double)g.bs[1] / g.N[1], (double)g.bs[2] / g.N[2]};
+    double x[3];
+    for (int k = 0; k < 3; ++k)
+        x[k] = sd[0] * g.lat[k] + sd[1] * g.lat[3 + k] + sd[2] * g.lat[6 + k];
+    const double rad = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    for (int i = 0; i < 3; ++i) {
+        const double bn =
+            std::sqrt(g.rec[3 * i] * g.rec[3 * i] + g.rec[3 * i + 1] * g.rec[3 * i + 1] + g.rec[3 * i + 2] * g.rec[3 * i + 2]);
+        m = std::max(m, (rc + rad) * bn + 2.0);
+    }
+    return m;
+}
+
+template <typename T>
+gint_status read_scalar(gint_plan p, const T *dev, T *host)
+{
+    HIPCHK(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return GINT_OK;
+}
+
+// Rebuild every list that depends on the atom positions (GintInfo).
+gint_status rebuild_lists(gint_plan p, bool resort)
+{
+    Geo &g = p->geo;
+    hipStream_t s = p->stream;
+    const int na = p->natom;
+    HIPCHK(launch_wrap(s, g, p->pos_in.as<double>(), p->xw_in.as<double>(),
+                       resort ? p->keys.as<unsigned long long>() : nullptr));
+    if (resort)
+        HIPCHK(launch_sort_perm(s, na, p->keys.as<unsigned long long>(), p->perm.as<int>(), p->inv_perm.as<int>()));
+    HIPCHK(launch_gather_internal(s, na, p->perm.as<int>(), p->xw_in.as<double>(), p->spc_in.as<int>(),
+                                  p->xw.as<double>(), p->spc.as<int>()));
+
+    const long long nb = g.nbatch;
+    STCHK(p->cnt_e.ensure(sizeof(int) * nb));
+    STCHK(p->cnt_i.ensure(sizeof(int) * nb));
+    STCHK(p->cnt_g.ensure(sizeof(int) * nb));
+    STCHK(p->cnt_s.ensure(sizeof(long long) * nb));
+    STCHK(p->bptr.ensure(sizeof(int) * (nb + 1)));
+    STCHK(p->iptr.ensure(sizeof(int) * (nb + 1)));
+    STCHK(p->bgptr.ensure(sizeof(int) * (nb + 1)));
+    STCHK(p->soff.ensure(sizeof(long long) * (nb + 1)));
+    const Basis B = p->basis();
+    HIPCHK(launch_bin_count(s, g, B, p->cnt_e.as<int>(), p->cnt_i.as<int>(), p->cnt_g.as<int>(),
+                            p->cnt_s.as<long long>()));
+    HIPCHK(launch_scan_i32(s, p->cnt_e.as<int>(), nb, p->bptr.as<int>()));
+    HIPCHK(launch_scan_i32(s, p->cnt_i.as<int>(), nb, p->iptr.as<int>()));
+    HIPCHK(launch_scan_i32(s, p->cnt_g.as<int>(), nb, p->bgptr.as<int>()));
+    HIPCHK(launch_scan_i64(s, p->cnt_s.as<long long>(), nb, p->soff.as<long long>()));
+    // totals (counts are far below 2^31 for any mesh this library accepts,
+    // but the image total is checked explicitly)
+    int tot[3];
+    long long tslot;
+    STCHK(p->readback.ensure(64));
+    HIPCHK(hipMemcpyAsync(&tot[0], p->bptr.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tot[1], p->iptr.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tot[2], p->bgptr.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tslot, p->soff.as<long long>() + nb, sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (tot[0] < 0 || tot[1] < 0 || tot[2] < 0 || tslot < 0)
+        return fail(GINT_EUNSUPPORTED, "binning lists exceed 2^31 entries");
+    p->nent = tot[0];
+    p->nimg = tot[1];
+    p->ngb = tot[2];
+    p->nslot = tslot;
+    STCHK(p->ent_atom.ensure(sizeof(int) * (p->nent + 1)));
+    STCHK(p->ent_img.ensure(sizeof(int) * (p->nent + 1)));
+    STCHK(p->img.ensure(sizeof(int) * (p->nimg + 1)));
+    STCHK(p->bgrp.ensure(sizeof(int) * (p->ngb + 1)));
+    HIPCHK(launch_bin_fill(s, g, B, p->bptr.as<int>(), p->iptr.as<int>(), p->bgptr.as<int>(), p->ent_atom.as<int>(),
+                           p->ent_img.as<int>(), p->img.as<int>(), p->bgrp.as<int>()));
+
+    // per-group batch lists
+    const int ng = g.ngroup;
+    STCHK(p->gcnt.ensure(sizeof(int) * ng));
+    STCHK(p->gptr.ensure(sizeof(int) * (ng + 1)));
+    HIPCHK(launch_group_count(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gcnt.as<int>()));
+    HIPCHK(launch_scan_i32(s, p->gcnt.as<int>(), ng, p->gptr.as<int>()));
+    int tg = 0;
+    STCHK(read_scalar(p, p->gptr.as<int>() + ng, &tg));
+    p->ngbatch = tg;
+    STCHK(p->gbatch.ensure(sizeof(int) * (p->ngbatch + 1)));
+    HIPCHK(launch_group_fill(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gptr.as<int>(), p->gbatch.as<int>()));
+
+    // active group pairs
+    const long long nn = (long long)ng * ng;
+    STCHK(p->mark.ensure(sizeof(int) * nn));
+    STCHK(p->mscan.ensure(sizeof(int) * (nn + 1)));
+    STCHK(p->pair_index.ensure(sizeof(int) * nn));
+    HIPCHK(launch_fill_i32(s, p->mark.as<int>(), nn, 0));
+    HIPCHK(launch_pair_mark(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->mark.as<int>()));
+    HIPCHK(launch_scan_i32(s, p->mark.as<int>(), nn, p->mscan.as<int>()));
+    int tp = 0;
+    STCHK(read_scalar(p, p->mscan.as<int>() + nn, &tp));
+    p->npair = tp;
+    STCHK(p->pairA.ensure(sizeof(int) * (p->npair + 1)));
+    STCHK(p->pairB.ensure(sizeof(int) * (p->npair + 1)));
+    HIPCHK(launch_pair_list(s, ng, p->mark.as<int>(), p->mscan.as<int>(), p->pair_index.as<int>(),
+                            p->pairA.as<int>(), p->pairB.as<int>()));
+
+    // chunks: enough workgroups to cover the chip several times
+    int nch = p->nchunk_req;
+    if (nch <= 0) {
+        nch = 1;
+        while ((long long)p->npair * nch < 4096 && nch < 64)
+            nch *= 2;
+    }
+    p->nchunk = nch;
+    const long long nwg = p->npair * (long long)nch;
+    if (nwg > 0x7fffffffLL)
+        return fail(GINT_EUNSUPPORTED, "too many group-pair workgroups");
+    STCHK(p->Hblk.ensure(sizeof(double) * 16 * 256 * nwg));
+    STCHK(p->Fpart.ensure(sizeof(double) * 24 * nwg));
+    STCHK(p->rho_part.ensure(sizeof(double) * (size_t)g.P * p->nslot));
+    return GINT_OK;
+}
+
+gint_status validate_species(int nspecies, const gint_species *species, double *rc_max)
+{
+    if (nspecies <= 0 || !species)
+        return fail(GINT_EINVAL, "nspecies must be >= 1 and species non-NULL");
+    *rc_max = 0.0;
+    for (int s = 0; s < nspecies; ++s) {
+        const gint_species &S = species[s];
+        if (S.nradial <= 0 || !S.radial)
+            return fail(GINT_EINVAL, "species %d has no radials", s);
+        if (S.nradial > kMaxRad)
+            return fail(GINT_EUNSUPPORTED, "species %d has %d radials (max %d)", s, S.nradial, kMaxRad);
+        int norb = 0;
+        for (int k = 0; k < S.nradial; ++k) {
+            const gint_radial &R = S.radial[k];
+            if (R.l < 0)
+                return fail(GINT_EINVAL, "species %d radial %d: l < 0", s, k);
+            if (R.l > 2)
+                return fail(GINT_EUNSUPPORTED, "species %d radial %d: l = %d (max 2)", s, k, R.l);
+            if (R.nr < 4)
+                return fail(GINT_EINVAL, "species %d radial %d: nr = %d (need >= 4)", s, k, R.nr);
+            if (!(R.dr > 0.0) || !std::isfinite(R.dr))
+                return fail(GINT_EINVAL, "species %d radial %d: dr must be positive", s, k);
+            if (!R.f)
+                return fail(GINT_EINVAL, "species %d radial %d: f is NULL", s, k);
+            if (!finite3(R.f, R.nr) || !std::isfinite(R.dfdr_0) || !std::isfinite(R.dfdr_rc))
+                return fail(GINT_EINVAL, "species %d radial %d: non-finite table", s, k);
+            norb += 2 * R.l + 1;
+            *rc_max = std::max(*rc_max, (R.nr - 1) * R.dr);
+        }
+        if (norb > kMaxOrb)
+            return fail(GINT_EUNSUPPORTED, "species %d has %d orbitals (max %d)", s, norb, kMaxOrb);
+    }
+    return GINT_OK;
+}
+
+gint_status validate_geometry(const double *lattice, const int *grid, Geo &g)
+{
+    if (!lattice || !grid)
+        return fail(GINT_EINVAL, "lattice and grid must be non-NULL");
+    if (!finite3(lattice, 9))
+        return fail(GINT_EINVAL, "lattice has non-finite entries");
+    for (int k = 0; k < 3; ++k)
+        if (grid[k] < 1)
+            return fail(GINT_EINVAL, "grid[%d] = %d must be >= 1", k, grid[k]);
+    const long long ng = (long long)grid[0] * grid[1] * grid[2];
+    if (ng >= 0x7fffffffLL)
+        return fail(GINT_EUNSUPPORTED, "mesh of %lld points exceeds 2^31", ng);
+    const double *a1 = lattice, *a2 = lattice + 3, *a3 = lattice + 6;
+    const double det = a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) - a1[1] * (a2[0] * a3[2] - a2[2] * a3[0]) +
+                       a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]);
+    double scale = 0.0;
+    for (int i = 0; i < 9; ++i)
+        scale = std::max(scale, std::fabs(lattice[i]));
+    if (!(std::fabs(det) > 1e-12 * scale * scale * scale) || scale == 0.0)
+        return fail(GINT_EINVAL, "lattice is singular");
+    std::memcpy(g.lat, lattice, sizeof(double) * 9);
+    const double *A[3] = {a1, a2, a3};
+    for (int i = 0; i < 3; ++i) {
+        const double *u = A[(i + 1) % 3], *v = A[(i + 2) % 3];
+        g.rec[3 * i + 0] = (u[1] * v[2] - u[2] * v[1]) / det;
+        g.rec[3 * i + 1] = (u[2] * v[0] - u[0] * v[2]) / det;
+        g.rec[3 * i + 2] = (u[0] * v[1] - u[1] * v[0]) / det;
+    }
+    g.ortho = (lattice[1] == 0.0 && lattice[2] == 0.0 && lattice[3] == 0.0 && lattice[5] == 0.0 &&
+               lattice[6] == 0.0 && lattice[7] == 0.0)
+                  ? 1
+                  : 0;
+    for (int k = 0; k < 3; ++k)
+        g.N[k] = grid[k];
+    return GINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gint_status_string(gint_status s)
+{
+    switch (s) {
+    case GINT_OK:
+        return "GINT_OK";
+    case GINT_EINVAL:
+        return "GINT_EINVAL: invalid argument";
+    case GINT_ENOMEM:
+        return "GINT_ENOMEM: allocation failed";
+    case GINT_EDEVICE:
+        return "GINT_EDEVICE: device unavailable or HIP error";
+    case GINT_EUNSUPPORTED:
+        return "GINT_EUNSUPPORTED: valid but unsupported request";
+    case GINT_ESTATE:
+        return "GINT_ESTATE: invalid plan state";
+    }
+    return "unknown gint_status";
+}
+
+const char *gint_last_error(void) { return g_last_error.c_str(); }
+
+gint_status gint_plan_create(const double lattice[9], const int grid[3], int nspecies, const gint_species *species,
+                             int natom, const int *species_of_atom, const double *positions, gint_precision prec,
+                             void *hip_stream, gint_plan *out)
+{
+    if (!out)
+        return fail(GINT_EINVAL, "out is NULL");
+    Geo g{};
+    STCHK(validate_geometry(lattice, grid, g));
+    double rc_max = 0.0;
+    STCHK(validate_species(nspecies, species, &rc_max));
+    if (natom < 1 || natom > kMaxAtoms)
+        return fail(GINT_EINVAL, "natom = %d outside [1, %d]", natom, kMaxAtoms);
+    if (!species_of_atom || !positions)
+        return fail(GINT_EINVAL, "species_of_atom and positions must be non-NULL");
+    for (int i = 0; i < natom; ++i)
+        if (species_of_atom[i] < 0 || species_of_atom[i] >= nspecies)
+            return fail(GINT_EINVAL, "species_of_atom[%d] = %d out of range", i, species_of_atom[i]);
+    if (!finite3(positions, 3LL * natom))
+        return fail(GINT_EINVAL, "positions have non-finite entries");
+    if ((int)prec < 0 || (int)prec > 3)
+        return fail(GINT_EINVAL, "unknown precision %d", (int)prec);
+    if (prec != GINT_FP64)
+        return fail(GINT_EUNSUPPORTED, "precision %d is not available in this build", (int)prec);
+    g.natom = natom;
+    g.ngroup = (natom + kGroup - 1) / kGroup;
+    const int bs0[3] = {4, 4, 2};
+    set_batch(g, bs0);
+    if (max_image_index(g, rc_max) >= 126.0)
+        return fail(GINT_EUNSUPPORTED, "cutoff spans more than 125 cells");
+
+    // host tables: radials sorted by l (stable), orbital slots, orbital maps
+    std::vector<DevRadial> rad;
+    std::vector<DevSpecies> sp(nspecies);
+    std::vector<double> knots, s0, sn;
+    int coef_off = 0;
+    for (int s = 0; s < nspecies; ++s) {
+        const gint_species &S = species[s];
+        sp[s].rad0 = (int)rad.size();
+        sp[s].nrad = S.nradial;
+        sp[s].rc = 0.0;
+        int orb = 0;
+        for (int l = 0; l <= 2; ++l)
+            for (int k = 0; k < S.nradial; ++k) {
+                const gint_radial &R = S.radial[k];
+                if (R.l != l)
+                    continue;
+                DevRadial d;
+                d.dr = R.dr;
+                d.inv_dr = 1.0 / R.dr;
+                d.rc = (R.nr - 1) * R.dr;
+                d.l = R.l;
+                d.nr = R.nr;
+                d.orb0 = orb;
+                d.coef_off = coef_off;
+                d.knot_off = (int)knots.size();
+                coef_off += 4 * (R.nr - 1);
+                knots.insert(knots.end(), R.f, R.f + R.nr);
+                s0.push_back(R.dfdr_0);
+                sn.push_back(R.dfdr_rc);
+                rad.push_back(d);
+                orb += 2 * l + 1;
+                sp[s].rc = std::max(sp[s].rc, d.rc);
+            }
+        sp[s].norb = orb;
+    }
+    std::vector<int> orb0(natom + 1);
+    int norb = 0;
+    for (int i = 0; i < natom; ++i) {
+        orb0[i] = norb;
+        norb += sp[species_of_atom[i]].norb;
+    }
+    orb0[natom] = norb;
+    std::vector<int> orb_atom(norb);
+    for (int i = 0; i < natom; ++i)
+        for (int o = orb0[i]; o < orb0[i + 1]; ++o)
+            orb_atom[o] = i;
+
+    int dev = 0;
+    STCHK(device_ok(&dev));
+
+    gint_plan p = new (std::nothrow) gint_plan_s();
+    if (!p)
+        return fail(GINT_ENOMEM, "host allocation failed");
+    p->device = dev;
+    p->stream = (hipStream_t)hip_stream;
+    p->prec = prec;
+    p->geo = g;
+    p->natom = natom;
+    p->norb = norb;
+    p->nrad = (int)rad.size();
+    p->nspecies = nspecies;
+    p->rc_max = rc_max;
+    p->dV = std::fabs(g.lat[0] * (g.lat[4] * g.lat[8] - g.lat[5] * g.lat[7]) -
+                      g.lat[1] * (g.lat[3] * g.lat[8] - g.lat[5] * g.lat[6]) +
+                      g.lat[2] * (g.lat[3] * g.lat[7] - g.lat[4] * g.lat[6])) /
+            ((double)g.N[0] * g.N[1] * g.N[2]);
+
+    auto upload = [&](DevBuf &b, const void *h, size_t bytes) -> gint_status {
+        STCHK(b.ensure(bytes));
+        if (bytes)
+            HIPCHK(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, p->stream));
+        return GINT_OK;
+    };
+    gint_status st = GINT_OK;
+    int npow2 = 1;
+    while (npow2 < natom)
+        npow2 <<= 1;
+    do {
+        if ((st = upload(p->rad, rad.data(), sizeof(DevRadial) * rad.size())) != GINT_OK) break;
+        if ((st = upload(p->sp, sp.data(), sizeof(DevSpecies) * sp.size())) != GINT_OK) break;
+        if ((st = upload(p->knots, knots.data(), sizeof(double) * knots.size())) != GINT_OK) break;
+        if ((st = upload(p->s0, s0.data(), sizeof(double) * s0.size())) != GINT_OK) break;
+        if ((st = upload(p->sn, sn.data(), sizeof(double) * sn.size())) != GINT_OK) break;
+        if ((st = upload(p->spc_in, species_of_atom, sizeof(int) * natom)) != GINT_OK) break;
+        if ((st = upload(p->pos_in, positions, sizeof(double) * 3 * natom)) != GINT_OK) break;
+        if ((st = upload(p->orb0, orb0.data(), sizeof(int) * (natom + 1))) != GINT_OK) break;
+        if ((st = upload(p->orb_atom, orb_atom.data(), sizeof(int) * std::max(norb, 1))) != GINT_OK) break;
+        if ((st = p->coef.ensure(sizeof(double) * coef_off)) != GINT_OK) break;
+        if ((st = p->scratch.ensure(sizeof(double) * 3 * knots.size())) != GINT_OK) break;
+        if ((st = p->spc.ensure(sizeof(int) * natom)) != GINT_OK) break;
+        if ((st = p->xw_in.ensure(sizeof(double) * 3 * natom)) != GINT_OK) break;
+        if ((st = p->xw.ensure(sizeof(double) * 3 * natom)) != GINT_OK) break;
+        if ((st = p->keys.ensure(sizeof(unsigned long long) * npow2)) != GINT_OK) break;
+        if ((st = p->perm.ensure(sizeof(int) * natom)) != GINT_OK) break;
+        if ((st = p->inv_perm.ensure(sizeof(int) * natom)) != GINT_OK) break;
+        hipError_t e = launch_spline(p->stream, p->nrad, p->rad.as<DevRadial>(), p->knots.as<double>(),
+                                     p->s0.as<double>(), p->sn.as<double>(), p->coef.as<double>(),
+                                     p->scratch.as<double>());
+        if (e != hipSuccess) {
+            st = fail(GINT_EDEVICE, "spline kernel launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if ((st = rebuild_lists(p, true)) != GINT_OK) break;
+        e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) {
+            st = fail(GINT_EDEVICE, "plan construction failed on the device: %s", hipGetErrorString(e));
+            break;
+        }
+    } while (0);
+    if (st != GINT_OK) {
+        (void)hipStreamSynchronize(p->stream);
+        p->magic = 0;
+        delete p;
+        return st;
+    }
+    *out = p;
+    return GINT_OK;
+}
+
+gint_status gint_plan_set_positions(gint_plan p, const double *positions)
+{
+    STCHK(check_plan(p));
+    if (!positions)
+        return fail(GINT_EINVAL, "positions is NULL");
+    if (!finite3(positions, 3LL * p->natom))
+        return fail(GINT_EINVAL, "positions have non-finite entries");
+    HIPCHK(hipSetDevice(p->device));
+    HIPCHK(hipMemcpyAsync(p->pos_in.p, positions, sizeof(double) * 3 * p->natom, hipMemcpyHostToDevice, p->stream));
+    STCHK(rebuild_lists(p, false));
+    return GINT_OK;
+}
+
+gint_status gint_plan_tune(gint_plan p, const int batch[3], int nchunk)
+{
+    STCHK(check_plan(p));
+    if (!batch)
+        return fail(GINT_EINVAL, "batch is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (batch[k] < 1)
+            return fail(GINT_EINVAL, "batch[%d] = %d must be >= 1", k, batch[k]);
+    const int P = batch[0] * batch[1] * batch[2];
+    if (P != 16 && P != 32)
+        return fail(GINT_EINVAL, "batch holds %d points (must be 16 or 32)", P);
+    if (nchunk < 0 || nchunk > 4096)
+        return fail(GINT_EINVAL, "nchunk = %d outside [0, 4096]", nchunk);
+    Geo g = p->geo;
+    set_batch(g, batch);
+    if (max_image_index(g, p->rc_max) >= 126.0)
+        return fail(GINT_EUNSUPPORTED, "cutoff spans more than 125 cells");
+    HIPCHK(hipSetDevice(p->device));
+    p->geo = g;
+    p->nchunk_req = nchunk;
+    STCHK(rebuild_lists(p, false));
+    return GINT_OK;
+}
+
+gint_status gint_plan_set_stream(gint_plan p, void *hip_stream)
+{
+    STCHK(check_plan(p));
+    p->stream = (hipStream_t)hip_stream;
+    return GINT_OK;
+}
+
+static gint_status build_H_impl(gint_plan p, const double *W, double wscale, double *H)
+{
+    STCHK(check_plan(p));
+    if (!W || !H)
+        return fail(GINT_EINVAL, "V and H must be non-NULL device pointers");
+    HIPCHK(hipSetDevice(p->device));
+    const Bins bn = p->bins();
+    const Basis B = p->basis();
+    HIPCHK(launch_pairs_H(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, p->Hblk.as<double>()));
+    HIPCHK(launch_H_convert(p->stream, p->geo, bn, B, p->norb, p->nchunk, p->Hblk.as<double>(), H));
+    return GINT_OK;
+}
+
+gint_status gint_build_H(gint_plan p, const double *V_dev, double *H_dev)
+{
+    STCHK(check_plan(p));
+    return build_H_impl(p, V_dev, p->dV, H_dev);
+}
+
+gint_status gint_build_H_weighted(gint_plan p, const double *w_dev, double *H_dev)
+{
+    return build_H_impl(p, w_dev, 1.0, H_dev);
+}
+
+gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
+{
+    STCHK(check_plan(p));
+    if (!D_dev || !rho_dev)
+        return fail(GINT_EINVAL, "D and rho must be non-NULL device pointers");
+    HIPCHK(hipSetDevice(p->device));
+    const Bins bn = p->bins();
+    const Basis B = p->basis();
+    HIPCHK(launch_pairs_rho(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, D_dev, p->norb,
+                            p->rho_part.as<double>()));
+    HIPCHK(launch_rho_reduce(p->stream, p->geo, bn, p->rho_part.as<double>(), rho_dev));
+    return GINT_OK;
+}
+
+static gint_status force_impl(gint_plan p, const double *W, double wscale, const double *D, double *dEdR)
+{
+    STCHK(check_plan(p));
+    if (!W || !D || !dEdR)
+        return fail(GINT_EINVAL, "W, D and dEdR must be non-NULL device pointers");
+    HIPCHK(hipSetDevice(p->device));
+    const Bins bn = p->bins();
+    const Basis B = p->basis();
+    HIPCHK(launch_pairs_force(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, D, p->norb,
+                              p->Fpart.as<double>()));
+    HIPCHK(launch_force_reduce(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, p->Fpart.as<double>(), dEdR));
+    return GINT_OK;
+}
+
+gint_status gint_force(gint_plan p, const double *W_dev, const double *D_dev, double *dEdR_dev)
+{
+    STCHK(check_plan(p));
+    return force_impl(p, W_dev, p->dV, D_dev, dEdR_dev);
+}
+
+gint_status gint_force_weighted(gint_plan p, const double *w_dev, const double *D_dev, double *dEdR_dev)
+{
+    return force_impl(p, w_dev, 1.0, D_dev, dEdR_dev);
+}
+
+gint_status gint_plan_sync(gint_plan p)
+{
+    STCHK(check_plan(p));
+    HIPCHK(hipSetDevice(p->device));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipGetLastError());
+    return GINT_OK;
+}
+
+gint_status gint_plan_work(gint_plan p, gint_work *out)
+{
+    STCHK(check_plan(p));
+    if (!out)
+        return fail(GINT_EINVAL, "out is NULL");
+    HIPCHK(hipSetDevice(p->device));
+    const int nblk = 2048;
+    STCHK(p->sums.ensure(sizeof(double) * 2 * nblk));
+    HIPCHK(launch_support_count(p->stream, p->geo, p->bins(), p->basis(), p->sums.as<double>(), nblk));
+    std::vector<double> h(2 * nblk);
+    HIPCHK(hipMemcpyAsync(h.data(), p->sums.p, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        s1 += h[2 * i];
+        s2 += h[2 * i + 1];
+    }
+    out->ngrid = (long long)p->geo.N[0] * p->geo.N[1] * p->geo.N[2];
+    out->nbatch = p->geo.nbatch;
+    out->nentry = p->nent;
+    out->npair = p->npair;
+    out->sum_ng = s1;
+    out->sum_ng2 = s2;
+    for (int k = 0; k < 3; ++k)
+        out->batch[k] = p->geo.bs[k];
+    out->nchunk = p->nchunk;
+    return GINT_OK;
+}
+
+int gint_norb(gint_plan p) { return (p && p->magic == kMagic) ? p->norb : -1; }
+int gint_natom(gint_plan p) { return (p && p->magic == kMagic) ? p->natom : -1; }
+double gint_dV(gint_plan p) { return (p && p->magic == kMagic) ? p->dV : -1.0; }
+
+void gint_plan_destroy(gint_plan p)
+{
+    if (!p || p->magic != kMagic)
+        return;
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    p->magic = 0;
+    delete p;
+}
+
+}  // extern "C"

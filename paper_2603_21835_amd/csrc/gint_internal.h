@@ -1,0 +1,119 @@
+// gint_internal.h -- device-side views and launchers shared by the host API
+// (gint_api.hip) and the kernels (gint_kernels.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gint {
+
+constexpr int kMaxOrb = 16;       // orbital slots per atom (l <= 2)
+constexpr int kMaxRad = 16;       // radials per species
+constexpr int kGroup = 4;         // atoms per group (output tile = 4x4 atom blocks)
+constexpr int kMaxP = 32;         // mesh points per batch
+constexpr int kMaxAtoms = 16384;
+constexpr int kRow = 18;          // doubles per staged (slot, point) row in LDS
+constexpr double kRTiny = 1e-12;  // |d| below this: the atom's own position
+
+// Mesh, lattice and batch shape.  Batches tile the mesh with bs[0] x bs[1] x
+// bs[2] points (n3 fastest inside a batch); edge batches are partial.
+struct Geo {
+    double lat[9];  // rows a1, a2, a3
+    double rec[9];  // rows b_i, a_i . b_j = delta_ij
+    int N[3];
+    int bs[3];
+    int nb[3];
+    int P;       // bs[0]*bs[1]*bs[2]
+    int nbatch;  // nb[0]*nb[1]*nb[2]
+    int ortho;   // lattice rows are along the cartesian axes
+    int natom;
+    int ngroup;  // ceil(natom / kGroup)
+};
+
+struct DevRadial {
+    double dr, inv_dr, rc;
+    int l, nr, orb0;  // orb0: first orbital slot of this radial inside the atom
+    int coef_off;     // offset (doubles) of the (nr-1) x 4 coefficient table
+    int knot_off;     // offset (doubles) of the knot values
+};
+
+struct DevSpecies {
+    int rad0, nrad, norb;
+    double rc;  // largest cutoff of the species
+};
+
+// Binning lists (all device pointers).
+struct Bins {
+    const int *bptr;        // nbatch+1: entries of each batch
+    const int *ent_atom;    // internal atom id, increasing within a batch
+    const int *ent_img;     // nent+1: image offsets of each entry
+    const int *img;         // packed signed 8-bit lattice multiples (n1, n2, n3)
+    const int *bgptr;       // nbatch+1: distinct groups of each batch
+    const int *bgrp;        // group ids, increasing within a batch
+    const long long *soff;  // nbatch+1: rho partial slots of each batch
+    const int *gptr;        // ngroup+1: batches of each group
+    const int *gbatch;      // batch ids, increasing within a group
+    const int *pairA;       // npair
+    const int *pairB;       // npair
+    const int *pair_index;  // ngroup*ngroup -> pair id or -1 (A <= B)
+};
+
+struct Basis {
+    const DevRadial *rad;
+    const DevSpecies *sp;
+    const double *coef;
+    const int *spc;      // species of each internal atom
+    const double *xw;    // wrapped cartesian position of each internal atom
+    const int *perm;     // internal -> input atom
+    const int *inv_perm; // input -> internal atom
+    const int *orb0;     // input atom -> first orbital (natom+1)
+    const int *orb_atom; // orbital -> input atom
+};
+
+// ---- launchers (gint_kernels.hip); each returns hipGetLastError() ----
+hipError_t launch_spline(hipStream_t s, int nrad, const DevRadial *rad, const double *knots,
+                         const double *s0, const double *sn, double *coef, double *scratch);
+hipError_t launch_wrap(hipStream_t s, const Geo &g, const double *pos_in, double *xw_in,
+                       unsigned long long *keys);
+hipError_t launch_sort_perm(hipStream_t s, int natom, unsigned long long *keys, int *perm,
+                            int *inv_perm);
+hipError_t launch_gather_internal(hipStream_t s, int natom, const int *perm, const double *xw_in,
+                                  const int *spc_in, double *xw, int *spc);
+hipError_t launch_bin_count(hipStream_t s, const Geo &g, const Basis &b, int *cnt_e, int *cnt_i,
+                            int *cnt_g, long long *cnt_s);
+hipError_t launch_bin_fill(hipStream_t s, const Geo &g, const Basis &b, const int *bptr,
+                           const int *iptr, const int *bgptr, int *ent_atom, int *ent_img, int *img,
+                           int *bgrp);
+hipError_t launch_scan_i32(hipStream_t s, const int *in, long long n, int *out);
+hipError_t launch_scan_i64(hipStream_t s, const long long *in, long long n, long long *out);
+hipError_t launch_group_count(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
+                              int *gcnt);
+hipError_t launch_group_fill(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
+                             const int *gptr, int *gbatch);
+hipError_t launch_fill_i32(hipStream_t s, int *p, long long n, int v);
+hipError_t launch_pair_mark(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
+                            int *mark);
+hipError_t launch_pair_list(hipStream_t s, int ngroup, const int *mark, const int *mark_scan,
+                            int *pair_index, int *pairA, int *pairB);
+hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
+                                double *sums /* 2 per block */, int nblocks);
+
+// Contractions over group pairs (output-stationary over atom-pair blocks).
+hipError_t launch_pairs_H(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                          int nchunk, const double *W, double wscale, double *Hblk);
+hipError_t launch_pairs_rho(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                            int nchunk, const double *D, int norb, double *rho_part);
+hipError_t launch_pairs_force(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
+                              int npair, int nchunk, const double *W, double wscale,
+                              const double *D, int norb, double *Fpart);
+
+// Cross-batch reductions and conversion to the output layouts.
+hipError_t launch_H_convert(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int norb,
+                            int nchunk, const double *Hblk, double *H);
+hipError_t launch_rho_reduce(hipStream_t s, const Geo &g, const Bins &bn, const double *rho_part,
+                             double *rho);
+hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
+                               int npair, int nchunk, const double *Fpart, double *dEdR);
+
+}  // namespace gint

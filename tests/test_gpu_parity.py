@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP64 bar (the target accuracy for the FP64 path): relative error <= 1e-10,
+measured as max|dH|/max|H|, ||d rho||_2/||rho||_2 and max|dF|/max|F|.  The
+GPU sums in a different order (per 4-atom group pair, per batch), so only
+roundoff separates the two.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gint_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_21835_amd as g
+
+    g.load_library()  # fails loudly if the HIP library is missing
+    return torch, torch.device("cuda:0")
+
+
+def _dev(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def _gpu_all(torch, dev, w, batch=None, nchunk=0):
+    import paper_2603_21835_amd as g
+
+    plan = g.GintPlan.from_workload(w)
+    if batch is not None:
+        plan.tune(batch, nchunk)
+    V = _dev(torch, dev, w.V)
+    D = _dev(torch, dev, w.D)
+    H = plan.build_H(V).cpu().numpy()
+    rho = plan.build_rho(D).cpu().numpy()
+    F = plan.force(V, D).cpu().numpy()
+    plan.sync()
+    return plan, H, rho, F
+
+
+def _rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _compare_full(oracle_mod, w, H, rho, F):
+    o = oracle_mod.Oracle.from_workload(w)
+    Ho, rho_o, Fo = o.H(w.V), o.rho(w.D), o.force(w.V, w.D)
+    eH, er, eF = _rel_max(H, Ho), _rel_l2(rho, rho_o), _rel_max(F, Fo)
+    _say(f"  {w.name}: H {eH:.2e}  rho {er:.2e}  F {eF:.2e}")
+    assert eH <= TOL and er <= TOL and eF <= TOL, (eH, er, eF)
+    assert np.array_equal(H, H.T), "H must be exactly symmetric"
+
+
+def _triclinic_two_species():
+    sp = gi.Species([gi.nao_like_radial(0, 0.4, 5.0), gi.nao_like_radial(1, 0.9, 5.0),
+                     gi.nao_like_radial(2, 0.7, 5.0)])
+    lat = np.array([[6.0, 0.0, 0.0], [0.7, 6.5, 0.0], [-0.4, 0.3, 7.0]])
+    pos = np.array([[0.3, 0.2, 0.1], [3.1, 2.7, 3.9], [5.0, 5.5, 0.2]])
+    return gi.small_cell(pos, lat, (15, 17, 18), [sp, gi.sz_species(4.0)], species_of_atom=[0, 1, 0],
+                         n_waves=6, nocc=3, seed=7)
+
+
+def _long_range_tiny():
+    sp = gi.Species([gi.nao_like_radial(0, 0.08, 5.5), gi.nao_like_radial(1, 0.1, 5.5),
+                     gi.nao_like_radial(2, 0.12, 5.5)])
+    lat = np.array([[4.0, 0.0, 0.0], [0.0, 4.4, 0.0], [0.5, 0.0, 4.2]])
+    pos = np.array([[0.2, 0.3, 0.1], [2.1, 2.4, 1.9]])
+    return gi.small_cell(pos, lat, (7, 8, 8), [sp], n_waves=5, nocc=4, seed=9)
+
+
+def _ragged_five_atoms():
+    # 5 atoms (one group has a single atom), mesh not a multiple of any batch
+    rng = np.random.default_rng(3)
+    lat = np.diag([9.0, 10.0, 11.0])
+    pos = rng.uniform(0, 9, (5, 3))
+    return gi.small_cell(pos, lat, (13, 11, 19), [gi.dzp_species(rc=4.5)], n_waves=6, nocc=5, seed=5)
+
+
+def _vacuum_single_atom():
+    # one atom in a big box: most batches are empty
+    lat = np.diag([16.0, 16.0, 16.0])
+    pos = np.array([[3.0, 4.0, 5.0]])
+    return gi.small_cell(pos, lat, (24, 24, 24), [gi.dzp_species(rc=4.0)], n_waves=4, nocc=2, seed=6)
+
+
+def test_si8_sz_full(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    w = gi.si8_sz()
+    _say(f"case si8_sz grid {w.grid}")
+    plan, H, rho, F = _gpu_all(torch, dev, w)
+    _compare_full(oracle_mod, w, H, rho, F)
+
+
+@pytest.mark.parametrize("make", [_triclinic_two_species, _long_range_tiny, _ragged_five_atoms,
+                                  _vacuum_single_atom])
+def test_small_cells_full(oracle_mod, torch_dev, make):
+    torch, dev = torch_dev
+    w = make()
+    _say(f"case {make.__name__} grid {w.grid} natom {w.natom}")
+    plan, H, rho, F = _gpu_all(torch, dev, w)
+    _compare_full(oracle_mod, w, H, rho, F)
+
+
+@pytest.mark.parametrize("batch,nchunk", [((4, 4, 2), 1), ((2, 2, 4), 0), ((4, 2, 2), 3), ((2, 4, 4), 0)])
+def test_batch_shapes_and_chunks(oracle_mod, torch_dev, batch, nchunk):
+    torch, dev = torch_dev
+    w = _ragged_five_atoms()
+    _say(f"case ragged batch {batch} nchunk {nchunk}")
+    plan, H, rho, F = _gpu_all(torch, dev, w, batch=batch, nchunk=nchunk)
+    _compare_full(oracle_mod, w, H, rho, F)
+
+
+def test_nonsymmetric_density_matrix(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    w = _triclinic_two_species()
+    rng = np.random.default_rng(12)
+    w.D = rng.standard_normal((w.norb, w.norb)) * 0.2
+    _say("case nonsymmetric D")
+    plan, H, rho, F = _gpu_all(torch, dev, w)
+    _compare_full(oracle_mod, w, H, rho, F)
+
+
+def test_repeat_calls_bitwise_identical(torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si8_sz()
+    _say("case determinism si8")
+    plan = g.GintPlan.from_workload(w)
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    a = [plan.build_H(V).cpu().numpy(), plan.build_rho(D).cpu().numpy(), plan.force(V, D).cpu().numpy()]
+    b = [plan.build_H(V).cpu().numpy(), plan.build_rho(D).cpu().numpy(), plan.force(V, D).cpu().numpy()]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_set_positions_matches_fresh_plan(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _ragged_five_atoms()
+    _say("case set_positions")
+    plan = g.GintPlan.from_workload(w)
+    rng = np.random.default_rng(1)
+    w.positions = w.positions + rng.normal(0, 0.3, w.positions.shape) + w.lattice[0]
+    plan.set_positions(w.positions)
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    H, rho, F = plan.build_H(V).cpu().numpy(), plan.build_rho(D).cpu().numpy(), plan.force(V, D).cpu().numpy()
+    _compare_full(oracle_mod, w, H, rho, F)
+
+
+def test_si64_dzp_sampled(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    w = gi.si64_dzp()
+    _say(f"case si64_dzp grid {w.grid}")
+    plan, H, rho, F = _gpu_all(torch, dev, w)
+    o = oracle_mod.Oracle.from_workload(w)
+    atoms = [0, 17, 42, 63]
+    for I in atoms:
+        rows = o.H_rows(w.V, I, I + 1)
+        r0 = o.atom_orb0[I]
+        e = _rel_max(H[r0:r0 + rows.shape[0]], rows)
+        _say(f"  H rows atom {I}: {e:.2e}")
+        assert e <= TOL
+    rng = np.random.default_rng(0)
+    idx = rng.choice(w.ngrid, 20000, replace=False)
+    er = _rel_l2(rho[idx], o.rho(w.D, idx))
+    _say(f"  rho sampled: {er:.2e}")
+    assert er <= TOL
+    Fo = o.force(w.V, w.D, atoms)
+    eF = _rel_max(F[atoms], Fo)
+    _say(f"  F sampled: {eF:.2e}")
+    assert eF <= TOL
+    # invariants at full size: E = Tr(D H) and dV sum rho = Tr(D S)
+    E = plan.dV * float(np.dot(w.V, rho))
+    assert abs(E - np.sum(w.D * H)) <= 1e-11 * np.sum(np.abs(w.D * H))
