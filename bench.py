@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the grid-integration step on one MI355X.
+
+One step is the whole hot path on the Si-512 DZP workload (4x4x4 diamond
+supercell, atoms displaced N(0, 0.05 bohr), 6656 orbitals, rc = 8 bohr,
+192^3 mesh): re-binning of the batch/atom lists for the current positions,
+the local-potential matrix H, the density rho and the grid force dE/dR
+(the cal_gint_vl + cal_gint_rho + cal_gint_fvl triple that the paper times
+per step in its Gint scaling test, Sec. 4.3.1).  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def _kernel_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("gint_kernels.hip", "gint_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_21835_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sha") != _kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the same
+    workload and extrapolate to one full step: H rows and dE/dR of one atom
+    per oracle thread (the oracle is parallel over atoms for both) summed
+    over a random quarter of the mesh points, and rho at 20000 mesh points
+    (parallel over points)."""
+    import oracle
+
+    o = oracle.Oracle.from_workload(w)
+    nthr = oracle.num_threads()
+    rng = np.random.default_rng(0)
+    na = min(w.natom, max(nthr, 1))
+    lo = int(rng.integers(0, w.natom - na + 1))
+    atoms = np.arange(lo, lo + na, dtype=np.int32)
+    npts = min(20000, w.ngrid)
+    idx = np.sort(rng.choice(w.ngrid, npts, replace=False))
+    nsub = max(1, w.ngrid // 4)
+    sub = np.sort(rng.choice(w.ngrid, nsub, replace=False))
+    t = time.perf_counter()
+    o.H_rows(w.V, lo, lo + na, points=sub)
+    tH = time.perf_counter() - t
+    t = time.perf_counter()
+    o.force(w.V, w.D, atoms, points=sub)
+    tF = time.perf_counter() - t
+    t = time.perf_counter()
+    o.rho(w.D, idx)
+    tR = time.perf_counter() - t
+    t_step = (tH + tF) * (w.natom / na) * (w.ngrid / nsub) + tR * w.ngrid / npts
+    return {
+        "value": w.ngrid / t_step,
+        "unit": "grid pts/s",
+        "cores": int(nthr),
+        "kind": "oracle",
+        "sample": (f"{w.name}: H rows of atoms {lo}..{lo + na - 1} ({tH:.1f} s) and dE/dR of the same "
+                   f"{na} atoms ({tF:.1f} s), both over {nsub} random mesh points; rho at {npts} random "
+                   f"mesh points ({tR:.1f} s); "
+                   f"extrapolated linearly to all {w.natom} atoms and {w.ngrid} points = "
+                   f"{t_step:.0f} s per step"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="si512", choices=["si512", "si64", "si8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
+              f"sharding of this path is a design note, not a built path).", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs as a single process on one GPU.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gint_inputs as gi
+    import paper_2603_21835_amd as g
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    g.load_library()
+    dev = torch.device("cuda:0")
+    _progress(f"generating {args.workload}")
+    w = {"si512": gi.si512_dzp, "si64": gi.si64_dzp, "si8": gi.si8_sz}[args.workload]()
+    _progress("plan")
+
+    plan = g.GintPlan.from_workload(w)
+    V = torch.from_numpy(w.V).to(dev)
+    D = torch.from_numpy(w.D).to(dev)
+    H = torch.empty((plan.norb, plan.norb), dtype=torch.float64, device=dev)
+    rho = torch.empty(plan.ngrid, dtype=torch.float64, device=dev)
+    F = torch.empty((plan.natom, 3), dtype=torch.float64, device=dev)
+    work = plan.work()
+
+    def step():
+        plan.set_positions(w.positions)
+        plan.build_H(V, out=H)
+        plan.build_rho(D, out=rho)
+        plan.force(V, D, out=F)
+
+    _progress(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _progress(f"timed {args.steps} steps")
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = plan.timing()
+    plan.set_timing(False)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = w.ngrid / ((t1 - t0) / args.steps)
+
+    s1, s2 = work["sum_ng"], work["sum_ng2"]
+    flops = {"H_pairs": 2 * s2, "rho_pairs": 2 * s2 + 2 * s1, "force_pairs": 2 * s2 + 6 * s1}
+    kernels = {}
+    for k, (ms, n) in timing.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        kernels[k] = {"avg_ms": round(avg, 4), "launches": n}
+        if k in flops:
+            kernels[k]["alg_tflops"] = round(flops[k] / (avg * 1e-3) / 1e12, 3)
+    dom = max(kernels, key=lambda k: timing[k][0])
+    roof = None
+    if dom in flops:
+        ach = flops[dom] / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": _traffic(dom, args.workload),
+                "kernel": dom, "alg_flops_per_launch": flops[dom]}
+
+    # full-size consistency check: dV sum V rho == Tr(D H)  (adjoint identity)
+    E1 = plan.dV * float(torch.dot(V, rho))
+    E2 = float(torch.sum(D * H))
+    check = abs(E1 - E2) / max(abs(E2), 1e-300)
+
+    out = {
+        "metric": "gint grid pts/s + MFMA util: FP64 vs mixed precision at stated |dH| (Si-512)",
+        "value": value,
+        "unit": "grid pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh {'x'.join(map(str, w.grid))}, "
+                        "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR",
+            "batch": list(work["batch"]), "nchunk": work["nchunk"], "group_pairs": work["npair"],
+            "sum_ng2": s2, "sum_ng": s1,
+        },
+        "roofline": roof,
+        "kernels": kernels,
+        "check_E_equals_trDH": check,
+    }
+    if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

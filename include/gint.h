@@ -162,6 +162,28 @@ gint_status gint_force(gint_plan plan, const double *W_dev, const double *D_dev,
 gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const double *D_dev,
                                 double *dEdR_dev);
 
+/* Kernel classes reported by gint_plan_timing. */
+enum {
+    GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
+    GINT_K_H_PAIRS = 1,   /* H contraction (group pairs)                            */
+    GINT_K_H_CONVERT = 2, /* H reduction over chunks and dense symmetric output     */
+    GINT_K_RHO_PAIRS = 3, /* rho contraction (group pairs)                          */
+    GINT_K_RHO_REDUCE = 4,/* rho reduction over group pairs                         */
+    GINT_K_F_PAIRS = 5,   /* force contraction (group pairs)                        */
+    GINT_K_F_REDUCE = 6,  /* force reduction over group pairs                       */
+    GINT_NKERNEL = 7
+};
+
+/* Enable (1) or disable (0) timing: each kernel launch of later calls is
+ * bracketed by HIP events recorded on the plan's stream.  Enabling resets the
+ * accumulated totals. */
+gint_status gint_plan_set_timing(gint_plan plan, int enable);
+
+/* Accumulated device time (ms) and launch count per kernel class since
+ * timing was enabled (synchronises the stream).  ms and launches are host
+ * arrays of GINT_NKERNEL entries. */
+gint_status gint_plan_timing(gint_plan plan, double *ms, int *launches);
+
 /* Wait for the plan's stream and report any asynchronous device error. */
 gint_status gint_plan_sync(gint_plan plan);
 

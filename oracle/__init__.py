@@ -59,9 +59,9 @@ def _load():
     lib.oracle_radial.restype = ctypes.c_double
     lib.oracle_ylm.argtypes = [ctypes.c_int, dp, dp]
     lib.oracle_phi.argtypes = [P, dp, dp, dp]
-    lib.oracle_H_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_H_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, lp, dp]
     lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
-    lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, dp]
+    lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, ctypes.c_long, lp, dp]
     lib.oracle_set_positions.argtypes = [P, dp]
     lib.oracle_support_stats.argtypes = [P, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -163,12 +163,22 @@ class Oracle:
         return a.value, b.value
 
     # -- integrals -------------------------------------------------------------
-    def H_rows(self, V, I0: int, I1: int) -> np.ndarray:
+    @staticmethod
+    def _points(points):
+        if points is None:
+            return 0, None, None
+        idx = np.ascontiguousarray(points, dtype=np.int64)
+        return idx.size, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), idx
+
+    def H_rows(self, V, I0: int, I1: int, points: Optional[Sequence[int]] = None) -> np.ndarray:
+        """Rows of H for atoms I0..I1-1; the mesh sum runs over ``points``
+        (all mesh points when None)."""
         V = np.ascontiguousarray(V, dtype=np.float64)
         assert V.size == self.ngrid
         n = int(self.atom_orb0[I1] - self.atom_orb0[I0])
         out = np.zeros((n, self.norb))
-        self._lib.oracle_H_rows(self._ctx, _dp(V), int(I0), int(I1), _dp(out))
+        npts, ip_, keep = self._points(points)
+        self._lib.oracle_H_rows(self._ctx, _dp(V), int(I0), int(I1), npts, ip_, _dp(out))
         return out
 
     def H(self, V) -> np.ndarray:
@@ -187,13 +197,16 @@ class Oracle:
                                  idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))
         return out
 
-    def force(self, V, D, atoms: Optional[Sequence[int]] = None) -> np.ndarray:
-        """dE/dR_I (not the force) for the chosen atoms, E = dV sum V rho."""
+    def force(self, V, D, atoms: Optional[Sequence[int]] = None,
+              points: Optional[Sequence[int]] = None) -> np.ndarray:
+        """dE/dR_I (not the force) for the chosen atoms, E = dV sum V rho;
+        the mesh sum runs over ``points`` (all mesh points when None)."""
         V = np.ascontiguousarray(V, dtype=np.float64)
         D = np.ascontiguousarray(D, dtype=np.float64)
-        sel = np.arange(self.natom, dtype=np.int32) if atoms is None else np.asarray(atoms, dtype=np.int32)
+        sel = np.arange(self.natom, dtype=np.int32) if atoms is None else np.ascontiguousarray(atoms, dtype=np.int32)
         out = np.zeros((sel.size, 3))
-        self._lib.oracle_force(self._ctx, _dp(V), _dp(D), int(sel.size), _ip(sel), _dp(out))
+        npts, ip_, keep = self._points(points)
+        self._lib.oracle_force(self._ctx, _dp(V), _dp(D), int(sel.size), _ip(sel), npts, ip_, _dp(out))
         return out
 
     def energy(self, V, D) -> float:

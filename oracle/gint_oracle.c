@@ -490,9 +490,11 @@ void oracle_support_stats(void *p, double *sum_n, double *sum_n2)
 
 /*
  * Rows of H for atoms I in [I0, I1): out is (orb rows of I0..I1-1) x norb,
- * row-major, overwritten.  Parallel over atoms; each thread owns its rows.
+ * row-major, overwritten.  The mesh sum runs over the points idx[0..npts)
+ * (all points when idx == NULL).  Parallel over atoms; each thread owns its
+ * rows.
  */
-void oracle_H_rows(void *p, const double *V, int I0, int I1, double *out)
+void oracle_H_rows(void *p, const double *V, int I0, int I1, long npts, const long *idx, double *out)
 {
     const octx *c = (const octx *)p;
     const int norb = c->norb;
@@ -506,7 +508,9 @@ void oracle_H_rows(void *p, const double *V, int I0, int I1, double *out)
         for (int I = I0; I < I1; ++I) {
             const int nI = c->sp_norb[c->spc[I]];
             double *rows = out + (size_t)(c->atom_orb0[I] - row0) * norb;
-            for (long g = 0; g < c->ng; ++g) {
+            const long nq = idx ? npts : c->ng;
+            for (long q = 0; q < nq; ++q) {
+                const long g = idx ? idx[q] : q;
                 double r[3];
                 mesh_point(c, g, r);
                 if (atom_phi(c, I, r, phiI, NULL) == 0)
@@ -572,10 +576,12 @@ void oracle_rho(void *p, const double *D, long npts, const long *idx, double *rh
 }
 
 /*
- * dE/dR for the atoms listed in sel[0..nsel), E = dV sum_g V_g rho_g.
+ * dE/dR for the atoms listed in sel[0..nsel), E = dV sum_g V_g rho_g, with
+ * the mesh sum over idx[0..npts) (all points when idx == NULL).
  * out is nsel x 3.  Parallel over the selected atoms.
  */
-void oracle_force(void *p, const double *V, const double *D, int nsel, const int *sel, double *out)
+void oracle_force(void *p, const double *V, const double *D, int nsel, const int *sel, long npts, const long *idx,
+                  double *out)
 {
     const octx *c = (const octx *)p;
     const int norb = c->norb;
@@ -591,7 +597,9 @@ void oracle_force(void *p, const double *V, const double *D, int nsel, const int
             const int nI = c->sp_norb[c->spc[I]];
             const int i0 = c->atom_orb0[I];
             double acc[3] = {0.0, 0.0, 0.0};
-            for (long g = 0; g < c->ng; ++g) {
+            const long nq = idx ? npts : c->ng;
+            for (long qq = 0; qq < nq; ++qq) {
+                const long g = idx ? idx[qq] : qq;
                 double r[3];
                 mesh_point(c, g, r);
                 if (atom_phi(c, I, r, tmp, gI) == 0)

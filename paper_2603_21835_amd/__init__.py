@@ -30,7 +30,9 @@ EXPORTS = (
     "gint_build_H", "gint_build_H_weighted", "gint_build_rho", "gint_force",
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
+    "gint_plan_set_timing", "gint_plan_timing",
 )
+KERNELS = ("bin", "H_pairs", "H_convert", "rho_pairs", "rho_reduce", "force_pairs", "force_reduce")
 
 
 class GintError(RuntimeError):
@@ -100,6 +102,10 @@ def load_library(path: str = LIB_PATH):
     lib.gint_status_string.argtypes = [ctypes.c_int]
     lib.gint_last_error.restype = ctypes.c_char_p
     lib.gint_last_error.argtypes = []
+    lib.gint_plan_set_timing.restype = st
+    lib.gint_plan_set_timing.argtypes = [P, ctypes.c_int]
+    lib.gint_plan_timing.restype = st
+    lib.gint_plan_timing.argtypes = [P, dp, ip]
     lib.gint_plan_destroy.restype = None
     lib.gint_plan_destroy.argtypes = [P]
     _lib = lib
@@ -221,6 +227,16 @@ class GintPlan:
         _check(self._lib.gint_plan_work(self._handle(), ctypes.byref(w)))
         return {"ngrid": w.ngrid, "nbatch": w.nbatch, "nentry": w.nentry, "npair": w.npair,
                 "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nchunk": w.nchunk}
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.gint_plan_set_timing(self._handle(), 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """{kernel: (total_ms, launches)} since timing was enabled."""
+        ms = np.zeros(len(KERNELS))
+        n = np.zeros(len(KERNELS), dtype=np.int32)
+        _check(self._lib.gint_plan_timing(self._handle(), _dptr(ms), _iptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     # -- the three grid integrals ----------------------------------------------------
     def build_H(self, V, out=None, weighted: bool = False):

@@ -108,6 +108,27 @@ struct gint_plan_s {
     // work buffers
     DevBuf Hblk, rho_part, Fpart, sums, readback;
 
+    // optional per-kernel timing (events on the plan's stream)
+    bool timing = false;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> event_pool;
+    double timed_ms[GINT_NKERNEL] = {0};
+    int timed_n[GINT_NKERNEL] = {0};
+
+    ~gint_plan_s()
+    {
+        for (auto &m : marks) {
+            (void)hipEventDestroy(m.a);
+            (void)hipEventDestroy(m.b);
+        }
+        for (auto e : event_pool)
+            (void)hipEventDestroy(e);
+    }
+
     Basis basis() const
     {
         Basis b;
@@ -202,6 +223,59 @@ double max_image_index(const Geo &g, double rc)
     return m;
 }
 
+hipEvent_t take_event(gint_plan p)
+{
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Fold finished marks into the totals and recycle their events.
+gint_status drain_marks(gint_plan p)
+{
+    if (p->marks.empty())
+        return GINT_OK;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (auto &m : p->marks) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, m.a, m.b));
+        p->timed_ms[m.kind] += ms;
+        p->timed_n[m.kind] += 1;
+        p->event_pool.push_back(m.a);
+        p->event_pool.push_back(m.b);
+    }
+    p->marks.clear();
+    return GINT_OK;
+}
+
+// Run `launch` (returns hipError_t), bracketed by events when timing is on.
+template <typename F>
+gint_status timed(gint_plan p, int kind, F launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (p->timing) {
+        if (p->marks.size() > 4096)
+            STCHK(drain_marks(p));
+        a = take_event(p);
+        b = take_event(p);
+        if (!a || !b)
+            return fail(GINT_EDEVICE, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(a, p->stream));
+    }
+    HIPCHK(launch());
+    if (p->timing) {
+        HIPCHK(hipEventRecord(b, p->stream));
+        p->marks.push_back({kind, a, b});
+    }
+    return GINT_OK;
+}
+
 template <typename T>
 gint_status read_scalar(gint_plan p, const T *dev, T *host)
 {
@@ -233,8 +307,10 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->bgptr.ensure(sizeof(int) * (nb + 1)));
     STCHK(p->soff.ensure(sizeof(long long) * (nb + 1)));
     const Basis B = p->basis();
-    HIPCHK(launch_bin_count(s, g, B, p->cnt_e.as<int>(), p->cnt_i.as<int>(), p->cnt_g.as<int>(),
-                            p->cnt_s.as<long long>()));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_bin_count(s, g, B, p->cnt_e.as<int>(), p->cnt_i.as<int>(), p->cnt_g.as<int>(),
+                                p->cnt_s.as<long long>());
+    }));
     HIPCHK(launch_scan_i32(s, p->cnt_e.as<int>(), nb, p->bptr.as<int>()));
     HIPCHK(launch_scan_i32(s, p->cnt_i.as<int>(), nb, p->iptr.as<int>()));
     HIPCHK(launch_scan_i32(s, p->cnt_g.as<int>(), nb, p->bgptr.as<int>()));
@@ -259,20 +335,26 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->ent_img.ensure(sizeof(int) * (p->nent + 1)));
     STCHK(p->img.ensure(sizeof(int) * (p->nimg + 1)));
     STCHK(p->bgrp.ensure(sizeof(int) * (p->ngb + 1)));
-    HIPCHK(launch_bin_fill(s, g, B, p->bptr.as<int>(), p->iptr.as<int>(), p->bgptr.as<int>(), p->ent_atom.as<int>(),
-                           p->ent_img.as<int>(), p->img.as<int>(), p->bgrp.as<int>()));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_bin_fill(s, g, B, p->bptr.as<int>(), p->iptr.as<int>(), p->bgptr.as<int>(),
+                               p->ent_atom.as<int>(), p->ent_img.as<int>(), p->img.as<int>(), p->bgrp.as<int>());
+    }));
 
     // per-group batch lists
     const int ng = g.ngroup;
     STCHK(p->gcnt.ensure(sizeof(int) * ng));
     STCHK(p->gptr.ensure(sizeof(int) * (ng + 1)));
-    HIPCHK(launch_group_count(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gcnt.as<int>()));
+    STCHK(timed(p, GINT_K_BIN,
+                [&] { return launch_group_count(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gcnt.as<int>()); }));
     HIPCHK(launch_scan_i32(s, p->gcnt.as<int>(), ng, p->gptr.as<int>()));
     int tg = 0;
     STCHK(read_scalar(p, p->gptr.as<int>() + ng, &tg));
     p->ngbatch = tg;
     STCHK(p->gbatch.ensure(sizeof(int) * (p->ngbatch + 1)));
-    HIPCHK(launch_group_fill(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gptr.as<int>(), p->gbatch.as<int>()));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_group_fill(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gptr.as<int>(),
+                                 p->gbatch.as<int>());
+    }));
 
     // active group pairs
     const long long nn = (long long)ng * ng;
@@ -280,7 +362,8 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->mscan.ensure(sizeof(int) * (nn + 1)));
     STCHK(p->pair_index.ensure(sizeof(int) * nn));
     HIPCHK(launch_fill_i32(s, p->mark.as<int>(), nn, 0));
-    HIPCHK(launch_pair_mark(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->mark.as<int>()));
+    STCHK(timed(p, GINT_K_BIN,
+                [&] { return launch_pair_mark(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->mark.as<int>()); }));
     HIPCHK(launch_scan_i32(s, p->mark.as<int>(), nn, p->mscan.as<int>()));
     int tp = 0;
     STCHK(read_scalar(p, p->mscan.as<int>() + nn, &tp));
@@ -605,8 +688,12 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    HIPCHK(launch_pairs_H(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, p->Hblk.as<double>()));
-    HIPCHK(launch_H_convert(p->stream, p->geo, bn, B, p->norb, p->nchunk, p->Hblk.as<double>(), H));
+    STCHK(timed(p, GINT_K_H_PAIRS, [&] {
+        return launch_pairs_H(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, p->Hblk.as<double>());
+    }));
+    STCHK(timed(p, GINT_K_H_CONVERT, [&] {
+        return launch_H_convert(p->stream, p->geo, bn, B, p->norb, p->nchunk, p->Hblk.as<double>(), H);
+    }));
     return GINT_OK;
 }
 
@@ -629,9 +716,12 @@ gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    HIPCHK(launch_pairs_rho(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, D_dev, p->norb,
-                            p->rho_part.as<double>()));
-    HIPCHK(launch_rho_reduce(p->stream, p->geo, bn, p->rho_part.as<double>(), rho_dev));
+    STCHK(timed(p, GINT_K_RHO_PAIRS, [&] {
+        return launch_pairs_rho(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, D_dev, p->norb,
+                                p->rho_part.as<double>());
+    }));
+    STCHK(timed(p, GINT_K_RHO_REDUCE,
+                [&] { return launch_rho_reduce(p->stream, p->geo, bn, p->rho_part.as<double>(), rho_dev); }));
     return GINT_OK;
 }
 
@@ -643,9 +733,13 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    HIPCHK(launch_pairs_force(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, D, p->norb,
-                              p->Fpart.as<double>()));
-    HIPCHK(launch_force_reduce(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, p->Fpart.as<double>(), dEdR));
+    STCHK(timed(p, GINT_K_F_PAIRS, [&] {
+        return launch_pairs_force(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, D, p->norb,
+                                  p->Fpart.as<double>());
+    }));
+    STCHK(timed(p, GINT_K_F_REDUCE, [&] {
+        return launch_force_reduce(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, p->Fpart.as<double>(), dEdR);
+    }));
     return GINT_OK;
 }
 
@@ -695,6 +789,33 @@ gint_status gint_plan_work(gint_plan p, gint_work *out)
     for (int k = 0; k < 3; ++k)
         out->batch[k] = p->geo.bs[k];
     out->nchunk = p->nchunk;
+    return GINT_OK;
+}
+
+gint_status gint_plan_set_timing(gint_plan p, int enable)
+{
+    STCHK(check_plan(p));
+    HIPCHK(hipSetDevice(p->device));
+    STCHK(drain_marks(p));
+    p->timing = enable != 0;
+    for (int k = 0; k < GINT_NKERNEL; ++k) {
+        p->timed_ms[k] = 0.0;
+        p->timed_n[k] = 0;
+    }
+    return GINT_OK;
+}
+
+gint_status gint_plan_timing(gint_plan p, double *ms, int *launches)
+{
+    STCHK(check_plan(p));
+    if (!ms || !launches)
+        return fail(GINT_EINVAL, "ms and launches must be non-NULL");
+    HIPCHK(hipSetDevice(p->device));
+    STCHK(drain_marks(p));
+    for (int k = 0; k < GINT_NKERNEL; ++k) {
+        ms[k] = p->timed_ms[k];
+        launches[k] = p->timed_n[k];
+    }
     return GINT_OK;
 }
 

@@ -125,3 +125,18 @@ def test_support_stats_si8(oracle_mod):
     mean_atoms = s1 / w.ngrid / 4
     assert 4.0 < mean_atoms <= 8.0
     assert s2 >= s1 * s1 / w.ngrid  # Cauchy-Schwarz
+
+
+def test_point_subsets_add_up(oracle_mod):
+    # the sampled forms are the same mesh sums restricted to a point subset
+    w = gi.si8_sz()
+    o = oracle_mod.Oracle.from_workload(w)
+    rng = np.random.default_rng(2)
+    perm = rng.permutation(w.ngrid)
+    a, b = np.sort(perm[: w.ngrid // 3]), np.sort(perm[w.ngrid // 3:])
+    Hfull = o.H_rows(w.V, 2, 5)
+    np.testing.assert_allclose(o.H_rows(w.V, 2, 5, a) + o.H_rows(w.V, 2, 5, b), Hfull,
+                               rtol=0, atol=1e-14 * np.abs(Hfull).max())
+    Ffull = o.force(w.V, w.D, [1, 6])
+    np.testing.assert_allclose(o.force(w.V, w.D, [1, 6], a) + o.force(w.V, w.D, [1, 6], b), Ffull,
+                               rtol=0, atol=1e-13 * np.abs(Ffull).max())
