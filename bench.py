@@ -155,7 +155,7 @@ def main():
     value = w.ngrid / ((t1 - t0) / args.steps)
 
     s1, s2 = work["sum_ng"], work["sum_ng2"]
-    flops = {"H_pairs": 2 * s2, "rho_pairs": 2 * s2 + 2 * s1, "force_pairs": 2 * s2 + 6 * s1}
+    flops = {"H_pairs": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1}
     kernels = {}
     for k, (ms, n) in timing.items():
         if n == 0:

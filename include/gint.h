@@ -165,12 +165,12 @@ gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const doubl
 /* Kernel classes reported by gint_plan_timing. */
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
-    GINT_K_H_PAIRS = 1,   /* H contraction (group pairs)                            */
+    GINT_K_H_PAIRS = 1,   /* H contraction (atom-group pairs over their batches)     */
     GINT_K_H_CONVERT = 2, /* H reduction over chunks and dense symmetric output     */
-    GINT_K_RHO_PAIRS = 3, /* rho contraction (group pairs)                          */
-    GINT_K_RHO_REDUCE = 4,/* rho reduction over group pairs                         */
-    GINT_K_F_PAIRS = 5,   /* force contraction (group pairs)                        */
-    GINT_K_F_REDUCE = 6,  /* force reduction over group pairs                       */
+    GINT_K_RHO = 3,       /* rho contraction (one workgroup per mesh batch)         */
+    GINT_K_PACK = 4,      /* D + D^T packed into matrix-core fragments (rho, force) */
+    GINT_K_FORCE = 5,     /* force contraction (one workgroup per mesh batch)       */
+    GINT_K_F_REDUCE = 6,  /* force reduction per atom                               */
     GINT_NKERNEL = 7
 };
 

@@ -32,7 +32,7 @@ EXPORTS = (
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing",
 )
-KERNELS = ("bin", "H_pairs", "H_convert", "rho_pairs", "rho_reduce", "force_pairs", "force_reduce")
+KERNELS = ("bin", "H_pairs", "H_convert", "rho", "pack_D", "force", "force_reduce")
 
 
 class GintError(RuntimeError):

@@ -95,18 +95,19 @@ struct gint_plan_s {
     double rc_max = 0.0;
     int nchunk_req = 0;  // 0 = automatic
     int nchunk = 1;
-    long long nent = 0, nimg = 0, nslot = 0, ngb = 0, npair = 0, ngbatch = 0;
+    long long nent = 0, nimg = 0, ngb = 0, npair = 0, ngbatch = 0;
 
     // basis and atoms
     DevBuf rad, sp, knots, s0, sn, coef, scratch;
     DevBuf spc_in, spc, pos_in, xw_in, xw, keys, perm, inv_perm, orb0, orb_atom;
     // binning lists
-    DevBuf cnt_e, cnt_i, cnt_g, cnt_s, bptr, iptr, bgptr, soff;
+    DevBuf cnt_e, cnt_i, cnt_g, cnt_s, bptr, iptr, bgptr, soff, maxv;
     DevBuf ent_atom, ent_img, img, bgrp;
     DevBuf gcnt, gptr, gbatch;
     DevBuf mark, mscan, pair_index, pairA, pairB;
     // work buffers
-    DevBuf Hblk, rho_part, Fpart, sums, readback;
+    DevBuf Hblk, S2pk, Fent, sums, readback;
+    int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
 
     // optional per-kernel timing (events on the plan's stream)
     bool timing = false;
@@ -152,7 +153,6 @@ struct gint_plan_s {
         b.img = img.as<int>();
         b.bgptr = bgptr.as<int>();
         b.bgrp = bgrp.as<int>();
-        b.soff = soff.as<long long>();
         b.gptr = gptr.as<int>();
         b.gbatch = gbatch.as<int>();
         b.pairA = pairA.as<int>();
@@ -301,36 +301,37 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->cnt_e.ensure(sizeof(int) * nb));
     STCHK(p->cnt_i.ensure(sizeof(int) * nb));
     STCHK(p->cnt_g.ensure(sizeof(int) * nb));
-    STCHK(p->cnt_s.ensure(sizeof(long long) * nb));
     STCHK(p->bptr.ensure(sizeof(int) * (nb + 1)));
     STCHK(p->iptr.ensure(sizeof(int) * (nb + 1)));
     STCHK(p->bgptr.ensure(sizeof(int) * (nb + 1)));
-    STCHK(p->soff.ensure(sizeof(long long) * (nb + 1)));
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_BIN, [&] {
-        return launch_bin_count(s, g, B, p->cnt_e.as<int>(), p->cnt_i.as<int>(), p->cnt_g.as<int>(),
-                                p->cnt_s.as<long long>());
+        return launch_bin_count(s, g, B, p->cnt_e.as<int>(), p->cnt_i.as<int>(), p->cnt_g.as<int>());
     }));
     HIPCHK(launch_scan_i32(s, p->cnt_e.as<int>(), nb, p->bptr.as<int>()));
     HIPCHK(launch_scan_i32(s, p->cnt_i.as<int>(), nb, p->iptr.as<int>()));
     HIPCHK(launch_scan_i32(s, p->cnt_g.as<int>(), nb, p->bgptr.as<int>()));
-    HIPCHK(launch_scan_i64(s, p->cnt_s.as<long long>(), nb, p->soff.as<long long>()));
     // totals (counts are far below 2^31 for any mesh this library accepts,
     // but the image total is checked explicitly)
-    int tot[3];
-    long long tslot;
-    STCHK(p->readback.ensure(64));
+    int tot[5];
+    STCHK(p->maxv.ensure(2 * sizeof(int)));
+    HIPCHK(launch_max_i32(s, p->cnt_e.as<int>(), nb, p->maxv.as<int>()));
+    HIPCHK(launch_max_i32(s, p->cnt_g.as<int>(), nb, p->maxv.as<int>() + 1));
     HIPCHK(hipMemcpyAsync(&tot[0], p->bptr.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&tot[1], p->iptr.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&tot[2], p->bgptr.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&tslot, p->soff.as<long long>() + nb, sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tot[3], p->maxv.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (tot[0] < 0 || tot[1] < 0 || tot[2] < 0 || tslot < 0)
+    if (tot[0] < 0 || tot[1] < 0 || tot[2] < 0)
         return fail(GINT_EUNSUPPORTED, "binning lists exceed 2^31 entries");
     p->nent = tot[0];
     p->nimg = tot[1];
     p->ngb = tot[2];
-    p->nslot = tslot;
+    p->nbmax = tot[3];
+    p->ngbmax = tot[4];
+    if (p->nbmax > kMaxBatchAtoms || p->ngbmax > kMaxBatchGroups)
+        return fail(GINT_EUNSUPPORTED, "%d atoms / %d atom groups reach one mesh batch (max %d / %d); use a smaller batch",
+                    p->nbmax, p->ngbmax, kMaxBatchAtoms, kMaxBatchGroups);
     STCHK(p->ent_atom.ensure(sizeof(int) * (p->nent + 1)));
     STCHK(p->ent_img.ensure(sizeof(int) * (p->nent + 1)));
     STCHK(p->img.ensure(sizeof(int) * (p->nimg + 1)));
@@ -385,8 +386,8 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     if (nwg > 0x7fffffffLL)
         return fail(GINT_EUNSUPPORTED, "too many group-pair workgroups");
     STCHK(p->Hblk.ensure(sizeof(double) * 16 * 256 * nwg));
-    STCHK(p->Fpart.ensure(sizeof(double) * 24 * nwg));
-    STCHK(p->rho_part.ensure(sizeof(double) * (size_t)g.P * p->nslot));
+    STCHK(p->S2pk.ensure(sizeof(double) * 16 * 512 * (size_t)p->npair));
+    STCHK(p->Fent.ensure(sizeof(double) * 3 * (size_t)(p->nent + 1)));
     return GINT_OK;
 }
 
@@ -394,6 +395,13 @@ gint_status validate_species(int nspecies, const gint_species *species, double *
 {
     if (nspecies <= 0 || !species)
         return fail(GINT_EINVAL, "nspecies must be >= 1 and species non-NULL");
+    if (nspecies > kMaxSpecies)
+        return fail(GINT_EUNSUPPORTED, "%d species (max %d)", nspecies, kMaxSpecies);
+    int nrad_total = 0;
+    for (int s = 0; s < nspecies; ++s)
+        nrad_total += species[s].nradial > 0 ? species[s].nradial : 0;
+    if (nrad_total > kMaxRadTotal)
+        return fail(GINT_EUNSUPPORTED, "%d radials over all species (max %d)", nrad_total, kMaxRadTotal);
     *rc_max = 0.0;
     for (int s = 0; s < nspecies; ++s) {
         const gint_species &S = species[s];
@@ -459,6 +467,9 @@ gint_status validate_geometry(const double *lattice, const int *grid, Geo &g)
                   : 0;
     for (int k = 0; k < 3; ++k)
         g.N[k] = grid[k];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+            g.h[3 * i + k] = lattice[3 * i + k] / grid[i];
     return GINT_OK;
 }
 
@@ -525,6 +536,10 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
     for (int s = 0; s < nspecies; ++s) {
         const gint_species &S = species[s];
         sp[s].rad0 = (int)rad.size();
+        for (int o = 0; o < kMaxOrb; ++o) {
+            sp[s].orb_rad[o] = 0;
+            sp[s].orb_m[o] = 0;
+        }
         sp[s].nrad = S.nradial;
         sp[s].rc = 0.0;
         int orb = 0;
@@ -534,6 +549,10 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
                 if (R.l != l)
                     continue;
                 DevRadial d;
+                for (int m = 0; m < 2 * l + 1; ++m) {
+                    sp[s].orb_rad[orb + m] = (signed char)rad.size();
+                    sp[s].orb_m[orb + m] = (signed char)(m - l);
+                }
                 d.dr = R.dr;
                 d.inv_dr = 1.0 / R.dr;
                 d.rc = (R.nr - 1) * R.dr;
@@ -577,6 +596,8 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
     p->natom = natom;
     p->norb = norb;
     p->nrad = (int)rad.size();
+    p->geo.nrad = p->nrad;
+    p->geo.nspecies = nspecies;
     p->nspecies = nspecies;
     p->rc_max = rc_max;
     p->dV = std::fabs(g.lat[0] * (g.lat[4] * g.lat[8] - g.lat[5] * g.lat[7]) -
@@ -716,12 +737,11 @@ gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    STCHK(timed(p, GINT_K_RHO_PAIRS, [&] {
-        return launch_pairs_rho(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, D_dev, p->norb,
-                                p->rho_part.as<double>());
+    STCHK(timed(p, GINT_K_PACK, [&] {
+        return launch_pack_S2(p->stream, p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.as<double>());
     }));
-    STCHK(timed(p, GINT_K_RHO_REDUCE,
-                [&] { return launch_rho_reduce(p->stream, p->geo, bn, p->rho_part.as<double>(), rho_dev); }));
+    STCHK(timed(p, GINT_K_RHO,
+                [&] { return launch_rho_batch(p->stream, p->geo, bn, B, p->nbmax, p->S2pk.as<double>(), rho_dev); }));
     return GINT_OK;
 }
 
@@ -733,13 +753,15 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    STCHK(timed(p, GINT_K_F_PAIRS, [&] {
-        return launch_pairs_force(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, D, p->norb,
-                                  p->Fpart.as<double>());
+    STCHK(timed(p, GINT_K_PACK, [&] {
+        return launch_pack_S2(p->stream, p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.as<double>());
     }));
-    STCHK(timed(p, GINT_K_F_REDUCE, [&] {
-        return launch_force_reduce(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, p->Fpart.as<double>(), dEdR);
+    STCHK(timed(p, GINT_K_FORCE, [&] {
+        return launch_force_batch(p->stream, p->geo, bn, B, p->nbmax, p->S2pk.as<double>(), W, wscale,
+                                  p->Fent.as<double>());
     }));
+    STCHK(timed(p, GINT_K_F_REDUCE,
+                [&] { return launch_force_reduce(p->stream, p->geo, bn, B, p->Fent.as<double>(), dEdR); }));
     return GINT_OK;
 }
 

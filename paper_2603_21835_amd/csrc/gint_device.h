@@ -1,0 +1,347 @@
+// gint_device.h -- device helpers shared by the gfx950 kernels: geometry,
+// the numerical-atomic-orbital evaluation (PhiOperator role) and small
+// search utilities.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gint_internal.h"
+
+namespace gint {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// real spherical harmonics (no Condon-Shortley phase)
+#define Y_C00 0.28209479177387814
+#define Y_C1 0.4886025119029199
+#define Y_C2 1.0925484305920792
+#define Y_C20 0.31539156525252005
+#define Y_C22 0.5462742152960396
+
+__device__ __forceinline__ void frac_of(const Geo &g, const double *x, double *s)
+{
+    for (int i = 0; i < 3; ++i)
+        s[i] = g.rec[3 * i] * x[0] + g.rec[3 * i + 1] * x[1] + g.rec[3 * i + 2] * x[2];
+}
+
+__device__ __forceinline__ void cart_of(const Geo &g, const double *s, double *x)
+{
+    for (int k = 0; k < 3; ++k)
+        x[k] = s[0] * g.lat[k] + s[1] * g.lat[3 + k] + s[2] * g.lat[6 + k];
+}
+
+__device__ __forceinline__ void batch_coords(const Geo &g, int b, int *ib)
+{
+    ib[2] = b % g.nb[2];
+    ib[1] = (b / g.nb[2]) % g.nb[1];
+    ib[0] = b / (g.nb[2] * g.nb[1]);
+}
+
+// Mesh indices of point q of batch (i0, i1, i2); false outside the mesh.
+__device__ __forceinline__ bool batch_point(const Geo &g, const int *ib, int q, int *n)
+{
+    const int l2 = q % g.bs[2], l1 = (q / g.bs[2]) % g.bs[1], l0 = q / (g.bs[2] * g.bs[1]);
+    n[0] = ib[0] * g.bs[0] + l0;
+    n[1] = ib[1] * g.bs[1] + l1;
+    n[2] = ib[2] * g.bs[2] + l2;
+    return q < g.P && n[0] < g.N[0] && n[1] < g.N[1] && n[2] < g.N[2];
+}
+
+// r = sum_i n_i a_i / N_i
+__device__ __forceinline__ void mesh_cart(const Geo &g, const int *n, double *r)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        r[k] = n[0] * g.h[k] + n[1] * g.h[3 + k] + n[2] * g.h[6 + k];
+}
+
+// 1/sqrt(x) for x > 0 to full FP64 accuracy: hardware estimate refined by
+// two Newton steps.
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// First index in [lo, hi) of a[] that is >= key.
+__device__ __forceinline__ int lower_bound_i(const int *__restrict__ a, int lo, int hi, int key)
+{
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void unpack_image(int pk, int *n)
+{
+    n[0] = (int)(signed char)(pk & 0xff);
+    n[1] = (int)(signed char)((pk >> 8) & 0xff);
+    n[2] = (int)(signed char)((pk >> 16) & 0xff);
+}
+
+// Spline interval and offset for radius rr (left-closed intervals, last
+// interval extended to rc).
+__device__ __forceinline__ int spline_interval(const DevRadial &R, double rr, double *t)
+{
+    int iv = (int)(rr * R.inv_dr);
+    // the reciprocal can round across a knot: settle on floor(r/dr)
+    if (iv * R.dr > rr)
+        --iv;
+    else if ((iv + 1) * R.dr <= rr)
+        ++iv;
+    iv = iv > R.nr - 2 ? R.nr - 2 : (iv < 0 ? 0 : iv);
+    *t = rr - iv * R.dr;
+    return iv;
+}
+
+// Folded orbitals of one atom at cartesian point r, for the radials
+// k0..k1-1 of its species (radial descriptors in LDS).  Writes every orbital
+// those radials own: assignment for the first listed image, accumulation
+// for further images (several images of one atom reach a point only in
+// cells smaller than the cutoff sphere).  pk0 is the first packed image;
+// further ones are read from img[ioff + i].  The radial loop is unrolled by
+// 8 so that all spline-coefficient loads of an image are in flight together.
+template <bool GRAD>
+__device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__restrict__ rads, int k0, int k1,
+                                              double rc, const double *__restrict__ coef, const double *X,
+                                              int icnt, int pk0, int ioff, const int *__restrict__ img,
+                                              const double *r, double *row, double *gx, double *gy, double *gz)
+{
+    const double rc2 = rc * rc;
+    for (int i = 0; i < icnt; ++i) {
+        const int pk = (i == 0) ? pk0 : img[ioff + i];
+        int n[3];
+        unpack_image(pk, n);
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            d[k] = r[k] - (X[k] + n[0] * g.lat[k] + n[1] * g.lat[3 + k] + n[2] * g.lat[6 + k]);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const bool inside = r2 < rc2;
+        const bool tiny = r2 < kRTiny * kRTiny;
+        double ir = 0.0, rr = 0.0;
+        if (inside && !tiny) {
+            ir = rsqrt_f64(r2);
+            rr = r2 * ir;
+        }
+        const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
+        const bool add = i > 0;
+        for (int kb = k0; kb < k1; kb += 8) {
+            double2 c01[8], c23[8];
+            double tt[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = kb + u;
+                c01[u] = double2{0.0, 0.0};
+                c23[u] = double2{0.0, 0.0};
+                tt[u] = 0.0;
+                if (k < k1) {
+                    const DevRadial R = rads[k];
+                    if (inside && rr < R.rc) {
+                        const int iv = spline_interval(R, rr, &tt[u]);
+                        c01[u] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
+                        c23[u] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = kb + u;
+                if (k >= k1)
+                    break;
+                const int l = rads[k].l, o = rads[k].orb0;
+                const double t = tt[u];
+                const double f = c01[u].x + t * (c01[u].y + t * (c23[u].x + t * c23[u].y));
+                const double fp = c01[u].y + t * (2.0 * c23[u].x + t * 3.0 * c23[u].y);
+                if (l == 0) {
+                    const double v = f * Y_C00;
+                    row[o] = add ? row[o] + v : v;
+                    if (GRAD) {
+                        const double q = tiny ? 0.0 : fp * Y_C00;
+                        gx[o] = add ? gx[o] + q * ux : q * ux;
+                        gy[o] = add ? gy[o] + q * uy : q * uy;
+                        gz[o] = add ? gz[o] + q * uz : q * uz;
+                    }
+                } else if (l == 1) {
+                    // at the centre phi_1m -> 0 and grad phi_1m -> f'(0) C1 e_m, e = (y, z, x)
+                    const double Y[3] = {Y_C1 * uy, Y_C1 * uz, Y_C1 * ux};
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+                        row[o + m] = add ? row[o + m] + f * Y[m] : f * Y[m];
+                    if (GRAD) {
+                        const double fr = f * ir;
+                        const double G[3][3] = {{0.0, Y_C1, 0.0}, {0.0, 0.0, Y_C1}, {Y_C1, 0.0, 0.0}};
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) {
+                            double vx, vy, vz;
+                            if (tiny) {
+                                vx = fp * G[m][0];
+                                vy = fp * G[m][1];
+                                vz = fp * G[m][2];
+                            } else {
+                                // grad Y(d/|d|) = (grad_u Yhat - l Yhat u)/|d|
+                                vx = fp * Y[m] * ux + fr * (G[m][0] - Y[m] * ux);
+                                vy = fp * Y[m] * uy + fr * (G[m][1] - Y[m] * uy);
+                                vz = fp * Y[m] * uz + fr * (G[m][2] - Y[m] * uz);
+                            }
+                            gx[o + m] = add ? gx[o + m] + vx : vx;
+                            gy[o + m] = add ? gy[o + m] + vy : vy;
+                            gz[o + m] = add ? gz[o + m] + vz : vz;
+                        }
+                    }
+                } else {
+                    // phi_2m and its gradient vanish at the centre (u = 0 there)
+                    const double Y[5] = {Y_C2 * ux * uy, Y_C2 * uy * uz, Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy),
+                                         Y_C2 * ux * uz, Y_C22 * (ux * ux - uy * uy)};
+#pragma unroll
+                    for (int m = 0; m < 5; ++m)
+                        row[o + m] = add ? row[o + m] + f * Y[m] : f * Y[m];
+                    if (GRAD) {
+                        const double fr = f * ir;
+                        const double G[5][3] = {{Y_C2 * uy, Y_C2 * ux, 0.0},
+                                                {0.0, Y_C2 * uz, Y_C2 * uy},
+                                                {-2.0 * Y_C20 * ux, -2.0 * Y_C20 * uy, 4.0 * Y_C20 * uz},
+                                                {Y_C2 * uz, 0.0, Y_C2 * ux},
+                                                {2.0 * Y_C22 * ux, -2.0 * Y_C22 * uy, 0.0}};
+#pragma unroll
+                        for (int m = 0; m < 5; ++m) {
+                            const double vx = fp * Y[m] * ux + fr * (G[m][0] - 2.0 * Y[m] * ux);
+                            const double vy = fp * Y[m] * uy + fr * (G[m][1] - 2.0 * Y[m] * uy);
+                            const double vz = fp * Y[m] * uz + fr * (G[m][2] - 2.0 * Y[m] * uz);
+                            gx[o + m] = add ? gx[o + m] + vx : vx;
+                            gy[o + m] = add ? gy[o + m] + vy : vy;
+                            gz[o + m] = add ? gz[o + m] + vz : vz;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Gradients of four orbitals o_v = o0 + 4 v (v < 4) of one atom at point r
+// (zero for o_v >= norb), summed over the listed images.  orb_rad[o] is the
+// radial (index into rads) owning orbital o, orb_m[o] its m.  Used where
+// each lane needs exactly the orbitals of its MFMA result rows.
+__device__ __forceinline__ void grad4(const Geo &g, const DevRadial *__restrict__ rads,
+                                      const signed char *__restrict__ orb_rad, const signed char *__restrict__ orb_m,
+                                      int norb, double rc, const double *__restrict__ coef, const double *X, int icnt,
+                                      int pk0, int ioff, const int *__restrict__ img, const double *r, int o0,
+                                      double (*gr)[4])
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        gr[0][v] = gr[1][v] = gr[2][v] = 0.0;
+    const double rc2 = rc * rc;
+    for (int i = 0; i < icnt; ++i) {
+        const int pk = (i == 0) ? pk0 : img[ioff + i];
+        int n[3];
+        unpack_image(pk, n);
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            d[k] = r[k] - (X[k] + n[0] * g.lat[k] + n[1] * g.lat[3 + k] + n[2] * g.lat[6 + k]);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(r2 < rc2))
+            continue;
+        const bool tiny = r2 < kRTiny * kRTiny;
+        double ir = 0.0, rr = 0.0;
+        if (!tiny) {
+            ir = rsqrt_f64(r2);
+            rr = r2 * ir;
+        }
+        const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
+        double2 c01[4], c23[4];
+        double tt[4];
+        int lv[4], mv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = o0 + 4 * v;
+            c01[v] = double2{0.0, 0.0};
+            c23[v] = double2{0.0, 0.0};
+            tt[v] = 0.0;
+            lv[v] = -1;
+            mv[v] = 0;
+            if (o < norb) {
+                const DevRadial R = rads[orb_rad[o]];
+                lv[v] = R.l;
+                mv[v] = orb_m[o];
+                if (rr < R.rc) {
+                    const int iv = spline_interval(R, rr, &tt[v]);
+                    c01[v] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
+                    c23[v] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (lv[v] < 0)
+                continue;
+            const double t = tt[v];
+            const double f = c01[v].x + t * (c01[v].y + t * (c23[v].x + t * c23[v].y));
+            const double fp = c01[v].y + t * (2.0 * c23[v].x + t * 3.0 * c23[v].y);
+            const int m = mv[v];
+            double Y, G0, G1, G2;
+            if (lv[v] == 0) {
+                Y = Y_C00;
+                G0 = G1 = G2 = 0.0;
+            } else if (lv[v] == 1) {
+                // m = -1, 0, 1 -> y, z, x
+                Y = Y_C1 * (m == -1 ? uy : (m == 0 ? uz : ux));
+                G0 = (m == 1) ? Y_C1 : 0.0;
+                G1 = (m == -1) ? Y_C1 : 0.0;
+                G2 = (m == 0) ? Y_C1 : 0.0;
+            } else {
+                if (m == -2) {
+                    Y = Y_C2 * ux * uy;
+                    G0 = Y_C2 * uy;
+                    G1 = Y_C2 * ux;
+                    G2 = 0.0;
+                } else if (m == -1) {
+                    Y = Y_C2 * uy * uz;
+                    G0 = 0.0;
+                    G1 = Y_C2 * uz;
+                    G2 = Y_C2 * uy;
+                } else if (m == 0) {
+                    Y = Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy);
+                    G0 = -2.0 * Y_C20 * ux;
+                    G1 = -2.0 * Y_C20 * uy;
+                    G2 = 4.0 * Y_C20 * uz;
+                } else if (m == 1) {
+                    Y = Y_C2 * ux * uz;
+                    G0 = Y_C2 * uz;
+                    G1 = 0.0;
+                    G2 = Y_C2 * ux;
+                } else {
+                    Y = Y_C22 * (ux * ux - uy * uy);
+                    G0 = 2.0 * Y_C22 * ux;
+                    G1 = -2.0 * Y_C22 * uy;
+                    G2 = 0.0;
+                }
+            }
+            if (tiny) {
+                // only p orbitals keep a gradient at the centre: f'(0) C1 e_m
+                if (lv[v] == 1) {
+                    gr[0][v] += fp * G0;
+                    gr[1][v] += fp * G1;
+                    gr[2][v] += fp * G2;
+                }
+                continue;
+            }
+            const double fr = f * ir;
+            const double lY = lv[v] * Y;
+            gr[0][v] += fp * Y * ux + fr * (G0 - lY * ux);
+            gr[1][v] += fp * Y * uy + fr * (G1 - lY * uy);
+            gr[2][v] += fp * Y * uz + fr * (G2 - lY * uz);
+        }
+    }
+}
+
+}  // namespace gint

@@ -13,6 +13,10 @@ constexpr int kMaxRad = 16;       // radials per species
 constexpr int kGroup = 4;         // atoms per group (output tile = 4x4 atom blocks)
 constexpr int kMaxP = 32;         // mesh points per batch
 constexpr int kMaxAtoms = 16384;
+constexpr int kMaxRadTotal = 64;  // radials over all species (staged in LDS)
+constexpr int kMaxSpecies = 16;
+constexpr int kMaxBatchAtoms = 64;   // atoms reaching one mesh batch
+constexpr int kMaxBatchGroups = 32;  // atom groups reaching one mesh batch
 constexpr int kRow = 18;          // doubles per staged (slot, point) row in LDS
 constexpr double kRTiny = 1e-12;  // |d| below this: the atom's own position
 
@@ -21,6 +25,7 @@ constexpr double kRTiny = 1e-12;  // |d| below this: the atom's own position
 struct Geo {
     double lat[9];  // rows a1, a2, a3
     double rec[9];  // rows b_i, a_i . b_j = delta_ij
+    double h[9];    // mesh steps: rows a_i / N_i
     int N[3];
     int bs[3];
     int nb[3];
@@ -29,6 +34,8 @@ struct Geo {
     int ortho;   // lattice rows are along the cartesian axes
     int natom;
     int ngroup;  // ceil(natom / kGroup)
+    int nrad;    // radials over all species
+    int nspecies;
 };
 
 struct DevRadial {
@@ -40,7 +47,9 @@ struct DevRadial {
 
 struct DevSpecies {
     int rad0, nrad, norb;
-    double rc;  // largest cutoff of the species
+    double rc;                   // largest cutoff of the species
+    signed char orb_rad[kMaxOrb];  // radial (global index) owning each orbital
+    signed char orb_m[kMaxOrb];    // m of each orbital
 };
 
 // Binning lists (all device pointers).
@@ -51,7 +60,6 @@ struct Bins {
     const int *img;         // packed signed 8-bit lattice multiples (n1, n2, n3)
     const int *bgptr;       // nbatch+1: distinct groups of each batch
     const int *bgrp;        // group ids, increasing within a batch
-    const long long *soff;  // nbatch+1: rho partial slots of each batch
     const int *gptr;        // ngroup+1: batches of each group
     const int *gbatch;      // batch ids, increasing within a group
     const int *pairA;       // npair
@@ -81,7 +89,7 @@ hipError_t launch_sort_perm(hipStream_t s, int natom, unsigned long long *keys, 
 hipError_t launch_gather_internal(hipStream_t s, int natom, const int *perm, const double *xw_in,
                                   const int *spc_in, double *xw, int *spc);
 hipError_t launch_bin_count(hipStream_t s, const Geo &g, const Basis &b, int *cnt_e, int *cnt_i,
-                            int *cnt_g, long long *cnt_s);
+                            int *cnt_g);
 hipError_t launch_bin_fill(hipStream_t s, const Geo &g, const Basis &b, const int *bptr,
                            const int *iptr, const int *bgptr, int *ent_atom, int *ent_img, int *img,
                            int *bgrp);
@@ -99,21 +107,20 @@ hipError_t launch_pair_list(hipStream_t s, int ngroup, const int *mark, const in
 hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
                                 double *sums /* 2 per block */, int nblocks);
 
-// Contractions over group pairs (output-stationary over atom-pair blocks).
+// Contractions (gint_contract.hip).
 hipError_t launch_pairs_H(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
                           int nchunk, const double *W, double wscale, double *Hblk);
-hipError_t launch_pairs_rho(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
-                            int nchunk, const double *D, int norb, double *rho_part);
-hipError_t launch_pairs_force(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
-                              int npair, int nchunk, const double *W, double wscale,
-                              const double *D, int norb, double *Fpart);
-
-// Cross-batch reductions and conversion to the output layouts.
 hipError_t launch_H_convert(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int norb,
                             int nchunk, const double *Hblk, double *H);
-hipError_t launch_rho_reduce(hipStream_t s, const Geo &g, const Bins &bn, const double *rho_part,
-                             double *rho);
+hipError_t launch_pack_S2(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                          const double *D, int norb, double *pk);
+size_t batch_lds_bytes(int nbmax);
+hipError_t launch_rho_batch(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                            const double *pk, double *rho);
+hipError_t launch_force_batch(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                              const double *pk, const double *W, double wscale, double *Fent);
 hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
-                               int npair, int nchunk, const double *Fpart, double *dEdR);
+                               const double *Fent, double *dEdR);
+hipError_t launch_max_i32(hipStream_t s, const int *a, long long n, int *out);
 
 }  // namespace gint

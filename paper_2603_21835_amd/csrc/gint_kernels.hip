@@ -19,18 +19,9 @@
 
 #include <climits>
 
-#include "gint_internal.h"
+#include "gint_device.h"
 
 namespace gint {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-// real spherical harmonics (no Condon-Shortley phase)
-#define Y_C00 0.28209479177387814
-#define Y_C1 0.4886025119029199
-#define Y_C2 1.0925484305920792
-#define Y_C20 0.31539156525252005
-#define Y_C22 0.5462742152960396
 
 // ---------------------------------------------------------------------------
 // Clamped cubic spline, Hermite form: unknown knot slopes k_i with
@@ -91,19 +82,7 @@ hipError_t launch_spline(hipStream_t s, int nrad, const DevRadial *rad, const do
 }
 
 // ---------------------------------------------------------------------------
-// Geometry helpers
-
-__device__ __forceinline__ void frac_of(const Geo &g, const double *x, double *s)
-{
-    for (int i = 0; i < 3; ++i)
-        s[i] = g.rec[3 * i] * x[0] + g.rec[3 * i + 1] * x[1] + g.rec[3 * i + 2] * x[2];
-}
-
-__device__ __forceinline__ void cart_of(const Geo &g, const double *s, double *x)
-{
-    for (int k = 0; k < 3; ++k)
-        x[k] = s[0] * g.lat[k] + s[1] * g.lat[3 + k] + s[2] * g.lat[6 + k];
-}
+// Atom wrapping and Morton ordering
 
 __device__ __forceinline__ unsigned int spread10(unsigned int v)
 {
@@ -230,13 +209,6 @@ hipError_t launch_gather_internal(hipStream_t s, int natom, const int *perm, con
 // sphere of the batch's point parallelepiped otherwise.  Entries are in
 // increasing internal atom order, images in (n1, n2, n3) loop order.
 
-__device__ __forceinline__ void batch_coords(const Geo &g, int b, int *ib)
-{
-    ib[2] = b % g.nb[2];
-    ib[1] = (b / g.nb[2]) % g.nb[1];
-    ib[0] = b / (g.nb[2] * g.nb[1]);
-}
-
 template <bool FILL>
 __device__ void bin_one_batch(const Geo &g, const Basis &bs, int b, int *ne, int *ni, int *ng, int *ent_atom,
                               int *ent_img, int *img, int *bgrp, int e0, int i0, int g0)
@@ -351,7 +323,7 @@ __device__ void bin_one_batch(const Geo &g, const Basis &bs, int b, int *ne, int
 }
 
 __global__ void k_bin_count(Geo g, Basis bs, int *__restrict__ cnt_e, int *__restrict__ cnt_i,
-                            int *__restrict__ cnt_g, long long *__restrict__ cnt_s)
+                            int *__restrict__ cnt_g)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= g.nbatch)
@@ -361,14 +333,11 @@ __global__ void k_bin_count(Geo g, Basis bs, int *__restrict__ cnt_e, int *__res
     cnt_e[b] = ne;
     cnt_i[b] = ni;
     cnt_g[b] = ng;
-    cnt_s[b] = (long long)ng * (ng + 1) / 2;
 }
 
-hipError_t launch_bin_count(hipStream_t s, const Geo &g, const Basis &b, int *cnt_e, int *cnt_i, int *cnt_g,
-                            long long *cnt_s)
+hipError_t launch_bin_count(hipStream_t s, const Geo &g, const Basis &b, int *cnt_e, int *cnt_i, int *cnt_g)
 {
-    hipLaunchKernelGGL(k_bin_count, dim3((g.nbatch + 127) / 128), dim3(128), 0, s, g, b, cnt_e, cnt_i, cnt_g,
-                       cnt_s);
+    hipLaunchKernelGGL(k_bin_count, dim3((g.nbatch + 127) / 128), dim3(128), 0, s, g, b, cnt_e, cnt_i, cnt_g);
     return hipGetLastError();
 }
 
@@ -574,605 +543,42 @@ hipError_t launch_pair_list(hipStream_t s, int ngroup, const int *mark, const in
 }
 
 // ---------------------------------------------------------------------------
-// Orbital evaluation (PhiOperator).  The folded orbitals of one atom at one
-// mesh point, accumulated over the atom's listed images into a 16-slot LDS
-// row (and, with GRAD, three gradient rows).  Angular part: closed-form real
-// Y_lm and their analytic tangential gradients; radial part: the spline and
-// its derivative.
+// Mesh point q of batch b: cartesian position and flat mesh index (-1 if
+// outside the mesh).
 
 __device__ __forceinline__ void mesh_point(const Geo &g, int b, int q, double *r, int *gidx)
 {
-    int ib[3];
+    int ib[3], n[3];
     batch_coords(g, b, ib);
-    const int l2 = q % g.bs[2];
-    const int l1 = (q / g.bs[2]) % g.bs[1];
-    const int l0 = q / (g.bs[2] * g.bs[1]);
-    const int n0 = ib[0] * g.bs[0] + l0, n1 = ib[1] * g.bs[1] + l1, n2 = ib[2] * g.bs[2] + l2;
-    if (q >= g.P || n0 >= g.N[0] || n1 >= g.N[1] || n2 >= g.N[2]) {
+    if (!batch_point(g, ib, q, n)) {
         *gidx = -1;
         return;
     }
-    *gidx = (n0 * g.N[1] + n1) * g.N[2] + n2;
-    const double s[3] = {(double)n0 / g.N[0], (double)n1 / g.N[1], (double)n2 / g.N[2]};
-    cart_of(g, s, r);
+    *gidx = (n[0] * g.N[1] + n[1]) * g.N[2] + n[2];
+    mesh_cart(g, n, r);
 }
 
-template <bool GRAD>
-__device__ void eval_atom(const Geo &g, const Basis &bs, int e, const int *__restrict__ ent_atom,
-                          const int *__restrict__ ent_img, const int *__restrict__ img, const double *r,
-                          double *row, double *gx, double *gy, double *gz)
+// Maximum of an int array (one workgroup).
+__global__ __launch_bounds__(256) void k_max_i32(const int *__restrict__ a, long long n, int *__restrict__ out)
 {
-    const int a = ent_atom[e];
-    const DevSpecies S = bs.sp[bs.spc[a]];
-    const double X[3] = {bs.xw[3 * a], bs.xw[3 * a + 1], bs.xw[3 * a + 2]};
-    const int i1 = ent_img[e + 1];
-    for (int im = ent_img[e]; im < i1; ++im) {
-        const int pk = img[im];
-        const int n0 = (int)(signed char)(pk & 0xff), n1 = (int)(signed char)((pk >> 8) & 0xff),
-                  n2 = (int)(signed char)((pk >> 16) & 0xff);
-        double d[3];
-        for (int k = 0; k < 3; ++k)
-            d[k] = r[k] - (X[k] + n0 * g.lat[k] + n1 * g.lat[3 + k] + n2 * g.lat[6 + k]);
-        const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        if (!(rr < S.rc))
-            continue;
-        const bool tiny = rr < kRTiny;
-        const double ir = tiny ? 0.0 : 1.0 / rr;
-        const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
-        for (int k = S.rad0; k < S.rad0 + S.nrad; ++k) {
-            const DevRadial R = bs.rad[k];
-            if (!(rr < R.rc))
-                continue;
-            int iv = (int)(rr * R.inv_dr);
-            // the reciprocal can round across a knot: settle on floor(r/dr)
-            if (iv * R.dr > rr)
-                --iv;
-            else if ((iv + 1) * R.dr <= rr)
-                ++iv;
-            if (iv > R.nr - 2)
-                iv = R.nr - 2;
-            if (iv < 0)
-                iv = 0;
-            const double t = rr - iv * R.dr;
-            const double2 c01 = *reinterpret_cast<const double2 *>(bs.coef + R.coef_off + 4 * iv);
-            const double2 c23 = *reinterpret_cast<const double2 *>(bs.coef + R.coef_off + 4 * iv + 2);
-            const double f = c01.x + t * (c01.y + t * (c23.x + t * c23.y));
-            const double fp = c01.y + t * (2.0 * c23.x + t * 3.0 * c23.y);
-            const int o = R.orb0;
-            if (R.l == 0) {
-                row[o] += f * Y_C00;
-                if (GRAD && !tiny) {
-                    const double q = fp * Y_C00;
-                    gx[o] += q * ux;
-                    gy[o] += q * uy;
-                    gz[o] += q * uz;
-                }
-            } else if (R.l == 1) {
-                if (tiny) {
-                    // phi_1m -> 0, grad phi_1m -> f'(0) C1 e_m, e = (y, z, x)
-                    if (GRAD) {
-                        gy[o + 0] += fp * Y_C1;
-                        gz[o + 1] += fp * Y_C1;
-                        gx[o + 2] += fp * Y_C1;
-                    }
-                    continue;
-                }
-                const double Y[3] = {Y_C1 * uy, Y_C1 * uz, Y_C1 * ux};
-                row[o + 0] += f * Y[0];
-                row[o + 1] += f * Y[1];
-                row[o + 2] += f * Y[2];
-                if (GRAD) {
-                    const double fr = f * ir;
-                    // grad Y(d/|d|) = (grad_u Yhat - l Yhat u)/|d|
-                    const double G[3][3] = {{0.0, Y_C1, 0.0}, {0.0, 0.0, Y_C1}, {Y_C1, 0.0, 0.0}};
-                    for (int m = 0; m < 3; ++m) {
-                        gx[o + m] += fp * Y[m] * ux + fr * (G[m][0] - Y[m] * ux);
-                        gy[o + m] += fp * Y[m] * uy + fr * (G[m][1] - Y[m] * uy);
-                        gz[o + m] += fp * Y[m] * uz + fr * (G[m][2] - Y[m] * uz);
-                    }
-                }
-            } else {
-                if (tiny)
-                    continue;  // phi_2m and its gradient vanish at the centre
-                const double Y[5] = {Y_C2 * ux * uy, Y_C2 * uy * uz, Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy),
-                                     Y_C2 * ux * uz, Y_C22 * (ux * ux - uy * uy)};
-                for (int m = 0; m < 5; ++m)
-                    row[o + m] += f * Y[m];
-                if (GRAD) {
-                    const double fr = f * ir;
-                    const double G[5][3] = {{Y_C2 * uy, Y_C2 * ux, 0.0},
-                                            {0.0, Y_C2 * uz, Y_C2 * uy},
-                                            {-2.0 * Y_C20 * ux, -2.0 * Y_C20 * uy, 4.0 * Y_C20 * uz},
-                                            {Y_C2 * uz, 0.0, Y_C2 * ux},
-                                            {2.0 * Y_C22 * ux, -2.0 * Y_C22 * uy, 0.0}};
-                    for (int m = 0; m < 5; ++m) {
-                        gx[o + m] += fp * Y[m] * ux + fr * (G[m][0] - 2.0 * Y[m] * ux);
-                        gy[o + m] += fp * Y[m] * uy + fr * (G[m][1] - 2.0 * Y[m] * uy);
-                        gz[o + m] += fp * Y[m] * uz + fr * (G[m][2] - 2.0 * Y[m] * uz);
-                    }
-                }
-            }
-        }
-    }
-}
-
-// Entry of internal atom `atom` in batch b, or -1.
-__device__ __forceinline__ int find_entry(const Bins &bn, int b, int atom)
-{
-    int lo = bn.bptr[b], hi = bn.bptr[b + 1];
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const int v = bn.ent_atom[mid];
-        if (v == atom)
-            return mid;
-        if (v < atom)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return -1;
-}
-
-// Rank of group g in batch b's sorted group list.
-__device__ __forceinline__ int group_rank(const Bins &bn, int b, int grp)
-{
-    int lo = bn.bgptr[b], hi = bn.bgptr[b + 1];
-    const int base = lo;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (bn.bgrp[mid] < grp)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo - base;
-}
-
-// ---------------------------------------------------------------------------
-// Group-pair contractions.
-//
-// Workgroup = (group pair (A, B), chunk of A's batch list); 4 waves.  Wave w
-// owns the row atom I = 4A + w and the blocks (I, J = 4B + j), j = 0..3 (for
-// A == B only j >= w).  Per batch the workgroup stages the folded orbitals of
-// the <= 8 atoms of A and B at the batch's points into LDS as
-// s_phi[slot][point][orbital] (row pitch kRow doubles), then each wave runs
-// its blocks on v_mfma_f64_16x16x4:
-//
-//   operand lane layout (lane l):  A[i][k], B[k][j] with i, j = l & 15, k = l >> 4
-//   result lane layout:            C[i][j] with i = (l >> 4) + 4 v, j = l & 15, v < 4
-//                                  (checked on gfx950 with a lane-layout probe)
-//
-//   H     C_IJ += (w phi_I)^T phi_J over the batch points         (16x16 per block)
-//   rho   u = S'_IJ phi_J^T, rho_p += sum_a phi_I[a](p) u[a][p]   with S' = D_II for
-//         I = J and D_IJ + D_JI^T otherwise (rho = sum over I <= J)
-//   force u = S2_IJ phi_J^T with S2 = D + D^T, dE/dR_I -= w_p grad phi_I . u and,
-//         for I != J, the mirrored product for dE/dR_J
-
-enum { MODE_H = 0, MODE_RHO = 1, MODE_FORCE = 2 };
-
-template <int MODE>
-__global__ __launch_bounds__(256) void k_pairs(Geo g, Bins bn, Basis bs, int nchunk, const double *__restrict__ W,
-                                               double wscale, const double *__restrict__ D, int norb,
-                                               double *__restrict__ out)
-{
-    constexpr int PT = (MODE == MODE_FORCE) ? 16 : 32;  // points staged per step
-    constexpr int NG = (MODE == MODE_FORCE) ? 3 : 1;    // gradient rows
-    __shared__ double s_phi[8][PT][kRow];
-    __shared__ double s_grad[NG][(MODE == MODE_FORCE) ? 8 : 1][(MODE == MODE_FORCE) ? PT : 1][kRow];
-    __shared__ double s_w[PT];
-    __shared__ double s_red[4][PT];
-    __shared__ int s_list[256];
-    __shared__ int s_wcnt[4];
-    __shared__ int s_ent[8];
-    __shared__ long long s_slot;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int pair = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
-    const int A = bn.pairA[pair], B = bn.pairB[pair];
-    const bool diag = (A == B);
-    const int natom = g.natom;
-    const int Iint = A * kGroup + wave;
-    const bool Iex = Iint < natom;
-
-    // ---- density-matrix fragments of this wave's blocks (loaded once) ----
-    double fa[4][4], fb[4][4];
-    if (MODE != MODE_H) {
-        const int Iin = Iex ? bs.perm[Iint] : 0;
-        const int mu0 = bs.orb0[Iin];
-        const int nI = Iex ? bs.orb0[Iin + 1] - mu0 : 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int Jint = B * kGroup + j;
-            const bool act = Iex && Jint < natom && (!diag || j >= wave);
-            const int Jin = act ? bs.perm[Jint] : 0;
-            const int nu0 = bs.orb0[Jin];
-            const int nJ = act ? bs.orb0[Jin + 1] - nu0 : 0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int kb = 4 * c + lk;
-                // fa: S[a = li][b = kb]   (rho: S'; force: S2)
-                double v = 0.0;
-                if (li < nI && kb < nJ) {
-                    const double dij = D[(size_t)(mu0 + li) * norb + nu0 + kb];
-                    const double dji = D[(size_t)(nu0 + kb) * norb + mu0 + li];
-                    if (MODE == MODE_RHO)
-                        v = (diag && j == wave) ? dij : dij + dji;
-                    else
-                        v = dij + dji;
-                }
-                fa[j][c] = v;
-                // fb (force only): S2_JI[b = li][a = kb] = S2_IJ[kb][li]
-                double u = 0.0;
-                if (MODE == MODE_FORCE && kb < nI && li < nJ)
-                    u = D[(size_t)(mu0 + kb) * norb + nu0 + li] + D[(size_t)(nu0 + li) * norb + mu0 + kb];
-                fb[j][c] = u;
-            }
-        }
-    }
-
-    d4 acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-    double fI[3] = {0.0, 0.0, 0.0};
-    double fJ[4][3];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        fJ[j][0] = fJ[j][1] = fJ[j][2] = 0.0;
-
-    const int gb0 = bn.gptr[A], gb1 = bn.gptr[A + 1];
-    const long long len = gb1 - gb0;
-    const int c0 = gb0 + (int)(len * chunk / nchunk);
-    const int c1 = gb0 + (int)(len * (chunk + 1) / nchunk);
-
-    for (int base = c0; base < c1; base += 256) {
-        // ---- batches of this chunk that group B also reaches (ordered) ----
-        bool keep = false;
-        int bb = -1;
-        if (base + tid < c1) {
-            bb = bn.gbatch[base + tid];
-            keep = diag || batch_has_group(bn.bgptr, bn.bgrp, bb, B);
-        }
-        const unsigned long long m = __ballot(keep);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0)
-            s_wcnt[wave] = __popcll(m);
-        __syncthreads();
-        int off = 0;
-        for (int w = 0; w < wave; ++w)
-            off += s_wcnt[w];
-        if (keep)
-            s_list[off + pre] = bb;
-        const int nlist = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-        __syncthreads();
-
-        for (int it = 0; it < nlist; ++it) {
-            const int b = s_list[it];
-            if (tid < 8) {
-                const int atom = (tid < 4) ? A * kGroup + tid : B * kGroup + (tid - 4);
-                s_ent[tid] = (atom < natom && !(diag && tid >= 4)) ? find_entry(bn, b, atom) : -1;
-            }
-            if (MODE == MODE_RHO && tid == 0) {
-                const int n = bn.bgptr[b + 1] - bn.bgptr[b];
-                const int pa = group_rank(bn, b, A), pb = group_rank(bn, b, B);
-                s_slot = bn.soff[b] + (long long)pa * n - (long long)pa * (pa - 1) / 2 + (pb - pa);
-            }
-            __syncthreads();
-            const bool rowI = Iex && s_ent[wave] >= 0;
-
-            for (int sub = 0; sub < g.P; sub += PT) {
-                // ---- stage the folded orbitals (PhiOperator) ----
-                {
-                    const int s = tid / PT, p = tid % PT;
-                    if (s < 8) {
-                        double *row = &s_phi[s][p][0];
-                        double *gx = (MODE == MODE_FORCE) ? &s_grad[0][s % 8][p % PT][0] : nullptr;
-                        double *gy = (MODE == MODE_FORCE) ? &s_grad[NG > 1 ? 1 : 0][s % 8][p % PT][0] : nullptr;
-                        double *gz = (MODE == MODE_FORCE) ? &s_grad[NG > 2 ? 2 : 0][s % 8][p % PT][0] : nullptr;
-#pragma unroll
-                        for (int o = 0; o < kMaxOrb; ++o) {
-                            row[o] = 0.0;
-                            if (MODE == MODE_FORCE) {
-                                gx[o] = 0.0;
-                                gy[o] = 0.0;
-                                gz[o] = 0.0;
-                            }
-                        }
-                        const int e = s_ent[s];
-                        if (e >= 0) {
-                            double r[3];
-                            int gi;
-                            mesh_point(g, b, sub + p, r, &gi);
-                            if (gi >= 0)
-                                eval_atom<MODE == MODE_FORCE>(g, bs, e, bn.ent_atom, bn.ent_img, bn.img, r, row,
-                                                              gx, gy, gz);
-                        }
-                    }
-                    if (MODE != MODE_RHO && tid < PT) {
-                        double r[3];
-                        int gi;
-                        mesh_point(g, b, sub + tid, r, &gi);
-                        s_w[tid] = (gi >= 0) ? wscale * W[gi] : 0.0;
-                    }
-                }
-                __syncthreads();
-
-                // ---- contractions on the matrix cores ----
-                if (MODE == MODE_H) {
-                    if (rowI) {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int sj = diag ? j : 4 + j;
-                            if ((!diag || j >= wave) && s_ent[sj] >= 0) {
-#pragma unroll
-                                for (int kk = 0; kk < PT / 4; ++kk) {
-                                    const int p = 4 * kk + lk;
-                                    const double av = s_w[p] * s_phi[wave][p][li];
-                                    const double bv = s_phi[sj][p][li];
-                                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
-                                }
-                            }
-                        }
-                    }
-                } else if (MODE == MODE_RHO) {
-#pragma unroll
-                    for (int q = 0; q < PT / 16; ++q) {
-                        double rp = 0.0;
-                        if (rowI) {
-                            const int p = 16 * q + li;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const int sj = diag ? j : 4 + j;
-                                if ((!diag || j >= wave) && s_ent[sj] >= 0) {
-                                    d4 u = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                                    for (int c = 0; c < 4; ++c)
-                                        u = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j][c], s_phi[sj][p][4 * c + lk], u,
-                                                                                0, 0, 0);
-                                    const double *pI = &s_phi[wave][p][lk];
-                                    rp += u[0] * pI[0] + u[1] * pI[4] + u[2] * pI[8] + u[3] * pI[12];
-                                }
-                            }
-                        }
-                        rp += __shfl_xor(rp, 16);
-                        rp += __shfl_xor(rp, 32);
-                        if (lane < 16)
-                            s_red[wave][16 * q + lane] = rp;
-                    }
-                } else {
-                    if (rowI) {
-                        const int p = li;
-                        const double wp = s_w[p];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int sj = diag ? j : 4 + j;
-                            if ((!diag || j >= wave) && s_ent[sj] >= 0) {
-                                d4 u = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                                for (int c = 0; c < 4; ++c)
-                                    u = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j][c], s_phi[sj][p][4 * c + lk], u, 0,
-                                                                            0, 0);
-#pragma unroll
-                                for (int x = 0; x < 3; ++x) {
-                                    const double *gI = &s_grad[x][wave][p][lk];
-                                    fI[x] += wp * (u[0] * gI[0] + u[1] * gI[4] + u[2] * gI[8] + u[3] * gI[12]);
-                                }
-                                if (!(diag && j == wave)) {
-                                    d4 u2 = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                                    for (int c = 0; c < 4; ++c)
-                                        u2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j][c], s_phi[wave][p][4 * c + lk],
-                                                                                 u2, 0, 0, 0);
-#pragma unroll
-                                    for (int x = 0; x < 3; ++x) {
-                                        const double *gJ = &s_grad[x][sj][p][lk];
-                                        fJ[j][x] +=
-                                            wp * (u2[0] * gJ[0] + u2[1] * gJ[4] + u2[2] * gJ[8] + u2[3] * gJ[12]);
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-
-                if (MODE == MODE_RHO) {
-                    // fixed-order sum over the 4 waves, one partial per batch point
-                    if (tid < PT && sub + tid < g.P)
-                        out[(size_t)s_slot * g.P + sub + tid] =
-                            ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
-                    __syncthreads();
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- outputs ----
-    if (MODE == MODE_H) {
-        double *blk = out + (size_t)blockIdx.x * 16 * 256;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (!diag || j >= wave) {
-                double *o = blk + (size_t)(wave * 4 + j) * 256;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    o[(lk + 4 * v) * 16 + li] = acc[j][v];
-            }
-        }
-    } else if (MODE == MODE_FORCE) {
-        // wave sums (fixed butterfly), then slots: A atoms in 0..3, B atoms in 4..7
-        __shared__ double s_f[4][5][3];
-#pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            double v = fI[x];
-            for (int o = 32; o > 0; o >>= 1)
-                v += __shfl_xor(v, o);
-            if (lane == 0)
-                s_f[wave][4][x] = v;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double u = fJ[j][x];
-                for (int o = 32; o > 0; o >>= 1)
-                    u += __shfl_xor(u, o);
-                if (lane == 0)
-                    s_f[wave][j][x] = u;
-            }
-        }
-        __syncthreads();
-        if (tid < 24) {
-            const int slot = tid / 3, x = tid % 3;
-            double v = 0.0;
-            if (slot < 4) {
-                v = s_f[slot][4][x];
-                if (diag)
-                    v += ((s_f[0][slot][x] + s_f[1][slot][x]) + s_f[2][slot][x]) + s_f[3][slot][x];
-            } else if (!diag) {
-                const int j = slot - 4;
-                v = ((s_f[0][j][x] + s_f[1][j][x]) + s_f[2][j][x]) + s_f[3][j][x];
-            }
-            out[(size_t)blockIdx.x * 24 + tid] = -v;
-        }
-    }
-}
-
-hipError_t launch_pairs_H(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair, int nchunk,
-                          const double *W, double wscale, double *Hblk)
-{
-    if (npair <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<MODE_H>, dim3(npair * nchunk), dim3(256), 0, s, g, bn, b, nchunk, W, wscale,
-                       (const double *)nullptr, 0, Hblk);
-    return hipGetLastError();
-}
-
-hipError_t launch_pairs_rho(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair, int nchunk,
-                            const double *D, int norb, double *rho_part)
-{
-    if (npair <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<MODE_RHO>, dim3(npair * nchunk), dim3(256), 0, s, g, bn, b, nchunk,
-                       (const double *)nullptr, 0.0, D, norb, rho_part);
-    return hipGetLastError();
-}
-
-hipError_t launch_pairs_force(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair, int nchunk,
-                              const double *W, double wscale, const double *D, int norb, double *Fpart)
-{
-    if (npair <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<MODE_FORCE>, dim3(npair * nchunk), dim3(256), 0, s, g, bn, b, nchunk, W, wscale, D,
-                       norb, Fpart);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Reductions and output layouts.
-
-// Dense symmetric H from the canonical (upper) atom-pair blocks, summing the
-// chunks in order.  H[mu][nu] and H[nu][mu] read the same stored value.
-__global__ void k_H_convert(Geo g, Bins bn, Basis bs, int norb, int nchunk, const double *__restrict__ Hblk,
-                            double *__restrict__ H)
-{
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)norb * norb)
-        return;
-    const int mu = (int)(idx / norb), nu = (int)(idx % norb);
-    const int Iin = bs.orb_atom[mu], Jin = bs.orb_atom[nu];
-    int a = mu - bs.orb0[Iin], c = nu - bs.orb0[Jin];
-    int ii = bs.inv_perm[Iin], jj = bs.inv_perm[Jin];
-    if (ii > jj || (ii == jj && a > c)) {
-        int t = ii;
-        ii = jj;
-        jj = t;
-        t = a;
-        a = c;
-        c = t;
-    }
-    const int gA = ii / kGroup, gB = jj / kGroup;
-    const int p = bn.pair_index[(size_t)gA * g.ngroup + gB];
-    double v = 0.0;
-    if (p >= 0) {
-        const int blk = (ii % kGroup) * 4 + (jj % kGroup);
-        for (int ch = 0; ch < nchunk; ++ch)
-            v += Hblk[((size_t)(p * nchunk + ch) * 16 + blk) * 256 + a * 16 + c];
-    }
-    H[idx] = v;
-}
-
-hipError_t launch_H_convert(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int norb, int nchunk,
-                            const double *Hblk, double *H)
-{
-    const long long n = (long long)norb * norb;
-    hipLaunchKernelGGL(k_H_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, bn, b, norb, nchunk,
-                       Hblk, H);
-    return hipGetLastError();
-}
-
-// rho(r_g) = fixed-order sum of the batch's group-pair partials.
-__global__ void k_rho_reduce(Geo g, Bins bn, const double *__restrict__ part, double *__restrict__ rho)
-{
-    const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long ng = (long long)g.N[0] * g.N[1] * g.N[2];
-    if (gi >= ng)
-        return;
-    const int n2 = (int)(gi % g.N[2]);
-    const int n1 = (int)((gi / g.N[2]) % g.N[1]);
-    const int n0 = (int)(gi / ((long long)g.N[2] * g.N[1]));
-    const int b = ((n0 / g.bs[0]) * g.nb[1] + n1 / g.bs[1]) * g.nb[2] + n2 / g.bs[2];
-    const int q = ((n0 % g.bs[0]) * g.bs[1] + n1 % g.bs[1]) * g.bs[2] + n2 % g.bs[2];
-    double v = 0.0;
-    for (long long k = bn.soff[b]; k < bn.soff[b + 1]; ++k)
-        v += part[(size_t)k * g.P + q];
-    rho[gi] = v;
-}
-
-hipError_t launch_rho_reduce(hipStream_t s, const Geo &g, const Bins &bn, const double *rho_part, double *rho)
-{
-    const long long n = (long long)g.N[0] * g.N[1] * g.N[2];
-    hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, bn, rho_part, rho);
-    return hipGetLastError();
-}
-
-// dE/dR per atom: fixed-order sum over the group pairs and chunks that hold
-// the atom (as row group A or column group B).
-__global__ __launch_bounds__(256) void k_force_reduce(Geo g, Bins bn, Basis bs, int npair, int nchunk,
-                                                      const double *__restrict__ Fpart, double *__restrict__ dEdR)
-{
-    __shared__ double red[3][256];
-    const int ii = blockIdx.x;
-    const int grp = ii / kGroup, sl = ii % kGroup;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < npair * nchunk; k += 256) {
-        const int p = k / nchunk;
-        const int A = bn.pairA[p], B = bn.pairB[p];
-        int slot = -1;
-        if (A == grp)
-            slot = sl;
-        else if (B == grp)
-            slot = 4 + sl;
-        if (slot >= 0)
-            for (int x = 0; x < 3; ++x)
-                v[x] += Fpart[(size_t)k * 24 + slot * 3 + x];
-    }
-    for (int x = 0; x < 3; ++x)
-        red[x][threadIdx.x] = v[x];
+    __shared__ int red[256];
+    int m = 0;
+    for (long long i = threadIdx.x; i < n; i += 256)
+        m = a[i] > m ? a[i] : m;
+    red[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o)
-            for (int x = 0; x < 3; ++x)
-                red[x][threadIdx.x] += red[x][threadIdx.x + o];
+            red[threadIdx.x] = red[threadIdx.x + o] > red[threadIdx.x] ? red[threadIdx.x + o] : red[threadIdx.x];
         __syncthreads();
     }
-    if (threadIdx.x < 3)
-        dEdR[3 * bs.perm[ii] + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x == 0)
+        *out = red[0];
 }
 
-hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair, int nchunk,
-                               const double *Fpart, double *dEdR)
+hipError_t launch_max_i32(hipStream_t s, const int *a, long long n, int *out)
 {
-    hipLaunchKernelGGL(k_force_reduce, dim3(g.natom), dim3(256), 0, s, g, bn, b, npair, nchunk, Fpart, dEdR);
+    hipLaunchKernelGGL(k_max_i32, dim3(1), dim3(256), 0, s, a, n, out);
     return hipGetLastError();
 }
 
