@@ -24,21 +24,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
 def _kernel_sha() -> str:
     h = hashlib.sha256()
-    for f in ("gint_kernels.hip", "gint_internal.h"):
+    for f in ("gint_kernels.hip", "gint_contract.hip", "gint_device.h", "gint_internal.h"):
         with open(os.path.join(ROOT, "paper_2603_21835_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, workload: str):
+def _traffic(kernel: str, workload: str, precision: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -93,13 +94,93 @@ def cpu_baseline(w):
     }
 
 
+def run_batched(args, torch, gi, g, dev):
+    """256 independent Si cells of 8..64 atoms: H, rho and dE/dR of every
+    cell per step, each quantity one replay of a captured hipGraph.  The
+    cells' geometry is fixed across steps (no re-binning in the step)."""
+    _progress(f"generating {args.cells} cells")
+    cells = gi.batched_cells(args.cells)
+    ngrid = sum(c.ngrid for c in cells)
+    _progress(f"batch plans ({ngrid} points)")
+    b = g.GintBatch(cells, cells[0].species, precision=args.precision)
+    V = [torch.from_numpy(c.V).to(dev) for c in cells]
+    D = [torch.from_numpy(c.D).to(dev) for c in cells]
+    H = [torch.empty((n, n), dtype=torch.float64, device=dev) for n in b.norb]
+    rho = [torch.empty(n, dtype=torch.float64, device=dev) for n in b.ngrid]
+    F = [torch.empty((n, 3), dtype=torch.float64, device=dev) for n in b.natom]
+
+    def step():
+        b.build_H(V, out=H)
+        b.build_rho(D, out=rho)
+        b.force(V, D, out=F)
+
+    def seq_step():
+        for i, p in enumerate(b.cells):
+            p.build_H(V[i], out=H[i])
+            p.build_rho(D[i], out=rho[i])
+            p.force(V[i], D[i], out=F[i])
+
+    _progress(f"warmup {args.warmup}")
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    _progress(f"timed {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    # the same work as per-cell calls on one stream, for comparison
+    seq_step()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    seq_step()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t2) * 1e3
+    s1 = sum(p.work()["sum_ng"] for p in b.cells)
+    s2 = sum(p.work()["sum_ng2"] for p in b.cells)
+    alg = 3 * 2 * s2 + 2 * s1 + 6 * s1
+    kinds = np.bincount(gi.batched_kinds(args.cells), minlength=4)
+    out = {
+        "metric": "gint grid pts/s + MFMA util: FP64 vs mixed precision at stated |dH| (Si-512)",
+        "value": ngrid / (ms_step * 1e-3),
+        "unit": "grid pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.cells} independent Si cells (8/16/32/64 atoms: {kinds.tolist()}), DZP rc=8 bohr, "
+                         f"{ngrid} mesh points in total; one step = H + rho + dE/dR of every cell, one graph "
+                         "replay each, fixed geometry"),
+            "sequential_ms_per_step": seq_ms,
+            "graph_speedup_vs_sequential": seq_ms / ms_step,
+            "alg_tflops_whole_step": alg / (ms_step * 1e-3) / 1e12,
+        },
+    }
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="si512", choices=["si512", "si64", "si8"])
+    ap.add_argument("--workload", default="si512", choices=["si512", "si64", "si8", "batched"])
+    ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--only", default=None, choices=["H", "rho", "force"],
+                    help="time one contraction only (short profiler runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -116,13 +197,25 @@ def main():
     import paper_2603_21835_amd as g
 
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n, "launches": 3}), flush=True)
+        return
     g.load_library()
     dev = torch.device("cuda:0")
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, torch, gi, g, dev)), flush=True)
+        return
     _progress(f"generating {args.workload}")
     w = {"si512": gi.si512_dzp, "si64": gi.si64_dzp, "si8": gi.si8_sz}[args.workload]()
     _progress("plan")
 
-    plan = g.GintPlan.from_workload(w)
+    plan = g.GintPlan.from_workload(w, precision=args.precision)
     V = torch.from_numpy(w.V).to(dev)
     D = torch.from_numpy(w.D).to(dev)
     H = torch.empty((plan.norb, plan.norb), dtype=torch.float64, device=dev)
@@ -131,10 +224,14 @@ def main():
     work = plan.work()
 
     def step():
-        plan.set_positions(w.positions)
-        plan.build_H(V, out=H)
-        plan.build_rho(D, out=rho)
-        plan.force(V, D, out=F)
+        if args.only is None:
+            plan.set_positions(w.positions)
+        if args.only in (None, "H"):
+            plan.build_H(V, out=H)
+        if args.only in (None, "rho"):
+            plan.build_rho(D, out=rho)
+        if args.only in (None, "force"):
+            plan.force(V, D, out=F)
 
     _progress(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -155,7 +252,7 @@ def main():
     value = w.ngrid / ((t1 - t0) / args.steps)
 
     s1, s2 = work["sum_ng"], work["sum_ng2"]
-    flops = {"H_pairs": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1}
+    flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1}
     kernels = {}
     for k, (ms, n) in timing.items():
         if n == 0:
@@ -168,14 +265,17 @@ def main():
     roof = None
     if dom in flops:
         ach = flops[dom] / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": _traffic(dom, args.workload),
+        peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": _traffic(dom, args.workload, args.precision),
                 "kernel": dom, "alg_flops_per_launch": flops[dom]}
 
     # full-size consistency check: dV sum V rho == Tr(D H)  (adjoint identity)
-    E1 = plan.dV * float(torch.dot(V, rho))
-    E2 = float(torch.sum(D * H))
-    check = abs(E1 - E2) / max(abs(E2), 1e-300)
+    check = None
+    if args.only is None:
+        E1 = plan.dV * float(torch.dot(V, rho))
+        E2 = float(torch.sum(D * H))
+        check = abs(E1 - E2) / max(abs(E2), 1e-300)
 
     out = {
         "metric": "gint grid pts/s + MFMA util: FP64 vs mixed precision at stated |dH| (Si-512)",
@@ -188,19 +288,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh {'x'.join(map(str, w.grid))}, "
                         "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR",
-            "batch": list(work["batch"]), "nchunk": work["nchunk"], "group_pairs": work["npair"],
+            "batch": list(work["batch"]), "h_slabs": work["nslab"], "group_pairs": work["npair"],
             "sum_ng2": s2, "sum_ng": s1,
         },
         "roofline": roof,
         "kernels": kernels,
         "check_E_equals_trDH": check,
     }
-    if not args.no_cpu_baseline:
+    if args.only is not None:
+        out["only"] = args.only
+    if not args.no_cpu_baseline and args.only is None:
         _progress("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -255,17 +255,25 @@ def si512_dzp(seed: int = 5) -> Workload:
 BATCH_REPS = [(1, 1, 1), (1, 1, 2), (1, 2, 2), (2, 2, 2)]
 
 
-def batched_cells(n_cells: int = 256, seed: int = 4) -> List[Workload]:
+def batched_kinds(n_cells: int = 256, seed: int = 4) -> np.ndarray:
+    """Size class (0..3 -> 8, 16, 32, 64 atoms) of each batched cell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, 4, size=n_cells)
+
+
+def batched_cells(n_cells: int = 256, seed: int = 4, select=None) -> List[Workload]:
     """Uneven independent cells for the batched launch.
 
     Sizes are drawn uniformly from {8, 16, 32, 64} atoms with the master seed;
     cell i then uses sub-seed 4000+i for V (16 waves) and C (2 per atom).
     Mesh spacing a/24 for 8/16-atom cells and a/48 for 32/64-atom cells.
+    ``select`` (indices) builds only those cells, identical to the full set's.
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    kinds = rng.integers(0, 4, size=n_cells)
+    kinds = batched_kinds(n_cells, seed)
     cells = []
     for i, k in enumerate(kinds):
+        if select is not None and i not in select:
+            continue
         rep = BATCH_REPS[int(k)]
         per = 24 if k < 2 else 48
         grid = tuple(per * r for r in rep)

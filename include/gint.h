@@ -99,7 +99,7 @@ typedef struct {
     double sum_ng;         /* sum over mesh points of supported orbitals n_g     */
     double sum_ng2;        /* sum over mesh points of n_g^2                      */
     int batch[3];          /* batch shape in mesh points                         */
-    int nchunk;            /* batch-list chunks per group pair                   */
+    int nslab;             /* batch ranges the H path is split into              */
 } gint_work;
 
 typedef struct gint_plan_s *gint_plan;
@@ -125,9 +125,11 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
 gint_status gint_plan_set_positions(gint_plan plan, const double *positions);
 
 /* Batch shape (mesh points per batch along each axis; product 16 or 32) and
- * the number of chunks each group pair's batch list is split into (0 =
- * automatic).  Rebuilds the lists; synchronises the stream. */
-gint_status gint_plan_tune(gint_plan plan, const int batch[3], int nchunk);
+ * the device-memory budget (bytes) of the H path's per-batch block partials
+ * (0 = automatic: min(16 GiB, a third of free memory)); a smaller budget
+ * splits H into more batch ranges.  Rebuilds the lists; synchronises the
+ * stream. */
+gint_status gint_plan_tune(gint_plan plan, const int batch[3], long long h_budget_bytes);
 
 /* Change the stream subsequent calls enqueue on. */
 gint_status gint_plan_set_stream(gint_plan plan, void *hip_stream);
@@ -165,8 +167,8 @@ gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const doubl
 /* Kernel classes reported by gint_plan_timing. */
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
-    GINT_K_H_PAIRS = 1,   /* H contraction (atom-group pairs over their batches)     */
-    GINT_K_H_CONVERT = 2, /* H reduction over chunks and dense symmetric output     */
+    GINT_K_H = 1,         /* H atom-pair blocks (one workgroup per mesh batch)      */
+    GINT_K_H_REDUCE = 2,  /* H zero fill and fixed-order block sums into dense H    */
     GINT_K_RHO = 3,       /* rho contraction (one workgroup per mesh batch)         */
     GINT_K_PACK = 4,      /* D + D^T packed into matrix-core fragments (rho, force) */
     GINT_K_FORCE = 5,     /* force contraction (one workgroup per mesh batch)       */
@@ -190,6 +192,49 @@ gint_status gint_plan_sync(gint_plan plan);
 /* Work counts of the current geometry (computes the exact sum_g n_g^2 on
  * the GPU; synchronises the stream). */
 gint_status gint_plan_work(gint_plan plan, gint_work *out);
+
+/* ---------------------------------------------------------------------
+ * Batched cells: many independent periodic cells of uneven size, one call
+ * for all of them.  The work of a call is captured once into a hipGraph of
+ * concurrent chains and replayed with a single graph launch on the batch's
+ * stream while the cells' geometry and the caller's device pointers stay
+ * the same.  Per-cell conventions are those of the single-cell calls.
+ * --------------------------------------------------------------------- */
+typedef struct {
+    double lattice[9];          /* rows a1, a2, a3                        */
+    int grid[3];
+    int natom;
+    const int *species_of_atom; /* host, natom                            */
+    const double *positions;    /* host, natom*3                          */
+} gint_cell;
+
+typedef struct gint_batch_s *gint_batch;
+
+/* Create plans for ncell cells sharing one basis (nspecies, species) and
+ * precision.  Synchronises the device. */
+gint_status gint_batch_create(int ncell, const gint_cell *cells, int nspecies, const gint_species *species,
+                              gint_precision prec, void *hip_stream, gint_batch *out);
+
+/* H of every cell.  V_dev, H_dev: host arrays of ncell device pointers. */
+gint_status gint_batch_build_H(gint_batch batch, const double *const *V_dev, double *const *H_dev);
+
+/* rho of every cell.  D_dev, rho_dev: host arrays of ncell device pointers. */
+gint_status gint_batch_build_rho(gint_batch batch, const double *const *D_dev, double *const *rho_dev);
+
+/* dE/dR of every cell (E = dV sum W rho per cell). */
+gint_status gint_batch_force(gint_batch batch, const double *const *W_dev, const double *const *D_dev,
+                             double *const *dEdR_dev);
+
+gint_status gint_batch_sync(gint_batch batch);
+int gint_batch_ncell(gint_batch batch);
+/* The plan of cell i (owned by the batch; do not destroy).  Moving its
+ * atoms or tuning it invalidates the captured graphs, which are re-captured
+ * on the next call.  Batched calls run each cell on a stream of the batch
+ * (gint_plan_set_stream on a cell affects only its single-cell calls, and
+ * per-kernel timing must be off for batched calls: GINT_ESTATE).  Each
+ * chain's cells share one H partial buffer of at most 8 GiB. */
+gint_plan gint_batch_cell(gint_batch batch, int i);
+void gint_batch_destroy(gint_batch batch);
 
 int gint_norb(gint_plan plan);   /* total orbitals, or -1 for an invalid plan */
 int gint_natom(gint_plan plan);  /* atoms, or -1                               */

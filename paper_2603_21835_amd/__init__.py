@@ -31,8 +31,10 @@ EXPORTS = (
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing",
+    "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
+    "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy",
 )
-KERNELS = ("bin", "H_pairs", "H_convert", "rho", "pack_D", "force", "force_reduce")
+KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce")
 
 
 class GintError(RuntimeError):
@@ -51,11 +53,16 @@ class _Species(ctypes.Structure):
     _fields_ = [("nradial", ctypes.c_int), ("radial", ctypes.POINTER(_Radial))]
 
 
+class _Cell(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_double * 9), ("grid", ctypes.c_int * 3), ("natom", ctypes.c_int),
+                ("species_of_atom", ctypes.POINTER(ctypes.c_int)), ("positions", ctypes.POINTER(ctypes.c_double))]
+
+
 class Work(ctypes.Structure):
     _fields_ = [("ngrid", ctypes.c_longlong), ("nbatch", ctypes.c_longlong),
                 ("nentry", ctypes.c_longlong), ("npair", ctypes.c_longlong),
                 ("sum_ng", ctypes.c_double), ("sum_ng2", ctypes.c_double),
-                ("batch", ctypes.c_int * 3), ("nchunk", ctypes.c_int)]
+                ("batch", ctypes.c_int * 3), ("nslab", ctypes.c_int)]
 
 
 _lib = None
@@ -79,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_set_positions.restype = st
     lib.gint_plan_set_positions.argtypes = [P, dp]
     lib.gint_plan_tune.restype = st
-    lib.gint_plan_tune.argtypes = [P, ip, ctypes.c_int]
+    lib.gint_plan_tune.argtypes = [P, ip, ctypes.c_longlong]
     lib.gint_plan_set_stream.restype = st
     lib.gint_plan_set_stream.argtypes = [P, P]
     for name in ("gint_build_H", "gint_build_H_weighted", "gint_build_rho"):
@@ -108,6 +115,23 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_timing.argtypes = [P, dp, ip]
     lib.gint_plan_destroy.restype = None
     lib.gint_plan_destroy.argtypes = [P]
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.gint_batch_create.restype = st
+    lib.gint_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_Cell), ctypes.c_int, ctypes.POINTER(_Species),
+                                      ctypes.c_int, P, ctypes.POINTER(ctypes.c_void_p)]
+    for name in ("gint_batch_build_H", "gint_batch_build_rho"):
+        getattr(lib, name).restype = st
+        getattr(lib, name).argtypes = [P, PP, PP]
+    lib.gint_batch_force.restype = st
+    lib.gint_batch_force.argtypes = [P, PP, PP, PP]
+    lib.gint_batch_sync.restype = st
+    lib.gint_batch_sync.argtypes = [P]
+    lib.gint_batch_ncell.restype = ctypes.c_int
+    lib.gint_batch_ncell.argtypes = [P]
+    lib.gint_batch_cell.restype = P
+    lib.gint_batch_cell.argtypes = [P, ctypes.c_int]
+    lib.gint_batch_destroy.restype = None
+    lib.gint_batch_destroy.argtypes = [P]
     _lib = lib
     return lib
 
@@ -146,6 +170,20 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _species_array(species, keep):
+    sp_arr = (_Species * len(species))()
+    for s, spc in enumerate(species):
+        rads = (_Radial * len(spc.radials))()
+        for k, r in enumerate(spc.radials):
+            f = np.ascontiguousarray(r.f, dtype=np.float64)
+            keep.append(f)
+            rads[k] = _Radial(int(r.l), int(f.size), float(r.dr), _dptr(f), float(r.dfdr0), float(r.dfdrc))
+        keep.append(rads)
+        sp_arr[s] = _Species(len(spc.radials), rads)
+    keep.append(sp_arr)
+    return sp_arr
+
+
 class GintPlan:
     """Geometry + mesh + basis of one periodic cell (the GintInfo of Fig. 2).
 
@@ -160,16 +198,7 @@ class GintPlan:
         self._lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
         self._grid = np.ascontiguousarray(grid, dtype=np.int32).reshape(3)
         self._keep = []
-        sp_arr = (_Species * len(species))()
-        for s, spc in enumerate(species):
-            rads = (_Radial * len(spc.radials))()
-            for k, r in enumerate(spc.radials):
-                f = np.ascontiguousarray(r.f, dtype=np.float64)
-                self._keep.append(f)
-                rads[k] = _Radial(int(r.l), int(f.size), float(r.dr), _dptr(f), float(r.dfdr0), float(r.dfdrc))
-            self._keep.append(rads)
-            sp_arr[s] = _Species(len(spc.radials), rads)
-        self._keep.append(sp_arr)
+        sp_arr = _species_array(species, self._keep)
         self._soa = np.ascontiguousarray(species_of_atom, dtype=np.int32)
         pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
         self.natom = int(self._soa.size)
@@ -189,7 +218,25 @@ class GintPlan:
         return cls(w.lattice, w.grid, w.species, w.species_of_atom, w.positions, precision, stream)
 
     # -- lifecycle -------------------------------------------------------------
+    @classmethod
+    def _borrowed(cls, handle, lattice, grid, natom, precision):
+        """A view of a plan owned by a GintBatch (never destroyed by the view)."""
+        self = cls.__new__(cls)
+        self._lib = load_library()
+        self._owner = False
+        self._h = ctypes.c_void_p(handle)
+        self.natom = int(natom)
+        self.grid = tuple(int(x) for x in grid)
+        self.ngrid = int(np.prod(self.grid))
+        self.norb = int(self._lib.gint_norb(self._h))
+        self.dV = float(self._lib.gint_dV(self._h))
+        self.precision = precision
+        return self
+
     def close(self):
+        if not getattr(self, "_owner", True):
+            self._h = None
+            return
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.gint_plan_destroy(self._h)
             self._h = None
@@ -212,9 +259,11 @@ class GintPlan:
             raise ValueError("positions must have natom*3 entries")
         _check(self._lib.gint_plan_set_positions(self._handle(), _dptr(pos)))
 
-    def tune(self, batch: Sequence[int], nchunk: int = 0):
+    def tune(self, batch: Sequence[int], h_budget_bytes: int = 0):
+        """Batch shape and the device-memory budget of the H path's block
+        partials (0 = automatic); rebuilds the lists."""
         b = np.ascontiguousarray(batch, dtype=np.int32)
-        _check(self._lib.gint_plan_tune(self._handle(), _iptr(b), int(nchunk)))
+        _check(self._lib.gint_plan_tune(self._handle(), _iptr(b), int(h_budget_bytes)))
 
     def set_stream(self, stream=None):
         _check(self._lib.gint_plan_set_stream(self._handle(), _stream_handle(stream)))
@@ -226,7 +275,7 @@ class GintPlan:
         w = Work()
         _check(self._lib.gint_plan_work(self._handle(), ctypes.byref(w)))
         return {"ngrid": w.ngrid, "nbatch": w.nbatch, "nentry": w.nentry, "npair": w.npair,
-                "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nchunk": w.nchunk}
+                "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nslab": w.nslab}
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.gint_plan_set_timing(self._handle(), 1 if enable else 0))
@@ -285,3 +334,104 @@ def build_rho(plan: GintPlan, D, out=None):
 
 def force(plan: GintPlan, W, D, out=None):
     return plan.force(W, D, out)
+
+
+class GintBatch:
+    """Many independent periodic cells (uneven sizes, one basis) behind one
+    call per quantity; each call replays one captured hipGraph while the
+    geometries and the tensors passed stay the same.
+
+    ``cells``: list of workloads (objects with lattice, grid,
+    species_of_atom, positions).  Pass ``out=`` lists to keep the device
+    pointers, and so the captured graph, the same from call to call.
+    """
+
+    def __init__(self, cells, species, precision: str = "fp64", stream=None):
+        lib = load_library()
+        self._lib = lib
+        self._keep = []
+        sp_arr = _species_array(species, self._keep)
+        n = len(cells)
+        arr = (_Cell * n)()
+        self.ngrid, self.natom, self.grid = [], [], []
+        for i, c in enumerate(cells):
+            lat = np.ascontiguousarray(c.lattice, dtype=np.float64).reshape(9)
+            grid = np.ascontiguousarray(c.grid, dtype=np.int32).reshape(3)
+            soa = np.ascontiguousarray(c.species_of_atom, dtype=np.int32)
+            pos = np.ascontiguousarray(c.positions, dtype=np.float64).reshape(-1)
+            self._keep += [soa, pos]
+            arr[i].lattice[:] = list(lat)
+            arr[i].grid[:] = [int(x) for x in grid]
+            arr[i].natom = int(soa.size)
+            arr[i].species_of_atom = _iptr(soa)
+            arr[i].positions = _dptr(pos)
+            self.ngrid.append(int(np.prod(grid)))
+            self.natom.append(int(soa.size))
+            self.grid.append(tuple(int(x) for x in grid))
+        handle = ctypes.c_void_p()
+        _check(lib.gint_batch_create(n, arr, len(species), sp_arr, PRECISIONS[precision], _stream_handle(stream),
+                                     ctypes.byref(handle)))
+        self._h = handle
+        self.ncell = n
+        self.precision = precision
+        self.cells = [GintPlan._borrowed(lib.gint_batch_cell(handle, i), cells[i].lattice, self.grid[i],
+                                         self.natom[i], precision) for i in range(n)]
+        self.norb = [p.norb for p in self.cells]
+        self.dV = [p.dV for p in self.cells]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for p in self.cells:
+                p.close()
+            self._lib.gint_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if self._h is None:
+            raise GintError(GINT_ESTATE, "batch is closed")
+        return self._h
+
+    def _ptrs(self, ts, sizes, what):
+        if len(ts) != self.ncell:
+            raise ValueError(f"{what}: expected {self.ncell} tensors")
+        arr = (ctypes.c_void_p * self.ncell)()
+        for i, (t, n) in enumerate(zip(ts, sizes)):
+            arr[i] = _dev_ptr(t, n, f"{what}[{i}]").value
+        return arr
+
+    def _outs(self, out, shapes, like):
+        import torch
+
+        if out is None:
+            out = [torch.empty(sh, dtype=torch.float64, device=like.device) for sh in shapes]
+        return out
+
+    def sync(self):
+        _check(self._lib.gint_batch_sync(self._handle()))
+
+    def build_H(self, V, out=None):
+        nn = [n * n for n in self.norb]
+        out = self._outs(out, [(n, n) for n in self.norb], V[0])
+        _check(self._lib.gint_batch_build_H(self._handle(), self._ptrs(V, self.ngrid, "V"),
+                                            self._ptrs(out, nn, "H")))
+        return out
+
+    def build_rho(self, D, out=None):
+        nn = [n * n for n in self.norb]
+        out = self._outs(out, [(g,) for g in self.ngrid], D[0])
+        _check(self._lib.gint_batch_build_rho(self._handle(), self._ptrs(D, nn, "D"),
+                                              self._ptrs(out, self.ngrid, "rho")))
+        return out
+
+    def force(self, W, D, out=None):
+        nn = [n * n for n in self.norb]
+        out = self._outs(out, [(a, 3) for a in self.natom], W[0])
+        _check(self._lib.gint_batch_force(self._handle(), self._ptrs(W, self.ngrid, "W"), self._ptrs(D, nn, "D"),
+                                          self._ptrs(out, [3 * a for a in self.natom], "dEdR")))
+        return out

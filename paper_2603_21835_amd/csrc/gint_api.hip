@@ -93,8 +93,13 @@ struct gint_plan_s {
     int natom = 0, norb = 0, nrad = 0, nspecies = 0;
     double dV = 0.0;
     double rc_max = 0.0;
-    int nchunk_req = 0;  // 0 = automatic
-    int nchunk = 1;
+    long long hbudget_req = 0;  // H partial-buffer budget in bytes (0 = automatic)
+    void *ext_hpart = nullptr;  // H partial buffer lent by a batch (shared by its chain)
+    size_t ext_hpart_bytes = 0;
+    long long gen = 0;          // bumped whenever the lists are rebuilt
+    int mno = 0;                // most orbitals of any species
+    double brad = 0.0;          // radius of a full batch's point box
+    std::vector<int> slab;      // batch ranges [slab[i], slab[i+1]) of the H path
     long long nent = 0, nimg = 0, ngb = 0, npair = 0, ngbatch = 0;
 
     // basis and atoms
@@ -106,7 +111,8 @@ struct gint_plan_s {
     DevBuf gcnt, gptr, gbatch;
     DevBuf mark, mscan, pair_index, pairA, pairB;
     // work buffers
-    DevBuf Hblk, S2pk, Fent, sums, readback;
+    DevBuf Hpart, S2pk, Fent, sums, readback;
+    DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist;
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
 
     // optional per-kernel timing (events on the plan's stream)
@@ -130,6 +136,18 @@ struct gint_plan_s {
             (void)hipEventDestroy(e);
     }
 
+    bool f32() const { return prec == GINT_FP32; }
+    void *hpart() const { return ext_hpart ? ext_hpart : Hpart.p; }
+    AtomLists atom_lists() const
+    {
+        AtomLists a;
+        a.aptr = aptr.as<int>();
+        a.aent = aent.as<int>();
+        a.abat = abat.as<int>();
+        a.pptr = pptr.as<int>();
+        a.plist = plist.as<int>();
+        return a;
+    }
     Basis basis() const
     {
         Basis b;
@@ -204,6 +222,23 @@ void set_batch(Geo &g, const int bs[3])
     }
     g.P = bs[0] * bs[1] * bs[2];
     g.nbatch = g.nb[0] * g.nb[1] * g.nb[2];
+}
+
+// Radius of the bounding sphere of a full batch's point box.
+double batch_radius(const Geo &g)
+{
+    double rad = 0.0;
+    for (int m = 0; m < 8; ++m) {
+        double x[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3; ++k) {
+            const double sgn = (m >> k) & 1 ? 0.5 : -0.5;
+            const double f = sgn * (double)(g.bs[k] - 1) / g.N[k];
+            for (int c = 0; c < 3; ++c)
+                x[c] += f * g.lat[3 * k + c];
+        }
+        rad = std::max(rad, std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+    }
+    return rad;
 }
 
 // Largest lattice multiple any batch can need, given the batch shape.
@@ -332,6 +367,14 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     if (p->nbmax > kMaxBatchAtoms || p->ngbmax > kMaxBatchGroups)
         return fail(GINT_EUNSUPPORTED, "%d atoms / %d atom groups reach one mesh batch (max %d / %d); use a smaller batch",
                     p->nbmax, p->ngbmax, kMaxBatchAtoms, kMaxBatchGroups);
+    {
+        // LDS of the point-stationary kernels: every atom of a batch at once
+        const size_t esz = p->prec == GINT_FP32 ? sizeof(float) : sizeof(double);
+        const size_t lds_H = esz * (size_t)p->nbmax * g.P * kRow + 8192;
+        if (lds_H > 163840)
+            return fail(GINT_EUNSUPPORTED, "%d atoms reach one %d-point batch: %zu bytes of LDS; use a smaller batch",
+                        p->nbmax, g.P, lds_H);
+    }
     STCHK(p->ent_atom.ensure(sizeof(int) * (p->nent + 1)));
     STCHK(p->ent_img.ensure(sizeof(int) * (p->nent + 1)));
     STCHK(p->img.ensure(sizeof(int) * (p->nimg + 1)));
@@ -374,19 +417,74 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     HIPCHK(launch_pair_list(s, ng, p->mark.as<int>(), p->mscan.as<int>(), p->pair_index.as<int>(),
                             p->pairA.as<int>(), p->pairB.as<int>()));
 
-    // chunks: enough workgroups to cover the chip several times
-    int nch = p->nchunk_req;
-    if (nch <= 0) {
-        nch = 1;
-        while ((long long)p->npair * nch < 4096 && nch < 64)
-            nch *= 2;
+    // point-stationary H: per-batch block offsets, per-atom entry lists and
+    // owned-partner lists, and the batch ranges (slabs) whose block partials
+    // fit the partial-buffer budget
+    STCHK(p->cnt_blk.ensure(sizeof(int) * nb));
+    STCHK(p->boff.ensure(sizeof(int) * (nb + 1)));
+    HIPCHK(launch_block_count(s, g.nbatch, p->bptr.as<int>(), p->cnt_blk.as<int>()));
+    HIPCHK(launch_scan_i32(s, p->cnt_blk.as<int>(), nb, p->boff.as<int>()));
+    // (na: atom count, set above)
+    STCHK(p->acnt.ensure(sizeof(int) * na));
+    STCHK(p->aptr.ensure(sizeof(int) * (na + 1)));
+    STCHK(p->aent.ensure(sizeof(int) * (p->nent + 1)));
+    STCHK(p->abat.ensure(sizeof(int) * (p->nent + 1)));
+    HIPCHK(launch_fill_i32(s, p->acnt.as<int>(), na, 0));
+    STCHK(timed(p, GINT_K_BIN, [&] { return launch_atom_count(s, p->nent, p->ent_atom.as<int>(), p->acnt.as<int>()); }));
+    HIPCHK(launch_scan_i32(s, p->acnt.as<int>(), na, p->aptr.as<int>()));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_atom_fill(s, na, p->gptr.as<int>(), p->gbatch.as<int>(), p->bptr.as<int>(),
+                                p->ent_atom.as<int>(), p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>());
+    }));
+    STCHK(p->pcnt.ensure(sizeof(int) * na));
+    STCHK(p->pptr.ensure(sizeof(int) * (na + 1)));
+    const Basis B2 = p->basis();
+    STCHK(timed(p, GINT_K_BIN, [&] { return launch_partners(s, g, B2, p->brad, nullptr, p->pcnt.as<int>(), nullptr); }));
+    HIPCHK(launch_scan_i32(s, p->pcnt.as<int>(), na, p->pptr.as<int>()));
+    std::vector<int> hboff(nb + 1);
+    int tpart = 0;
+    HIPCHK(hipMemcpyAsync(hboff.data(), p->boff.p, sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tpart, p->pptr.as<int>() + na, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hboff[nb] < 0 || tpart < 0)
+        return fail(GINT_EUNSUPPORTED, "block lists exceed 2^31 entries");
+    STCHK(p->plist.ensure(sizeof(int) * (tpart + 1)));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_partners(s, g, B2, p->brad, p->pptr.as<int>(), p->pcnt.as<int>(), p->plist.as<int>());
+    }));
+    const size_t esz = p->prec == GINT_FP32 ? sizeof(float) : sizeof(double);
+    const size_t blk_bytes = esz * (size_t)p->mno * p->mno;
+    size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)16 << 30;
+    if (p->ext_hpart)
+        budget = p->ext_hpart_bytes;
+    else if (p->hbudget_req <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr / 3 < budget)
+            budget = fr / 3;
     }
-    p->nchunk = nch;
-    const long long nwg = p->npair * (long long)nch;
-    if (nwg > 0x7fffffffLL)
-        return fail(GINT_EUNSUPPORTED, "too many group-pair workgroups");
-    STCHK(p->Hblk.ensure(sizeof(double) * 16 * 256 * nwg));
-    STCHK(p->S2pk.ensure(sizeof(double) * 16 * 512 * (size_t)p->npair));
+    long long per_slab = (long long)(budget / blk_bytes);
+    if (per_slab < kMaxBatchAtoms * (kMaxBatchAtoms + 1) / 2)
+        per_slab = kMaxBatchAtoms * (kMaxBatchAtoms + 1) / 2;
+    p->slab.assign(1, 0);
+    long long most = 0;
+    for (int b = 0; b < nb;) {
+        int e = b;
+        while (e < nb && (long long)hboff[e + 1] - hboff[b] <= per_slab)
+            ++e;
+        if (e == b)
+            ++e;
+        most = std::max(most, (long long)hboff[e] - hboff[b]);
+        p->slab.push_back(e);
+        b = e;
+    }
+    if (p->ext_hpart) {
+        if (blk_bytes * (size_t)most > p->ext_hpart_bytes)
+            return fail(GINT_ENOMEM, "a batch of the cell needs %zu bytes of H partials", blk_bytes * (size_t)most);
+    } else {
+        STCHK(p->Hpart.ensure(blk_bytes * (size_t)std::max(most, 1LL)));
+    }
+    ++p->gen;
+    STCHK(p->S2pk.ensure(esz * 16 * 512 * (size_t)p->npair));
     STCHK(p->Fent.ensure(sizeof(double) * 3 * (size_t)(p->nent + 1)));
     return GINT_OK;
 }
@@ -498,9 +596,21 @@ const char *gint_status_string(gint_status s)
 
 const char *gint_last_error(void) { return g_last_error.c_str(); }
 
+static gint_status plan_create(const double lattice[9], const int grid[3], int nspecies, const gint_species *species,
+                               int natom, const int *species_of_atom, const double *positions, gint_precision prec,
+                               void *hip_stream, void *ext_hpart, size_t ext_hpart_bytes, gint_plan *out);
+
 gint_status gint_plan_create(const double lattice[9], const int grid[3], int nspecies, const gint_species *species,
                              int natom, const int *species_of_atom, const double *positions, gint_precision prec,
                              void *hip_stream, gint_plan *out)
+{
+    return plan_create(lattice, grid, nspecies, species, natom, species_of_atom, positions, prec, hip_stream, nullptr,
+                       0, out);
+}
+
+static gint_status plan_create(const double lattice[9], const int grid[3], int nspecies, const gint_species *species,
+                               int natom, const int *species_of_atom, const double *positions, gint_precision prec,
+                               void *hip_stream, void *ext_hpart, size_t ext_hpart_bytes, gint_plan *out)
 {
     if (!out)
         return fail(GINT_EINVAL, "out is NULL");
@@ -519,7 +629,7 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
         return fail(GINT_EINVAL, "positions have non-finite entries");
     if ((int)prec < 0 || (int)prec > 3)
         return fail(GINT_EINVAL, "unknown precision %d", (int)prec);
-    if (prec != GINT_FP64)
+    if (prec != GINT_FP64 && prec != GINT_FP32)
         return fail(GINT_EUNSUPPORTED, "precision %d is not available in this build", (int)prec);
     g.natom = natom;
     g.ngroup = (natom + kGroup - 1) / kGroup;
@@ -591,6 +701,8 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
         return fail(GINT_ENOMEM, "host allocation failed");
     p->device = dev;
     p->stream = (hipStream_t)hip_stream;
+    p->ext_hpart = ext_hpart;
+    p->ext_hpart_bytes = ext_hpart_bytes;
     p->prec = prec;
     p->geo = g;
     p->natom = natom;
@@ -600,6 +712,9 @@ gint_status gint_plan_create(const double lattice[9], const int grid[3], int nsp
     p->geo.nspecies = nspecies;
     p->nspecies = nspecies;
     p->rc_max = rc_max;
+    for (int s = 0; s < nspecies; ++s)
+        p->mno = std::max(p->mno, sp[s].norb);
+    p->brad = batch_radius(g);
     p->dV = std::fabs(g.lat[0] * (g.lat[4] * g.lat[8] - g.lat[5] * g.lat[7]) -
                       g.lat[1] * (g.lat[3] * g.lat[8] - g.lat[5] * g.lat[6]) +
                       g.lat[2] * (g.lat[3] * g.lat[7] - g.lat[4] * g.lat[6])) /
@@ -670,7 +785,7 @@ gint_status gint_plan_set_positions(gint_plan p, const double *positions)
     return GINT_OK;
 }
 
-gint_status gint_plan_tune(gint_plan p, const int batch[3], int nchunk)
+gint_status gint_plan_tune(gint_plan p, const int batch[3], long long h_budget_bytes)
 {
     STCHK(check_plan(p));
     if (!batch)
@@ -681,15 +796,16 @@ gint_status gint_plan_tune(gint_plan p, const int batch[3], int nchunk)
     const int P = batch[0] * batch[1] * batch[2];
     if (P != 16 && P != 32)
         return fail(GINT_EINVAL, "batch holds %d points (must be 16 or 32)", P);
-    if (nchunk < 0 || nchunk > 4096)
-        return fail(GINT_EINVAL, "nchunk = %d outside [0, 4096]", nchunk);
+    if (h_budget_bytes < 0)
+        return fail(GINT_EINVAL, "h_budget_bytes must be >= 0");
     Geo g = p->geo;
     set_batch(g, batch);
     if (max_image_index(g, p->rc_max) >= 126.0)
         return fail(GINT_EUNSUPPORTED, "cutoff spans more than 125 cells");
     HIPCHK(hipSetDevice(p->device));
     p->geo = g;
-    p->nchunk_req = nchunk;
+    p->brad = batch_radius(g);
+    p->hbudget_req = h_budget_bytes;
     STCHK(rebuild_lists(p, false));
     return GINT_OK;
 }
@@ -709,12 +825,20 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    STCHK(timed(p, GINT_K_H_PAIRS, [&] {
-        return launch_pairs_H(p->stream, p->geo, bn, B, (int)p->npair, p->nchunk, W, wscale, p->Hblk.as<double>());
-    }));
-    STCHK(timed(p, GINT_K_H_CONVERT, [&] {
-        return launch_H_convert(p->stream, p->geo, bn, B, p->norb, p->nchunk, p->Hblk.as<double>(), H);
-    }));
+    const AtomLists al = p->atom_lists();
+    STCHK(timed(p, GINT_K_H_REDUCE,
+                [&] { return launch_fill_f64(p->stream, H, (long long)p->norb * p->norb, 0.0); }));
+    for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
+        const int b0 = p->slab[i], b1 = p->slab[i + 1];
+        STCHK(timed(p, GINT_K_H, [&] {
+            return launch_H_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, b0, b1, W, wscale, p->boff.as<int>(),
+                                  p->mno, p->hpart());
+        }));
+        STCHK(timed(p, GINT_K_H_REDUCE, [&] {
+            return launch_H_rowreduce(p->stream, p->f32(), p->geo, bn, B, al, p->mno, p->norb, p->hpart(),
+                                      p->boff.as<int>(), b0, b1, i > 0 ? 1 : 0, H);
+        }));
+    }
     return GINT_OK;
 }
 
@@ -738,10 +862,10 @@ gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
     const Bins bn = p->bins();
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_PACK, [&] {
-        return launch_pack_S2(p->stream, p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.as<double>());
+        return launch_pack_S2(p->stream, p->f32(), p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.p);
     }));
     STCHK(timed(p, GINT_K_RHO,
-                [&] { return launch_rho_batch(p->stream, p->geo, bn, B, p->nbmax, p->S2pk.as<double>(), rho_dev); }));
+                [&] { return launch_rho_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, p->S2pk.p, rho_dev); }));
     return GINT_OK;
 }
 
@@ -754,10 +878,10 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
     const Bins bn = p->bins();
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_PACK, [&] {
-        return launch_pack_S2(p->stream, p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.as<double>());
+        return launch_pack_S2(p->stream, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
     }));
     STCHK(timed(p, GINT_K_FORCE, [&] {
-        return launch_force_batch(p->stream, p->geo, bn, B, p->nbmax, p->S2pk.as<double>(), W, wscale,
+        return launch_force_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, p->S2pk.p, W, wscale,
                                   p->Fent.as<double>());
     }));
     STCHK(timed(p, GINT_K_F_REDUCE,
@@ -810,7 +934,7 @@ gint_status gint_plan_work(gint_plan p, gint_work *out)
     out->sum_ng2 = s2;
     for (int k = 0; k < 3; ++k)
         out->batch[k] = p->geo.bs[k];
-    out->nchunk = p->nchunk;
+    out->nslab = (int)p->slab.size() - 1;
     return GINT_OK;
 }
 
@@ -853,6 +977,318 @@ void gint_plan_destroy(gint_plan p)
     (void)hipStreamSynchronize(p->stream);
     p->magic = 0;
     delete p;
+}
+
+}  // extern "C"
+
+
+// ===========================================================================
+// Batched cells: one plan per cell; every call on the batch is captured once
+// into a hipGraph made of kChains concurrent chains (cells assigned longest
+// first to the least loaded chain, each chain with its own H partial buffer)
+// and replayed with a single hipGraphLaunch while the geometry and the
+// caller's pointers stay the same.
+
+namespace {
+constexpr unsigned kBatchMagic = 0x47424154u;  // "GBAT"
+constexpr int kChains = 4;                     // one per hardware queue of the process
+
+struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> sig;
+    std::vector<long long> gens;
+};
+}  // namespace
+
+struct gint_batch_s {
+    unsigned magic = kBatchMagic;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<gint_plan> plans;
+    std::vector<int> chain_of;
+    std::vector<int> order;  // cells by decreasing cost
+    hipStream_t cap = nullptr;  // private origin stream of the captures
+    hipStream_t chains[kChains] = {};
+    hipEvent_t fork = nullptr, join[kChains] = {};
+    DevBuf hpart[kChains];
+    GraphSlot gH, gR, gF;
+
+    ~gint_batch_s()
+    {
+        for (GraphSlot *g : {&gH, &gR, &gF})
+            if (g->exec)
+                (void)hipGraphExecDestroy(g->exec);
+        for (auto p : plans)
+            gint_plan_destroy(p);
+        for (int c = 0; c < kChains; ++c) {
+            if (join[c])
+                (void)hipEventDestroy(join[c]);
+            if (chains[c])
+                (void)hipStreamDestroy(chains[c]);
+        }
+        if (fork)
+            (void)hipEventDestroy(fork);
+        if (cap)
+            (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+gint_status check_batch(gint_batch b)
+{
+    if (!b)
+        return fail(GINT_EINVAL, "batch is NULL");
+    if (b->magic != kBatchMagic)
+        return fail(GINT_ESTATE, "batch is destroyed or corrupted");
+    return GINT_OK;
+}
+
+// Capture `body` (which enqueues every cell's work on its chain stream) into
+// the slot's graph unless the pointers and geometries are unchanged, then
+// launch the graph on the batch stream.
+template <typename F>
+gint_status run_graph(gint_batch b, GraphSlot &slot, const std::vector<const void *> &sig, F body)
+{
+    std::vector<long long> gens;
+    for (auto p : b->plans)
+        gens.push_back(p->gen);
+    if (!slot.exec || slot.sig != sig || slot.gens != gens) {
+        if (slot.exec) {
+            (void)hipGraphExecDestroy(slot.exec);
+            slot.exec = nullptr;
+        }
+        for (auto p : b->plans)
+            if (p->timing)
+                return fail(GINT_ESTATE, "disable per-kernel timing on the cells before batched calls");
+        // during the capture every cell runs on its chain's stream
+        std::vector<hipStream_t> own(b->plans.size());
+        for (size_t i = 0; i < b->plans.size(); ++i) {
+            own[i] = b->plans[i]->stream;
+            b->plans[i]->stream = b->chains[b->chain_of[i]];
+        }
+        struct Restore {
+            gint_batch b;
+            std::vector<hipStream_t> &own;
+            ~Restore()
+            {
+                for (size_t i = 0; i < b->plans.size(); ++i)
+                    b->plans[i]->stream = own[i];
+            }
+        } restore{b, own};
+        HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+        gint_status st = GINT_OK;
+        hipError_t e = hipEventRecord(b->fork, b->cap);
+        for (int c = 0; c < kChains && e == hipSuccess; ++c)
+            e = hipStreamWaitEvent(b->chains[c], b->fork, 0);
+        if (e == hipSuccess)
+            st = body();
+        for (int c = 0; c < kChains && e == hipSuccess; ++c) {
+            e = hipEventRecord(b->join[c], b->chains[c]);
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(b->cap, b->join[c], 0);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+        if (st != GINT_OK) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return fail(GINT_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            slot.exec = nullptr;
+            return fail(GINT_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        }
+        slot.sig = sig;
+        slot.gens = gens;
+    }
+    HIPCHK(hipGraphLaunch(slot.exec, b->stream));
+    return GINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gint_status gint_batch_create(int ncell, const gint_cell *cells, int nspecies, const gint_species *species,
+                              gint_precision prec, void *hip_stream, gint_batch *out)
+{
+    if (!out)
+        return fail(GINT_EINVAL, "out is NULL");
+    if (ncell < 1 || !cells)
+        return fail(GINT_EINVAL, "ncell must be >= 1 and cells non-NULL");
+    double rc_max = 0.0;
+    STCHK(validate_species(nspecies, species, &rc_max));
+    for (int i = 0; i < ncell; ++i) {
+        Geo g{};
+        STCHK(validate_geometry(cells[i].lattice, cells[i].grid, g));
+        if (cells[i].natom < 1 || cells[i].natom > kMaxAtoms || !cells[i].species_of_atom || !cells[i].positions)
+            return fail(GINT_EINVAL, "cell %d: invalid atoms", i);
+    }
+    int dev = 0;
+    STCHK(device_ok(&dev));
+    gint_batch b = new (std::nothrow) gint_batch_s();
+    if (!b)
+        return fail(GINT_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->stream = (hipStream_t)hip_stream;
+    gint_status st = GINT_OK;
+    auto bail = [&](gint_status s2) {
+        if (b->stream)
+            (void)hipStreamSynchronize(b->stream);
+        b->magic = 0;
+        delete b;
+        return s2;
+    };
+    for (int c = 0; c < kChains; ++c) {
+        if (hipStreamCreateWithFlags(&b->chains[c], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(GINT_EDEVICE, "stream/event creation failed"));
+    }
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(GINT_EDEVICE, "event creation failed"));
+    // per-chain H partial buffers (a chain runs its cells one after the
+    // other): at most 8 GiB each and a third of free memory overall
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess)
+        return bail(fail(GINT_EDEVICE, "hipMemGetInfo failed"));
+    size_t per_chain = std::min((size_t)8 << 30, fr / (3 * kChains));
+    for (int c = 0; c < kChains; ++c)
+        if ((st = b->hpart[c].ensure(per_chain)) != GINT_OK)
+            return bail(st);
+    // plans, cost, longest-first assignment to the least loaded chain
+    std::vector<double> cost(ncell);
+    for (int i = 0; i < ncell; ++i) {
+        gint_plan p = nullptr;
+        st = plan_create(cells[i].lattice, cells[i].grid, nspecies, species, cells[i].natom, cells[i].species_of_atom,
+                         cells[i].positions, prec, b->chains[0], b->hpart[0].p, per_chain, &p);
+        if (st != GINT_OK)
+            return bail(st);
+        b->plans.push_back(p);
+        cost[i] = (double)p->nent * p->geo.P * p->nbmax;
+    }
+    b->order.resize(ncell);
+    for (int i = 0; i < ncell; ++i)
+        b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->chain_of.assign(ncell, 0);
+    double load[kChains] = {0};
+    for (int i : b->order) {
+        int c = 0;
+        for (int k = 1; k < kChains; ++k)
+            if (load[k] < load[c])
+                c = k;
+        load[c] += cost[i];
+        b->chain_of[i] = c;
+        b->plans[i]->stream = b->stream;  // single-cell calls run on the batch's stream
+        b->plans[i]->ext_hpart = b->hpart[c].p;
+    }
+    if (hipDeviceSynchronize() != hipSuccess)
+        return bail(fail(GINT_EDEVICE, "batch construction failed on the device"));
+    *out = b;
+    return GINT_OK;
+}
+
+int gint_batch_ncell(gint_batch b) { return check_batch(b) == GINT_OK ? (int)b->plans.size() : -1; }
+
+gint_plan gint_batch_cell(gint_batch b, int i)
+{
+    if (check_batch(b) != GINT_OK || i < 0 || i >= (int)b->plans.size())
+        return nullptr;
+    return b->plans[i];
+}
+
+gint_status gint_batch_build_H(gint_batch b, const double *const *V_dev, double *const *H_dev)
+{
+    STCHK(check_batch(b));
+    if (!V_dev || !H_dev)
+        return fail(GINT_EINVAL, "pointer arrays must be non-NULL");
+    const int n = (int)b->plans.size();
+    std::vector<const void *> sig;
+    for (int i = 0; i < n; ++i) {
+        if (!V_dev[i] || !H_dev[i])
+            return fail(GINT_EINVAL, "cell %d: NULL device pointer", i);
+        sig.push_back(V_dev[i]);
+        sig.push_back(H_dev[i]);
+    }
+    HIPCHK(hipSetDevice(b->device));
+    return run_graph(b, b->gH, sig, [&]() -> gint_status {
+        for (int i : b->order)
+            STCHK(build_H_impl(b->plans[i], V_dev[i], b->plans[i]->dV, H_dev[i]));
+        return GINT_OK;
+    });
+}
+
+gint_status gint_batch_build_rho(gint_batch b, const double *const *D_dev, double *const *rho_dev)
+{
+    STCHK(check_batch(b));
+    if (!D_dev || !rho_dev)
+        return fail(GINT_EINVAL, "pointer arrays must be non-NULL");
+    const int n = (int)b->plans.size();
+    std::vector<const void *> sig;
+    for (int i = 0; i < n; ++i) {
+        if (!D_dev[i] || !rho_dev[i])
+            return fail(GINT_EINVAL, "cell %d: NULL device pointer", i);
+        sig.push_back(D_dev[i]);
+        sig.push_back(rho_dev[i]);
+    }
+    HIPCHK(hipSetDevice(b->device));
+    return run_graph(b, b->gR, sig, [&]() -> gint_status {
+        for (int i : b->order)
+            STCHK(gint_build_rho(b->plans[i], D_dev[i], rho_dev[i]));
+        return GINT_OK;
+    });
+}
+
+gint_status gint_batch_force(gint_batch b, const double *const *W_dev, const double *const *D_dev,
+                             double *const *dEdR_dev)
+{
+    STCHK(check_batch(b));
+    if (!W_dev || !D_dev || !dEdR_dev)
+        return fail(GINT_EINVAL, "pointer arrays must be non-NULL");
+    const int n = (int)b->plans.size();
+    std::vector<const void *> sig;
+    for (int i = 0; i < n; ++i) {
+        if (!W_dev[i] || !D_dev[i] || !dEdR_dev[i])
+            return fail(GINT_EINVAL, "cell %d: NULL device pointer", i);
+        sig.push_back(W_dev[i]);
+        sig.push_back(D_dev[i]);
+        sig.push_back(dEdR_dev[i]);
+    }
+    HIPCHK(hipSetDevice(b->device));
+    return run_graph(b, b->gF, sig, [&]() -> gint_status {
+        for (int i : b->order)
+            STCHK(force_impl(b->plans[i], W_dev[i], b->plans[i]->dV, D_dev[i], dEdR_dev[i]));
+        return GINT_OK;
+    });
+}
+
+gint_status gint_batch_sync(gint_batch b)
+{
+    STCHK(check_batch(b));
+    HIPCHK(hipSetDevice(b->device));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipGetLastError());
+    return GINT_OK;
+}
+
+void gint_batch_destroy(gint_batch b)
+{
+    if (!b || b->magic != kBatchMagic)
+        return;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipDeviceSynchronize();
+    b->magic = 0;
+    delete b;
 }
 
 }  // extern "C"

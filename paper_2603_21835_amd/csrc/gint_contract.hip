@@ -1,9 +1,13 @@
 // gint_contract.hip -- the grid contractions of Sec. 3.3.1 of arXiv:2603.21835
-// on gfx950 matrix cores (v_mfma_f64_16x16x4), and their reductions.
+// on gfx950 matrix cores, and their reductions.  Orbital tiles, packed D and
+// H block partials are FP64 (v_mfma_f64_16x16x4) or FP32
+// (v_mfma_f32_16x16x4); sums across batches and all dot products are FP64.
 //
-//   H^loc   output-stationary over atom-pair blocks: a workgroup owns a pair
-//           of 4-atom groups and streams the mesh batches both reach, so H
-//           leaves the chip once (k_pairs_H, k_H_convert).
+//   H^loc   point-stationary: a workgroup owns a mesh batch and forms every
+//           atom-pair block of it from orbitals evaluated once into LDS
+//           (k_H_batch); a per-atom workgroup then sums each block over the
+//           atom's batches in a fixed order into dense symmetric H
+//           (k_H_rowreduce).
 //   rho     point-stationary: a workgroup owns a mesh batch, evaluates every
 //           atom's folded orbitals there once into LDS and contracts all
 //           atom-pair blocks against packed D + D^T fragments (k_rho_batch).
@@ -11,10 +15,8 @@
 //           batch, dotted with grad phi_I; per-(batch, atom) partials are
 //           summed per atom in a fixed order (k_force_batch, k_force_reduce).
 //
-// MFMA lane layouts (lane l, checked on gfx950 with a lane-layout probe):
-//   operands   A[i][k], B[k][j] with i, j = l & 15, k = l >> 4
-//   result     C[i][j] with i = (l >> 4) + 4 v, j = l & 15, v < 4
-// Orbital tiles in LDS: [atom slot][point][orbital], row pitch kRow doubles.
+// MFMA lane layouts: see MM<T> in gint_device.h.
+// Orbital tiles in LDS: [atom slot][point][orbital], row pitch kRow elements.
 #include <hip/hip_runtime.h>
 
 #include "gint_device.h"
@@ -22,242 +24,275 @@
 namespace gint {
 
 // ---------------------------------------------------------------------------
-// H: group-pair workgroups.
+// H^loc, point-stationary.
 //
-// Workgroup = (group pair (A, B), chunk of A's batch list); 4 waves.  Wave w
-// owns the row atom I = 4A + w and the blocks (I, J = 4B + j), j = 0..3 (for
-// A == B only j >= w).  The workgroup first filters its chunk of A's batch
-// list for batches that B also reaches and records, for each kept batch, the
-// batch coordinates and the image lists of its <= 8 atoms (slots 0-3: group
-// A, 4-7: group B).  Per kept batch it stages the folded orbitals of the 8
-// slots at the batch's points into LDS and each wave accumulates
-// C_IJ += (w phi_I)^T phi_J over the points on the matrix cores.
+// k_H_batch: one workgroup per mesh batch evaluates the folded orbitals of
+// every atom reaching the batch once (all P points in LDS) and forms every
+// atom-pair block (ia <= ja in the batch's atom order)
+//     C_IJ = sum_{p in batch} (w_p phi_I(p)) phi_J(p)^T
+// on the matrix cores, writing it to a partial buffer (n_I x n_J of a
+// mno x mno tile; block k of batch b at boff[b] + k).
+//
+// k_H_rowreduce: one workgroup per atom I owns the blocks (I, J) of the
+// partners J it owns (each unordered pair has one owner) and sums their
+// partials over I's batches in increasing batch order (fixed order, no
+// atomics), then writes H_IJ and its mirror H_JI into the dense matrix, so
+// H is exactly symmetric.
 
-constexpr int kNL = 128;  // candidate batches per filter round
-
-__global__ __launch_bounds__(256) void k_pairs_H(Geo g, Bins bn, Basis bs, int nchunk, const double *__restrict__ W,
-                                                 double wscale, double *__restrict__ out)
+template <typename T>
+__global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
+                                                 double wscale, int b0, const int *__restrict__ boff, int mno,
+                                                 T *__restrict__ part)
 {
-    constexpr int PT = 32;  // points staged per step (a whole batch)
-    __shared__ double s_phi[8][PT][kRow];
-    __shared__ double s_w[PT];
-    __shared__ double s_X[8][3];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
     __shared__ DevRadial s_rad[kMaxRadTotal];
-    __shared__ int s_k0[8], s_k1[8], s_norb[8];
-    __shared__ double s_rc[8];
-    __shared__ int s_bi[3][kNL];
-    __shared__ int s_icnt[8][kNL], s_ipk[8][kNL], s_ioff[8][kNL];
-    __shared__ int s_wcnt[4];
+    __shared__ DevSpecies s_sp[kMaxSpecies];
+    __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms];
+    __shared__ double s_w[kMaxP];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int pair = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
-    const int A = bn.pairA[pair], B = bn.pairB[pair];
-    const bool diag = (A == B);
-    const int natom = g.natom;
-    const bool Iex = A * kGroup + wave < natom;
+    const int b = b0 + blockIdx.x;
+    const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
+    const int P = g.P;
+    int ib[3];
+    batch_coords(g, b, ib);
 
-    for (int k = tid; k < g.nrad; k += 256)
+    for (int k = tid; k < g.nrad; k += blockDim.x)
         s_rad[k] = bs.rad[k];
-    if (tid < 8) {
-        const int atom = (tid < 4) ? A * kGroup + tid : B * kGroup + (tid - 4);
-        const bool ok = atom < natom && !(diag && tid >= 4);
-        if (ok) {
-            const DevSpecies S = bs.sp[bs.spc[atom]];
-            s_X[tid][0] = bs.xw[3 * atom];
-            s_X[tid][1] = bs.xw[3 * atom + 1];
-            s_X[tid][2] = bs.xw[3 * atom + 2];
-            s_k0[tid] = S.rad0;
-            s_k1[tid] = S.rad0 + S.nrad;
-            s_norb[tid] = S.norb;
-            s_rc[tid] = S.rc;
-        } else {
-            s_X[tid][0] = s_X[tid][1] = s_X[tid][2] = 0.0;
-            s_k0[tid] = s_k1[tid] = 0;
-            s_norb[tid] = 0;
-            s_rc[tid] = 0.0;
-        }
+    for (int k = tid; k < g.nspecies; k += blockDim.x)
+        s_sp[k] = bs.sp[k];
+    for (int a = tid; a < nb; a += blockDim.x) {
+        const int atom = bn.ent_atom[e0 + a];
+        s_atom[a] = atom;
+        s_nor[a] = bs.sp[bs.spc[atom]].norb;
     }
-
-    d4 acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-
-    const int st_s = tid / PT, st_p = tid % PT;
-    const int gb0 = bn.gptr[A], gb1 = bn.gptr[A + 1];
-    const long long len = gb1 - gb0;
-    const int c0 = gb0 + (int)(len * chunk / nchunk);
-    const int c1 = gb0 + (int)(len * (chunk + 1) / nchunk);
+    for (int p = tid; p < P; p += blockDim.x) {
+        int n[3];
+        s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
+    }
     __syncthreads();
 
-    for (int base = c0; base < c1; base += kNL) {
-        // ---- filter: batches of this chunk that group B also reaches ----
-        bool keep = false;
-        int b = -1, e_a = 0, e_b = 0, e_end = 0;
-        if (tid < kNL && base + tid < c1) {
-            b = bn.gbatch[base + tid];
-            const int e0 = bn.bptr[b];
-            e_end = bn.bptr[b + 1];
-            e_a = lower_bound_i(bn.ent_atom, e0, e_end, A * kGroup);
-            if (diag) {
-                keep = true;
-            } else {
-                e_b = lower_bound_i(bn.ent_atom, e_a, e_end, B * kGroup);
-                keep = e_b < e_end && bn.ent_atom[e_b] < (B + 1) * kGroup;
-            }
-        }
-        const unsigned long long m = __ballot(keep);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0)
-            s_wcnt[wave] = __popcll(m);
-        __syncthreads();
-        int off = 0;
-        for (int w = 0; w < wave; ++w)
-            off += s_wcnt[w];
-        const int nlist = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-        if (keep) {
-            const int q = off + pre;
-            int ib[3];
-            batch_coords(g, b, ib);
-            s_bi[0][q] = ib[0];
-            s_bi[1][q] = ib[1];
-            s_bi[2][q] = ib[2];
-            int ea = e_a, eb = e_b;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int grp = (s < 4) ? A : B;
-                int &e = (s < 4) ? ea : eb;
-                int cnt = 0, pk = 0, io = 0;
-                if (!(diag && s >= 4) && e < e_end && bn.ent_atom[e] == grp * kGroup + (s & 3)) {
-                    io = bn.ent_img[e];
-                    cnt = bn.ent_img[e + 1] - io;
-                    pk = bn.img[io];
-                    ++e;
-                }
-                s_icnt[s][q] = cnt;
-                s_ipk[s][q] = pk;
-                s_ioff[s][q] = io;
-            }
-        }
-        __syncthreads();
-
-        // weight of this thread's point in the first kept batch
-        double wnext = 0.0;
-        if (tid < PT && nlist > 0) {
-            const int ib[3] = {s_bi[0][0], s_bi[1][0], s_bi[2][0]};
-            int n[3];
-            if (batch_point(g, ib, tid, n))
-                wnext = wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]];
-        }
-
-        for (int it = 0; it < nlist; ++it) {
-            // ---- stage the folded orbitals (PhiOperator) ----
-            {
-                double *row = &s_phi[st_s][st_p][0];
-                const int ib[3] = {s_bi[0][it], s_bi[1][it], s_bi[2][it]};
-                int n[3];
-                const bool valid = batch_point(g, ib, st_p, n);
-                const int icnt = valid ? s_icnt[st_s][it] : 0;
-                const int zlo = (icnt > 0) ? s_norb[st_s] : 0;
-                for (int o = zlo; o < kMaxOrb; ++o)
-                    row[o] = 0.0;
-                if (icnt > 0) {
-                    double r[3];
-                    mesh_cart(g, n, r);
-                    eval_orbitals<false>(g, s_rad, s_k0[st_s], s_k1[st_s], s_rc[st_s], bs.coef, s_X[st_s], icnt,
-                                         s_ipk[st_s][it], s_ioff[st_s][it], bn.img, r, row, nullptr, nullptr,
-                                         nullptr);
-                }
-                if (tid < PT)
-                    s_w[tid] = wnext;
-            }
-            __syncthreads();
-            // prefetch the next batch's weight while the matrix cores run
-            if (tid < PT && it + 1 < nlist) {
-                const int ib[3] = {s_bi[0][it + 1], s_bi[1][it + 1], s_bi[2][it + 1]};
-                int n[3];
-                wnext = batch_point(g, ib, tid, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
-            }
-
-            // ---- contraction on the matrix cores ----
-            if (Iex && s_icnt[wave][it] > 0) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int sj = diag ? j : 4 + j;
-                    if ((!diag || j >= wave) && s_icnt[sj][it] > 0) {
-#pragma unroll
-                        for (int kk = 0; kk < PT / 4; ++kk) {
-                            const int p = 4 * kk + lk;
-                            const double av = s_w[p] * s_phi[wave][p][li];
-                            const double bv = s_phi[sj][p][li];
-                            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
+    // ---- stage the folded orbitals of every atom at every batch point ----
+    for (int idx = tid; idx < nb * P; idx += blockDim.x) {
+        const int a = idx / P, p = idx % P;
+        const int e = e0 + a;
+        const int atom = s_atom[a];
+        T *row = s_phi + (size_t)(a * P + p) * kRow;
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[o] = (T)0;
+        if (valid) {
+            const int io = bn.ent_img[e];
+            const int cnt = bn.ent_img[e + 1] - io;
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            double r[3];
+            mesh_cart(g, n, r);
+            eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                             row);
         }
     }
+    __syncthreads();
 
-    double *blk = out + (size_t)blockIdx.x * 16 * 256;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (!diag || j >= wave) {
-            double *o = blk + (size_t)(wave * 4 + j) * 256;
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                o[(lk + 4 * v) * 16 + li] = acc[j][v];
+    // ---- every block (ia <= ja), round-robin over the waves ----
+    const int nblk = nb * (nb + 1) / 2;
+    int ia = 0, ja = 0;
+    for (int k = 0; k < wave; ++k)
+        if (++ja == nb) {
+            ++ia;
+            ja = ia;
         }
+    const size_t mm = (size_t)mno * mno;
+    for (int k = wave; k < nblk; k += nw) {
+        const T *pI = s_phi + (size_t)(ia * P) * kRow;
+        const T *pJ = s_phi + (size_t)(ja * P) * kRow;
+        typename MM<T>::acc acc = MM<T>::zero();
+#pragma unroll
+        for (int kk = 0; kk < kMaxP / 4; ++kk) {
+            if (4 * kk < P) {
+                const int p = 4 * kk + lk;
+                const T av = (T)s_w[p] * pI[p * kRow + li];
+                const T bv = pJ[p * kRow + li];
+                acc = MM<T>::mma(av, bv, acc);
+            }
+        }
+        const int nI = s_nor[ia], nJ = s_nor[ja];
+        T *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = MM<T>::row(lk, v);
+            if (row < nI && li < nJ)
+                o[row * mno + li] = acc[v];
+        }
+        for (int s = 0; s < nw; ++s)
+            if (++ja == nb) {
+                ++ia;
+                ja = ia;
+            }
     }
 }
 
-hipError_t launch_pairs_H(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair, int nchunk,
-                          const double *W, double wscale, double *Hblk)
+template <typename T>
+static hipError_t launch_H_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
+                                   int b1, const double *W, double wscale, const int *boff, int mno, void *part)
 {
-    if (npair <= 0)
+    if (b1 <= b0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_pairs_H, dim3(npair * nchunk), dim3(256), 0, s, g, bn, b, nchunk, W, wscale, Hblk);
+    const size_t lds = sizeof(T) * (size_t)nbmax * g.P * kRow;
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_H_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_H_batch<T>, dim3(b1 - b0), dim3(512), lds, s, g, bn, b, W, wscale, b0, boff, mno,
+                       static_cast<T *>(part));
     return hipGetLastError();
 }
 
-// Dense symmetric H from the canonical (upper) atom-pair blocks, summing the
-// chunks in order.  H[mu][nu] and H[nu][mu] read the same stored value.
-__global__ void k_H_convert(Geo g, Bins bn, Basis bs, int norb, int nchunk, const double *__restrict__ Hblk,
-                            double *__restrict__ H)
+hipError_t launch_H_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
+                          int b1, const double *W, double wscale, const int *boff, int mno, void *part)
 {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)norb * norb)
-        return;
-    const int mu = (int)(idx / norb), nu = (int)(idx % norb);
-    const int Iin = bs.orb_atom[mu], Jin = bs.orb_atom[nu];
-    int a = mu - bs.orb0[Iin], c = nu - bs.orb0[Jin];
-    int ii = bs.inv_perm[Iin], jj = bs.inv_perm[Jin];
-    if (ii > jj || (ii == jj && a > c)) {
-        int t = ii;
-        ii = jj;
-        jj = t;
-        t = a;
-        a = c;
-        c = t;
-    }
-    const int gA = ii / kGroup, gB = jj / kGroup;
-    const int p = bn.pair_index[(size_t)gA * g.ngroup + gB];
-    double v = 0.0;
-    if (p >= 0) {
-        const int blk = (ii % kGroup) * 4 + (jj % kGroup);
-        for (int ch = 0; ch < nchunk; ++ch)
-            v += Hblk[((size_t)(p * nchunk + ch) * 16 + blk) * 256 + a * 16 + c];
-    }
-    H[idx] = v;
+    return f32 ? launch_H_batch_t<float>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part)
+               : launch_H_batch_t<double>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
 }
 
-hipError_t launch_H_convert(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int norb, int nchunk,
-                            const double *Hblk, double *H)
+constexpr int kRowChunk = 16;         // batches staged per round
+constexpr int kMaxPartnerPass = 128;  // partners per pass
+constexpr int kRowThreads = 1024;
+
+__device__ __forceinline__ int tri_index(int lo, int hi, int n) { return lo * n - lo * (lo - 1) / 2 + (hi - lo); }
+
+// Thread (partner slot sl, orbital row a of I) accumulates the row a of block
+// (I, J_sl) over I's batches in increasing batch order.
+template <typename T>
+__global__ __launch_bounds__(kRowThreads) void k_H_rowreduce(Geo g, Bins bn, Basis bs, AtomLists al, int mno,
+                                                             int norb, const T *__restrict__ part,
+                                                             const int *__restrict__ boff, int b0, int b1,
+                                                             int accumulate, double *__restrict__ H)
 {
-    const long long n = (long long)norb * norb;
-    hipLaunchKernelGGL(k_H_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, bn, b, norb, nchunk,
-                       Hblk, H);
+    __shared__ int s_pos[kRowChunk][kMaxPartnerPass];
+    __shared__ int s_part[kMaxPartnerPass];
+    __shared__ int s_ia[kRowChunk], s_nb[kRowChunk], s_e0[kRowChunk], s_pb[kRowChunk];
+
+    const int tid = threadIdx.x;
+    const int I = blockIdx.x;
+    const int Iin = bs.perm[I];
+    const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
+    const int np = al.pptr[I + 1] - al.pptr[I];
+    const size_t mm = (size_t)mno * mno;
+    // this atom's entries inside the batch range [b0, b1)
+    const int ent_lo = lower_bound_i(al.aent, al.aptr[I], al.aptr[I + 1], bn.bptr[b0]);
+    const int ent_hi = lower_bound_i(al.aent, al.aptr[I], al.aptr[I + 1], bn.bptr[b1]);
+    int npc_max = kRowThreads / nI;
+    if (npc_max > kMaxPartnerPass)
+        npc_max = kMaxPartnerPass;
+    const int sl = tid / nI, a = tid % nI;
+
+    for (int s0 = 0; s0 < np; s0 += npc_max) {
+        const int npc = (np - s0 < npc_max) ? np - s0 : npc_max;
+        __syncthreads();
+        for (int j = tid; j < npc; j += kRowThreads)
+            s_part[j] = al.plist[al.pptr[I] + s0 + j];
+        const bool mine = sl < npc;
+        double acc[kMaxOrb];
+#pragma unroll
+        for (int c = 0; c < kMaxOrb; ++c)
+            acc[c] = 0.0;
+
+        for (int c0 = ent_lo; c0 < ent_hi; c0 += kRowChunk) {
+            const int nk = (ent_hi - c0 < kRowChunk) ? ent_hi - c0 : kRowChunk;
+            __syncthreads();
+            for (int idx = tid; idx < kRowChunk * npc; idx += kRowThreads)
+                s_pos[idx / npc][idx % npc] = -1;
+            if (tid < nk) {
+                const int e = al.aent[c0 + tid];
+                const int b = al.abat[c0 + tid];
+                s_e0[tid] = bn.bptr[b];
+                s_ia[tid] = e - bn.bptr[b];
+                s_nb[tid] = bn.bptr[b + 1] - bn.bptr[b];
+                s_pb[tid] = boff[b] - boff[b0];
+            }
+            __syncthreads();
+            // positions of this pass's partners in each staged batch
+            for (int idx = tid; idx < nk * kMaxBatchAtoms; idx += kRowThreads) {
+                const int k = idx / kMaxBatchAtoms, j = idx % kMaxBatchAtoms;
+                if (j < s_nb[k]) {
+                    const int J = bn.ent_atom[s_e0[k] + j];
+                    const int f = lower_bound_i(s_part, 0, npc, J);
+                    if (f < npc && s_part[f] == J)
+                        s_pos[k][f] = j;
+                }
+            }
+            __syncthreads();
+            if (mine) {
+                for (int k = 0; k < nk; ++k) {
+                    const int ja = s_pos[k][sl];
+                    if (ja < 0)
+                        continue;
+                    const int ia = s_ia[k];
+                    if (ia <= ja) {
+                        const T *src = part + (size_t)(s_pb[k] + tri_index(ia, ja, s_nb[k])) * mm + a * mno;
+#pragma unroll
+                        for (int c = 0; c < kMaxOrb; ++c)
+                            if (c < mno)
+                                acc[c] += (double)src[c];
+                    } else {
+                        const T *src = part + (size_t)(s_pb[k] + tri_index(ja, ia, s_nb[k])) * mm + a;
+#pragma unroll
+                        for (int c = 0; c < kMaxOrb; ++c)
+                            if (c < mno)
+                                acc[c] += (double)src[c * mno];
+                    }
+                }
+            }
+        }
+        // H_IJ row a and its mirror column (diagonal blocks: c >= a, mirrored)
+        if (mine) {
+            const int J = s_part[sl];
+            const int Jin = bs.perm[J];
+            const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
+#pragma unroll
+            for (int c = 0; c < kMaxOrb; ++c) {
+                if (c < nJ && !(J == I && c < a)) {
+                    const size_t i1 = (size_t)(mu0 + a) * norb + nu0 + c;
+                    const size_t i2 = (size_t)(nu0 + c) * norb + mu0 + a;
+                    const double v = accumulate ? H[i1] + acc[c] : acc[c];
+                    H[i1] = v;
+                    H[i2] = v;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_H_rowreduce(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b,
+                              const AtomLists &al, int mno, int norb, const void *part, const int *boff, int b0,
+                              int b1, int accumulate, double *H)
+{
+    if (f32)
+        hipLaunchKernelGGL(k_H_rowreduce<float>, dim3(g.natom), dim3(kRowThreads), 0, s, g, bn, b, al, mno, norb,
+                           static_cast<const float *>(part), boff, b0, b1, accumulate, H);
+    else
+        hipLaunchKernelGGL(k_H_rowreduce<double>, dim3(g.natom), dim3(kRowThreads), 0, s, g, bn, b, al, mno, norb,
+                           static_cast<const double *>(part), boff, b0, b1, accumulate, H);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_f64(double *p, long long n, double v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+hipError_t launch_fill_f64(hipStream_t s, double *p, long long n, double v)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
@@ -269,8 +304,9 @@ hipError_t launch_H_convert(hipStream_t s, const Geo &g, const Bins &bn, const B
 //   orient 1: lane l, chunk c holds S2_XY[4c + (l >> 4)][l & 15]   (S2_YX as A)
 // so each lane reads its four values of a block with two 16-byte loads.
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_pack_S2(Geo g, Bins bn, Basis bs, const double *__restrict__ D, int norb,
-                                                 double *__restrict__ pk)
+                                                 T *__restrict__ pk)
 {
     const int pair = blockIdx.x >> 4, blk = blockIdx.x & 15;
     const int A = bn.pairA[pair], B = bn.pairB[pair];
@@ -290,16 +326,21 @@ __global__ __launch_bounds__(256) void k_pack_S2(Geo g, Bins bn, Basis bs, const
             v1 = D[(size_t)(mx + kb) * norb + my + li] + D[(size_t)(my + li) * norb + mx + kb];
     }
     const size_t base = (size_t)blockIdx.x * 512;
-    pk[base + t] = v0;
-    pk[base + 256 + t] = v1;
+    pk[base + t] = (T)v0;
+    pk[base + 256 + t] = (T)v1;
 }
 
-hipError_t launch_pack_S2(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair, const double *D,
-                          int norb, double *pk)
+hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                          const double *D, int norb, void *pk)
 {
     if (npair <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_pack_S2, dim3(npair * 16), dim3(256), 0, s, g, bn, b, D, norb, pk);
+    if (f32)
+        hipLaunchKernelGGL(k_pack_S2<float>, dim3(npair * 16), dim3(256), 0, s, g, bn, b, D, norb,
+                           static_cast<float *>(pk));
+    else
+        hipLaunchKernelGGL(k_pack_S2<double>, dim3(npair * 16), dim3(256), 0, s, g, bn, b, D, norb,
+                           static_cast<double *>(pk));
     return hipGetLastError();
 }
 
@@ -309,11 +350,12 @@ hipError_t launch_pack_S2(hipStream_t s, const Geo &g, const Bins &bn, const Bas
 // Per-batch setup shared by rho and force: radial and species tables, the
 // batch's atoms and their group ranks, and the pair ids of the batch's group
 // pairs (canonical order).
-template <bool FORCE>
-__global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const double *__restrict__ pk,
+template <bool FORCE, typename T>
+__global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
                                                const double *__restrict__ W, double wscale, double *__restrict__ out)
 {
-    extern __shared__ double s_phi[];  // [nbmax][16][kRow]
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][16][kRow]
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_grank[kMaxBatchAtoms];
@@ -354,21 +396,21 @@ __global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const d
             const int a = idx >> 4, p = idx & 15;
             const int e = e0 + a;
             const int atom = s_atom[a];
-            double *row = s_phi + (size_t)(a * 16 + p) * kRow;
+            T *row = s_phi + (size_t)(a * 16 + p) * kRow;
             int n[3];
             const bool valid = batch_point(g, ib, sub + p, n);
             const DevSpecies &S = s_sp[bs.spc[atom]];
             const int zlo = valid ? S.norb : 0;
             for (int o = zlo; o < kMaxOrb; ++o)
-                row[o] = 0.0;
+                row[o] = (T)0;
             if (valid) {
                 const int io = bn.ent_img[e];
                 const int cnt = bn.ent_img[e + 1] - io;
                 const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
                 double r[3];
                 mesh_cart(g, n, r);
-                eval_orbitals<false>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io,
-                                     bn.img, r, row, nullptr, nullptr, nullptr);
+                eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
+                                 r, row);
             }
         }
         if (FORCE && tid < 16) {
@@ -391,16 +433,19 @@ __global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const d
                 const int I = s_atom[ia], J = s_atom[ja];
                 const int pr = s_ptab[s_grank[ia] * ngb + s_grank[ja]];  // active: both groups are here
                 const int blk = (I % kGroup) * 4 + (J % kGroup);
-                const double *f = pk + ((size_t)(pr * 16 + blk) * 2) * 256 + lane;
-                const double fa0 = f[0], fa1 = f[64], fa2 = f[128], fa3 = f[192];
-                const double *pJ = s_phi + (size_t)(ja * 16 + li) * kRow + lk;
-                d4 u = d4{0.0, 0.0, 0.0, 0.0};
-                u = __builtin_amdgcn_mfma_f64_16x16x4f64(fa0, pJ[0], u, 0, 0, 0);
-                u = __builtin_amdgcn_mfma_f64_16x16x4f64(fa1, pJ[4], u, 0, 0, 0);
-                u = __builtin_amdgcn_mfma_f64_16x16x4f64(fa2, pJ[8], u, 0, 0, 0);
-                u = __builtin_amdgcn_mfma_f64_16x16x4f64(fa3, pJ[12], u, 0, 0, 0);
-                const double *pI = s_phi + (size_t)(ia * 16 + li) * kRow + lk;
-                const double dot = u[0] * pI[0] + u[1] * pI[4] + u[2] * pI[8] + u[3] * pI[12];
+                const T *f = pk + ((size_t)(pr * 16 + blk) * 2) * 256 + lane;
+                const T fa0 = f[0], fa1 = f[64], fa2 = f[128], fa3 = f[192];
+                const T *pJ = s_phi + (size_t)(ja * 16 + li) * kRow + lk;
+                typename MM<T>::acc u = MM<T>::zero();
+                u = MM<T>::mma(fa0, pJ[0], u);
+                u = MM<T>::mma(fa1, pJ[4], u);
+                u = MM<T>::mma(fa2, pJ[8], u);
+                u = MM<T>::mma(fa3, pJ[12], u);
+                const T *pI = s_phi + (size_t)(ia * 16 + li) * kRow;
+                double dot = 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    dot += (double)u[v] * (double)pI[MM<T>::row(lk, v)];
                 rp += (ia == ja) ? 0.5 * dot : dot;
                 for (int s = 0; s < 4; ++s)
                     if (++ja == nb) {
@@ -428,32 +473,34 @@ __global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const d
             const double wp = s_w[li];
             for (int ia = wave; ia < nb; ia += 4) {
                 const int I = s_atom[ia];
-                d4 T = d4{0.0, 0.0, 0.0, 0.0};
+                typename MM<T>::acc Tt = MM<T>::zero();
                 for (int ja = 0; ja < nb; ++ja) {
                     const int J = s_atom[ja];
                     const bool fwd = ia <= ja;
                     const int ra = fwd ? s_grank[ia] : s_grank[ja], rb = fwd ? s_grank[ja] : s_grank[ia];
                     const int pr = s_ptab[ra * ngb + rb];
                     const int blk = fwd ? (I % kGroup) * 4 + (J % kGroup) : (J % kGroup) * 4 + (I % kGroup);
-                    const double *f = pk + ((size_t)(pr * 16 + blk) * 2 + (fwd ? 0 : 1)) * 256 + lane;
-                    const double *pJ = s_phi + (size_t)(ja * 16 + li) * kRow + lk;
-                    T = __builtin_amdgcn_mfma_f64_16x16x4f64(f[0], pJ[0], T, 0, 0, 0);
-                    T = __builtin_amdgcn_mfma_f64_16x16x4f64(f[64], pJ[4], T, 0, 0, 0);
-                    T = __builtin_amdgcn_mfma_f64_16x16x4f64(f[128], pJ[8], T, 0, 0, 0);
-                    T = __builtin_amdgcn_mfma_f64_16x16x4f64(f[192], pJ[12], T, 0, 0, 0);
+                    const T *f = pk + ((size_t)(pr * 16 + blk) * 2 + (fwd ? 0 : 1)) * 256 + lane;
+                    const T *pJ = s_phi + (size_t)(ja * 16 + li) * kRow + lk;
+                    Tt = MM<T>::mma(f[0], pJ[0], Tt);
+                    Tt = MM<T>::mma(f[64], pJ[4], Tt);
+                    Tt = MM<T>::mma(f[128], pJ[8], Tt);
+                    Tt = MM<T>::mma(f[192], pJ[12], Tt);
                 }
-                // gradients of orbitals lk + 4v of atom I at point li
+                // gradients of orbitals row(lk, v) of atom I at point li
                 double gr[3][4];
                 const int e = e0 + ia;
                 const DevSpecies &S = s_sp[bs.spc[I]];
                 const double X[3] = {bs.xw[3 * I], bs.xw[3 * I + 1], bs.xw[3 * I + 2]};
                 const int io = bn.ent_img[e];
                 const int cnt = pvalid ? bn.ent_img[e + 1] - io : 0;
-                grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r, lk, gr);
+                grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                      MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), gr);
                 double fx[3];
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
-                    double v = wp * (T[0] * gr[x][0] + T[1] * gr[x][1] + T[2] * gr[x][2] + T[3] * gr[x][3]);
+                    double v = wp * ((double)Tt[0] * gr[x][0] + (double)Tt[1] * gr[x][1] + (double)Tt[2] * gr[x][2] +
+                                     (double)Tt[3] * gr[x][3]);
                     for (int o = 32; o > 0; o >>= 1)
                         v += __shfl_xor(v, o);
                     fx[x] = v;
@@ -472,31 +519,34 @@ __global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const d
             out[(size_t)(e0 + k / 3) * 3 + k % 3] = s_F[k / 3][k % 3];
 }
 
-size_t batch_lds_bytes(int nbmax) { return sizeof(double) * (size_t)nbmax * 16 * kRow; }
+size_t batch_lds_bytes(int nbmax, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * 16 * kRow; }
 
-hipError_t launch_rho_batch(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, const double *pk,
-                            double *rho)
+template <bool FORCE, typename T>
+static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                                 const void *pk, const double *W, double wscale, double *out)
 {
-    const size_t lds = batch_lds_bytes(nbmax);
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    const size_t lds = sizeof(T) * (size_t)nbmax * 16 * kRow;
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_batch<FORCE, T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_batch<false>, dim3(g.nbatch), dim3(256), lds, s, g, bn, b, pk, (const double *)nullptr,
-                       0.0, rho);
+    hipLaunchKernelGGL((k_batch<FORCE, T>), dim3(g.nbatch), dim3(256), lds, s, g, bn, b, static_cast<const T *>(pk),
+                       W, wscale, out);
     return hipGetLastError();
 }
 
-hipError_t launch_force_batch(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              const double *pk, const double *W, double wscale, double *Fent)
+hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                            const void *pk, double *rho)
 {
-    const size_t lds = batch_lds_bytes(nbmax);
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_batch<true>, dim3(g.nbatch), dim3(256), lds, s, g, bn, b, pk, W, wscale, Fent);
-    return hipGetLastError();
+    return f32 ? launch_batch_t<false, float>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho)
+               : launch_batch_t<false, double>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho);
+}
+
+hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                              const void *pk, const double *W, double wscale, double *Fent)
+{
+    return f32 ? launch_batch_t<true, float>(s, g, bn, b, nbmax, pk, W, wscale, Fent)
+               : launch_batch_t<true, double>(s, g, bn, b, nbmax, pk, W, wscale, Fent);
 }
 
 // dE/dR per atom: fixed-order sum of its per-(batch, atom) partials over the

@@ -10,6 +10,35 @@
 namespace gint {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// 16x16 matrix-core products on orbital tiles of element type T with 4
+// accumulator registers per lane:
+//   operands   A[i][k], B[k][j] with i, j = lane & 15, k = lane >> 4
+//   result     register v of lane l holds C[row(l >> 4, v)][l & 15]
+// (both layouts checked on gfx950 with a lane-layout probe).
+template <typename T>
+struct MM;
+template <>
+struct MM<double> {
+    typedef d4 acc;
+    static __device__ __forceinline__ acc zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc mma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct MM<float> {
+    typedef f4 acc;
+    static __device__ __forceinline__ acc zero() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+    static __device__ __forceinline__ acc mma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
 
 // real spherical harmonics (no Condon-Shortley phase)
 #define Y_C00 0.28209479177387814
@@ -102,17 +131,18 @@ __device__ __forceinline__ int spline_interval(const DevRadial &R, double rr, do
 }
 
 // Folded orbitals of one atom at cartesian point r, for the radials
-// k0..k1-1 of its species (radial descriptors in LDS).  Writes every orbital
-// those radials own: assignment for the first listed image, accumulation
-// for further images (several images of one atom reach a point only in
-// cells smaller than the cutoff sphere).  pk0 is the first packed image;
-// further ones are read from img[ioff + i].  The radial loop is unrolled by
-// 8 so that all spline-coefficient loads of an image are in flight together.
-template <bool GRAD>
+// k0..k1-1 of its species (radial descriptors in LDS), evaluated in FP64
+// and stored as T.  Writes every orbital those radials own: assignment for
+// the first listed image, accumulation for further images (several images
+// of one atom reach a point only in cells smaller than the cutoff sphere).
+// pk0 is the first packed image; further ones are read from img[ioff + i].
+// The radial loop is unrolled by 8 so that all spline-coefficient loads of
+// an image are in flight together.
+template <typename T>
 __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__restrict__ rads, int k0, int k1,
                                               double rc, const double *__restrict__ coef, const double *X,
                                               int icnt, int pk0, int ioff, const int *__restrict__ img,
-                                              const double *r, double *row, double *gx, double *gy, double *gz)
+                                              const double *r, T *row)
 {
     const double rc2 = rc * rc;
     for (int i = 0; i < icnt; ++i) {
@@ -159,74 +189,29 @@ __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__r
                 const int l = rads[k].l, o = rads[k].orb0;
                 const double t = tt[u];
                 const double f = c01[u].x + t * (c01[u].y + t * (c23[u].x + t * c23[u].y));
-                const double fp = c01[u].y + t * (2.0 * c23[u].x + t * 3.0 * c23[u].y);
                 if (l == 0) {
                     const double v = f * Y_C00;
-                    row[o] = add ? row[o] + v : v;
-                    if (GRAD) {
-                        const double q = tiny ? 0.0 : fp * Y_C00;
-                        gx[o] = add ? gx[o] + q * ux : q * ux;
-                        gy[o] = add ? gy[o] + q * uy : q * uy;
-                        gz[o] = add ? gz[o] + q * uz : q * uz;
-                    }
+                    row[o] = add ? (T)(row[o] + v) : (T)v;
                 } else if (l == 1) {
-                    // at the centre phi_1m -> 0 and grad phi_1m -> f'(0) C1 e_m, e = (y, z, x)
+                    // phi_1m vanishes at the centre (u = 0 there)
                     const double Y[3] = {Y_C1 * uy, Y_C1 * uz, Y_C1 * ux};
 #pragma unroll
                     for (int m = 0; m < 3; ++m)
-                        row[o + m] = add ? row[o + m] + f * Y[m] : f * Y[m];
-                    if (GRAD) {
-                        const double fr = f * ir;
-                        const double G[3][3] = {{0.0, Y_C1, 0.0}, {0.0, 0.0, Y_C1}, {Y_C1, 0.0, 0.0}};
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) {
-                            double vx, vy, vz;
-                            if (tiny) {
-                                vx = fp * G[m][0];
-                                vy = fp * G[m][1];
-                                vz = fp * G[m][2];
-                            } else {
-                                // grad Y(d/|d|) = (grad_u Yhat - l Yhat u)/|d|
-                                vx = fp * Y[m] * ux + fr * (G[m][0] - Y[m] * ux);
-                                vy = fp * Y[m] * uy + fr * (G[m][1] - Y[m] * uy);
-                                vz = fp * Y[m] * uz + fr * (G[m][2] - Y[m] * uz);
-                            }
-                            gx[o + m] = add ? gx[o + m] + vx : vx;
-                            gy[o + m] = add ? gy[o + m] + vy : vy;
-                            gz[o + m] = add ? gz[o + m] + vz : vz;
-                        }
-                    }
+                        row[o + m] = add ? (T)(row[o + m] + f * Y[m]) : (T)(f * Y[m]);
                 } else {
-                    // phi_2m and its gradient vanish at the centre (u = 0 there)
+                    // phi_2m vanishes at the centre
                     const double Y[5] = {Y_C2 * ux * uy, Y_C2 * uy * uz, Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy),
                                          Y_C2 * ux * uz, Y_C22 * (ux * ux - uy * uy)};
 #pragma unroll
                     for (int m = 0; m < 5; ++m)
-                        row[o + m] = add ? row[o + m] + f * Y[m] : f * Y[m];
-                    if (GRAD) {
-                        const double fr = f * ir;
-                        const double G[5][3] = {{Y_C2 * uy, Y_C2 * ux, 0.0},
-                                                {0.0, Y_C2 * uz, Y_C2 * uy},
-                                                {-2.0 * Y_C20 * ux, -2.0 * Y_C20 * uy, 4.0 * Y_C20 * uz},
-                                                {Y_C2 * uz, 0.0, Y_C2 * ux},
-                                                {2.0 * Y_C22 * ux, -2.0 * Y_C22 * uy, 0.0}};
-#pragma unroll
-                        for (int m = 0; m < 5; ++m) {
-                            const double vx = fp * Y[m] * ux + fr * (G[m][0] - 2.0 * Y[m] * ux);
-                            const double vy = fp * Y[m] * uy + fr * (G[m][1] - 2.0 * Y[m] * uy);
-                            const double vz = fp * Y[m] * uz + fr * (G[m][2] - 2.0 * Y[m] * uz);
-                            gx[o + m] = add ? gx[o + m] + vx : vx;
-                            gy[o + m] = add ? gy[o + m] + vy : vy;
-                            gz[o + m] = add ? gz[o + m] + vz : vz;
-                        }
-                    }
+                        row[o + m] = add ? (T)(row[o + m] + f * Y[m]) : (T)(f * Y[m]);
                 }
             }
         }
     }
 }
 
-// Gradients of four orbitals o_v = o0 + 4 v (v < 4) of one atom at point r
+// Gradients of four orbitals o_v = o0 + step v (v < 4) of one atom at point r
 // (zero for o_v >= norb), summed over the listed images.  orb_rad[o] is the
 // radial (index into rads) owning orbital o, orb_m[o] its m.  Used where
 // each lane needs exactly the orbitals of its MFMA result rows.
@@ -234,7 +219,7 @@ __device__ __forceinline__ void grad4(const Geo &g, const DevRadial *__restrict_
                                       const signed char *__restrict__ orb_rad, const signed char *__restrict__ orb_m,
                                       int norb, double rc, const double *__restrict__ coef, const double *X, int icnt,
                                       int pk0, int ioff, const int *__restrict__ img, const double *r, int o0,
-                                      double (*gr)[4])
+                                      int step, double (*gr)[4])
 {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -263,7 +248,7 @@ __device__ __forceinline__ void grad4(const Geo &g, const DevRadial *__restrict_
         int lv[4], mv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int o = o0 + 4 * v;
+            const int o = o0 + step * v;
             c01[v] = double2{0.0, 0.0};
             c23[v] = double2{0.0, 0.0};
             tt[v] = 0.0;

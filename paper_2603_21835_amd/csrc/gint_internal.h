@@ -67,6 +67,15 @@ struct Bins {
     const int *pair_index;  // ngroup*ngroup -> pair id or -1 (A <= B)
 };
 
+// Per-atom lists for the point-stationary H path.
+struct AtomLists {
+    const int *aptr;   // natom+1: entries of each atom
+    const int *aent;   // entry indices, increasing (= increasing batch)
+    const int *abat;   // batch of each of those entries
+    const int *pptr;   // natom+1: partners of each atom
+    const int *plist;  // owned partner atoms, increasing
+};
+
 struct Basis {
     const DevRadial *rad;
     const DevSpecies *sp;
@@ -108,17 +117,26 @@ hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, con
                                 double *sums /* 2 per block */, int nblocks);
 
 // Contractions (gint_contract.hip).
-hipError_t launch_pairs_H(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
-                          int nchunk, const double *W, double wscale, double *Hblk);
-hipError_t launch_H_convert(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int norb,
-                            int nchunk, const double *Hblk, double *H);
-hipError_t launch_pack_S2(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
-                          const double *D, int norb, double *pk);
-size_t batch_lds_bytes(int nbmax);
-hipError_t launch_rho_batch(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                            const double *pk, double *rho);
-hipError_t launch_force_batch(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              const double *pk, const double *W, double wscale, double *Fent);
+// f32 selects FP32 orbital tiles, packed D and H partials (else FP64).
+hipError_t launch_H_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                          int b0, int b1, const double *W, double wscale, const int *boff, int mno, void *part);
+hipError_t launch_H_rowreduce(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b,
+                              const AtomLists &al, int mno, int norb, const void *part, const int *boff,
+                              int b0, int b1, int accumulate, double *H);
+hipError_t launch_fill_f64(hipStream_t s, double *p, long long n, double v);
+hipError_t launch_block_count(hipStream_t s, int nbatch, const int *bptr, int *cnt);
+hipError_t launch_atom_count(hipStream_t s, long long nent, const int *ent_atom, int *acnt);
+hipError_t launch_atom_fill(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
+                            const int *ent_atom, const int *aptr, int *aent, int *abat);
+hipError_t launch_partners(hipStream_t s, const Geo &g, const Basis &b, double brad, const int *pptr,
+                           int *pcnt, int *plist);
+hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                          const double *D, int norb, void *pk);
+size_t batch_lds_bytes(int nbmax, bool f32);
+hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                            const void *pk, double *rho);
+hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                              const void *pk, const double *W, double wscale, double *Fent);
 hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
                                const double *Fent, double *dEdR);
 hipError_t launch_max_i32(hipStream_t s, const int *a, long long n, int *out);

@@ -645,3 +645,167 @@ hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, con
 }
 
 }  // namespace gint
+
+namespace gint {
+
+// ---------------------------------------------------------------------------
+// Lists for the point-stationary H path.
+
+// Atom-pair blocks (ia <= ja) of each batch: n_b (n_b + 1) / 2.
+__global__ void k_block_count(int nbatch, const int *__restrict__ bptr, int *__restrict__ cnt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbatch)
+        return;
+    const int n = bptr[b + 1] - bptr[b];
+    cnt[b] = n * (n + 1) / 2;
+}
+
+hipError_t launch_block_count(hipStream_t s, int nbatch, const int *bptr, int *cnt)
+{
+    hipLaunchKernelGGL(k_block_count, dim3((nbatch + 255) / 256), dim3(256), 0, s, nbatch, bptr, cnt);
+    return hipGetLastError();
+}
+
+// Entries per atom (integer atomics: the counts are order independent).
+__global__ void k_atom_count(long long nent, const int *__restrict__ ent_atom, int *__restrict__ acnt)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nent)
+        atomicAdd(&acnt[ent_atom[e]], 1);
+}
+
+hipError_t launch_atom_count(hipStream_t s, long long nent, const int *ent_atom, int *acnt)
+{
+    if (nent <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_atom_count, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, nent, ent_atom, acnt);
+    return hipGetLastError();
+}
+
+// Entry indices of each atom in increasing batch order: one workgroup per
+// atom scans its group's batch list and compacts in order.
+__global__ __launch_bounds__(256) void k_atom_fill(const int *__restrict__ gptr, const int *__restrict__ gbatch,
+                                                   const int *__restrict__ bptr, const int *__restrict__ ent_atom,
+                                                   const int *__restrict__ aptr, int *__restrict__ aent,
+                                                   int *__restrict__ abat)
+{
+    __shared__ int wcnt[4];
+    const int ii = blockIdx.x, grp = ii / kGroup;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int run = aptr[ii];
+    for (int base = gptr[grp]; base < gptr[grp + 1]; base += 256) {
+        const int k = base + threadIdx.x;
+        int e = -1, b = -1;
+        if (k < gptr[grp + 1]) {
+            b = gbatch[k];
+            const int lo = bptr[b], hi = bptr[b + 1];
+            const int f = lower_bound_i(ent_atom, lo, hi, ii);
+            if (f < hi && ent_atom[f] == ii)
+                e = f;
+        }
+        const unsigned long long m = __ballot(e >= 0);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wcnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wave; ++w)
+            off += wcnt[w];
+        if (e >= 0) {
+            aent[run + off + pre] = e;
+            abat[run + off + pre] = b;
+        }
+        run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_atom_fill(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
+                            const int *ent_atom, const int *aptr, int *aent, int *abat)
+{
+    hipLaunchKernelGGL(k_atom_fill, dim3(natom), dim3(256), 0, s, gptr, gbatch, bptr, ent_atom, aptr, aent, abat);
+    return hipGetLastError();
+}
+
+// Partners of atom I whose H block (I, J) atom I owns: every J that can share
+// a mesh batch with I (some images within rc_I + rc_J + 2 * batch radius),
+// with each unordered pair owned by exactly one of its atoms (circulant rule
+// on the internal order: J - I mod natom in [0, natom/2), ties to the
+// smaller index).  Listed in increasing J.
+__device__ __forceinline__ bool owns_pair(int I, int J, int natom)
+{
+    const int d = ((J - I) % natom + natom) % natom;
+    if (d == 0)
+        return true;
+    if (2 * d < natom)
+        return true;
+    return 2 * d == natom && I < J;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_partners(Geo g, Basis bs, double brad, const int *__restrict__ pptr,
+                                                  int *__restrict__ pcnt, int *__restrict__ plist)
+{
+    __shared__ int wcnt[4];
+    const int I = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double *XI = bs.xw + 3 * I;
+    const double rcI = bs.sp[bs.spc[I]].rc;
+    double bn[3];
+    for (int i = 0; i < 3; ++i)
+        bn[i] = sqrt(g.rec[3 * i] * g.rec[3 * i] + g.rec[3 * i + 1] * g.rec[3 * i + 1] +
+                     g.rec[3 * i + 2] * g.rec[3 * i + 2]);
+    int run = FILL ? pptr[I] : 0;
+    for (int base = 0; base < g.natom; base += 256) {
+        const int J = base + threadIdx.x;
+        bool keep = false;
+        if (J < g.natom && owns_pair(I, J, g.natom)) {
+            const double reach = rcI + bs.sp[bs.spc[J]].rc + 2.0 * brad + 1e-6;
+            const double dx[3] = {XI[0] - bs.xw[3 * J], XI[1] - bs.xw[3 * J + 1], XI[2] - bs.xw[3 * J + 2]};
+            double ds[3];
+            frac_of(g, dx, ds);
+            int lo[3], hi[3];
+            for (int i = 0; i < 3; ++i) {
+                lo[i] = (int)floor(ds[i] - reach * bn[i]);
+                hi[i] = (int)ceil(ds[i] + reach * bn[i]);
+            }
+            for (int n0 = lo[0]; n0 <= hi[0] && !keep; ++n0)
+                for (int n1 = lo[1]; n1 <= hi[1] && !keep; ++n1)
+                    for (int n2 = lo[2]; n2 <= hi[2] && !keep; ++n2) {
+                        double d2 = 0.0;
+                        for (int k = 0; k < 3; ++k) {
+                            const double v = dx[k] - (n0 * g.lat[k] + n1 * g.lat[3 + k] + n2 * g.lat[6 + k]);
+                            d2 += v * v;
+                        }
+                        keep = d2 < reach * reach;
+                    }
+        }
+        const unsigned long long m = __ballot(keep);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wcnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wave; ++w)
+            off += wcnt[w];
+        if (FILL && keep)
+            plist[run + off + pre] = J;
+        run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+    }
+    if (!FILL && threadIdx.x == 0)
+        pcnt[I] = run;
+}
+
+hipError_t launch_partners(hipStream_t s, const Geo &g, const Basis &b, double brad, const int *pptr, int *pcnt,
+                           int *plist)
+{
+    if (plist)
+        hipLaunchKernelGGL(k_partners<true>, dim3(g.natom), dim3(256), 0, s, g, b, brad, pptr, pcnt, plist);
+    else
+        hipLaunchKernelGGL(k_partners<false>, dim3(g.natom), dim3(256), 0, s, g, b, brad, pptr, pcnt, plist);
+    return hipGetLastError();
+}
+
+}  // namespace gint

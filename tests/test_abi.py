@@ -141,3 +141,31 @@ def test_valid_plan_without_gpu_reports_device_error(lib):
     a, k = _args(w)
     st, out = _create(lib, a)
     assert st == g.GINT_EDEVICE and out == 12345
+
+
+def test_batch_invalid_arguments(lib):
+    import paper_2603_21835_amd as g
+
+    out = ctypes.c_void_p(777)
+    assert lib.gint_batch_create(0, None, 0, None, 0, None, ctypes.byref(out)) == g.GINT_EINVAL
+    w = gi.si8_sz()
+    a, k = _args(w)
+    cell = g._Cell()
+    cell.lattice[:] = list(np.asarray(w.lattice, dtype=np.float64).reshape(9))
+    cell.grid[:] = [24, 0, 24]
+    cell.natom = w.natom
+    soa = np.zeros(w.natom, dtype=np.int32)
+    pos = np.ascontiguousarray(w.positions).reshape(-1)
+    cell.species_of_atom = g._iptr(soa)
+    cell.positions = g._dptr(pos)
+    cells = (g._Cell * 1)(cell)
+    assert lib.gint_batch_create(1, cells, a["nspecies"], a["species"], 0, None, ctypes.byref(out)) == g.GINT_EINVAL
+    assert out.value == 777
+    assert lib.gint_batch_create(1, cells, a["nspecies"], a["species"], 0, None, None) == g.GINT_EINVAL
+    assert lib.gint_batch_build_H(None, None, None) == g.GINT_EINVAL
+    assert lib.gint_batch_build_rho(None, None, None) == g.GINT_EINVAL
+    assert lib.gint_batch_force(None, None, None, None) == g.GINT_EINVAL
+    assert lib.gint_batch_sync(None) == g.GINT_EINVAL
+    assert lib.gint_batch_ncell(None) == -1
+    assert lib.gint_batch_cell(None, 0) is None
+    lib.gint_batch_destroy(None)  # accepted

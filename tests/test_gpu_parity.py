@@ -37,12 +37,12 @@ def _dev(torch, dev, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
 
 
-def _gpu_all(torch, dev, w, batch=None, nchunk=0):
+def _gpu_all(torch, dev, w, batch=None, h_budget=0):
     import paper_2603_21835_amd as g
 
     plan = g.GintPlan.from_workload(w)
     if batch is not None:
-        plan.tune(batch, nchunk)
+        plan.tune(batch, h_budget)
     V = _dev(torch, dev, w.V)
     D = _dev(torch, dev, w.D)
     H = plan.build_H(V).cpu().numpy()
@@ -119,12 +119,15 @@ def test_small_cells_full(oracle_mod, torch_dev, make):
     _compare_full(oracle_mod, w, H, rho, F)
 
 
-@pytest.mark.parametrize("batch,nchunk", [((4, 4, 2), 1), ((2, 2, 4), 0), ((4, 2, 2), 3), ((2, 4, 4), 0)])
-def test_batch_shapes_and_chunks(oracle_mod, torch_dev, batch, nchunk):
+# a tiny H partial budget forces the H path into many batch ranges
+@pytest.mark.parametrize("batch,h_budget", [((4, 4, 2), 0), ((2, 2, 4), 0), ((4, 2, 2), 1), ((2, 4, 4), 200000)])
+def test_batch_shapes_and_slabs(oracle_mod, torch_dev, batch, h_budget):
     torch, dev = torch_dev
     w = _ragged_five_atoms()
-    _say(f"case ragged batch {batch} nchunk {nchunk}")
-    plan, H, rho, F = _gpu_all(torch, dev, w, batch=batch, nchunk=nchunk)
+    _say(f"case ragged batch {batch} H budget {h_budget}")
+    plan, H, rho, F = _gpu_all(torch, dev, w, batch=batch, h_budget=h_budget)
+    if h_budget:
+        assert plan.work()["nslab"] > 1
     _compare_full(oracle_mod, w, H, rho, F)
 
 
@@ -190,5 +193,28 @@ def test_si64_dzp_sampled(oracle_mod, torch_dev):
     _say(f"  F sampled: {eF:.2e}")
     assert eF <= TOL
     # invariants at full size: E = Tr(D H) and dV sum rho = Tr(D S)
+    E = plan.dV * float(np.dot(w.V, rho))
+    assert abs(E - np.sum(w.D * H)) <= 1e-11 * np.sum(np.abs(w.D * H))
+
+
+def test_si512_sampled(oracle_mod, torch_dev):
+    # full-size workload in the benchmark's configuration: sampled outputs
+    torch, dev = torch_dev
+    w = gi.si512_dzp()
+    _say(f"case si512_dzp grid {w.grid}")
+    plan, H, rho, F = _gpu_all(torch, dev, w)
+    o = oracle_mod.Oracle.from_workload(w)
+    I = int(w.fd_atoms[0])
+    rows = o.H_rows(w.V, I, I + 1)
+    r0 = o.atom_orb0[I]
+    e = _rel_max(H[r0:r0 + rows.shape[0]], rows)
+    _say(f"  H rows atom {I}: {e:.2e}")
+    assert e <= TOL
+    rng = np.random.default_rng(1)
+    idx = rng.choice(w.ngrid, 5000, replace=False)
+    er = _rel_l2(rho[idx], o.rho(w.D, idx))
+    _say(f"  rho sampled: {er:.2e}")
+    assert er <= TOL
+    assert np.array_equal(H, H.T)
     E = plan.dV * float(np.dot(w.V, rho))
     assert abs(E - np.sum(w.D * H)) <= 1e-11 * np.sum(np.abs(w.D * H))
