@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
+# arithmetic type of the path per mode: H operands (+ rho/force operands) and accumulation
+DTYPES = {"fp64": "f64", "fp32": "f32 (f64 sums)", "bf16": "bf16 H, f32 rho/force (f64 sums)",
+          "fp16": "f16 H, f32 rho/force (f64 sums)", "bf16x3": "bf16 hi/lo H, f32 rho/force (f64 sums)",
+          "fp16x3": "f16 hi/lo H, f32 rho/force (f64 sums)"}
 PEAK_HBM_GBS = 8000.0
 
 
@@ -153,7 +158,7 @@ def run_batched(args, torch, gi, g, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.cells} independent Si cells (8/16/32/64 atoms: {kinds.tolist()}), DZP rc=8 bohr, "
@@ -176,7 +181,7 @@ def main():
     ap.add_argument("--workload", default="si512", choices=["si512", "si64", "si8", "batched"])
     ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
     ap.add_argument("--only", default=None, choices=["H", "rho", "force"],
                     help="time one contraction only (short profiler runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -252,23 +257,44 @@ def main():
     value = w.ngrid / ((t1 - t0) / args.steps)
 
     s1, s2 = work["sum_ng"], work["sum_ng2"]
+    # algorithmic work per step (per unit: one mesh point with n_g orbitals)
     flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1}
+    # the H reduction moves every block partial once and writes H's blocks
+    hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
+              "H_fill": 8 * plan.norb ** 2}
     kernels = {}
     for k, (ms, n) in timing.items():
         if n == 0:
             continue
-        avg = ms / n
-        kernels[k] = {"avg_ms": round(avg, 4), "launches": n}
+        per_step = n // args.steps if n % args.steps == 0 else n / args.steps
+        kernels[k] = {"avg_ms": round(ms / n, 4), "launches": n, "ms_per_step": round(ms / args.steps, 4)}
         if k in flops:
-            kernels[k]["alg_tflops"] = round(flops[k] / (avg * 1e-3) / 1e12, 3)
+            kernels[k]["alg_tflops"] = round(flops[k] / (ms / args.steps * 1e-3) / 1e12, 3)
+        if k in hbytes:
+            kernels[k]["alg_gbs"] = round(hbytes[k] / (ms / args.steps * 1e-3) / 1e9, 1)
+        kernels[k]["launches_per_step"] = per_step
     dom = max(kernels, key=lambda k: timing[k][0])
     roof = None
-    if dom in flops:
-        ach = flops[dom] / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": _traffic(dom, args.workload, args.precision),
-                "kernel": dom, "alg_flops_per_launch": flops[dom]}
+    if dom in flops or dom in hbytes:
+        lps = timing[dom][1] / args.steps
+        avg_s = kernels[dom]["avg_ms"] * 1e-3
+        if dom in flops:
+            if args.precision == "fp64":
+                peak = PEAK_FP64_TFLOPS
+            elif dom == "H_blocks" and args.precision != "fp32":
+                peak = PEAK_16BIT_TFLOPS
+            else:
+                peak = PEAK_FP32_TFLOPS
+            per_launch = flops[dom] / lps
+            ach = per_launch / avg_s / 1e12
+            roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(ach / peak, 4), "kernel": dom, "alg_flops_per_launch": per_launch}
+        else:
+            per_launch = hbytes[dom] / lps
+            ach = per_launch / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": dom, "alg_bytes_per_launch": per_launch}
+        roof["traffic"] = _traffic(dom, args.workload, args.precision)
 
     # full-size consistency check: dV sum V rho == Tr(D H)  (adjoint identity)
     check = None
@@ -288,7 +314,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh {'x'.join(map(str, w.grid))}, "
@@ -300,6 +326,20 @@ def main():
         "kernels": kernels,
         "check_E_equals_trDH": check,
     }
+    if args.precision != "fp64" and args.only is None:
+        # accuracy of the mixed mode at full size, against the FP64 path
+        _progress("FP64 reference for the mixed-precision error")
+        ref = g.GintPlan.from_workload(w, precision="fp64")
+        H64 = ref.build_H(V)
+        rho64 = ref.build_rho(D)
+        F64 = ref.force(V, D)
+        torch.cuda.synchronize()
+        out["mixed_error_vs_fp64"] = {
+            "max_abs_dH_Ha": float((H - H64).abs().max()),
+            "rho_rel_l2": float(torch.linalg.norm(rho - rho64) / torch.linalg.norm(rho64)),
+            "force_rel_max": float((F - F64).abs().max() / F64.abs().max()),
+        }
+        ref.close()
     if args.only is not None:
         out["only"] = args.only
     if not args.no_cpu_baseline and args.only is None:

@@ -64,12 +64,17 @@ typedef enum {
 } gint_status;
 
 /* Arithmetic of the contractions.  Inputs/outputs stay FP64 in all modes;
-   the cross-batch reductions are FP64 in all modes. */
+   the cross-batch reductions and the final dot products are FP64 in all
+   modes.  The 16-bit modes apply to H; rho and the force then run as in
+   GINT_FP32.  Split modes write each H operand as hi + lo (both 16-bit) and
+   sum hi.hi + hi.lo + lo.hi on the matrix cores (3 products). */
 typedef enum {
-    GINT_FP64 = 0, /* FP64 orbitals, FP64 MFMA                                 */
-    GINT_FP32 = 1, /* FP32 orbitals and FP32 accumulation                      */
-    GINT_BF16 = 2, /* BF16 MFMA operands, FP32 accumulation                    */
-    GINT_FP16 = 3  /* FP16 MFMA operands, FP32 accumulation                    */
+    GINT_FP64 = 0,       /* FP64 orbitals, FP64 MFMA                          */
+    GINT_FP32 = 1,       /* FP32 orbitals, FP32 MFMA (FP32 within a batch)     */
+    GINT_BF16 = 2,       /* H: BF16 operands, FP32 accumulation, one product   */
+    GINT_FP16 = 3,       /* H: FP16 operands (scaled), FP32 accumulation       */
+    GINT_BF16_SPLIT = 4, /* H: BF16 hi/lo operands, 3 products                 */
+    GINT_FP16_SPLIT = 5  /* H: FP16 hi/lo operands (scaled), 3 products        */
 } gint_precision;
 
 /* One radial function, tabulated on the host at r_i = i*dr, i < nr; its
@@ -100,6 +105,9 @@ typedef struct {
     double sum_ng2;        /* sum over mesh points of n_g^2                      */
     int batch[3];          /* batch shape in mesh points                         */
     int nslab;             /* batch ranges the H path is split into              */
+    long long nblock;      /* H atom-pair block partials over all batches         */
+    int mno;               /* block partial edge (most orbitals of one atom)      */
+    int partial_bytes;     /* bytes per block partial element (8 FP64, 4 else)    */
 } gint_work;
 
 typedef struct gint_plan_s *gint_plan;
@@ -168,12 +176,13 @@ gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const doubl
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
     GINT_K_H = 1,         /* H atom-pair blocks (one workgroup per mesh batch)      */
-    GINT_K_H_REDUCE = 2,  /* H zero fill and fixed-order block sums into dense H    */
+    GINT_K_H_REDUCE = 2,  /* fixed-order block sums into dense H                    */
     GINT_K_RHO = 3,       /* rho contraction (one workgroup per mesh batch)         */
     GINT_K_PACK = 4,      /* D + D^T packed into matrix-core fragments (rho, force) */
     GINT_K_FORCE = 5,     /* force contraction (one workgroup per mesh batch)       */
     GINT_K_F_REDUCE = 6,  /* force reduction per atom                               */
-    GINT_NKERNEL = 7
+    GINT_K_H_FILL = 7,    /* zero fill of dense H                                   */
+    GINT_NKERNEL = 8
 };
 
 /* Enable (1) or disable (0) timing: each kernel launch of later calls is
@@ -224,6 +233,19 @@ gint_status gint_batch_build_rho(gint_batch batch, const double *const *D_dev, d
 /* dE/dR of every cell (E = dV sum W rho per cell). */
 gint_status gint_batch_force(gint_batch batch, const double *const *W_dev, const double *const *D_dev,
                              double *const *dEdR_dev);
+
+/* Choose each cell's batch shape by timing: for every class of cells with
+ * the same mesh and atom count, time `reps` rounds of H + rho + dE/dR of
+ * the class's first cell on the batch stream for each candidate shape
+ * (32-point boxes 4x4x2, 4x2x4, 2x4x4, 8x2x2, 2x2x8 and, except in the
+ * 16-bit modes, 16-point 2x2x4 and 4x2x2) and apply the fastest to the
+ * whole class.  The buffers are the caller's (device pointers as in the
+ * batched calls; their contents are overwritten).  chosen (host, 3*ncell
+ * ints, may be NULL) receives each cell's shape.  Synchronises the batch
+ * stream; invalidates the captured graphs. */
+gint_status gint_batch_autotune(gint_batch batch, const double *const *V_dev, const double *const *D_dev,
+                                double *const *H_dev, double *const *rho_dev, double *const *dEdR_dev, int reps,
+                                int *chosen);
 
 gint_status gint_batch_sync(gint_batch batch);
 int gint_batch_ncell(gint_batch batch);

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgint.so")
 
 GINT_OK, GINT_EINVAL, GINT_ENOMEM, GINT_EDEVICE, GINT_EUNSUPPORTED, GINT_ESTATE = range(6)
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4, "fp16x3": 5}
 
 # Every symbol include/gint.h declares.
 EXPORTS = (
@@ -32,9 +32,9 @@ EXPORTS = (
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
-    "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy",
+    "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
-KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce")
+KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill")
 
 
 class GintError(RuntimeError):
@@ -62,7 +62,8 @@ class Work(ctypes.Structure):
     _fields_ = [("ngrid", ctypes.c_longlong), ("nbatch", ctypes.c_longlong),
                 ("nentry", ctypes.c_longlong), ("npair", ctypes.c_longlong),
                 ("sum_ng", ctypes.c_double), ("sum_ng2", ctypes.c_double),
-                ("batch", ctypes.c_int * 3), ("nslab", ctypes.c_int)]
+                ("batch", ctypes.c_int * 3), ("nslab", ctypes.c_int), ("nblock", ctypes.c_longlong),
+                ("mno", ctypes.c_int), ("partial_bytes", ctypes.c_int)]
 
 
 _lib = None
@@ -124,6 +125,8 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).argtypes = [P, PP, PP]
     lib.gint_batch_force.restype = st
     lib.gint_batch_force.argtypes = [P, PP, PP, PP]
+    lib.gint_batch_autotune.restype = st
+    lib.gint_batch_autotune.argtypes = [P, PP, PP, PP, PP, PP, ctypes.c_int, ip]
     lib.gint_batch_sync.restype = st
     lib.gint_batch_sync.argtypes = [P]
     lib.gint_batch_ncell.restype = ctypes.c_int
@@ -275,7 +278,8 @@ class GintPlan:
         w = Work()
         _check(self._lib.gint_plan_work(self._handle(), ctypes.byref(w)))
         return {"ngrid": w.ngrid, "nbatch": w.nbatch, "nentry": w.nentry, "npair": w.npair,
-                "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nslab": w.nslab}
+                "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nslab": w.nslab,
+                "nblock": w.nblock, "mno": w.mno, "partial_bytes": w.partial_bytes}
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.gint_plan_set_timing(self._handle(), 1 if enable else 0))
@@ -414,6 +418,17 @@ class GintBatch:
 
     def sync(self):
         _check(self._lib.gint_batch_sync(self._handle()))
+
+    def autotune(self, V, D, H, rho, F, reps: int = 2):
+        """Time the candidate batch shapes per class of equal cells (mesh and
+        atom count) and keep the fastest; returns each cell's shape."""
+        nn = [n * n for n in self.norb]
+        chosen = np.zeros(3 * self.ncell, dtype=np.int32)
+        _check(self._lib.gint_batch_autotune(self._handle(), self._ptrs(V, self.ngrid, "V"), self._ptrs(D, nn, "D"),
+                                             self._ptrs(H, nn, "H"), self._ptrs(rho, self.ngrid, "rho"),
+                                             self._ptrs(F, [3 * a for a in self.natom], "dEdR"), int(reps),
+                                             _iptr(chosen)))
+        return [tuple(int(x) for x in chosen[3 * i:3 * i + 3]) for i in range(self.ncell)]
 
     def build_H(self, V, out=None):
         nn = [n * n for n in self.norb]

@@ -94,6 +94,7 @@ struct gint_plan_s {
     double dV = 0.0;
     double rc_max = 0.0;
     long long hbudget_req = 0;  // H partial-buffer budget in bytes (0 = automatic)
+    long long nblock = 0;       // H block partials over all batches
     void *ext_hpart = nullptr;  // H partial buffer lent by a batch (shared by its chain)
     size_t ext_hpart_bytes = 0;
     long long gen = 0;          // bumped whenever the lists are rebuilt
@@ -136,7 +137,7 @@ struct gint_plan_s {
             (void)hipEventDestroy(e);
     }
 
-    bool f32() const { return prec == GINT_FP32; }
+    bool f32() const { return prec != GINT_FP64; }  // FP32 tiles for all but FP64
     void *hpart() const { return ext_hpart ? ext_hpart : Hpart.p; }
     AtomLists atom_lists() const
     {
@@ -369,8 +370,8 @@ gint_status rebuild_lists(gint_plan p, bool resort)
                     p->nbmax, p->ngbmax, kMaxBatchAtoms, kMaxBatchGroups);
     {
         // LDS of the point-stationary kernels: every atom of a batch at once
-        const size_t esz = p->prec == GINT_FP32 ? sizeof(float) : sizeof(double);
-        const size_t lds_H = esz * (size_t)p->nbmax * g.P * kRow + 8192;
+        const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
+        const size_t lds_H = esz * (size_t)p->nbmax * g.P * kRow + 16384;
         if (lds_H > 163840)
             return fail(GINT_EUNSUPPORTED, "%d atoms reach one %d-point batch: %zu bytes of LDS; use a smaller batch",
                         p->nbmax, g.P, lds_H);
@@ -448,11 +449,12 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     HIPCHK(hipStreamSynchronize(s));
     if (hboff[nb] < 0 || tpart < 0)
         return fail(GINT_EUNSUPPORTED, "block lists exceed 2^31 entries");
+    p->nblock = hboff[nb];
     STCHK(p->plist.ensure(sizeof(int) * (tpart + 1)));
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_partners(s, g, B2, p->brad, p->pptr.as<int>(), p->pcnt.as<int>(), p->plist.as<int>());
     }));
-    const size_t esz = p->prec == GINT_FP32 ? sizeof(float) : sizeof(double);
+    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
     const size_t blk_bytes = esz * (size_t)p->mno * p->mno;
     size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)16 << 30;
     if (p->ext_hpart)
@@ -462,9 +464,10 @@ gint_status rebuild_lists(gint_plan p, bool resort)
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr / 3 < budget)
             budget = fr / 3;
     }
+    // a range holds at least one whole batch
     long long per_slab = (long long)(budget / blk_bytes);
-    if (per_slab < kMaxBatchAtoms * (kMaxBatchAtoms + 1) / 2)
-        per_slab = kMaxBatchAtoms * (kMaxBatchAtoms + 1) / 2;
+    for (int b = 0; b < nb; ++b)
+        per_slab = std::max(per_slab, (long long)hboff[b + 1] - hboff[b]);
     p->slab.assign(1, 0);
     long long most = 0;
     for (int b = 0; b < nb;) {
@@ -627,10 +630,8 @@ static gint_status plan_create(const double lattice[9], const int grid[3], int n
             return fail(GINT_EINVAL, "species_of_atom[%d] = %d out of range", i, species_of_atom[i]);
     if (!finite3(positions, 3LL * natom))
         return fail(GINT_EINVAL, "positions have non-finite entries");
-    if ((int)prec < 0 || (int)prec > 3)
+    if ((int)prec < GINT_FP64 || (int)prec > GINT_FP16_SPLIT)
         return fail(GINT_EINVAL, "unknown precision %d", (int)prec);
-    if (prec != GINT_FP64 && prec != GINT_FP32)
-        return fail(GINT_EUNSUPPORTED, "precision %d is not available in this build", (int)prec);
     g.natom = natom;
     g.ngroup = (natom + kGroup - 1) / kGroup;
     const int bs0[3] = {4, 4, 2};
@@ -796,6 +797,8 @@ gint_status gint_plan_tune(gint_plan p, const int batch[3], long long h_budget_b
     const int P = batch[0] * batch[1] * batch[2];
     if (P != 16 && P != 32)
         return fail(GINT_EINVAL, "batch holds %d points (must be 16 or 32)", P);
+    if (P != 32 && p->prec != GINT_FP64 && p->prec != GINT_FP32)
+        return fail(GINT_EINVAL, "16-bit modes need 32-point batches (one instruction's K)");
     if (h_budget_bytes < 0)
         return fail(GINT_EINVAL, "h_budget_bytes must be >= 0");
     Geo g = p->geo;
@@ -803,10 +806,23 @@ gint_status gint_plan_tune(gint_plan p, const int batch[3], long long h_budget_b
     if (max_image_index(g, p->rc_max) >= 126.0)
         return fail(GINT_EUNSUPPORTED, "cutoff spans more than 125 cells");
     HIPCHK(hipSetDevice(p->device));
+    const Geo g_old = p->geo;
+    const double brad_old = p->brad;
+    const long long hb_old = p->hbudget_req;
     p->geo = g;
     p->brad = batch_radius(g);
     p->hbudget_req = h_budget_bytes;
-    STCHK(rebuild_lists(p, false));
+    const gint_status st = rebuild_lists(p, false);
+    if (st != GINT_OK) {
+        // keep the plan usable with its previous shape
+        const std::string why = g_last_error;
+        p->geo = g_old;
+        p->brad = brad_old;
+        p->hbudget_req = hb_old;
+        if (rebuild_lists(p, false) != GINT_OK)
+            p->magic = 0;
+        return fail(st, "%s", why.c_str());
+    }
     return GINT_OK;
 }
 
@@ -826,12 +842,12 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
     const Bins bn = p->bins();
     const Basis B = p->basis();
     const AtomLists al = p->atom_lists();
-    STCHK(timed(p, GINT_K_H_REDUCE,
+    STCHK(timed(p, GINT_K_H_FILL,
                 [&] { return launch_fill_f64(p->stream, H, (long long)p->norb * p->norb, 0.0); }));
     for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
         const int b0 = p->slab[i], b1 = p->slab[i + 1];
         STCHK(timed(p, GINT_K_H, [&] {
-            return launch_H_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, b0, b1, W, wscale, p->boff.as<int>(),
+            return launch_H_batch(p->stream, (int)p->prec, p->geo, bn, B, p->nbmax, b0, b1, W, wscale, p->boff.as<int>(),
                                   p->mno, p->hpart());
         }));
         STCHK(timed(p, GINT_K_H_REDUCE, [&] {
@@ -935,6 +951,9 @@ gint_status gint_plan_work(gint_plan p, gint_work *out)
     for (int k = 0; k < 3; ++k)
         out->batch[k] = p->geo.bs[k];
     out->nslab = (int)p->slab.size() - 1;
+    out->nblock = p->nblock;
+    out->mno = p->mno;
+    out->partial_bytes = p->f32() ? 4 : 8;
     return GINT_OK;
 }
 
@@ -1269,6 +1288,97 @@ gint_status gint_batch_force(gint_batch b, const double *const *W_dev, const dou
             STCHK(force_impl(b->plans[i], W_dev[i], b->plans[i]->dV, D_dev[i], dEdR_dev[i]));
         return GINT_OK;
     });
+}
+
+gint_status gint_batch_autotune(gint_batch b, const double *const *V_dev, const double *const *D_dev,
+                                double *const *H_dev, double *const *rho_dev, double *const *dEdR_dev, int reps,
+                                int *chosen)
+{
+    STCHK(check_batch(b));
+    if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
+        return fail(GINT_EINVAL, "pointer arrays must be non-NULL");
+    if (reps < 1)
+        return fail(GINT_EINVAL, "reps must be >= 1");
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i)
+        if (!V_dev[i] || !D_dev[i] || !H_dev[i] || !rho_dev[i] || !dEdR_dev[i])
+            return fail(GINT_EINVAL, "cell %d: NULL device pointer", i);
+    HIPCHK(hipSetDevice(b->device));
+    // candidate batch shapes: 32-point boxes first, then 16-point ones
+    static const int cand[][3] = {{4, 4, 2}, {4, 2, 4}, {2, 4, 4}, {8, 2, 2}, {2, 2, 8}, {2, 2, 4}, {4, 2, 2}};
+    const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return fail(GINT_EDEVICE, "event creation failed");
+    }
+    gint_status st = GINT_OK;
+    std::vector<int> done(n, 0);
+    for (int i0 = 0; i0 < n && st == GINT_OK; ++i0) {
+        if (done[i0])
+            continue;
+        gint_plan p = b->plans[i0];
+        // every cell with the same mesh and atom count takes i0's choice
+        std::vector<int> cls;
+        for (int i = i0; i < n; ++i) {
+            gint_plan q = b->plans[i];
+            if (!done[i] && q->natom == p->natom && q->geo.N[0] == p->geo.N[0] && q->geo.N[1] == p->geo.N[1] &&
+                q->geo.N[2] == p->geo.N[2])
+                cls.push_back(i);
+        }
+        const hipStream_t own = p->stream;
+        p->stream = b->stream;
+        float best = 0.0f;
+        int bi = -1;
+        for (int c = 0; c < ncand && st == GINT_OK; ++c) {
+            const int P = cand[c][0] * cand[c][1] * cand[c][2];
+            if (P != 32 && p->prec != GINT_FP64 && p->prec != GINT_FP32)
+                continue;
+            if (gint_plan_tune(p, cand[c], 0) != GINT_OK)
+                continue;  // e.g. too many atoms reach one batch of this shape
+            auto run = [&]() -> gint_status {
+                STCHK(build_H_impl(p, V_dev[i0], p->dV, H_dev[i0]));
+                STCHK(gint_build_rho(p, D_dev[i0], rho_dev[i0]));
+                return force_impl(p, V_dev[i0], p->dV, D_dev[i0], dEdR_dev[i0]);
+            };
+            if ((st = run()) != GINT_OK)
+                break;
+            float ms = 0.0f;
+            if (hipEventRecord(ev[0], b->stream) != hipSuccess) {
+                st = fail(GINT_EDEVICE, "hipEventRecord failed");
+                break;
+            }
+            for (int r = 0; r < reps && st == GINT_OK; ++r)
+                st = run();
+            if (st != GINT_OK)
+                break;
+            if (hipEventRecord(ev[1], b->stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+                st = fail(GINT_EDEVICE, "event timing failed");
+                break;
+            }
+            if (bi < 0 || ms < best) {
+                best = ms;
+                bi = c;
+            }
+        }
+        p->stream = own;
+        if (st == GINT_OK && bi < 0)
+            st = fail(GINT_EUNSUPPORTED, "cell %d: no candidate batch shape fits", i0);
+        for (int i : cls) {
+            if (st != GINT_OK)
+                break;
+            st = gint_plan_tune(b->plans[i], cand[bi], 0);
+            done[i] = 1;
+            if (chosen)
+                for (int k = 0; k < 3; ++k)
+                    chosen[3 * i + k] = cand[bi][k];
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return st;
 }
 
 gint_status gint_batch_sync(gint_batch b)

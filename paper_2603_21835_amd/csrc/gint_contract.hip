@@ -136,6 +136,207 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
     }
 }
 
+// ---------------------------------------------------------------------------
+// H^loc with 16-bit matrix-core operands (v_mfma_f32_16x16x32_{bf16,f16}),
+// FP32 accumulation within a batch and FP64 across batches (k_H_rowreduce).
+//
+// With psi_p = sqrt|w_p| phi(p) and s_p = sign(w_p),
+//     C_IJ = sum_p (s_p psi_I(p)) psi_J(p)^T,
+// so one 16-bit tile per atom serves as both operands (the sign is a bit
+// flip, exact).  In the split modes psi = hi + lo with hi = round16(psi) and
+// lo = round16(psi - hi), and C = hi.hi + hi.lo + lo.hi (the lo.lo term is
+// below the FP32 accumulation's rounding).  FP16 operands carry a 2^8 scale
+// (removed exactly at the end) that keeps lo clear of the subnormal range.
+//
+// After the FP32 orbitals are staged, each atom's region is rewritten in
+// place as planes [hi | lo][chunk 0..3][orbital 0..15][8 points]: lane
+// l = 16 chunk + orbital then reads its whole operand (8 points of one
+// orbital, k = 8 chunk + j) with one 16-byte load at plane + 16 l.  A batch
+// holds exactly 32 points (the K of one instruction).
+
+namespace {
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+// round-to-nearest-even FP32 -> BF16 bits (finite inputs)
+__device__ __forceinline__ unsigned bf16_bits(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_value(unsigned h) { return __uint_as_float(h << 16); }
+
+template <bool F16>
+__device__ __forceinline__ void split16(float x, unsigned &hi, unsigned &lo)
+{
+    if (F16) {
+        const _Float16 h = (_Float16)x;
+        const _Float16 l = (_Float16)(x - (float)h);
+        hi = __builtin_bit_cast(unsigned short, h);
+        lo = __builtin_bit_cast(unsigned short, l);
+    } else {
+        hi = bf16_bits(x);
+        lo = bf16_bits(x - bf16_value(hi));
+    }
+}
+
+template <bool F16>
+__device__ __forceinline__ f4 mma16(u4v a, u4v b, f4 c)
+{
+    if (F16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0,
+                                                      0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c,
+                                                       0, 0, 0);
+}
+}  // namespace
+
+template <bool F16, bool SPLIT>
+__global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
+                                                   double wscale, int b0, const int *__restrict__ boff, int mno,
+                                                   float *__restrict__ part)
+{
+    constexpr int P = 32;
+    constexpr float kScale = F16 ? 256.0f : 1.0f;
+    constexpr float kUnscale = 1.0f / (kScale * kScale);
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    float *s_phi = reinterpret_cast<float *>(s_dyn);  // [nbmax][P][kRow], then the 16-bit planes
+    __shared__ DevRadial s_rad[kMaxRadTotal];
+    __shared__ DevSpecies s_sp[kMaxSpecies];
+    __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms];
+    __shared__ float s_sw[P];
+    __shared__ unsigned s_neg[P];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = b0 + blockIdx.x;
+    const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
+    int ib[3];
+    batch_coords(g, b, ib);
+
+    for (int k = tid; k < g.nrad; k += blockDim.x)
+        s_rad[k] = bs.rad[k];
+    for (int k = tid; k < g.nspecies; k += blockDim.x)
+        s_sp[k] = bs.sp[k];
+    for (int a = tid; a < nb; a += blockDim.x) {
+        const int atom = bn.ent_atom[e0 + a];
+        s_atom[a] = atom;
+        s_nor[a] = bs.sp[bs.spc[atom]].norb;
+    }
+    for (int p = tid; p < P; p += blockDim.x) {
+        int n[3];
+        const double w = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
+        s_sw[p] = (float)(sqrt(fabs(w)) * (double)kScale);
+        s_neg[p] = w < 0.0 ? 1u : 0u;
+    }
+    __syncthreads();
+
+    for (int idx = tid; idx < nb * P; idx += blockDim.x) {
+        const int a = idx / P, p = idx % P;
+        const int e = e0 + a;
+        const int atom = s_atom[a];
+        float *row = s_phi + (size_t)(a * P + p) * kRow;
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[o] = 0.0f;
+        if (valid) {
+            const int io = bn.ent_img[e];
+            const int cnt = bn.ent_img[e + 1] - io;
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            double r[3];
+            mesh_cart(g, n, r);
+            eval_orbitals<float>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
+                                 r, row);
+        }
+    }
+    __syncthreads();
+
+    // ---- in place: FP32 [p][orbital] -> 16-bit planes, one wave per atom ----
+    // (a wave reads its atom's region completely before it writes it)
+    for (int a = wave; a < nb; a += nw) {
+        float *reg = s_phi + (size_t)a * P * kRow;
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            v[j] = reg[(8 * lk + j) * kRow + li] * s_sw[8 * lk + j];
+        unsigned hi[8], lo[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            split16<F16>(v[j], hi[j], lo[j]);
+        u4v H, L;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            H[d] = hi[2 * d] | (hi[2 * d + 1] << 16);
+            L[d] = lo[2 * d] | (lo[2 * d + 1] << 16);
+        }
+        u4v *pl = reinterpret_cast<u4v *>(reg);
+        pl[lane] = H;
+        pl[64 + lane] = L;
+    }
+    // the sign of w at this lane's eight points, as a mask on packed pairs
+    u4v neg;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        neg[d] = (s_neg[8 * lk + 2 * d] << 15) | (s_neg[8 * lk + 2 * d + 1] << 31);
+    __syncthreads();
+
+    const int nblk = nb * (nb + 1) / 2;
+    int ia = 0, ja = 0;
+    for (int k = 0; k < wave; ++k)
+        if (++ja == nb) {
+            ++ia;
+            ja = ia;
+        }
+    const size_t mm = (size_t)mno * mno;
+    const u4v *pl = reinterpret_cast<const u4v *>(s_phi);
+    const int apitch = P * kRow / 4;  // u4v per atom region
+    for (int k = wave; k < nblk; k += nw) {
+        const u4v aH = pl[ia * apitch + lane] ^ neg;
+        const u4v bH = pl[ja * apitch + lane];
+        f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mma16<F16>(aH, bH, acc);
+        if (SPLIT) {
+            const u4v aL = pl[ia * apitch + 64 + lane] ^ neg;
+            const u4v bL = pl[ja * apitch + 64 + lane];
+            acc = mma16<F16>(aH, bL, acc);
+            acc = mma16<F16>(aL, bH, acc);
+        }
+        const int nI = s_nor[ia], nJ = s_nor[ja];
+        float *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * lk + v;
+            if (row < nI && li < nJ)
+                o[row * mno + li] = acc[v] * kUnscale;
+        }
+        for (int s2 = 0; s2 < nw; ++s2)
+            if (++ja == nb) {
+                ++ia;
+                ja = ia;
+            }
+    }
+}
+
+template <bool F16, bool SPLIT>
+static hipError_t launch_H16_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0, int b1,
+                               const double *W, double wscale, const int *boff, int mno, void *part)
+{
+    const size_t lds = sizeof(float) * (size_t)nbmax * g.P * kRow;
+    hipError_t e = hipFuncSetAttribute((const void *)k_H_batch16<F16, SPLIT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_H_batch16<F16, SPLIT>), dim3(b1 - b0), dim3(512), lds, s, g, bn, b, W, wscale, b0, boff,
+                       mno, static_cast<float *>(part));
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_H_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                                    int b1, const double *W, double wscale, const int *boff, int mno, void *part)
@@ -152,21 +353,35 @@ static hipError_t launch_H_batch_t(hipStream_t s, const Geo &g, const Bins &bn, 
     return hipGetLastError();
 }
 
-hipError_t launch_H_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
+hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                           int b1, const double *W, double wscale, const int *boff, int mno, void *part)
 {
-    return f32 ? launch_H_batch_t<float>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part)
-               : launch_H_batch_t<double>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    if (b1 <= b0)
+        return hipSuccess;
+    if (mode != kModeF64 && mode != kModeF32 && g.P != 32)
+        return hipErrorInvalidValue;
+    switch (mode) {
+    case kModeF64: return launch_H_batch_t<double>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    case kModeF32: return launch_H_batch_t<float>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    case kModeBF16: return launch_H16_t<false, false>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    case kModeF16: return launch_H16_t<true, false>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    case kModeBF16x3: return launch_H16_t<false, true>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    case kModeF16x3: return launch_H16_t<true, true>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 constexpr int kRowChunk = 16;         // batches staged per round
 constexpr int kMaxPartnerPass = 128;  // partners per pass
 constexpr int kRowThreads = 1024;
+constexpr int kRowElems = 8;  // block elements per thread and pass
 
 __device__ __forceinline__ int tri_index(int lo, int hi, int n) { return lo * n - lo * (lo - 1) / 2 + (hi - lo); }
 
-// Thread (partner slot sl, orbital row a of I) accumulates the row a of block
-// (I, J_sl) over I's batches in increasing batch order.
+// Thread t owns elements t + kRowThreads j (j < kRowElems) of the pass's
+// blocks laid end to end ([partner slot][mno*mno], row-major (I row, J
+// column)) and sums each over I's batches in increasing batch order, so the
+// lanes of a wave read consecutive elements of a block partial.
 template <typename T>
 __global__ __launch_bounds__(kRowThreads) void k_H_rowreduce(Geo g, Bins bn, Basis bs, AtomLists al, int mno,
                                                              int norb, const T *__restrict__ part,
@@ -176,31 +391,48 @@ __global__ __launch_bounds__(kRowThreads) void k_H_rowreduce(Geo g, Bins bn, Bas
     __shared__ int s_pos[kRowChunk][kMaxPartnerPass];
     __shared__ int s_part[kMaxPartnerPass];
     __shared__ int s_ia[kRowChunk], s_nb[kRowChunk], s_e0[kRowChunk], s_pb[kRowChunk];
+    __shared__ int s_tr[kMaxOrb * kMaxOrb];  // element -> transposed element
 
     const int tid = threadIdx.x;
     const int I = blockIdx.x;
     const int Iin = bs.perm[I];
     const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
     const int np = al.pptr[I + 1] - al.pptr[I];
-    const size_t mm = (size_t)mno * mno;
+    const int mm = mno * mno;
     // this atom's entries inside the batch range [b0, b1)
     const int ent_lo = lower_bound_i(al.aent, al.aptr[I], al.aptr[I + 1], bn.bptr[b0]);
     const int ent_hi = lower_bound_i(al.aent, al.aptr[I], al.aptr[I + 1], bn.bptr[b1]);
-    int npc_max = kRowThreads / nI;
+    // no batch of this range holds I: a later range only adds zeros
+    if (accumulate && ent_lo == ent_hi)
+        return;
+    int npc_max = kRowThreads * kRowElems / mm;
     if (npc_max > kMaxPartnerPass)
         npc_max = kMaxPartnerPass;
-    const int sl = tid / nI, a = tid % nI;
+
+    for (int e = tid; e < mm; e += kRowThreads) {
+        const int r = e / mno, c = e - r * mno;
+        s_tr[e] = c * mno + r;
+    }
+    // this thread's elements, packed as partner slot << 16 | element
+    int el[kRowElems];
+#pragma unroll
+    for (int j = 0; j < kRowElems; ++j) {
+        const int idx = tid + j * kRowThreads;
+        const int sl = idx / mm;
+        el[j] = (sl << 16) | (idx - sl * mm);
+    }
 
     for (int s0 = 0; s0 < np; s0 += npc_max) {
         const int npc = (np - s0 < npc_max) ? np - s0 : npc_max;
         __syncthreads();
         for (int j = tid; j < npc; j += kRowThreads)
             s_part[j] = al.plist[al.pptr[I] + s0 + j];
-        const bool mine = sl < npc;
-        double acc[kMaxOrb];
+        // the partner ids are read below even when no batch is staged
+        __syncthreads();
+        double acc[kRowElems];
 #pragma unroll
-        for (int c = 0; c < kMaxOrb; ++c)
-            acc[c] = 0.0;
+        for (int j = 0; j < kRowElems; ++j)
+            acc[j] = 0.0;
 
         for (int c0 = ent_lo; c0 < ent_hi; c0 += kRowChunk) {
             const int nk = (ent_hi - c0 < kRowChunk) ? ent_hi - c0 : kRowChunk;
@@ -227,39 +459,39 @@ __global__ __launch_bounds__(kRowThreads) void k_H_rowreduce(Geo g, Bins bn, Bas
                 }
             }
             __syncthreads();
-            if (mine) {
-                for (int k = 0; k < nk; ++k) {
-                    const int ja = s_pos[k][sl];
-                    if (ja < 0)
-                        continue;
-                    const int ia = s_ia[k];
-                    if (ia <= ja) {
-                        const T *src = part + (size_t)(s_pb[k] + tri_index(ia, ja, s_nb[k])) * mm + a * mno;
 #pragma unroll
-                        for (int c = 0; c < kMaxOrb; ++c)
-                            if (c < mno)
-                                acc[c] += (double)src[c];
-                    } else {
-                        const T *src = part + (size_t)(s_pb[k] + tri_index(ja, ia, s_nb[k])) * mm + a;
-#pragma unroll
-                        for (int c = 0; c < kMaxOrb; ++c)
-                            if (c < mno)
-                                acc[c] += (double)src[c * mno];
+            for (int j = 0; j < kRowElems; ++j) {
+                const int sl = el[j] >> 16;
+                if (sl < npc) {
+                    const int e = el[j] & 0xffff, et = s_tr[e];
+                    double v = acc[j];
+                    for (int k = 0; k < nk; ++k) {
+                        const int ja = s_pos[k][sl];
+                        if (ja < 0)
+                            continue;
+                        const int ia = s_ia[k];
+                        const bool up = ia <= ja;
+                        const int blk = up ? tri_index(ia, ja, s_nb[k]) : tri_index(ja, ia, s_nb[k]);
+                        v += (double)part[(size_t)(s_pb[k] + blk) * mm + (up ? e : et)];
                     }
+                    acc[j] = v;
                 }
             }
         }
-        // H_IJ row a and its mirror column (diagonal blocks: c >= a, mirrored)
-        if (mine) {
-            const int J = s_part[sl];
-            const int Jin = bs.perm[J];
-            const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
+        // H_IJ and its mirror (diagonal blocks: upper triangle, mirrored)
 #pragma unroll
-            for (int c = 0; c < kMaxOrb; ++c) {
-                if (c < nJ && !(J == I && c < a)) {
-                    const size_t i1 = (size_t)(mu0 + a) * norb + nu0 + c;
-                    const size_t i2 = (size_t)(nu0 + c) * norb + mu0 + a;
-                    const double v = accumulate ? H[i1] + acc[c] : acc[c];
+        for (int j = 0; j < kRowElems; ++j) {
+            const int sl = el[j] >> 16;
+            if (sl < npc) {
+                const int J = s_part[sl];
+                const int Jin = bs.perm[J];
+                const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
+                const int e = el[j] & 0xffff;
+                const int r = e / mno, c = e - r * mno;
+                if (r < nI && c < nJ && !(J == I && c < r)) {
+                    const size_t i1 = (size_t)(mu0 + r) * norb + nu0 + c;
+                    const size_t i2 = (size_t)(nu0 + c) * norb + mu0 + r;
+                    const double v = accumulate ? H[i1] + acc[j] : acc[j];
                     H[i1] = v;
                     H[i2] = v;
                 }
@@ -345,23 +577,29 @@ hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn,
 }
 
 // ---------------------------------------------------------------------------
-// Point-stationary kernels: one workgroup per mesh batch, 16-point tiles.
+// Point-stationary rho and force: one workgroup (8 waves) per mesh batch.
+// The folded orbitals of every atom reaching the batch are evaluated once
+// into LDS at all P points; each D + D^T fragment a wave loads is applied to
+// all P/16 sixteen-point tiles of the batch, and the next block's fragment is
+// loaded while the current one is in use.
 
-// Per-batch setup shared by rho and force: radial and species tables, the
-// batch's atoms and their group ranks, and the pair ids of the batch's group
-// pairs (canonical order).
+constexpr int kBatchWaves = 8;
+
 template <bool FORCE, typename T>
-__global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
-                                               const double *__restrict__ W, double wscale, double *__restrict__ out)
+__global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
+                                                            const double *__restrict__ W, double wscale,
+                                                            double *__restrict__ out)
 {
+    constexpr int NT = 64 * kBatchWaves;
+    constexpr int NS = kMaxP / 16;  // sixteen-point tiles per batch, at most
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][16][kRow]
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_grank[kMaxBatchAtoms];
     __shared__ int s_ptab[kMaxBatchGroups * kMaxBatchGroups];
-    __shared__ double s_red[4][16];
-    __shared__ double s_w[16];
+    __shared__ double s_red[FORCE ? 1 : kBatchWaves][kMaxP];
+    __shared__ double s_w[kMaxP];
     __shared__ double s_F[FORCE ? kMaxBatchAtoms : 1][3];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -369,169 +607,236 @@ __global__ __launch_bounds__(256) void k_batch(Geo g, Bins bn, Basis bs, const T
     const int b = blockIdx.x;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
     const int g0 = bn.bgptr[b], ngb = bn.bgptr[b + 1] - g0;
+    const int P = g.P, nsub = P >> 4;
     int ib[3];
     batch_coords(g, b, ib);
 
-    for (int k = tid; k < g.nrad; k += 256)
+    for (int k = tid; k < g.nrad; k += NT)
         s_rad[k] = bs.rad[k];
-    for (int k = tid; k < g.nspecies; k += 256)
+    for (int k = tid; k < g.nspecies; k += NT)
         s_sp[k] = bs.sp[k];
-    for (int a = tid; a < nb; a += 256) {
+    for (int a = tid; a < nb; a += NT) {
         const int atom = bn.ent_atom[e0 + a];
         s_atom[a] = atom;
         s_grank[a] = lower_bound_i(bn.bgrp, g0, g0 + ngb, atom / kGroup) - g0;
         if (FORCE)
             s_F[a][0] = s_F[a][1] = s_F[a][2] = 0.0;
     }
-    for (int k = tid; k < ngb * ngb; k += 256) {
+    for (int k = tid; k < ngb * ngb; k += NT) {
         const int ra = k / ngb, rb = k % ngb;
         const int ga = bn.bgrp[g0 + ra], gb = bn.bgrp[g0 + rb];
         s_ptab[k] = (ra <= rb) ? bn.pair_index[(size_t)ga * g.ngroup + gb] : -1;
     }
+    if (FORCE)
+        for (int p = tid; p < P; p += NT) {
+            int n[3];
+            s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
+        }
     __syncthreads();
 
-    for (int sub = 0; sub < g.P; sub += 16) {
-        // ---- stage the folded orbitals of every atom of the batch ----
-        for (int idx = tid; idx < nb * 16; idx += 256) {
-            const int a = idx >> 4, p = idx & 15;
-            const int e = e0 + a;
-            const int atom = s_atom[a];
-            T *row = s_phi + (size_t)(a * 16 + p) * kRow;
-            int n[3];
-            const bool valid = batch_point(g, ib, sub + p, n);
-            const DevSpecies &S = s_sp[bs.spc[atom]];
-            const int zlo = valid ? S.norb : 0;
-            for (int o = zlo; o < kMaxOrb; ++o)
-                row[o] = (T)0;
-            if (valid) {
-                const int io = bn.ent_img[e];
-                const int cnt = bn.ent_img[e + 1] - io;
-                const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
-                double r[3];
-                mesh_cart(g, n, r);
-                eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
-                                 r, row);
-            }
-        }
-        if (FORCE && tid < 16) {
-            int n[3];
-            s_w[tid] = batch_point(g, ib, sub + tid, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
-        }
-        __syncthreads();
-
-        if (!FORCE) {
-            // rho_p = sum_{I<J} phi_I . (S2_IJ phi_J) + 1/2 sum_I phi_I . (S2_II phi_I)
-            double rp = 0.0;
-            const int nblk = nb * (nb + 1) / 2;
-            int ia = 0, ja = 0;
-            for (int k = 0; k < wave; ++k)
-                if (++ja == nb) {
-                    ++ia;
-                    ja = ia;
-                }
-            for (int k = wave; k < nblk; k += 4) {
-                const int I = s_atom[ia], J = s_atom[ja];
-                const int pr = s_ptab[s_grank[ia] * ngb + s_grank[ja]];  // active: both groups are here
-                const int blk = (I % kGroup) * 4 + (J % kGroup);
-                const T *f = pk + ((size_t)(pr * 16 + blk) * 2) * 256 + lane;
-                const T fa0 = f[0], fa1 = f[64], fa2 = f[128], fa3 = f[192];
-                const T *pJ = s_phi + (size_t)(ja * 16 + li) * kRow + lk;
-                typename MM<T>::acc u = MM<T>::zero();
-                u = MM<T>::mma(fa0, pJ[0], u);
-                u = MM<T>::mma(fa1, pJ[4], u);
-                u = MM<T>::mma(fa2, pJ[8], u);
-                u = MM<T>::mma(fa3, pJ[12], u);
-                const T *pI = s_phi + (size_t)(ia * 16 + li) * kRow;
-                double dot = 0.0;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    dot += (double)u[v] * (double)pI[MM<T>::row(lk, v)];
-                rp += (ia == ja) ? 0.5 * dot : dot;
-                for (int s = 0; s < 4; ++s)
-                    if (++ja == nb) {
-                        ++ia;
-                        ja = ia;
-                    }
-            }
-            rp += __shfl_xor(rp, 16);
-            rp += __shfl_xor(rp, 32);
-            if (lane < 16)
-                s_red[wave][lane] = rp;
-            __syncthreads();
-            if (tid < 16) {
-                int n[3];
-                if (batch_point(g, ib, sub + tid, n))
-                    out[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] =
-                        ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
-            }
-        } else {
-            // dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p),  T_I = sum_J S2_IJ phi_J
-            int n[3];
-            const bool pvalid = batch_point(g, ib, sub + li, n);
+    // ---- stage the folded orbitals of every atom at every batch point ----
+    for (int idx = tid; idx < nb * P; idx += NT) {
+        const int a = idx / P, p = idx % P;
+        const int e = e0 + a;
+        const int atom = s_atom[a];
+        T *row = s_phi + (size_t)(a * P + p) * kRow;
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[o] = (T)0;
+        if (valid) {
+            const int io = bn.ent_img[e];
+            const int cnt = bn.ent_img[e + 1] - io;
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
             double r[3];
             mesh_cart(g, n, r);
-            const double wp = s_w[li];
-            for (int ia = wave; ia < nb; ia += 4) {
-                const int I = s_atom[ia];
-                typename MM<T>::acc Tt = MM<T>::zero();
-                for (int ja = 0; ja < nb; ++ja) {
-                    const int J = s_atom[ja];
-                    const bool fwd = ia <= ja;
-                    const int ra = fwd ? s_grank[ia] : s_grank[ja], rb = fwd ? s_grank[ja] : s_grank[ia];
-                    const int pr = s_ptab[ra * ngb + rb];
-                    const int blk = fwd ? (I % kGroup) * 4 + (J % kGroup) : (J % kGroup) * 4 + (I % kGroup);
-                    const T *f = pk + ((size_t)(pr * 16 + blk) * 2 + (fwd ? 0 : 1)) * 256 + lane;
-                    const T *pJ = s_phi + (size_t)(ja * 16 + li) * kRow + lk;
-                    Tt = MM<T>::mma(f[0], pJ[0], Tt);
-                    Tt = MM<T>::mma(f[64], pJ[4], Tt);
-                    Tt = MM<T>::mma(f[128], pJ[8], Tt);
-                    Tt = MM<T>::mma(f[192], pJ[12], Tt);
-                }
-                // gradients of orbitals row(lk, v) of atom I at point li
-                double gr[3][4];
-                const int e = e0 + ia;
-                const DevSpecies &S = s_sp[bs.spc[I]];
-                const double X[3] = {bs.xw[3 * I], bs.xw[3 * I + 1], bs.xw[3 * I + 2]};
-                const int io = bn.ent_img[e];
-                const int cnt = pvalid ? bn.ent_img[e + 1] - io : 0;
-                grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
-                      MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), gr);
-                double fx[3];
+            eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                             row);
+        }
+    }
+    __syncthreads();
+
+    // fragment f of block (x, y) in orientation o (0: S2_XY, 1: S2_YX as A)
+    auto frag = [&](int x, int y, int o) -> const T * {
+        const int X = s_atom[x], Y = s_atom[y];
+        const int pr = s_ptab[s_grank[x] * ngb + s_grank[y]];  // active: both groups reach the batch
+        const int blk = (X % kGroup) * 4 + (Y % kGroup);
+        return pk + ((size_t)(pr * 16 + blk) * 2 + o) * 256 + lane;
+    };
+
+    if (!FORCE) {
+        // rho_p = sum_{I<J} phi_I . (S2_IJ phi_J) + 1/2 sum_I phi_I . (S2_II phi_I)
+        double rp[NS];
 #pragma unroll
-                for (int x = 0; x < 3; ++x) {
-                    double v = wp * ((double)Tt[0] * gr[x][0] + (double)Tt[1] * gr[x][1] + (double)Tt[2] * gr[x][2] +
-                                     (double)Tt[3] * gr[x][3]);
-                    for (int o = 32; o > 0; o >>= 1)
-                        v += __shfl_xor(v, o);
-                    fx[x] = v;
+        for (int s2 = 0; s2 < NS; ++s2)
+            rp[s2] = 0.0;
+        const int nblk = nb * (nb + 1) / 2;
+        int ia = 0, ja = 0;
+        for (int k = 0; k < wave; ++k)
+            if (++ja == nb) {
+                ++ia;
+                ja = ia;
+            }
+        T fa[4];
+        if (wave < nblk) {
+            const T *f = frag(ia, ja, 0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                fa[c] = f[64 * c];
+        }
+        for (int k = wave; k < nblk; k += kBatchWaves) {
+            // the next block of this wave, and its fragment
+            int na = ia, nj = ja;
+            for (int s2 = 0; s2 < kBatchWaves; ++s2)
+                if (++nj == nb) {
+                    ++na;
+                    nj = na;
                 }
-                if (lane == 0) {
-                    s_F[ia][0] -= fx[0];
-                    s_F[ia][1] -= fx[1];
-                    s_F[ia][2] -= fx[2];
+            T fn[4] = {(T)0, (T)0, (T)0, (T)0};
+            if (k + kBatchWaves < nblk) {
+                const T *f = frag(na, nj, 0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    fn[c] = f[64 * c];
+            }
+            const double half = (ia == ja) ? 0.5 : 1.0;
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                if (s2 < nsub) {
+                    const T *pJ = s_phi + (size_t)(ja * P + 16 * s2 + li) * kRow + lk;
+                    typename MM<T>::acc u = MM<T>::zero();
+                    u = MM<T>::mma(fa[0], pJ[0], u);
+                    u = MM<T>::mma(fa[1], pJ[4], u);
+                    u = MM<T>::mma(fa[2], pJ[8], u);
+                    u = MM<T>::mma(fa[3], pJ[12], u);
+                    const T *pI = s_phi + (size_t)(ia * P + 16 * s2 + li) * kRow;
+                    double dot = 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        dot += (double)u[v] * (double)pI[MM<T>::row(lk, v)];
+                    rp[s2] += half * dot;
                 }
+            }
+            ia = na;
+            ja = nj;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                fa[c] = fn[c];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) {
+            double v = rp[s2];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16 && s2 < nsub)
+                s_red[wave][16 * s2 + lane] = v;
+        }
+        __syncthreads();
+        for (int p = tid; p < P; p += NT) {
+            int n[3];
+            if (batch_point(g, ib, p, n)) {
+                double v = s_red[0][p];
+                for (int w = 1; w < kBatchWaves; ++w)
+                    v += s_red[w][p];
+                out[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = v;
+            }
+        }
+    } else {
+        // dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p),  T_I = sum_J S2_IJ phi_J
+        for (int ia = wave; ia < nb; ia += kBatchWaves) {
+            const int I = s_atom[ia];
+            typename MM<T>::acc Tt[NS];
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2)
+                Tt[s2] = MM<T>::zero();
+            T fa[4];
+            {
+                const T *f = (ia <= 0) ? frag(ia, 0, 0) : frag(0, ia, 1);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    fa[c] = f[64 * c];
+            }
+            for (int ja = 0; ja < nb; ++ja) {
+                T fn[4] = {(T)0, (T)0, (T)0, (T)0};
+                if (ja + 1 < nb) {
+                    const int jn = ja + 1;
+                    const T *f = (ia <= jn) ? frag(ia, jn, 0) : frag(jn, ia, 1);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        fn[c] = f[64 * c];
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) {
+                    if (s2 < nsub) {
+                        const T *pJ = s_phi + (size_t)(ja * P + 16 * s2 + li) * kRow + lk;
+                        Tt[s2] = MM<T>::mma(fa[0], pJ[0], Tt[s2]);
+                        Tt[s2] = MM<T>::mma(fa[1], pJ[4], Tt[s2]);
+                        Tt[s2] = MM<T>::mma(fa[2], pJ[8], Tt[s2]);
+                        Tt[s2] = MM<T>::mma(fa[3], pJ[12], Tt[s2]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    fa[c] = fn[c];
+            }
+            // gradients of orbitals row(lk, v) of atom I at point 16 s + li
+            const int e = e0 + ia;
+            const DevSpecies &S = s_sp[bs.spc[I]];
+            const double X[3] = {bs.xw[3 * I], bs.xw[3 * I + 1], bs.xw[3 * I + 2]};
+            const int io = bn.ent_img[e];
+            double fx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                if (s2 < nsub) {
+                    int n[3];
+                    const bool pvalid = batch_point(g, ib, 16 * s2 + li, n);
+                    double r[3];
+                    mesh_cart(g, n, r);
+                    const int cnt = pvalid ? bn.ent_img[e + 1] - io : 0;
+                    double gr[3][4];
+                    grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                          MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), gr);
+                    const double wp = s_w[16 * s2 + li];
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+                        fx[x] += wp * ((double)Tt[s2][0] * gr[x][0] + (double)Tt[s2][1] * gr[x][1] +
+                                       (double)Tt[s2][2] * gr[x][2] + (double)Tt[s2][3] * gr[x][3]);
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                double v = fx[x];
+                for (int o = 32; o > 0; o >>= 1)
+                    v += __shfl_xor(v, o);
+                fx[x] = v;
+            }
+            if (lane == 0) {
+                s_F[ia][0] = -fx[0];
+                s_F[ia][1] = -fx[1];
+                s_F[ia][2] = -fx[2];
             }
         }
         __syncthreads();
-    }
-    if (FORCE)
-        for (int k = tid; k < nb * 3; k += 256)
+        for (int k = tid; k < nb * 3; k += NT)
             out[(size_t)(e0 + k / 3) * 3 + k % 3] = s_F[k / 3][k % 3];
+    }
 }
 
-size_t batch_lds_bytes(int nbmax, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * 16 * kRow; }
+size_t batch_lds_bytes(int nbmax, int P, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * P * kRow; }
 
 template <bool FORCE, typename T>
 static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                  const void *pk, const double *W, double wscale, double *out)
 {
-    const size_t lds = sizeof(T) * (size_t)nbmax * 16 * kRow;
+    const size_t lds = sizeof(T) * (size_t)nbmax * g.P * kRow;
     hipError_t e =
         hipFuncSetAttribute((const void *)k_batch<FORCE, T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_batch<FORCE, T>), dim3(g.nbatch), dim3(256), lds, s, g, bn, b, static_cast<const T *>(pk),
-                       W, wscale, out);
+    hipLaunchKernelGGL((k_batch<FORCE, T>), dim3(g.nbatch), dim3(64 * kBatchWaves), lds, s, g, bn, b,
+                       static_cast<const T *>(pk), W, wscale, out);
     return hipGetLastError();
 }
 

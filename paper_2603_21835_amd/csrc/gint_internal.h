@@ -118,8 +118,10 @@ hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, con
 
 // Contractions (gint_contract.hip).
 // f32 selects FP32 orbital tiles, packed D and H partials (else FP64).
-hipError_t launch_H_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                          int b0, int b1, const double *W, double wscale, const int *boff, int mno, void *part);
+// arithmetic modes of the H kernel (values of gint_precision)
+constexpr int kModeF64 = 0, kModeF32 = 1, kModeBF16 = 2, kModeF16 = 3, kModeBF16x3 = 4, kModeF16x3 = 5;
+hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
+                          int b1, const double *W, double wscale, const int *boff, int mno, void *part);
 hipError_t launch_H_rowreduce(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b,
                               const AtomLists &al, int mno, int norb, const void *part, const int *boff,
                               int b0, int b1, int accumulate, double *H);
@@ -132,7 +134,7 @@ hipError_t launch_partners(hipStream_t s, const Geo &g, const Basis &b, double b
                            int *pcnt, int *plist);
 hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int npair,
                           const double *D, int norb, void *pk);
-size_t batch_lds_bytes(int nbmax, bool f32);
+size_t batch_lds_bytes(int nbmax, int P, bool f32);
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                             const void *pk, double *rho);
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,

@@ -128,3 +128,24 @@ def test_batched_rejects_timing(tdev, cells):
     b.build_H(V)
     b.sync()
     b.close()
+
+
+def test_autotune_keeps_results(tdev, cells, oracle_mod):
+    torch, dev = tdev
+    import paper_2603_21835_amd as g
+
+    sel = [c for c in cells if c.natom <= 16][:3]
+    _say(f"case autotune {len(sel)} cells")
+    b = g.GintBatch(sel, sel[0].species)
+    V, D = _inputs(torch, dev, sel)
+    outs = [b.build_H(V), b.build_rho(D), b.force(V, D)]
+    shapes = b.autotune(V, D, *outs, reps=1)
+    _say(f"  chosen {shapes}")
+    for s in shapes:
+        assert int(np.prod(s)) in (16, 32)
+    res, _ = _batched(b, V, D, outs)
+    c = sel[0]
+    o = oracle_mod.Oracle.from_workload(c)
+    Ho = o.H(c.V)
+    assert np.abs(res[0][0] - Ho).max() / np.abs(Ho).max() <= 1e-10
+    b.close()
