@@ -113,7 +113,9 @@ struct gint_plan_s {
     DevBuf mark, mscan, pair_index, pairA, pairB;
     // work buffers
     DevBuf Hpart, S2pk, Fent, sums, readback;
-    DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist;
+    DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist, lcnt, lptr, blist;
+    int npair_owned = 0;          // owned atom pairs (entries of plist)
+    std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
 
     // optional per-kernel timing (events on the plan's stream)
@@ -223,6 +225,10 @@ void set_batch(Geo &g, const int bs[3])
     }
     g.P = bs[0] * bs[1] * bs[2];
     g.nbatch = g.nb[0] * g.nb[1] * g.nb[2];
+    // compact tiles of batches: a contiguous range of batch ids is a compact
+    // region of the mesh (the atoms, and D blocks, it needs overlap)
+    for (int k = 0; k < 3; ++k)
+        g.bt[k] = g.nb[k] % 4 == 0 ? 4 : (g.nb[k] % 2 == 0 ? 2 : 1);
 }
 
 // Radius of the bounding sphere of a full batch's point box.
@@ -454,6 +460,27 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_partners(s, g, B2, p->brad, p->pptr.as<int>(), p->pcnt.as<int>(), p->plist.as<int>());
     }));
+    // block lists of the owned pairs (batch order) for the H reduction
+    p->npair_owned = tpart;
+    STCHK(p->lcnt.ensure(sizeof(int) * (tpart + 1)));
+    STCHK(p->lptr.ensure(sizeof(int) * (tpart + 1)));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_pair_blocks(s, na, tpart, p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>(),
+                                  p->bptr.as<int>(), p->boff.as<int>(), p->pptr.as<int>(), p->plist.as<int>(),
+                                  p->lcnt.as<int>(), nullptr, nullptr);
+    }));
+    HIPCHK(launch_scan_i32(s, p->lcnt.as<int>(), tpart, p->lptr.as<int>()));
+    int tlist = 0;
+    HIPCHK(hipMemcpyAsync(&tlist, p->lptr.as<int>() + tpart, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (tlist < 0)
+        return fail(GINT_EUNSUPPORTED, "pair block lists exceed 2^31 entries");
+    STCHK(p->blist.ensure(sizeof(int) * ((size_t)tlist + 1)));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_pair_blocks(s, na, tpart, p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>(),
+                                  p->bptr.as<int>(), p->boff.as<int>(), p->pptr.as<int>(), p->plist.as<int>(),
+                                  p->lcnt.as<int>(), p->lptr.as<int>(), p->blist.as<int>());
+    }));
     const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
     const size_t blk_bytes = esz * (size_t)p->mno * p->mno;
     size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)16 << 30;
@@ -480,6 +507,9 @@ gint_status rebuild_lists(gint_plan p, bool resort)
         p->slab.push_back(e);
         b = e;
     }
+    p->slab_q.clear();
+    for (int b : p->slab)
+        p->slab_q.push_back(hboff[b]);
     if (p->ext_hpart) {
         if (blk_bytes * (size_t)most > p->ext_hpart_bytes)
             return fail(GINT_ENOMEM, "a batch of the cell needs %zu bytes of H partials", blk_bytes * (size_t)most);
@@ -841,7 +871,6 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
     HIPCHK(hipSetDevice(p->device));
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    const AtomLists al = p->atom_lists();
     STCHK(timed(p, GINT_K_H_FILL,
                 [&] { return launch_fill_f64(p->stream, H, (long long)p->norb * p->norb, 0.0); }));
     for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
@@ -851,8 +880,9 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
                                   p->mno, p->hpart());
         }));
         STCHK(timed(p, GINT_K_H_REDUCE, [&] {
-            return launch_H_rowreduce(p->stream, p->f32(), p->geo, bn, B, al, p->mno, p->norb, p->hpart(),
-                                      p->boff.as<int>(), b0, b1, i > 0 ? 1 : 0, H);
+            return launch_H_pairreduce(p->stream, p->f32(), p->natom, p->npair_owned, p->pptr.as<int>(),
+                                       p->plist.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), B, p->mno, p->norb,
+                                       p->hpart(), p->slab_q[i], p->slab_q[i + 1], i > 0 ? 1 : 0, H);
         }));
     }
     return GINT_OK;

@@ -5,15 +5,15 @@
 //
 //   H^loc   point-stationary: a workgroup owns a mesh batch and forms every
 //           atom-pair block of it from orbitals evaluated once into LDS
-//           (k_H_batch); a per-atom workgroup then sums each block over the
-//           atom's batches in a fixed order into dense symmetric H
-//           (k_H_rowreduce).
+//           (k_H_batch, k_H_batch16); one wave per owned atom pair then sums
+//           the pair's blocks over its batches in a fixed order into dense
+//           symmetric H (k_H_pairreduce).
 //   rho     point-stationary: a workgroup owns a mesh batch, evaluates every
 //           atom's folded orbitals there once into LDS and contracts all
-//           atom-pair blocks against packed D + D^T fragments (k_rho_batch).
+//           atom-pair blocks against packed D + D^T fragments (k_batch).
 //   force   point-stationary likewise: T_I = sum_J (D + D^T)_IJ phi_J per
 //           batch, dotted with grad phi_I; per-(batch, atom) partials are
-//           summed per atom in a fixed order (k_force_batch, k_force_reduce).
+//           summed per atom in a fixed order (k_batch, k_force_reduce).
 //
 // MFMA lane layouts: see MM<T> in gint_device.h.
 // Orbital tiles in LDS: [atom slot][point][orbital], row pitch kRow elements.
@@ -22,6 +22,9 @@
 #include "gint_device.h"
 
 namespace gint {
+
+// workgroups for n batches dispatched XCD-contiguously (xcd_batch)
+static unsigned xcd_grid(int n) { return (unsigned)(kXcd * ((n + kXcd - 1) / kXcd)); }
 
 // ---------------------------------------------------------------------------
 // H^loc, point-stationary.
@@ -33,15 +36,14 @@ namespace gint {
 // on the matrix cores, writing it to a partial buffer (n_I x n_J of a
 // mno x mno tile; block k of batch b at boff[b] + k).
 //
-// k_H_rowreduce: one workgroup per atom I owns the blocks (I, J) of the
-// partners J it owns (each unordered pair has one owner) and sums their
-// partials over I's batches in increasing batch order (fixed order, no
-// atomics), then writes H_IJ and its mirror H_JI into the dense matrix, so
-// H is exactly symmetric.
+// k_H_pairreduce: each unordered atom pair has one owner; one wave per
+// owned pair sums the pair's block partials over its batches in increasing
+// batch order (fixed order, no atomics), then writes H_IJ and its mirror
+// H_JI into the dense matrix, so H is exactly symmetric.
 
 template <typename T>
 __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
-                                                 double wscale, int b0, const int *__restrict__ boff, int mno,
+                                                 double wscale, int b0, int b1, const int *__restrict__ boff, int mno,
                                                  T *__restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -53,7 +55,9 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int b = b0 + blockIdx.x;
+    const int b = xcd_batch(blockIdx.x, b0, b1 - b0);
+    if (b < 0)
+        return;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
     const int P = g.P;
     int ib[3];
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
 
 // ---------------------------------------------------------------------------
 // H^loc with 16-bit matrix-core operands (v_mfma_f32_16x16x32_{bf16,f16}),
-// FP32 accumulation within a batch and FP64 across batches (k_H_rowreduce).
+// FP32 accumulation within a batch and FP64 across batches (k_H_pairreduce).
 //
 // With psi_p = sqrt|w_p| phi(p) and s_p = sign(w_p),
 //     C_IJ = sum_p (s_p psi_I(p)) psi_J(p)^T,
@@ -196,8 +200,8 @@ __device__ __forceinline__ f4 mma16(u4v a, u4v b, f4 c)
 
 template <bool F16, bool SPLIT>
 __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
-                                                   double wscale, int b0, const int *__restrict__ boff, int mno,
-                                                   float *__restrict__ part)
+                                                   double wscale, int b0, int b1, const int *__restrict__ boff,
+                                                   int mno, float *__restrict__ part)
 {
     constexpr int P = 32;
     constexpr float kScale = F16 ? 256.0f : 1.0f;
@@ -212,7 +216,9 @@ __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, con
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int b = b0 + blockIdx.x;
+    const int b = xcd_batch(blockIdx.x, b0, b1 - b0);
+    if (b < 0)
+        return;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
     int ib[3];
     batch_coords(g, b, ib);
@@ -332,8 +338,8 @@ static hipError_t launch_H16_t(hipStream_t s, const Geo &g, const Bins &bn, cons
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_H_batch16<F16, SPLIT>), dim3(b1 - b0), dim3(512), lds, s, g, bn, b, W, wscale, b0, boff,
-                       mno, static_cast<float *>(part));
+    hipLaunchKernelGGL((k_H_batch16<F16, SPLIT>), dim3(xcd_grid(b1 - b0)), dim3(512), lds, s, g, bn, b, W, wscale,
+                       b0, b1, boff, mno, static_cast<float *>(part));
     return hipGetLastError();
 }
 
@@ -348,8 +354,8 @@ static hipError_t launch_H_batch_t(hipStream_t s, const Geo &g, const Bins &bn, 
         hipFuncSetAttribute((const void *)k_H_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_H_batch<T>, dim3(b1 - b0), dim3(512), lds, s, g, bn, b, W, wscale, b0, boff, mno,
-                       static_cast<T *>(part));
+    hipLaunchKernelGGL(k_H_batch<T>, dim3(xcd_grid(b1 - b0)), dim3(512), lds, s, g, bn, b, W, wscale, b0, b1, boff,
+                       mno, static_cast<T *>(part));
     return hipGetLastError();
 }
 
@@ -371,145 +377,120 @@ hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn,
     }
 }
 
-constexpr int kRowChunk = 16;         // batches staged per round
-constexpr int kMaxPartnerPass = 128;  // partners per pass
-constexpr int kRowThreads = 1024;
-constexpr int kRowElems = 8;  // block elements per thread and pass
+// H^loc: fixed-order sums of the block partials.  One wave per owned atom
+// pair (I, J) walks the pair's block list (batch order) restricted to the
+// batch range [b0, b1), reading each partial block whole (lane l owns
+// elements l, l + 64, ... of the row-major n_I x n_J block), and writes H_IJ
+// and its mirror H_JI (for J = I only the upper triangle, mirrored).
+constexpr int kRedGroup = 8;  // list entries whose loads are in flight together
 
-__device__ __forceinline__ int tri_index(int lo, int hi, int n) { return lo * n - lo * (lo - 1) / 2 + (hi - lo); }
-
-// Thread t owns elements t + kRowThreads j (j < kRowElems) of the pass's
-// blocks laid end to end ([partner slot][mno*mno], row-major (I row, J
-// column)) and sums each over I's batches in increasing batch order, so the
-// lanes of a wave read consecutive elements of a block partial.
 template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_H_rowreduce(Geo g, Bins bn, Basis bs, AtomLists al, int mno,
-                                                             int norb, const T *__restrict__ part,
-                                                             const int *__restrict__ boff, int b0, int b1,
-                                                             int accumulate, double *__restrict__ H)
+__global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, const int *__restrict__ pptr,
+                                                      const int *__restrict__ plist, const int *__restrict__ lptr,
+                                                      const int *__restrict__ list, Basis bs, int mno, int norb,
+                                                      const T *__restrict__ part, int q0, int q1, int accumulate,
+                                                      double *__restrict__ H)
 {
-    __shared__ int s_pos[kRowChunk][kMaxPartnerPass];
-    __shared__ int s_part[kMaxPartnerPass];
-    __shared__ int s_ia[kRowChunk], s_nb[kRowChunk], s_e0[kRowChunk], s_pb[kRowChunk];
-    __shared__ int s_tr[kMaxOrb * kMaxOrb];  // element -> transposed element
-
-    const int tid = threadIdx.x;
-    const int I = blockIdx.x;
-    const int Iin = bs.perm[I];
-    const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
-    const int np = al.pptr[I + 1] - al.pptr[I];
-    const int mm = mno * mno;
-    // this atom's entries inside the batch range [b0, b1)
-    const int ent_lo = lower_bound_i(al.aent, al.aptr[I], al.aptr[I + 1], bn.bptr[b0]);
-    const int ent_hi = lower_bound_i(al.aent, al.aptr[I], al.aptr[I + 1], bn.bptr[b1]);
-    // no batch of this range holds I: a later range only adds zeros
-    if (accumulate && ent_lo == ent_hi)
+    constexpr int M = kMaxOrb * kMaxOrb / 64;  // elements per lane
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= npair)
         return;
-    int npc_max = kRowThreads * kRowElems / mm;
-    if (npc_max > kMaxPartnerPass)
-        npc_max = kMaxPartnerPass;
-
-    for (int e = tid; e < mm; e += kRowThreads) {
-        const int r = e / mno, c = e - r * mno;
-        s_tr[e] = c * mno + r;
+    // owner I of pair p
+    int lo = 0, hi = natom + 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pptr[mid] <= p)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    // this thread's elements, packed as partner slot << 16 | element
-    int el[kRowElems];
-#pragma unroll
-    for (int j = 0; j < kRowElems; ++j) {
-        const int idx = tid + j * kRowThreads;
-        const int sl = idx / mm;
-        el[j] = (sl << 16) | (idx - sl * mm);
-    }
-
-    for (int s0 = 0; s0 < np; s0 += npc_max) {
-        const int npc = (np - s0 < npc_max) ? np - s0 : npc_max;
-        __syncthreads();
-        for (int j = tid; j < npc; j += kRowThreads)
-            s_part[j] = al.plist[al.pptr[I] + s0 + j];
-        // the partner ids are read below even when no batch is staged
-        __syncthreads();
-        double acc[kRowElems];
-#pragma unroll
-        for (int j = 0; j < kRowElems; ++j)
-            acc[j] = 0.0;
-
-        for (int c0 = ent_lo; c0 < ent_hi; c0 += kRowChunk) {
-            const int nk = (ent_hi - c0 < kRowChunk) ? ent_hi - c0 : kRowChunk;
-            __syncthreads();
-            for (int idx = tid; idx < kRowChunk * npc; idx += kRowThreads)
-                s_pos[idx / npc][idx % npc] = -1;
-            if (tid < nk) {
-                const int e = al.aent[c0 + tid];
-                const int b = al.abat[c0 + tid];
-                s_e0[tid] = bn.bptr[b];
-                s_ia[tid] = e - bn.bptr[b];
-                s_nb[tid] = bn.bptr[b + 1] - bn.bptr[b];
-                s_pb[tid] = boff[b] - boff[b0];
-            }
-            __syncthreads();
-            // positions of this pass's partners in each staged batch
-            for (int idx = tid; idx < nk * kMaxBatchAtoms; idx += kRowThreads) {
-                const int k = idx / kMaxBatchAtoms, j = idx % kMaxBatchAtoms;
-                if (j < s_nb[k]) {
-                    const int J = bn.ent_atom[s_e0[k] + j];
-                    const int f = lower_bound_i(s_part, 0, npc, J);
-                    if (f < npc && s_part[f] == J)
-                        s_pos[k][f] = j;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kRowElems; ++j) {
-                const int sl = el[j] >> 16;
-                if (sl < npc) {
-                    const int e = el[j] & 0xffff, et = s_tr[e];
-                    double v = acc[j];
-                    for (int k = 0; k < nk; ++k) {
-                        const int ja = s_pos[k][sl];
-                        if (ja < 0)
-                            continue;
-                        const int ia = s_ia[k];
-                        const bool up = ia <= ja;
-                        const int blk = up ? tri_index(ia, ja, s_nb[k]) : tri_index(ja, ia, s_nb[k]);
-                        v += (double)part[(size_t)(s_pb[k] + blk) * mm + (up ? e : et)];
-                    }
-                    acc[j] = v;
-                }
-            }
+    const int I = lo - 1, J = plist[p];
+    // the part of the list inside the block range [q0, q1)
+    auto qof = [](int c) { return c >= 0 ? c : -c - 1; };
+    int l0 = lptr[p], l1 = lptr[p + 1];
+    {
+        int a = l0, z = l1;
+        while (a < z) {
+            const int mid = (a + z) >> 1;
+            if (qof(list[mid]) < q0)
+                a = mid + 1;
+            else
+                z = mid;
         }
-        // H_IJ and its mirror (diagonal blocks: upper triangle, mirrored)
+        const int s0 = a;
+        z = l1;
+        while (a < z) {
+            const int mid = (a + z) >> 1;
+            if (qof(list[mid]) < q1)
+                a = mid + 1;
+            else
+                z = mid;
+        }
+        l0 = s0;
+        l1 = a;
+    }
+    if (accumulate && l0 == l1)
+        return;
+    const int mm = mno * mno;
+    int eo[M], et[M];
+    double acc[M];
 #pragma unroll
-        for (int j = 0; j < kRowElems; ++j) {
-            const int sl = el[j] >> 16;
-            if (sl < npc) {
-                const int J = s_part[sl];
-                const int Jin = bs.perm[J];
-                const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
-                const int e = el[j] & 0xffff;
-                const int r = e / mno, c = e - r * mno;
-                if (r < nI && c < nJ && !(J == I && c < r)) {
-                    const size_t i1 = (size_t)(mu0 + r) * norb + nu0 + c;
-                    const size_t i2 = (size_t)(nu0 + c) * norb + mu0 + r;
-                    const double v = accumulate ? H[i1] + acc[j] : acc[j];
-                    H[i1] = v;
-                    H[i2] = v;
-                }
-            }
+    for (int m = 0; m < M; ++m) {
+        const int e = lane + 64 * m;
+        const int r = e / mno, c = e - r * mno;
+        eo[m] = e < mm ? e : 0;
+        et[m] = e < mm ? c * mno + r : 0;
+        acc[m] = 0.0;
+    }
+    for (int k0 = l0; k0 < l1; k0 += kRedGroup) {
+        T v[kRedGroup][M];
+#pragma unroll
+        for (int g = 0; g < kRedGroup; ++g) {
+            const int k = k0 + g;
+            const int code = k < l1 ? list[k] : 0;
+            const bool up = code >= 0;
+            const size_t base = (size_t)((up ? code : -code - 1) - q0) * mm;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                v[g][m] = (k < l1 && lane + 64 * m < mm) ? part[base + (up ? eo[m] : et[m])] : (T)0;
+        }
+#pragma unroll
+        for (int g = 0; g < kRedGroup; ++g)
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                acc[m] += (double)v[g][m];
+    }
+    const int Iin = bs.perm[I], Jin = bs.perm[J];
+    const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
+    const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int e = lane + 64 * m;
+        const int r = e / mno, c = e - r * mno;
+        if (e < mm && r < nI && c < nJ && !(J == I && c < r)) {
+            const size_t i1 = (size_t)(mu0 + r) * norb + nu0 + c;
+            const size_t i2 = (size_t)(nu0 + c) * norb + mu0 + r;
+            const double val = accumulate ? H[i1] + acc[m] : acc[m];
+            H[i1] = val;
+            H[i2] = val;
         }
     }
 }
 
-hipError_t launch_H_rowreduce(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b,
-                              const AtomLists &al, int mno, int norb, const void *part, const int *boff, int b0,
-                              int b1, int accumulate, double *H)
+hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int natom, int npair, const int *pptr, const int *plist,
+                               const int *lptr, const int *list, const Basis &b, int mno, int norb, const void *part,
+                               int q0, int q1, int accumulate, double *H)
 {
+    if (npair <= 0)
+        return hipSuccess;
+    const unsigned nblk = (unsigned)((npair + 3) / 4);
     if (f32)
-        hipLaunchKernelGGL(k_H_rowreduce<float>, dim3(g.natom), dim3(kRowThreads), 0, s, g, bn, b, al, mno, norb,
-                           static_cast<const float *>(part), boff, b0, b1, accumulate, H);
+        hipLaunchKernelGGL(k_H_pairreduce<float>, dim3(nblk), dim3(256), 0, s, natom, npair, pptr, plist, lptr, list,
+                           b, mno, norb, static_cast<const float *>(part), q0, q1, accumulate, H);
     else
-        hipLaunchKernelGGL(k_H_rowreduce<double>, dim3(g.natom), dim3(kRowThreads), 0, s, g, bn, b, al, mno, norb,
-                           static_cast<const double *>(part), boff, b0, b1, accumulate, H);
+        hipLaunchKernelGGL(k_H_pairreduce<double>, dim3(nblk), dim3(256), 0, s, natom, npair, pptr, plist, lptr,
+                           list, b, mno, norb, static_cast<const double *>(part), q0, q1, accumulate, H);
     return hipGetLastError();
 }
 
@@ -604,7 +585,9 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int b = blockIdx.x;
+    const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
+    if (b < 0)
+        return;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
     const int g0 = bn.bgptr[b], ngb = bn.bgptr[b + 1] - g0;
     const int P = g.P, nsub = P >> 4;
@@ -835,7 +818,7 @@ static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, co
         hipFuncSetAttribute((const void *)k_batch<FORCE, T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_batch<FORCE, T>), dim3(g.nbatch), dim3(64 * kBatchWaves), lds, s, g, bn, b,
+    hipLaunchKernelGGL((k_batch<FORCE, T>), dim3(xcd_grid(g.nbatch)), dim3(64 * kBatchWaves), lds, s, g, bn, b,
                        static_cast<const T *>(pk), W, wscale, out);
     return hipGetLastError();
 }

@@ -59,11 +59,29 @@ __device__ __forceinline__ void cart_of(const Geo &g, const double *s, double *x
         x[k] = s[0] * g.lat[k] + s[1] * g.lat[3 + k] + s[2] * g.lat[6 + k];
 }
 
+// Batch b -> batch coordinates: tiles of bt[0] x bt[1] x bt[2] batches in
+// row-major order, batches row-major inside a tile.
 __device__ __forceinline__ void batch_coords(const Geo &g, int b, int *ib)
 {
-    ib[2] = b % g.nb[2];
-    ib[1] = (b / g.nb[2]) % g.nb[1];
-    ib[0] = b / (g.nb[2] * g.nb[1]);
+    const int tsz = g.bt[0] * g.bt[1] * g.bt[2];
+    const int t = b / tsz, w = b - t * tsz;
+    const int m1 = g.nb[1] / g.bt[1], m2 = g.nb[2] / g.bt[2];
+    const int t2 = t % m2, t1 = (t / m2) % m1, t0 = t / (m2 * m1);
+    const int w2 = w % g.bt[2], w1 = (w / g.bt[2]) % g.bt[1], w0 = w / (g.bt[2] * g.bt[1]);
+    ib[0] = t0 * g.bt[0] + w0;
+    ib[1] = t1 * g.bt[1] + w1;
+    ib[2] = t2 * g.bt[2] + w2;
+}
+
+// Batch of workgroup i among n batches starting at b0, XCD-contiguous: XCD x
+// (workgroups i = x mod kXcd) takes the x-th contiguous run of batches, so
+// the workgroups an XCD runs together share atoms and D blocks in its L2.
+// Returns -1 for the padding workgroups of a grid of kXcd * ceil(n / kXcd).
+__device__ __forceinline__ int xcd_batch(int i, int b0, int n)
+{
+    const int run = (n + kXcd - 1) / kXcd;
+    const int q = (i % kXcd) * run + i / kXcd;
+    return q < n ? b0 + q : -1;
 }
 
 // Mesh indices of point q of batch (i0, i1, i2); false outside the mesh.

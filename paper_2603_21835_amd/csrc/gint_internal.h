@@ -17,6 +17,7 @@ constexpr int kMaxRadTotal = 64;  // radials over all species (staged in LDS)
 constexpr int kMaxSpecies = 16;
 constexpr int kMaxBatchAtoms = 64;   // atoms reaching one mesh batch
 constexpr int kMaxBatchGroups = 32;  // atom groups reaching one mesh batch
+constexpr int kXcd = 8;           // XCDs: workgroup i runs on XCD i % kXcd
 constexpr int kRow = 18;          // doubles per staged (slot, point) row in LDS
 constexpr double kRTiny = 1e-12;  // |d| below this: the atom's own position
 
@@ -29,6 +30,7 @@ struct Geo {
     int N[3];
     int bs[3];
     int nb[3];
+    int bt[3];   // batches per tile along each axis (divides nb): batch ids run tile by tile
     int P;       // bs[0]*bs[1]*bs[2]
     int nbatch;  // nb[0]*nb[1]*nb[2]
     int ortho;   // lattice rows are along the cartesian axes
@@ -122,9 +124,12 @@ hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, con
 constexpr int kModeF64 = 0, kModeF32 = 1, kModeBF16 = 2, kModeF16 = 3, kModeBF16x3 = 4, kModeF16x3 = 5;
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                           int b1, const double *W, double wscale, const int *boff, int mno, void *part);
-hipError_t launch_H_rowreduce(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b,
-                              const AtomLists &al, int mno, int norb, const void *part, const int *boff,
-                              int b0, int b1, int accumulate, double *H);
+hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int natom, int npair, const int *pptr, const int *plist,
+                               const int *lptr, const int *list, const Basis &b, int mno, int norb, const void *part,
+                               int q0, int q1, int accumulate, double *H);
+hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
+                              const int *abat, const int *bptr, const int *boff, const int *pptr, const int *plist,
+                              int *lcnt, const int *lptr, int *list);
 hipError_t launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 hipError_t launch_block_count(hipStream_t s, int nbatch, const int *bptr, int *cnt);
 hipError_t launch_atom_count(hipStream_t s, long long nent, const int *ent_atom, int *acnt);

@@ -809,3 +809,105 @@ hipError_t launch_partners(hipStream_t s, const Geo &g, const Basis &b, double b
 }
 
 }  // namespace gint
+
+namespace gint {
+
+// ---------------------------------------------------------------------------
+// Block lists of the owned atom pairs, for the H reduction.
+//
+// For owned pair p = (I, J) (I the owner, J = plist[p]) the list holds, in
+// increasing batch order, one code per batch that both atoms reach: the
+// index q of block (min(ia, ja), max(ia, ja)) among the H block partials, as
+// q when ia <= ja (the block is H_IJ) or -(q + 1) when it is H_JI.  One wave
+// per pair intersects the two atoms' batch-sorted entry lists 64 at a time:
+// each lane looks its batch up in the other window (a binary search over
+// lanes), and both windows then advance past the smaller window maximum, so
+// every common batch is met exactly once.
+
+namespace {
+__device__ __forceinline__ int upper_bound_i(const int *__restrict__ a, int lo, int hi, int key)
+{
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int tri_block(int lo, int hi, int n) { return lo * n - lo * (lo - 1) / 2 + (hi - lo); }
+}  // namespace
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_pair_blocks(int natom, int npair, const int *__restrict__ aptr,
+                                                     const int *__restrict__ aent, const int *__restrict__ abat,
+                                                     const int *__restrict__ bptr, const int *__restrict__ boff,
+                                                     const int *__restrict__ pptr, const int *__restrict__ plist,
+                                                     int *__restrict__ lcnt, const int *__restrict__ lptr,
+                                                     int *__restrict__ list)
+{
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= npair)
+        return;
+    const int I = upper_bound_i(pptr, 0, natom + 1, p) - 1;
+    const int J = plist[p];
+    const int a0 = aptr[I], nA = aptr[I + 1] - a0;
+    const int c0 = aptr[J], nB = aptr[J + 1] - c0;
+    int ia0 = 0, ib0 = 0, run = 0;
+    const int out0 = FILL ? lptr[p] : 0;
+    while (ia0 < nA && ib0 < nB) {
+        const int ka = ia0 + lane, kb = ib0 + lane;
+        const int av = ka < nA ? abat[a0 + ka] : INT_MAX;
+        const int bv = kb < nB ? abat[c0 + kb] : INT_MAX;
+        const int la = min(63, nA - 1 - ia0), lb = min(63, nB - 1 - ib0);
+        const int m = min(__shfl(av, la), __shfl(bv, lb));
+        // lanes of the B window holding values < av
+        int pos = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1) {
+            const int v = __shfl(bv, pos + st - 1);
+            if (v < av)
+                pos += st;
+        }
+        const int hit_b = __shfl(bv, min(pos, 63));
+        const bool hit = av <= m && pos < 64 && hit_b == av;
+        const unsigned long long mh = __ballot(hit);
+        if (FILL) {
+            const int ebv = kb < nB ? aent[c0 + kb] : 0;
+            const int eb = __shfl(ebv, min(pos, 63));
+            if (hit) {
+                const int b = av;
+                const int base = bptr[b], nb = bptr[b + 1] - base;
+                const int ia = aent[a0 + ka] - base, ja = eb - base;
+                const int q = boff[b] + (ia <= ja ? tri_block(ia, ja, nb) : tri_block(ja, ia, nb));
+                list[out0 + run + __popcll(mh & ((1ull << lane) - 1ull))] = ia <= ja ? q : -(q + 1);
+            }
+        }
+        run += __popcll(mh);
+        ia0 += __popcll(__ballot(av <= m));
+        ib0 += __popcll(__ballot(bv <= m));
+    }
+    if (!FILL && lane == 0)
+        lcnt[p] = run;
+}
+
+hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
+                              const int *abat, const int *bptr, const int *boff, const int *pptr, const int *plist,
+                              int *lcnt, const int *lptr, int *list)
+{
+    if (npair <= 0)
+        return hipSuccess;
+    const unsigned nblk = (unsigned)((npair + 3) / 4);
+    if (list)
+        hipLaunchKernelGGL(k_pair_blocks<true>, dim3(nblk), dim3(256), 0, s, natom, npair, aptr, aent, abat, bptr,
+                           boff, pptr, plist, lcnt, lptr, list);
+    else
+        hipLaunchKernelGGL(k_pair_blocks<false>, dim3(nblk), dim3(256), 0, s, natom, npair, aptr, aent, abat, bptr,
+                           boff, pptr, plist, lcnt, lptr, list);
+    return hipGetLastError();
+}
+
+}  // namespace gint

@@ -169,3 +169,11 @@ def test_batch_invalid_arguments(lib):
     assert lib.gint_batch_ncell(None) == -1
     assert lib.gint_batch_cell(None, 0) is None
     lib.gint_batch_destroy(None)  # accepted
+
+
+def test_library_resolves_every_symbol(lib):
+    # a launcher declared but defined in another namespace shows up only at
+    # the first call; binding every symbol at load time catches it on the CPU
+    import paper_2603_21835_amd as g
+
+    ctypes.CDLL(g.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)

@@ -78,11 +78,12 @@ def test_fp32_si64_sampled(tdev, oracle_mod):
     assert dH <= 1e-6 and er <= 1e-5 and eF <= 1e-4
 
 
-# max|dH| bounds per mode (Ha) on Si-64 DZP.  Split modes carry ~16 more
-# bits per operand and must meet the 1e-6 Ha target; single-pass 16-bit
-# operands are expected to miss it (unit roundoff 2^-9 / 2^-12 per operand)
-# and are bounded only loosely here, their error being the reported result.
-MODES16 = {"bf16x3": 1e-6, "fp16x3": 1e-6, "bf16": 2e-3, "fp16": 5e-4}
+# max|dH| bounds per mode (Ha) on Si-64 DZP.  FP16 hi/lo keeps 22 bits of
+# each operand and meets the 1e-6 Ha target (measured 6.6e-8).  BF16 hi/lo
+# keeps only 16 bits (8 + 8), and misses it (measured 4.0e-6 here, 1.4e-5 at
+# Si-512); single-pass 16-bit operands (unit roundoff 2^-9 / 2^-12) miss it
+# by more.  Those bounds are loose pins of the measured error, not targets.
+MODES16 = {"fp16x3": 1e-6, "bf16x3": 2e-5, "bf16": 2e-3, "fp16": 5e-4}
 
 
 @pytest.mark.parametrize("prec", list(MODES16))
