@@ -16,7 +16,10 @@
 //           summed per atom in a fixed order (k_batch, k_force_reduce).
 //
 // MFMA lane layouts: see MM<T> in gint_device.h.
-// Orbital tiles in LDS: [atom slot][point][orbital], row pitch kRow elements.
+// Orbital tiles in LDS: H kernels [atom slot][point][orbital] (row pitch
+// kRow = 16 elements, orbital o of point p in slot o ^ (p & 15)); rho /
+// force [atom slot][16-point tile][orbital][point].  Either way the 64 lanes
+// of one operand read touch 64 consecutive elements.
 #include <hip/hip_runtime.h>
 
 #include "gint_device.h"
@@ -41,7 +44,7 @@ static unsigned xcd_grid(int n) { return (unsigned)(kXcd * ((n + kXcd - 1) / kXc
 // batch order (fixed order, no atomics), then writes H_IJ and its mirror
 // H_JI into the dense matrix, so H is exactly symmetric.
 
-template <typename T>
+template <typename T, int P>
 __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
                                                  double wscale, int b0, int b1, const int *__restrict__ boff, int mno,
                                                  T *__restrict__ part)
@@ -59,7 +62,6 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
     if (b < 0)
         return;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
-    const int P = g.P;
     int ib[3];
     batch_coords(g, b, ib);
 
@@ -83,13 +85,16 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
         const int a = idx / P, p = idx % P;
         const int e = e0 + a;
         const int atom = s_atom[a];
+        // orbital o of point p at row[o ^ (p & 15)] (swizzled: the stores of
+        // consecutive points spread over the LDS banks)
         T *row = s_phi + (size_t)(a * P + p) * kRow;
+        const int swz = p & 15;
         int n[3];
         const bool valid = batch_point(g, ib, p, n);
         const DevSpecies &S = s_sp[bs.spc[atom]];
         const int zlo = valid ? S.norb : 0;
         for (int o = zlo; o < kMaxOrb; ++o)
-            row[o] = (T)0;
+            row[o ^ swz] = (T)0;
         if (valid) {
             const int io = bn.ent_img[e];
             const int cnt = bn.ent_img[e + 1] - io;
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
             double r[3];
             mesh_cart(g, n, r);
             eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
-                             row);
+                             row, swz);
         }
     }
     __syncthreads();
@@ -111,19 +116,29 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
             ja = ia;
         }
     const size_t mm = (size_t)mno * mno;
+    // this lane's points are 4 kk + lk: their weights stay in registers
+    // and the (swizzled) offsets of (point 4 kk + lk, orbital li)
+    T wl[P / 4];
+    int off[P / 4];
+#pragma unroll
+    for (int kk = 0; kk < P / 4; ++kk) {
+        const int p = 4 * kk + lk;
+        wl[kk] = (T)s_w[p];
+        off[kk] = p * kRow + (li ^ (p & 15));
+    }
     for (int k = wave; k < nblk; k += nw) {
         const T *pI = s_phi + (size_t)(ia * P) * kRow;
         const T *pJ = s_phi + (size_t)(ja * P) * kRow;
+        T av[P / 4], bv[P / 4];
+#pragma unroll
+        for (int kk = 0; kk < P / 4; ++kk) {
+            av[kk] = pI[off[kk]];
+            bv[kk] = pJ[off[kk]];
+        }
         typename MM<T>::acc acc = MM<T>::zero();
 #pragma unroll
-        for (int kk = 0; kk < kMaxP / 4; ++kk) {
-            if (4 * kk < P) {
-                const int p = 4 * kk + lk;
-                const T av = (T)s_w[p] * pI[p * kRow + li];
-                const T bv = pJ[p * kRow + li];
-                acc = MM<T>::mma(av, bv, acc);
-            }
-        }
+        for (int kk = 0; kk < P / 4; ++kk)
+            acc = MM<T>::mma(wl[kk] * av[kk], bv[kk], acc);
         const int nI = s_nor[ia], nJ = s_nor[ja];
         T *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
 #pragma unroll
@@ -244,13 +259,14 @@ __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, con
         const int a = idx / P, p = idx % P;
         const int e = e0 + a;
         const int atom = s_atom[a];
-        float *row = s_phi + (size_t)(a * P + p) * kRow;
+        float *row = s_phi + (size_t)(a * P + p) * kRow;  // swizzled as in k_H_batch
+        const int swz = p & 15;
         int n[3];
         const bool valid = batch_point(g, ib, p, n);
         const DevSpecies &S = s_sp[bs.spc[atom]];
         const int zlo = valid ? S.norb : 0;
         for (int o = zlo; o < kMaxOrb; ++o)
-            row[o] = 0.0f;
+            row[o ^ swz] = 0.0f;
         if (valid) {
             const int io = bn.ent_img[e];
             const int cnt = bn.ent_img[e + 1] - io;
@@ -258,7 +274,7 @@ __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, con
             double r[3];
             mesh_cart(g, n, r);
             eval_orbitals<float>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
-                                 r, row);
+                                 r, row, swz);
         }
     }
     __syncthreads();
@@ -270,7 +286,7 @@ __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, con
         float v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            v[j] = reg[(8 * lk + j) * kRow + li] * s_sw[8 * lk + j];
+            v[j] = reg[(8 * lk + j) * kRow + (li ^ ((8 * lk + j) & 15))] * s_sw[8 * lk + j];
         unsigned hi[8], lo[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j)
@@ -343,20 +359,29 @@ static hipError_t launch_H16_t(hipStream_t s, const Geo &g, const Bins &bn, cons
     return hipGetLastError();
 }
 
+template <typename T, int P>
+static hipError_t launch_H_batch_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
+                                   int b1, const double *W, double wscale, const int *boff, int mno, void *part)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow;
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_H_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_H_batch<T, P>), dim3(xcd_grid(b1 - b0)), dim3(512), lds, s, g, bn, b, W, wscale, b0, b1,
+                       boff, mno, static_cast<T *>(part));
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_H_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                                    int b1, const double *W, double wscale, const int *boff, int mno, void *part)
 {
-    if (b1 <= b0)
-        return hipSuccess;
-    const size_t lds = sizeof(T) * (size_t)nbmax * g.P * kRow;
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_H_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_H_batch<T>, dim3(xcd_grid(b1 - b0)), dim3(512), lds, s, g, bn, b, W, wscale, b0, b1, boff,
-                       mno, static_cast<T *>(part));
-    return hipGetLastError();
+    if (g.P == 32)
+        return launch_H_batch_p<T, 32>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    if (g.P == 16)
+        return launch_H_batch_p<T, 16>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
@@ -566,15 +591,15 @@ hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn,
 
 constexpr int kBatchWaves = 8;
 
-template <bool FORCE, typename T>
+template <bool FORCE, typename T, int P>
 __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
                                                             const double *__restrict__ W, double wscale,
                                                             double *__restrict__ out)
 {
     constexpr int NT = 64 * kBatchWaves;
-    constexpr int NS = kMaxP / 16;  // sixteen-point tiles per batch, at most
+    constexpr int NS = P / 16;  // sixteen-point tiles per batch
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P / 16][16 orbitals][16 points]
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_grank[kMaxBatchAtoms];
@@ -590,7 +615,6 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
         return;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
     const int g0 = bn.bgptr[b], ngb = bn.bgptr[b + 1] - g0;
-    const int P = g.P, nsub = P >> 4;
     int ib[3];
     batch_coords(g, b, ib);
 
@@ -622,24 +646,27 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
         const int a = idx / P, p = idx % P;
         const int e = e0 + a;
         const int atom = s_atom[a];
-        T *row = s_phi + (size_t)(a * P + p) * kRow;
+        // orbital o of this point at row[16 o]
+        T *row = s_phi + (size_t)(a * NS + (p >> 4)) * 256 + (p & 15);
         int n[3];
         const bool valid = batch_point(g, ib, p, n);
         const DevSpecies &S = s_sp[bs.spc[atom]];
         const int zlo = valid ? S.norb : 0;
         for (int o = zlo; o < kMaxOrb; ++o)
-            row[o] = (T)0;
+            row[16 * o] = (T)0;
         if (valid) {
             const int io = bn.ent_img[e];
             const int cnt = bn.ent_img[e + 1] - io;
             const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
             double r[3];
             mesh_cart(g, n, r);
-            eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
-                             row);
+            eval_orbitals<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
+                                 r, row);
         }
     }
     __syncthreads();
+    // tile s2 of atom slot x: element (orbital o, point q) at [16 o + q]
+    auto tile = [&](int x, int s2) -> const T * { return s_phi + (size_t)(x * NS + s2) * 256; };
 
     // fragment f of block (x, y) in orientation o (0: S2_XY, 1: S2_YX as A)
     auto frag = [&](int x, int y, int o) -> const T * {
@@ -656,64 +683,79 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
         for (int s2 = 0; s2 < NS; ++s2)
             rp[s2] = 0.0;
         const int nblk = nb * (nb + 1) / 2;
+        // this wave's blocks k = wave, wave + 8, ... as (ia <= ja); two
+        // fragment register sets alternate so that the next block's loads
+        // are in flight while the current block is on the matrix cores
         int ia = 0, ja = 0;
+        auto advance = [&](int &x, int &y) {
+            for (int s2 = 0; s2 < kBatchWaves; ++s2)
+                if (++y == nb) {
+                    ++x;
+                    y = x;
+                }
+        };
         for (int k = 0; k < wave; ++k)
             if (++ja == nb) {
                 ++ia;
                 ja = ia;
             }
-        T fa[4];
-        if (wave < nblk) {
-            const T *f = frag(ia, ja, 0);
+        // (the scheduling barrier keeps the loads where they are issued: plain
+        // scheduling would sink them to their first use, one block later)
+        auto load = [&](T (&f4)[4], int x, int y) {
+            const T *f = frag(x, y, 0);
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                fa[c] = f[64 * c];
-        }
-        for (int k = wave; k < nblk; k += kBatchWaves) {
-            // the next block of this wave, and its fragment
-            int na = ia, nj = ja;
-            for (int s2 = 0; s2 < kBatchWaves; ++s2)
-                if (++nj == nb) {
-                    ++na;
-                    nj = na;
-                }
-            T fn[4] = {(T)0, (T)0, (T)0, (T)0};
-            if (k + kBatchWaves < nblk) {
-                const T *f = frag(na, nj, 0);
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    fn[c] = f[64 * c];
-            }
-            const double half = (ia == ja) ? 0.5 : 1.0;
+                f4[c] = f[64 * c];
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto block = [&](const T (&f4)[4], int x, int y) {
+            const double half = (x == y) ? 0.5 : 1.0;
 #pragma unroll
             for (int s2 = 0; s2 < NS; ++s2) {
-                if (s2 < nsub) {
-                    const T *pJ = s_phi + (size_t)(ja * P + 16 * s2 + li) * kRow + lk;
-                    typename MM<T>::acc u = MM<T>::zero();
-                    u = MM<T>::mma(fa[0], pJ[0], u);
-                    u = MM<T>::mma(fa[1], pJ[4], u);
-                    u = MM<T>::mma(fa[2], pJ[8], u);
-                    u = MM<T>::mma(fa[3], pJ[12], u);
-                    const T *pI = s_phi + (size_t)(ia * P + 16 * s2 + li) * kRow;
-                    double dot = 0.0;
+                // B[k][j] = phi_y(orbital 4c + k, point j): k = lk, j = li
+                const T *pJ = tile(y, s2) + 16 * lk + li;
+                typename MM<T>::acc u = MM<T>::zero();
+                u = MM<T>::mma(f4[0], pJ[0], u);
+                u = MM<T>::mma(f4[1], pJ[64], u);
+                u = MM<T>::mma(f4[2], pJ[128], u);
+                u = MM<T>::mma(f4[3], pJ[192], u);
+                const T *pI = tile(x, s2) + li;
+                double dot = 0.0;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        dot += (double)u[v] * (double)pI[MM<T>::row(lk, v)];
-                    rp[s2] += half * dot;
-                }
+                for (int v = 0; v < 4; ++v)
+                    dot += (double)u[v] * (double)pI[16 * MM<T>::row(lk, v)];
+                rp[s2] += half * dot;
             }
-            ia = na;
-            ja = nj;
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                fa[c] = fn[c];
+        };
+        // (every path issues the same loads; past the end a block's own
+        // fragment is reloaded)
+        T fa[4], fb[4];
+        if (wave < nblk) {
+            load(fa, ia, ja);
+            for (int k = wave;; k += 2 * kBatchWaves) {
+                int ib2 = ia, jb2 = ja;
+                advance(ib2, jb2);
+                const bool has_b = k + kBatchWaves < nblk;
+                load(fb, has_b ? ib2 : ia, has_b ? jb2 : ja);
+                block(fa, ia, ja);
+                if (!has_b)
+                    break;
+                ia = ib2;
+                ja = jb2;
+                advance(ia, ja);
+                const bool has_a = k + 2 * kBatchWaves < nblk;
+                load(fa, has_a ? ia : ib2, has_a ? ja : jb2);
+                block(fb, ib2, jb2);
+                if (!has_a)
+                    break;
+            }
         }
 #pragma unroll
         for (int s2 = 0; s2 < NS; ++s2) {
             double v = rp[s2];
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
-            if (lane < 16 && s2 < nsub)
+            if (lane < 16)
                 s_red[wave][16 * s2 + lane] = v;
         }
         __syncthreads();
@@ -734,35 +776,37 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
 #pragma unroll
             for (int s2 = 0; s2 < NS; ++s2)
                 Tt[s2] = MM<T>::zero();
-            T fa[4];
-            {
-                const T *f = (ia <= 0) ? frag(ia, 0, 0) : frag(0, ia, 1);
+            // T_I over every ja; fragment register sets alternate as in rho
+            auto load = [&](T (&f4)[4], int y) {
+                const T *f = (ia <= y) ? frag(ia, y, 0) : frag(y, ia, 1);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    fa[c] = f[64 * c];
-            }
-            for (int ja = 0; ja < nb; ++ja) {
-                T fn[4] = {(T)0, (T)0, (T)0, (T)0};
-                if (ja + 1 < nb) {
-                    const int jn = ja + 1;
-                    const T *f = (ia <= jn) ? frag(ia, jn, 0) : frag(jn, ia, 1);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        fn[c] = f[64 * c];
-                }
+                    f4[c] = f[64 * c];
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            auto block = [&](const T (&f4)[4], int y) {
 #pragma unroll
                 for (int s2 = 0; s2 < NS; ++s2) {
-                    if (s2 < nsub) {
-                        const T *pJ = s_phi + (size_t)(ja * P + 16 * s2 + li) * kRow + lk;
-                        Tt[s2] = MM<T>::mma(fa[0], pJ[0], Tt[s2]);
-                        Tt[s2] = MM<T>::mma(fa[1], pJ[4], Tt[s2]);
-                        Tt[s2] = MM<T>::mma(fa[2], pJ[8], Tt[s2]);
-                        Tt[s2] = MM<T>::mma(fa[3], pJ[12], Tt[s2]);
-                    }
+                    const T *pJ = tile(y, s2) + 16 * lk + li;
+                    Tt[s2] = MM<T>::mma(f4[0], pJ[0], Tt[s2]);
+                    Tt[s2] = MM<T>::mma(f4[1], pJ[64], Tt[s2]);
+                    Tt[s2] = MM<T>::mma(f4[2], pJ[128], Tt[s2]);
+                    Tt[s2] = MM<T>::mma(f4[3], pJ[192], Tt[s2]);
                 }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    fa[c] = fn[c];
+            };
+            T fa[4], fb[4];
+            load(fa, 0);
+            for (int ja = 0;; ja += 2) {
+                const bool has_b = ja + 1 < nb;
+                load(fb, has_b ? ja + 1 : ja);
+                block(fa, ja);
+                if (!has_b)
+                    break;
+                const bool has_a = ja + 2 < nb;
+                load(fa, has_a ? ja + 2 : ja + 1);
+                block(fb, ja + 1);
+                if (!has_a)
+                    break;
             }
             // gradients of orbitals row(lk, v) of atom I at point 16 s + li
             const int e = e0 + ia;
@@ -770,23 +814,27 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
             const double X[3] = {bs.xw[3 * I], bs.xw[3 * I + 1], bs.xw[3 * I + 2]};
             const int io = bn.ent_img[e];
             double fx[3] = {0.0, 0.0, 0.0};
-#pragma unroll
+            // one tile at a time (the gradient code is large): select its T
+#pragma unroll 1
             for (int s2 = 0; s2 < NS; ++s2) {
-                if (s2 < nsub) {
-                    int n[3];
-                    const bool pvalid = batch_point(g, ib, 16 * s2 + li, n);
-                    double r[3];
-                    mesh_cart(g, n, r);
-                    const int cnt = pvalid ? bn.ent_img[e + 1] - io : 0;
-                    double gr[3][4];
-                    grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
-                          MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), gr);
-                    const double wp = s_w[16 * s2 + li];
+                typename MM<T>::acc Tc = Tt[0];
 #pragma unroll
-                    for (int x = 0; x < 3; ++x)
-                        fx[x] += wp * ((double)Tt[s2][0] * gr[x][0] + (double)Tt[s2][1] * gr[x][1] +
-                                       (double)Tt[s2][2] * gr[x][2] + (double)Tt[s2][3] * gr[x][3]);
-                }
+                for (int q = 1; q < NS; ++q)
+                    if (q == s2)
+                        Tc = Tt[q];
+                int n[3];
+                const bool pvalid = batch_point(g, ib, 16 * s2 + li, n);
+                double r[3];
+                mesh_cart(g, n, r);
+                const int cnt = pvalid ? bn.ent_img[e + 1] - io : 0;
+                double gr[3][4];
+                grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                      MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), gr);
+                const double wp = s_w[16 * s2 + li];
+#pragma unroll
+                for (int x = 0; x < 3; ++x)
+                    fx[x] += wp * ((double)Tc[0] * gr[x][0] + (double)Tc[1] * gr[x][1] + (double)Tc[2] * gr[x][2] +
+                                   (double)Tc[3] * gr[x][3]);
             }
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
@@ -807,20 +855,31 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
     }
 }
 
-size_t batch_lds_bytes(int nbmax, int P, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * P * kRow; }
+size_t batch_lds_bytes(int nbmax, int P, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * P * kMaxOrb; }
+
+template <bool FORCE, typename T, int P>
+static hipError_t launch_batch_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                                 const void *pk, const double *W, double wscale, double *out)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
+    hipError_t e = hipFuncSetAttribute((const void *)k_batch<FORCE, T, P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_batch<FORCE, T, P>), dim3(xcd_grid(g.nbatch)), dim3(64 * kBatchWaves), lds, s, g, bn, b,
+                       static_cast<const T *>(pk), W, wscale, out);
+    return hipGetLastError();
+}
 
 template <bool FORCE, typename T>
 static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                  const void *pk, const double *W, double wscale, double *out)
 {
-    const size_t lds = sizeof(T) * (size_t)nbmax * g.P * kRow;
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_batch<FORCE, T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((k_batch<FORCE, T>), dim3(xcd_grid(g.nbatch)), dim3(64 * kBatchWaves), lds, s, g, bn, b,
-                       static_cast<const T *>(pk), W, wscale, out);
-    return hipGetLastError();
+    if (g.P == 32)
+        return launch_batch_p<FORCE, T, 32>(s, g, bn, b, nbmax, pk, W, wscale, out);
+    if (g.P == 16)
+        return launch_batch_p<FORCE, T, 16>(s, g, bn, b, nbmax, pk, W, wscale, out);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,

@@ -155,12 +155,12 @@ __device__ __forceinline__ int spline_interval(const DevRadial &R, double rr, do
 // of one atom reach a point only in cells smaller than the cutoff sphere).
 // pk0 is the first packed image; further ones are read from img[ioff + i].
 // The radial loop is unrolled by 8 so that all spline-coefficient loads of
-// an image are in flight together.
-template <typename T>
+// an image are in flight together.  Orbital o goes to row[(o ^ swz) * ST].
+template <typename T, int ST = 1>
 __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__restrict__ rads, int k0, int k1,
                                               double rc, const double *__restrict__ coef, const double *X,
                                               int icnt, int pk0, int ioff, const int *__restrict__ img,
-                                              const double *r, T *row)
+                                              const double *r, T *row, int swz = 0)
 {
     const double rc2 = rc * rc;
     for (int i = 0; i < icnt; ++i) {
@@ -209,20 +209,20 @@ __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__r
                 const double f = c01[u].x + t * (c01[u].y + t * (c23[u].x + t * c23[u].y));
                 if (l == 0) {
                     const double v = f * Y_C00;
-                    row[o] = add ? (T)(row[o] + v) : (T)v;
+                    row[(o ^ swz) * ST] = add ? (T)(row[(o ^ swz) * ST] + v) : (T)v;
                 } else if (l == 1) {
                     // phi_1m vanishes at the centre (u = 0 there)
                     const double Y[3] = {Y_C1 * uy, Y_C1 * uz, Y_C1 * ux};
 #pragma unroll
                     for (int m = 0; m < 3; ++m)
-                        row[o + m] = add ? (T)(row[o + m] + f * Y[m]) : (T)(f * Y[m]);
+                        row[((o + m) ^ swz) * ST] = add ? (T)(row[((o + m) ^ swz) * ST] + f * Y[m]) : (T)(f * Y[m]);
                 } else {
                     // phi_2m vanishes at the centre
                     const double Y[5] = {Y_C2 * ux * uy, Y_C2 * uy * uz, Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy),
                                          Y_C2 * ux * uz, Y_C22 * (ux * ux - uy * uy)};
 #pragma unroll
                     for (int m = 0; m < 5; ++m)
-                        row[o + m] = add ? (T)(row[o + m] + f * Y[m]) : (T)(f * Y[m]);
+                        row[((o + m) ^ swz) * ST] = add ? (T)(row[((o + m) ^ swz) * ST] + f * Y[m]) : (T)(f * Y[m]);
                 }
             }
         }

@@ -18,7 +18,7 @@ constexpr int kMaxSpecies = 16;
 constexpr int kMaxBatchAtoms = 64;   // atoms reaching one mesh batch
 constexpr int kMaxBatchGroups = 32;  // atom groups reaching one mesh batch
 constexpr int kXcd = 8;           // XCDs: workgroup i runs on XCD i % kXcd
-constexpr int kRow = 18;          // doubles per staged (slot, point) row in LDS
+constexpr int kRow = 16;          // elements per staged (slot, point) row in LDS (H kernels)
 constexpr double kRTiny = 1e-12;  // |d| below this: the atom's own position
 
 // Mesh, lattice and batch shape.  Batches tile the mesh with bs[0] x bs[1] x
