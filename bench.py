@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
     ap.add_argument("--only", default=None, choices=["H", "rho", "force"],
                     help="time one contraction only (short profiler runs)")
+    ap.add_argument("--separate", action="store_true",
+                    help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -233,10 +235,13 @@ def main():
             plan.set_positions(w.positions)
         if args.only in (None, "H"):
             plan.build_H(V, out=H)
-        if args.only in (None, "rho"):
-            plan.build_rho(D, out=rho)
-        if args.only in (None, "force"):
-            plan.force(V, D, out=F)
+        if args.only is None and not args.separate:
+            plan.rho_force(V, D, rho=rho, out=F)  # rho from the force pass
+        else:
+            if args.only in (None, "rho"):
+                plan.build_rho(D, out=rho)
+            if args.only in (None, "force"):
+                plan.force(V, D, out=F)
 
     _progress(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -258,7 +263,8 @@ def main():
 
     s1, s2 = work["sum_ng"], work["sum_ng2"]
     # algorithmic work per step (per unit: one mesh point with n_g orbitals)
-    flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1}
+    flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1,
+             "rho_force": 2 * s2 + 8 * s1}
     # the H reduction moves every block partial once and writes H's blocks
     hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
               "H_fill": 8 * plan.norb ** 2}
@@ -318,7 +324,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh {'x'.join(map(str, w.grid))}, "
-                        "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR",
+                        "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR"
+                        + (" (rho and dE/dR as two passes)" if args.separate else " (rho from the force pass)"),
             "batch": list(work["batch"]), "h_slabs": work["nslab"], "group_pairs": work["npair"],
             "sum_ng2": s2, "sum_ng": s1,
         },

@@ -172,6 +172,14 @@ gint_status gint_force(gint_plan plan, const double *W_dev, const double *D_dev,
 gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const double *D_dev,
                                 double *dEdR_dev);
 
+/* rho and the gradient of E = dV sum_g W_g rho_g in one pass over the mesh:
+ * the force's T_I = sum_J (D + D^T)_IJ phit_J also gives
+ * rho_g = 1/2 sum_I phit_I(r_g) . T_I(r_g), so rho costs one dot product per
+ * (point, atom) on top of the force.  Arguments as gint_build_rho and
+ * gint_force; rho_dev and dEdR_dev are both overwritten. */
+gint_status gint_rho_force(gint_plan plan, const double *W_dev, const double *D_dev, double *rho_dev,
+                           double *dEdR_dev);
+
 /* Kernel classes reported by gint_plan_timing. */
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
@@ -182,7 +190,8 @@ enum {
     GINT_K_FORCE = 5,     /* force contraction (one workgroup per mesh batch)       */
     GINT_K_F_REDUCE = 6,  /* force reduction per atom                               */
     GINT_K_H_FILL = 7,    /* zero fill of dense H                                   */
-    GINT_NKERNEL = 8
+    GINT_K_RHO_FORCE = 8, /* rho and force contraction in one pass                  */
+    GINT_NKERNEL = 9
 };
 
 /* Enable (1) or disable (0) timing: each kernel launch of later calls is

@@ -30,11 +30,11 @@ EXPORTS = (
     "gint_build_H", "gint_build_H_weighted", "gint_build_rho", "gint_force",
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
-    "gint_plan_set_timing", "gint_plan_timing",
+    "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
-KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill")
+KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force")
 
 
 class GintError(RuntimeError):
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("gint_force", "gint_force_weighted"):
         getattr(lib, name).restype = st
         getattr(lib, name).argtypes = [P, P, P, P]
+    lib.gint_rho_force.restype = st
+    lib.gint_rho_force.argtypes = [P, P, P, P, P]
     lib.gint_plan_sync.restype = st
     lib.gint_plan_sync.argtypes = [P]
     lib.gint_plan_work.restype = st
@@ -326,6 +328,21 @@ class GintPlan:
         fn = self._lib.gint_force_weighted if weighted else self._lib.gint_force
         _check(fn(self._handle(), wp, dp, op))
         return out
+
+    def rho_force(self, W, D, rho=None, out=None):
+        """(rho, dE/dR) in one pass: E = dV sum W rho."""
+        import torch
+
+        wp = _dev_ptr(W, self.ngrid, "W")
+        dp = _dev_ptr(D, self.norb * self.norb, "D")
+        if rho is None:
+            rho = torch.empty(self.ngrid, dtype=torch.float64, device=W.device)
+        if out is None:
+            out = torch.empty((self.natom, 3), dtype=torch.float64, device=W.device)
+        rp = _dev_ptr(rho, self.ngrid, "rho")
+        op = _dev_ptr(out, self.natom * 3, "dEdR")
+        _check(self._lib.gint_rho_force(self._handle(), wp, dp, rp, op))
+        return rho, out
 
 
 def build_H(plan: GintPlan, V, out=None):

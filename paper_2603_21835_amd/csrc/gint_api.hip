@@ -915,7 +915,8 @@ gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
     return GINT_OK;
 }
 
-static gint_status force_impl(gint_plan p, const double *W, double wscale, const double *D, double *dEdR)
+static gint_status force_impl(gint_plan p, const double *W, double wscale, const double *D, double *dEdR,
+                              double *rho = nullptr)
 {
     STCHK(check_plan(p));
     if (!W || !D || !dEdR)
@@ -926,9 +927,9 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
     STCHK(timed(p, GINT_K_PACK, [&] {
         return launch_pack_S2(p->stream, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
     }));
-    STCHK(timed(p, GINT_K_FORCE, [&] {
+    STCHK(timed(p, rho ? GINT_K_RHO_FORCE : GINT_K_FORCE, [&] {
         return launch_force_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, p->S2pk.p, W, wscale,
-                                  p->Fent.as<double>());
+                                  p->Fent.as<double>(), rho);
     }));
     STCHK(timed(p, GINT_K_F_REDUCE,
                 [&] { return launch_force_reduce(p->stream, p->geo, bn, B, p->Fent.as<double>(), dEdR); }));
@@ -944,6 +945,14 @@ gint_status gint_force(gint_plan p, const double *W_dev, const double *D_dev, do
 gint_status gint_force_weighted(gint_plan p, const double *w_dev, const double *D_dev, double *dEdR_dev)
 {
     return force_impl(p, w_dev, 1.0, D_dev, dEdR_dev);
+}
+
+gint_status gint_rho_force(gint_plan p, const double *W_dev, const double *D_dev, double *rho_dev, double *dEdR_dev)
+{
+    STCHK(check_plan(p));
+    if (!rho_dev)
+        return fail(GINT_EINVAL, "rho must be a non-NULL device pointer");
+    return force_impl(p, W_dev, p->dV, D_dev, dEdR_dev, rho_dev);
 }
 
 gint_status gint_plan_sync(gint_plan p)

@@ -29,6 +29,19 @@ namespace gint {
 // workgroups for n batches dispatched XCD-contiguously (xcd_batch)
 static unsigned xcd_grid(int n) { return (unsigned)(kXcd * ((n + kXcd - 1) / kXcd)); }
 
+// Advance (ia, ja) by st places in the row-major order of the pairs
+// ia <= ja < nb (row ia holds ja = ia .. nb-1).
+__device__ __forceinline__ void tri_advance(int &ia, int &ja, int st, int nb)
+{
+    ja += st;
+    while (ja >= nb && ia < nb) {
+        ++ia;
+        ja += ia - nb;
+    }
+}
+
+constexpr int kHWaves = 16;  // waves of the H block kernels
+
 // ---------------------------------------------------------------------------
 // H^loc, point-stationary.
 //
@@ -45,7 +58,7 @@ static unsigned xcd_grid(int n) { return (unsigned)(kXcd * ((n + kXcd - 1) / kXc
 // H_JI into the dense matrix, so H is exactly symmetric.
 
 template <typename T, int P>
-__global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
+__global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
                                                  double wscale, int b0, int b1, const int *__restrict__ boff, int mno,
                                                  T *__restrict__ part)
 {
@@ -110,11 +123,7 @@ __global__ __launch_bounds__(512) void k_H_batch(Geo g, Bins bn, Basis bs, const
     // ---- every block (ia <= ja), round-robin over the waves ----
     const int nblk = nb * (nb + 1) / 2;
     int ia = 0, ja = 0;
-    for (int k = 0; k < wave; ++k)
-        if (++ja == nb) {
-            ++ia;
-            ja = ia;
-        }
+    tri_advance(ia, ja, wave, nb);
     const size_t mm = (size_t)mno * mno;
     // this lane's points are 4 kk + lk: their weights stay in registers
     // and the (swizzled) offsets of (point 4 kk + lk, orbital li)
@@ -214,7 +223,7 @@ __device__ __forceinline__ f4 mma16(u4v a, u4v b, f4 c)
 }  // namespace
 
 template <bool F16, bool SPLIT>
-__global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
+__global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
                                                    double wscale, int b0, int b1, const int *__restrict__ boff,
                                                    int mno, float *__restrict__ part)
 {
@@ -310,11 +319,7 @@ __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, con
 
     const int nblk = nb * (nb + 1) / 2;
     int ia = 0, ja = 0;
-    for (int k = 0; k < wave; ++k)
-        if (++ja == nb) {
-            ++ia;
-            ja = ia;
-        }
+    tri_advance(ia, ja, wave, nb);
     const size_t mm = (size_t)mno * mno;
     const u4v *pl = reinterpret_cast<const u4v *>(s_phi);
     const int apitch = P * kRow / 4;  // u4v per atom region
@@ -337,11 +342,7 @@ __global__ __launch_bounds__(512) void k_H_batch16(Geo g, Bins bn, Basis bs, con
             if (row < nI && li < nJ)
                 o[row * mno + li] = acc[v] * kUnscale;
         }
-        for (int s2 = 0; s2 < nw; ++s2)
-            if (++ja == nb) {
-                ++ia;
-                ja = ia;
-            }
+        tri_advance(ia, ja, nw, nb);
     }
 }
 
@@ -354,7 +355,7 @@ static hipError_t launch_H16_t(hipStream_t s, const Geo &g, const Bins &bn, cons
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_H_batch16<F16, SPLIT>), dim3(xcd_grid(b1 - b0)), dim3(512), lds, s, g, bn, b, W, wscale,
+    hipLaunchKernelGGL((k_H_batch16<F16, SPLIT>), dim3(xcd_grid(b1 - b0)), dim3(64 * kHWaves), lds, s, g, bn, b, W, wscale,
                        b0, b1, boff, mno, static_cast<float *>(part));
     return hipGetLastError();
 }
@@ -368,7 +369,7 @@ static hipError_t launch_H_batch_p(hipStream_t s, const Geo &g, const Bins &bn, 
         hipFuncSetAttribute((const void *)k_H_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_H_batch<T, P>), dim3(xcd_grid(b1 - b0)), dim3(512), lds, s, g, bn, b, W, wscale, b0, b1,
+    hipLaunchKernelGGL((k_H_batch<T, P>), dim3(xcd_grid(b1 - b0)), dim3(64 * kHWaves), lds, s, g, bn, b, W, wscale, b0, b1,
                        boff, mno, static_cast<T *>(part));
     return hipGetLastError();
 }
@@ -589,13 +590,20 @@ hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn,
 // all P/16 sixteen-point tiles of the batch, and the next block's fragment is
 // loaded while the current one is in use.
 
-constexpr int kBatchWaves = 8;
+// waves of k_batch: rho needs few registers and runs 16 waves, the force 8
+template <int MODE>
+constexpr int batch_waves() { return MODE == 0 ? 16 : 8; }
+// what k_batch computes: rho; the force; both (the force's T_I also gives
+// rho_p = 1/2 sum_I phi_I(p) . T_I(p), since sum_IJ phi_I S2_IJ phi_J = 2 rho_p)
+constexpr int kRho = 0, kForce = 1, kRhoForce = 2;
 
-template <bool FORCE, typename T, int P>
-__global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
+template <int MODE, typename T, int P>
+__global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
                                                             const double *__restrict__ W, double wscale,
-                                                            double *__restrict__ out)
+                                                            double *__restrict__ out, double *__restrict__ rho2)
 {
+    constexpr bool FORCE = MODE != kRho, RHO = MODE != kForce;
+    constexpr int kBatchWaves = batch_waves<MODE>();
     constexpr int NT = 64 * kBatchWaves;
     constexpr int NS = P / 16;  // sixteen-point tiles per batch
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -604,7 +612,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_grank[kMaxBatchAtoms];
     __shared__ int s_ptab[kMaxBatchGroups * kMaxBatchGroups];
-    __shared__ double s_red[FORCE ? 1 : kBatchWaves][kMaxP];
+    __shared__ double s_red[RHO ? kBatchWaves : 1][kMaxP];
     __shared__ double s_w[kMaxP];
     __shared__ double s_F[FORCE ? kMaxBatchAtoms : 1][3];
 
@@ -687,18 +695,8 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
         // fragment register sets alternate so that the next block's loads
         // are in flight while the current block is on the matrix cores
         int ia = 0, ja = 0;
-        auto advance = [&](int &x, int &y) {
-            for (int s2 = 0; s2 < kBatchWaves; ++s2)
-                if (++y == nb) {
-                    ++x;
-                    y = x;
-                }
-        };
-        for (int k = 0; k < wave; ++k)
-            if (++ja == nb) {
-                ++ia;
-                ja = ia;
-            }
+        auto advance = [&](int &x, int &y) { tri_advance(x, y, kBatchWaves, nb); };
+        tri_advance(ia, ja, wave, nb);
         // (the scheduling barrier keeps the loads where they are issued: plain
         // scheduling would sink them to their first use, one block later)
         auto load = [&](T (&f4)[4], int x, int y) {
@@ -770,6 +768,10 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
         }
     } else {
         // dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p),  T_I = sum_J S2_IJ phi_J
+        double rp[NS];
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2)
+            rp[s2] = 0.0;
         for (int ia = wave; ia < nb; ia += kBatchWaves) {
             const int I = s_atom[ia];
             typename MM<T>::acc Tt[NS];
@@ -807,6 +809,17 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
                 block(fb, ja + 1);
                 if (!has_a)
                     break;
+            }
+            if (RHO) {
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) {
+                    const T *pI = tile(ia, s2) + li;
+                    double dot = 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        dot += (double)Tt[s2][v] * (double)pI[16 * MM<T>::row(lk, v)];
+                    rp[s2] += dot;
+                }
             }
             // gradients of orbitals row(lk, v) of atom I at point 16 s + li
             const int e = e0 + ia;
@@ -849,51 +862,74 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(Geo g, Bins bn, Basi
                 s_F[ia][2] = -fx[2];
             }
         }
+        if (RHO) {
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                double v = rp[s2];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lane < 16)
+                    s_red[wave][16 * s2 + lane] = v;
+            }
+        }
         __syncthreads();
         for (int k = tid; k < nb * 3; k += NT)
             out[(size_t)(e0 + k / 3) * 3 + k % 3] = s_F[k / 3][k % 3];
+        if (RHO)
+            for (int p = tid; p < P; p += NT) {
+                int n[3];
+                if (batch_point(g, ib, p, n)) {
+                    double v = s_red[0][p];
+                    for (int w = 1; w < kBatchWaves; ++w)
+                        v += s_red[w][p];
+                    rho2[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = 0.5 * v;
+                }
+            }
     }
 }
 
 size_t batch_lds_bytes(int nbmax, int P, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * P * kMaxOrb; }
 
-template <bool FORCE, typename T, int P>
+template <int MODE, typename T, int P>
 static hipError_t launch_batch_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                                 const void *pk, const double *W, double wscale, double *out)
+                                 const void *pk, const double *W, double wscale, double *out, double *rho2)
 {
     const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch<FORCE, T, P>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_batch<MODE, T, P>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_batch<FORCE, T, P>), dim3(xcd_grid(g.nbatch)), dim3(64 * kBatchWaves), lds, s, g, bn, b,
-                       static_cast<const T *>(pk), W, wscale, out);
+    hipLaunchKernelGGL((k_batch<MODE, T, P>), dim3(xcd_grid(g.nbatch)), dim3(64 * batch_waves<MODE>()), lds, s, g, bn, b,
+                       static_cast<const T *>(pk), W, wscale, out, rho2);
     return hipGetLastError();
 }
 
-template <bool FORCE, typename T>
+template <int MODE, typename T>
 static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                                 const void *pk, const double *W, double wscale, double *out)
+                                 const void *pk, const double *W, double wscale, double *out, double *rho2)
 {
     if (g.P == 32)
-        return launch_batch_p<FORCE, T, 32>(s, g, bn, b, nbmax, pk, W, wscale, out);
+        return launch_batch_p<MODE, T, 32>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
     if (g.P == 16)
-        return launch_batch_p<FORCE, T, 16>(s, g, bn, b, nbmax, pk, W, wscale, out);
+        return launch_batch_p<MODE, T, 16>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                             const void *pk, double *rho)
 {
-    return f32 ? launch_batch_t<false, float>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho)
-               : launch_batch_t<false, double>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho);
+    return f32 ? launch_batch_t<kRho, float>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho, nullptr)
+               : launch_batch_t<kRho, double>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho, nullptr);
 }
 
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              const void *pk, const double *W, double wscale, double *Fent)
+                              const void *pk, const double *W, double wscale, double *Fent, double *rho)
 {
-    return f32 ? launch_batch_t<true, float>(s, g, bn, b, nbmax, pk, W, wscale, Fent)
-               : launch_batch_t<true, double>(s, g, bn, b, nbmax, pk, W, wscale, Fent);
+    if (rho)
+        return f32 ? launch_batch_t<kRhoForce, float>(s, g, bn, b, nbmax, pk, W, wscale, Fent, rho)
+                   : launch_batch_t<kRhoForce, double>(s, g, bn, b, nbmax, pk, W, wscale, Fent, rho);
+    return f32 ? launch_batch_t<kForce, float>(s, g, bn, b, nbmax, pk, W, wscale, Fent, nullptr)
+               : launch_batch_t<kForce, double>(s, g, bn, b, nbmax, pk, W, wscale, Fent, nullptr);
 }
 
 // dE/dR per atom: fixed-order sum of its per-(batch, atom) partials over the

@@ -143,7 +143,8 @@ size_t batch_lds_bytes(int nbmax, int P, bool f32);
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                             const void *pk, double *rho);
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              const void *pk, const double *W, double wscale, double *Fent);
+                              const void *pk, const double *W, double wscale, double *Fent,
+                              double *rho /* NULL, or rho as well */);
 hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
                                const double *Fent, double *dEdR);
 hipError_t launch_max_i32(hipStream_t s, const int *a, long long n, int *out);

@@ -218,3 +218,43 @@ def test_si512_sampled(oracle_mod, torch_dev):
     assert np.array_equal(H, H.T)
     E = plan.dV * float(np.dot(w.V, rho))
     assert abs(E - np.sum(w.D * H)) <= 1e-11 * np.sum(np.abs(w.D * H))
+
+
+@pytest.mark.parametrize("make", [_triclinic_two_species, _ragged_five_atoms, _long_range_tiny])
+def test_rho_force_fused(oracle_mod, torch_dev, make):
+    # gint_rho_force: rho from the force pass (1/2 sum_I phi_I . T_I)
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = make()
+    _say(f"case rho_force {make.__name__}")
+    plan = g.GintPlan.from_workload(w)
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    rho, F = plan.rho_force(V, D)
+    rho, F = rho.cpu().numpy(), F.cpu().numpy()
+    o = oracle_mod.Oracle.from_workload(w)
+    er, eF = _rel_l2(rho, o.rho(w.D)), _rel_max(F, o.force(w.V, w.D))
+    _say(f"  rho {er:.2e}  F {eF:.2e}")
+    assert er <= TOL and eF <= TOL
+    # the force part is the same kernel path as gint_force: identical bits
+    assert np.array_equal(F, plan.force(V, D).cpu().numpy())
+
+
+def test_rho_force_si512_sampled(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si512_dzp()
+    _say("case rho_force si512")
+    plan = g.GintPlan.from_workload(w)
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    rho, F = plan.rho_force(V, D)
+    rho2 = plan.build_rho(D)
+    d = float(torch.linalg.norm(rho - rho2) / torch.linalg.norm(rho2))
+    _say(f"  fused vs separate rho: {d:.2e}")
+    assert d <= 1e-13
+    o = oracle_mod.Oracle.from_workload(w)
+    idx = np.random.default_rng(2).choice(w.ngrid, 5000, replace=False)
+    er = _rel_l2(rho.cpu().numpy()[idx], o.rho(w.D, idx))
+    _say(f"  rho sampled: {er:.2e}")
+    assert er <= TOL
