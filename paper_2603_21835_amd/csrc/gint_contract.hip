@@ -590,9 +590,9 @@ hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn,
 // all P/16 sixteen-point tiles of the batch, and the next block's fragment is
 // loaded while the current one is in use.
 
-// waves of k_batch: rho needs few registers and runs 16 waves, the force 8
+// waves of k_batch (one workgroup per CU): rho 16, the force (more registers) 12
 template <int MODE>
-constexpr int batch_waves() { return MODE == 0 ? 16 : 8; }
+constexpr int batch_waves() { return MODE == 0 ? 16 : 12; }
 // what k_batch computes: rho; the force; both (the force's T_I also gives
 // rho_p = 1/2 sum_I phi_I(p) . T_I(p), since sum_IJ phi_I S2_IJ phi_J = 2 rho_p)
 constexpr int kRho = 0, kForce = 1, kRhoForce = 2;
@@ -810,17 +810,6 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                 if (!has_a)
                     break;
             }
-            if (RHO) {
-#pragma unroll
-                for (int s2 = 0; s2 < NS; ++s2) {
-                    const T *pI = tile(ia, s2) + li;
-                    double dot = 0.0;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        dot += (double)Tt[s2][v] * (double)pI[16 * MM<T>::row(lk, v)];
-                    rp[s2] += dot;
-                }
-            }
             // gradients of orbitals row(lk, v) of atom I at point 16 s + li
             const int e = e0 + ia;
             const DevSpecies &S = s_sp[bs.spc[I]];
@@ -835,19 +824,27 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                 for (int q = 1; q < NS; ++q)
                     if (q == s2)
                         Tc = Tt[q];
+                if (RHO) {
+                    const T *pI = tile(ia, s2) + li;
+                    double dot = 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        dot += (double)Tc[v] * (double)pI[16 * MM<T>::row(lk, v)];
+#pragma unroll
+                    for (int q = 0; q < NS; ++q)
+                        if (q == s2)
+                            rp[q] += dot;
+                }
                 int n[3];
                 const bool pvalid = batch_point(g, ib, 16 * s2 + li, n);
                 double r[3];
                 mesh_cart(g, n, r);
                 const int cnt = pvalid ? bn.ent_img[e + 1] - io : 0;
-                double gr[3][4];
-                grad4(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
-                      MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), gr);
                 const double wp = s_w[16 * s2 + li];
-#pragma unroll
-                for (int x = 0; x < 3; ++x)
-                    fx[x] += wp * ((double)Tc[0] * gr[x][0] + (double)Tc[1] * gr[x][1] + (double)Tc[2] * gr[x][2] +
-                                   (double)Tc[3] * gr[x][3]);
+                const double wv[4] = {wp * (double)Tc[0], wp * (double)Tc[1], wp * (double)Tc[2],
+                                      wp * (double)Tc[3]};
+                grad4_dot(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                          MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), wv, fx);
             }
 #pragma unroll
             for (int x = 0; x < 3; ++x) {

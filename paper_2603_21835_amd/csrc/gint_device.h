@@ -347,4 +347,126 @@ __device__ __forceinline__ void grad4(const Geo &g, const DevRadial *__restrict_
     }
 }
 
+// sum_v wv[v] grad phit_{o_v}(r) for four orbitals o_v = o0 + step v
+// (v < 4; zero for o_v >= norb) of one atom at point r, summed over the
+// listed images, added to fx.  orb_rad[o] is the radial (index into rads)
+// owning orbital o, orb_m[o] its m.  Used where each lane holds exactly the
+// orbitals of its MFMA result rows.
+__device__ __forceinline__ void grad4_dot(const Geo &g, const DevRadial *__restrict__ rads,
+                                          const signed char *__restrict__ orb_rad,
+                                          const signed char *__restrict__ orb_m, int norb, double rc,
+                                          const double *__restrict__ coef, const double *X, int icnt, int pk0,
+                                          int ioff, const int *__restrict__ img, const double *r, int o0, int step,
+                                          const double *wv, double *fx)
+{
+    const double rc2 = rc * rc;
+    for (int i = 0; i < icnt; ++i) {
+        const int pk = (i == 0) ? pk0 : img[ioff + i];
+        int n[3];
+        unpack_image(pk, n);
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            d[k] = r[k] - (X[k] + n[0] * g.lat[k] + n[1] * g.lat[3 + k] + n[2] * g.lat[6 + k]);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(r2 < rc2))
+            continue;
+        const bool tiny = r2 < kRTiny * kRTiny;
+        double ir = 0.0, rr = 0.0;
+        if (!tiny) {
+            ir = rsqrt_f64(r2);
+            rr = r2 * ir;
+        }
+        const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
+        // two orbitals at a time (fewer live coefficient registers)
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+        const double wh[2] = {h ? wv[2] : wv[0], h ? wv[3] : wv[1]};
+        double2 c01[2], c23[2];
+        double tt[2];
+        int lv[2], mv[2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int o = o0 + step * (2 * h + v);
+            c01[v] = double2{0.0, 0.0};
+            c23[v] = double2{0.0, 0.0};
+            tt[v] = 0.0;
+            lv[v] = -1;
+            mv[v] = 0;
+            if (o < norb) {
+                const DevRadial R = rads[orb_rad[o]];
+                lv[v] = R.l;
+                mv[v] = orb_m[o];
+                if (rr < R.rc) {
+                    const int iv = spline_interval(R, rr, &tt[v]);
+                    c01[v] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
+                    c23[v] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            if (lv[v] < 0)
+                continue;
+            const double t = tt[v];
+            const double f = c01[v].x + t * (c01[v].y + t * (c23[v].x + t * c23[v].y));
+            const double fp = c01[v].y + t * (2.0 * c23[v].x + t * 3.0 * c23[v].y);
+            const int m = mv[v];
+            double Y, G0, G1, G2;
+            if (lv[v] == 0) {
+                Y = Y_C00;
+                G0 = G1 = G2 = 0.0;
+            } else if (lv[v] == 1) {
+                // m = -1, 0, 1 -> y, z, x
+                Y = Y_C1 * (m == -1 ? uy : (m == 0 ? uz : ux));
+                G0 = (m == 1) ? Y_C1 : 0.0;
+                G1 = (m == -1) ? Y_C1 : 0.0;
+                G2 = (m == 0) ? Y_C1 : 0.0;
+            } else {
+                if (m == -2) {
+                    Y = Y_C2 * ux * uy;
+                    G0 = Y_C2 * uy;
+                    G1 = Y_C2 * ux;
+                    G2 = 0.0;
+                } else if (m == -1) {
+                    Y = Y_C2 * uy * uz;
+                    G0 = 0.0;
+                    G1 = Y_C2 * uz;
+                    G2 = Y_C2 * uy;
+                } else if (m == 0) {
+                    Y = Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy);
+                    G0 = -2.0 * Y_C20 * ux;
+                    G1 = -2.0 * Y_C20 * uy;
+                    G2 = 4.0 * Y_C20 * uz;
+                } else if (m == 1) {
+                    Y = Y_C2 * ux * uz;
+                    G0 = Y_C2 * uz;
+                    G1 = 0.0;
+                    G2 = Y_C2 * ux;
+                } else {
+                    Y = Y_C22 * (ux * ux - uy * uy);
+                    G0 = 2.0 * Y_C22 * ux;
+                    G1 = -2.0 * Y_C22 * uy;
+                    G2 = 0.0;
+                }
+            }
+            if (tiny) {
+                // only p orbitals keep a gradient at the centre: f'(0) C1 e_m
+                if (lv[v] == 1) {
+                    fx[0] += wh[v] * (fp * G0);
+                    fx[1] += wh[v] * (fp * G1);
+                    fx[2] += wh[v] * (fp * G2);
+                }
+                continue;
+            }
+            const double fr = f * ir;
+            const double lY = lv[v] * Y;
+            fx[0] += wh[v] * (fp * Y * ux + fr * (G0 - lY * ux));
+            fx[1] += wh[v] * (fp * Y * uy + fr * (G1 - lY * uy));
+            fx[2] += wh[v] * (fp * Y * uz + fr * (G2 - lY * uz));
+        }
+        }
+    }
+}
+
 }  // namespace gint

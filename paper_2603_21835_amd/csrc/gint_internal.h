@@ -106,10 +106,11 @@ hipError_t launch_bin_fill(hipStream_t s, const Geo &g, const Basis &b, const in
                            int *bgrp);
 hipError_t launch_scan_i32(hipStream_t s, const int *in, long long n, int *out);
 hipError_t launch_scan_i64(hipStream_t s, const long long *in, long long n, long long *out);
+int group_chunks(const Geo &g);  // chunks of the per-group batch list construction
 hipError_t launch_group_count(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
-                              int *gcnt);
-hipError_t launch_group_fill(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
-                             const int *gptr, int *gbatch);
+                              int *cnt /* ngroup * group_chunks */);
+hipError_t launch_group_fill(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp, const int *off,
+                             int *gbatch, int *gptr);
 hipError_t launch_fill_i32(hipStream_t s, int *p, long long n, int v);
 hipError_t launch_pair_mark(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
                             int *mark);
@@ -132,7 +133,8 @@ hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *ap
                               int *lcnt, const int *lptr, int *list);
 hipError_t launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 hipError_t launch_block_count(hipStream_t s, int nbatch, const int *bptr, int *cnt);
-hipError_t launch_atom_count(hipStream_t s, long long nent, const int *ent_atom, int *acnt);
+hipError_t launch_atom_count(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
+                             const int *ent_atom, int *acnt);
 hipError_t launch_atom_fill(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
                             const int *ent_atom, const int *aptr, int *aent, int *abat);
 hipError_t launch_partners(hipStream_t s, const Geo &g, const Basis &b, double brad, const int *pptr,

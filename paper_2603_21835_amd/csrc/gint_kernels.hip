@@ -441,61 +441,67 @@ __device__ __forceinline__ bool batch_has_group(const int *bgptr, const int *bgr
     return false;
 }
 
-__global__ __launch_bounds__(256) void k_group_count(Geo g, const int *__restrict__ bgptr,
-                                                     const int *__restrict__ bgrp, int *__restrict__ gcnt)
-{
-    __shared__ int red[256];
-    const int grp = blockIdx.x;
-    int c = 0;
-    for (int b = threadIdx.x; b < g.nbatch; b += 256)
-        c += batch_has_group(bgptr, bgrp, b, grp) ? 1 : 0;
-    red[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
-            red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        gcnt[grp] = red[0];
-}
+// Per-group batch lists, in increasing batch order.  The batches are cut
+// into chunks of kGroupChunk; workgroup (group, chunk) counts, then fills,
+// the chunk's batches that hold the group, so the counts scanned in
+// (group, chunk) order give every workgroup its output offset.
+constexpr int kGroupChunk = 4096;
 
-hipError_t launch_group_count(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp, int *gcnt)
-{
-    hipLaunchKernelGGL(k_group_count, dim3(g.ngroup), dim3(256), 0, s, g, bgptr, bgrp, gcnt);
-    return hipGetLastError();
-}
+int group_chunks(const Geo &g) { return (g.nbatch + kGroupChunk - 1) / kGroupChunk; }
 
-__global__ __launch_bounds__(256) void k_group_fill(Geo g, const int *__restrict__ bgptr,
-                                                    const int *__restrict__ bgrp, const int *__restrict__ gptr,
-                                                    int *__restrict__ gbatch)
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_group_lists(Geo g, int nchunk, const int *__restrict__ bgptr,
+                                                     const int *__restrict__ bgrp, int *__restrict__ cnt,
+                                                     const int *__restrict__ off, int *__restrict__ gbatch,
+                                                     int *__restrict__ gptr)
 {
     __shared__ int wcnt[4];
-    const int grp = blockIdx.x;
+    const int grp = blockIdx.x / nchunk, ch = blockIdx.x % nchunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int run = gptr[grp];
-    for (int base = 0; base < g.nbatch; base += 256) {
+    const int b0 = ch * kGroupChunk, b1 = min(b0 + kGroupChunk, g.nbatch);
+    int run = FILL ? off[blockIdx.x] : 0;
+    for (int base = b0; base < b1; base += 256) {
         const int b = base + threadIdx.x;
-        const bool keep = (b < g.nbatch) && batch_has_group(bgptr, bgrp, b, grp);
+        const bool keep = (b < b1) && batch_has_group(bgptr, bgrp, b, grp);
         const unsigned long long m = __ballot(keep);
         const int pre = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0)
             wcnt[wave] = __popcll(m);
         __syncthreads();
-        int off = 0;
+        int o = 0;
         for (int w = 0; w < wave; ++w)
-            off += wcnt[w];
-        if (keep)
-            gbatch[run + off + pre] = b;
+            o += wcnt[w];
+        if (FILL && keep)
+            gbatch[run + o + pre] = b;
         run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
         __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        if (!FILL)
+            cnt[blockIdx.x] = run;
+        else {
+            if (ch == 0)
+                gptr[grp] = off[blockIdx.x];
+            if (blockIdx.x == gridDim.x - 1)
+                gptr[g.ngroup] = off[gridDim.x];
+        }
+    }
 }
 
-hipError_t launch_group_fill(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp, const int *gptr,
-                             int *gbatch)
+hipError_t launch_group_count(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp, int *cnt)
 {
-    hipLaunchKernelGGL(k_group_fill, dim3(g.ngroup), dim3(256), 0, s, g, bgptr, bgrp, gptr, gbatch);
+    const int nc = group_chunks(g);
+    hipLaunchKernelGGL(k_group_lists<false>, dim3(g.ngroup * nc), dim3(256), 0, s, g, nc, bgptr, bgrp, cnt, nullptr,
+                       nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_fill(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp, const int *off,
+                             int *gbatch, int *gptr)
+{
+    const int nc = group_chunks(g);
+    hipLaunchKernelGGL(k_group_lists<true>, dim3(g.ngroup * nc), dim3(256), 0, s, g, nc, bgptr, bgrp, nullptr, off,
+                       gbatch, gptr);
     return hipGetLastError();
 }
 
@@ -667,33 +673,20 @@ hipError_t launch_block_count(hipStream_t s, int nbatch, const int *bptr, int *c
     return hipGetLastError();
 }
 
-// Entries per atom (integer atomics: the counts are order independent).
-__global__ void k_atom_count(long long nent, const int *__restrict__ ent_atom, int *__restrict__ acnt)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nent)
-        atomicAdd(&acnt[ent_atom[e]], 1);
-}
-
-hipError_t launch_atom_count(hipStream_t s, long long nent, const int *ent_atom, int *acnt)
-{
-    if (nent <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_atom_count, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, nent, ent_atom, acnt);
-    return hipGetLastError();
-}
-
 // Entry indices of each atom in increasing batch order: one workgroup per
 // atom scans its group's batch list and compacts in order.
+// With FILL false it only counts them into acnt (the count and fill passes
+// visit the same batches in the same way).
+template <bool FILL>
 __global__ __launch_bounds__(256) void k_atom_fill(const int *__restrict__ gptr, const int *__restrict__ gbatch,
                                                    const int *__restrict__ bptr, const int *__restrict__ ent_atom,
                                                    const int *__restrict__ aptr, int *__restrict__ aent,
-                                                   int *__restrict__ abat)
+                                                   int *__restrict__ abat, int *__restrict__ acnt)
 {
     __shared__ int wcnt[4];
     const int ii = blockIdx.x, grp = ii / kGroup;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int run = aptr[ii];
+    int run = FILL ? aptr[ii] : 0;
     for (int base = gptr[grp]; base < gptr[grp + 1]; base += 256) {
         const int k = base + threadIdx.x;
         int e = -1, b = -1;
@@ -712,19 +705,30 @@ __global__ __launch_bounds__(256) void k_atom_fill(const int *__restrict__ gptr,
         int off = 0;
         for (int w = 0; w < wave; ++w)
             off += wcnt[w];
-        if (e >= 0) {
+        if (FILL && e >= 0) {
             aent[run + off + pre] = e;
             abat[run + off + pre] = b;
         }
         run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
         __syncthreads();
     }
+    if (!FILL && threadIdx.x == 0)
+        acnt[ii] = run;
+}
+
+hipError_t launch_atom_count(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
+                             const int *ent_atom, int *acnt)
+{
+    hipLaunchKernelGGL(k_atom_fill<false>, dim3(natom), dim3(256), 0, s, gptr, gbatch, bptr, ent_atom, nullptr,
+                       nullptr, nullptr, acnt);
+    return hipGetLastError();
 }
 
 hipError_t launch_atom_fill(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
                             const int *ent_atom, const int *aptr, int *aent, int *abat)
 {
-    hipLaunchKernelGGL(k_atom_fill, dim3(natom), dim3(256), 0, s, gptr, gbatch, bptr, ent_atom, aptr, aent, abat);
+    hipLaunchKernelGGL(k_atom_fill<true>, dim3(natom), dim3(256), 0, s, gptr, gbatch, bptr, ent_atom, aptr, aent,
+                       abat, nullptr);
     return hipGetLastError();
 }
 
