@@ -95,11 +95,6 @@ struct gint_plan_s {
     double rc_max = 0.0;
     long long hbudget_req = 0;  // H partial-buffer budget in bytes (0 = automatic)
     long long nblock = 0;       // H block partials over all batches
-    // second stream of the H path: the block sums of one batch range run
-    // there while the next range's blocks are formed (two partial buffers)
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_blk[2] = {nullptr, nullptr}, ev_red[2] = {nullptr, nullptr}, ev_join = nullptr;
-    DevBuf Hpart2;
     void *ext_hpart = nullptr;  // H partial buffer lent by a batch (shared by its chain)
     size_t ext_hpart_bytes = 0;
     long long gen = 0;          // bumped whenever the lists are rebuilt
@@ -136,13 +131,6 @@ struct gint_plan_s {
 
     ~gint_plan_s()
     {
-        if (aux)
-            (void)hipStreamSynchronize(aux);
-        for (hipEvent_t e : {ev_blk[0], ev_blk[1], ev_red[0], ev_red[1], ev_join})
-            if (e)
-                (void)hipEventDestroy(e);
-        if (aux)
-            (void)hipStreamDestroy(aux);
         for (auto &m : marks) {
             (void)hipEventDestroy(m.a);
             (void)hipEventDestroy(m.b);
@@ -153,8 +141,6 @@ struct gint_plan_s {
 
     bool f32() const { return prec != GINT_FP64; }  // FP32 tiles for all but FP64
     void *hpart() const { return ext_hpart ? ext_hpart : Hpart.p; }
-    void *hpart_k(int k) const { return ext_hpart ? ext_hpart : (k ? Hpart2.p : Hpart.p); }
-    bool overlap() const { return !ext_hpart && aux && Hpart2.p && slab.size() > 2; }
     AtomLists atom_lists() const
     {
         AtomLists a;
@@ -508,15 +494,14 @@ gint_status rebuild_lists(gint_plan p, bool resort)
                                   p->lcnt.as<int>(), p->lptr.as<int>(), p->blist.as<int>());
     }));
     const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
-    const size_t blk_bytes = esz * (size_t)p->mno * p->mno;
-    // per partial buffer (two of them when the path is cut into ranges)
-    size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)8 << 30;
+    const size_t blk_bytes = esz * (size_t)block_pitch(p->mno, (int)esz);
+    size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)16 << 30;
     if (p->ext_hpart)
         budget = p->ext_hpart_bytes;
     else if (p->hbudget_req <= 0) {
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr / 6 < budget)
-            budget = fr / 6;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr / 3 < budget)
+            budget = fr / 3;
     }
     // a range holds at least one whole batch
     long long per_slab = (long long)(budget / blk_bytes);
@@ -542,8 +527,6 @@ gint_status rebuild_lists(gint_plan p, bool resort)
             return fail(GINT_ENOMEM, "a batch of the cell needs %zu bytes of H partials", blk_bytes * (size_t)most);
     } else {
         STCHK(p->Hpart.ensure(blk_bytes * (size_t)std::max(most, 1LL)));
-        if (p->slab.size() > 2)
-            STCHK(p->Hpart2.ensure(blk_bytes * (size_t)std::max(most, 1LL)));
     }
     ++p->gen;
     STCHK(p->S2pk.ensure(esz * 16 * 512 * (size_t)p->npair));
@@ -763,16 +746,6 @@ static gint_status plan_create(const double lattice[9], const int grid[3], int n
     p->stream = (hipStream_t)hip_stream;
     p->ext_hpart = ext_hpart;
     p->ext_hpart_bytes = ext_hpart_bytes;
-    if (!ext_hpart) {
-        bool ok = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) == hipSuccess;
-        for (hipEvent_t *e : {&p->ev_blk[0], &p->ev_blk[1], &p->ev_red[0], &p->ev_red[1], &p->ev_join})
-            ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
-        if (!ok) {
-            p->magic = 0;
-            delete p;
-            return fail(GINT_EDEVICE, "stream/event creation failed");
-        }
-    }
     p->prec = prec;
     p->geo = g;
     p->natom = natom;
@@ -912,31 +885,6 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_H_FILL,
                 [&] { return launch_fill_f64(p->stream, H, (long long)p->norb * p->norb, 0.0); }));
-    if (p->overlap()) {
-        // ranges alternate between two partial buffers; range i's block sums
-        // run on the second stream while range i + 1's blocks are formed
-        for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
-            const int b0 = p->slab[i], b1 = p->slab[i + 1], k = (int)(i & 1);
-            void *buf = p->hpart_k(k);
-            if (i >= 2)
-                HIPCHK(hipStreamWaitEvent(p->stream, p->ev_red[k], 0));
-            STCHK(timed(p, GINT_K_H, [&] {
-                return launch_H_batch(p->stream, (int)p->prec, p->geo, bn, B, p->nbmax, b0, b1, W, wscale,
-                                      p->boff.as<int>(), p->mno, buf);
-            }));
-            HIPCHK(hipEventRecord(p->ev_blk[k], p->stream));
-            HIPCHK(hipStreamWaitEvent(p->aux, p->ev_blk[k], 0));
-            STCHK(timed_on(p, p->aux, GINT_K_H_REDUCE, [&] {
-                return launch_H_pairreduce(p->aux, p->f32(), p->natom, p->npair_owned, p->pptr.as<int>(),
-                                           p->plist.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), B, p->mno,
-                                           p->norb, buf, p->slab_q[i], p->slab_q[i + 1], i > 0 ? 1 : 0, H);
-            }));
-            HIPCHK(hipEventRecord(p->ev_red[k], p->aux));
-        }
-        HIPCHK(hipEventRecord(p->ev_join, p->aux));
-        HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join, 0));
-        return GINT_OK;
-    }
     for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
         const int b0 = p->slab[i], b1 = p->slab[i + 1];
         STCHK(timed(p, GINT_K_H, [&] {

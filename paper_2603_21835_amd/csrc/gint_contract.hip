@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
     const int nblk = nb * (nb + 1) / 2;
     int ia = 0, ja = 0;
     tri_advance(ia, ja, wave, nb);
-    const size_t mm = (size_t)mno * mno;
+    const size_t mm = (size_t)block_pitch(mno, sizeof(T));
     // this lane's points are 4 kk + lk: their weights stay in registers
     // and the (swizzled) offsets of (point 4 kk + lk, orbital li)
     T wl[P / 4];
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
     const int nblk = nb * (nb + 1) / 2;
     int ia = 0, ja = 0;
     tri_advance(ia, ja, wave, nb);
-    const size_t mm = (size_t)mno * mno;
+    const size_t mm = (size_t)block_pitch(mno, sizeof(float));
     const u4v *pl = reinterpret_cast<const u4v *>(s_phi);
     const int apitch = P * kRow / 4;  // u4v per atom region
     for (int k = wave; k < nblk; k += nw) {
@@ -405,10 +405,31 @@ hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn,
 
 // H^loc: fixed-order sums of the block partials.  One wave per owned atom
 // pair (I, J) walks the pair's block list (batch order) restricted to the
-// batch range [b0, b1), reading each partial block whole (lane l owns
-// elements l, l + 64, ... of the row-major n_I x n_J block), and writes H_IJ
-// and its mirror H_JI (for J = I only the upper triangle, mirrored).
+// block range [q0, q1) and streams each stored block whole with 16-byte
+// loads (lane l owns stored elements V l .. V l + V - 1, V = 16 / element
+// size, and every 64 V further), summing the blocks stored as H_IJ and those
+// stored as H_JI separately, each in list order; the two sums meet through
+// LDS.  It writes H_IJ and its mirror H_JI (for J = I only the upper
+// triangle, mirrored).
 constexpr int kRedGroup = 8;  // list entries whose loads are in flight together
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    typedef double2 type;
+    static constexpr int V = 2;
+    static __device__ __forceinline__ double at(const double2 &x, int i) { return i ? x.y : x.x; }
+};
+template <>
+struct Vec16<float> {
+    typedef float4 type;
+    static constexpr int V = 4;
+    static __device__ __forceinline__ double at(const float4 &x, int i)
+    {
+        return (double)(i == 0 ? x.x : (i == 1 ? x.y : (i == 2 ? x.z : x.w)));
+    }
+};
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, const int *__restrict__ pptr,
@@ -417,9 +438,12 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
                                                       const T *__restrict__ part, int q0, int q1, int accumulate,
                                                       double *__restrict__ H)
 {
-    constexpr int M = kMaxOrb * kMaxOrb / 64;  // elements per lane
-    const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    typedef typename Vec16<T>::type VT;
+    constexpr int V = Vec16<T>::V;
+    constexpr int M = (kMaxOrb * kMaxOrb + 64 * V - 1) / (64 * V);  // vectors per lane
+    __shared__ double s_sum[4][2][kMaxOrb * kMaxOrb];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p = blockIdx.x * 4 + wv;
     if (p >= npair)
         return;
     // owner I of pair p
@@ -458,46 +482,63 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
     }
     if (accumulate && l0 == l1)
         return;
-    const int mm = mno * mno;
-    int eo[M], et[M];
-    double acc[M];
+    const int pitch = block_pitch(mno, sizeof(T));
+    double up[M][V], dn[M][V];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int e = lane + 64 * m;
-        const int r = e / mno, c = e - r * mno;
-        eo[m] = e < mm ? e : 0;
-        et[m] = e < mm ? c * mno + r : 0;
-        acc[m] = 0.0;
-    }
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            up[m][i] = dn[m][i] = 0.0;
     for (int k0 = l0; k0 < l1; k0 += kRedGroup) {
-        T v[kRedGroup][M];
+        VT v[kRedGroup][M];
+        bool isup[kRedGroup];
 #pragma unroll
         for (int g = 0; g < kRedGroup; ++g) {
             const int k = k0 + g;
             const int code = k < l1 ? list[k] : 0;
-            const bool up = code >= 0;
-            const size_t base = (size_t)((up ? code : -code - 1) - q0) * mm;
+            isup[g] = code >= 0;
+            const T *blk = part + (size_t)(qof(code) - q0) * pitch;
 #pragma unroll
-            for (int m = 0; m < M; ++m)
-                v[g][m] = (k < l1 && lane + 64 * m < mm) ? part[base + (up ? eo[m] : et[m])] : (T)0;
+            for (int m = 0; m < M; ++m) {
+                const int e = V * lane + 64 * V * m;
+                v[g][m] = (k < l1 && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
+            }
         }
 #pragma unroll
         for (int g = 0; g < kRedGroup; ++g)
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                acc[m] += (double)v[g][m];
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    const double x = Vec16<T>::at(v[g][m], i);
+                    if (isup[g])
+                        up[m][i] += x;
+                    else
+                        dn[m][i] += x;
+                }
     }
+    // H_IJ(r, c) = up(r mno + c) + dn(c mno + r)
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const int e = V * lane + 64 * V * m + i;
+            if (e < kMaxOrb * kMaxOrb) {
+                s_sum[wv][0][e] = up[m][i];
+                s_sum[wv][1][e] = dn[m][i];
+            }
+        }
     const int Iin = bs.perm[I], Jin = bs.perm[J];
     const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
     const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int e = lane + 64 * m;
+    const int mm = mno * mno;
+    for (int e = lane; e < mm; e += 64) {
         const int r = e / mno, c = e - r * mno;
-        if (e < mm && r < nI && c < nJ && !(J == I && c < r)) {
+        if (r < nI && c < nJ && !(J == I && c < r)) {
+            const double sum = s_sum[wv][0][e] + s_sum[wv][1][c * mno + r];
             const size_t i1 = (size_t)(mu0 + r) * norb + nu0 + c;
             const size_t i2 = (size_t)(nu0 + c) * norb + mu0 + r;
-            const double val = accumulate ? H[i1] + acc[m] : acc[m];
+            const double val = accumulate ? H[i1] + sum : sum;
             H[i1] = val;
             H[i2] = val;
         }

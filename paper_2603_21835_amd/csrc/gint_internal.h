@@ -121,6 +121,13 @@ hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, con
 
 // Contractions (gint_contract.hip).
 // f32 selects FP32 orbital tiles, packed D and H partials (else FP64).
+// Elements between consecutive H block partials: mno * mno rounded up to
+// 16 bytes, so that every block starts 16-byte aligned.
+__host__ __device__ inline int block_pitch(int mno, int esz)
+{
+    const int v = 16 / esz;
+    return (mno * mno + v - 1) / v * v;
+}
 // arithmetic modes of the H kernel (values of gint_precision)
 constexpr int kModeF64 = 0, kModeF32 = 1, kModeBF16 = 2, kModeF16 = 3, kModeBF16x3 = 4, kModeF16x3 = 5;
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
