@@ -62,8 +62,8 @@ def cpu_baseline(w):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
     workload and extrapolate to one full step: H rows and dE/dR of one atom
     per oracle thread (the oracle is parallel over atoms for both) summed
-    over a random quarter of the mesh points, and rho at 20000 mesh points
-    (parallel over points)."""
+    over a random half of the mesh points, and rho at 40000 mesh points
+    (parallel over points): about 10 s of host time."""
     import oracle
 
     o = oracle.Oracle.from_workload(w)
@@ -72,9 +72,9 @@ def cpu_baseline(w):
     na = min(w.natom, max(nthr, 1))
     lo = int(rng.integers(0, w.natom - na + 1))
     atoms = np.arange(lo, lo + na, dtype=np.int32)
-    npts = min(20000, w.ngrid)
+    npts = min(40000, w.ngrid)
     idx = np.sort(rng.choice(w.ngrid, npts, replace=False))
-    nsub = max(1, w.ngrid // 4)
+    nsub = max(1, w.ngrid // 2)
     sub = np.sort(rng.choice(w.ngrid, nsub, replace=False))
     t = time.perf_counter()
     o.H_rows(w.V, lo, lo + na, points=sub)
