@@ -135,19 +135,27 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
         wl[kk] = (T)s_w[p];
         off[kk] = p * kRow + (li ^ (p & 15));
     }
+    // a wave's consecutive blocks mostly share ia: its weighted operand
+    // w phi_I stays in registers until ia changes
+    int cur = -1;
+    T aw[P / 4];
     for (int k = wave; k < nblk; k += nw) {
-        const T *pI = s_phi + (size_t)(ia * P) * kRow;
-        const T *pJ = s_phi + (size_t)(ja * P) * kRow;
-        T av[P / 4], bv[P / 4];
+        if (ia != cur) {
+            const T *pI = s_phi + (size_t)(ia * P) * kRow;
 #pragma unroll
-        for (int kk = 0; kk < P / 4; ++kk) {
-            av[kk] = pI[off[kk]];
-            bv[kk] = pJ[off[kk]];
+            for (int kk = 0; kk < P / 4; ++kk)
+                aw[kk] = wl[kk] * pI[off[kk]];
+            cur = ia;
         }
+        const T *pJ = s_phi + (size_t)(ja * P) * kRow;
+        T bv[P / 4];
+#pragma unroll
+        for (int kk = 0; kk < P / 4; ++kk)
+            bv[kk] = pJ[off[kk]];
         typename MM<T>::acc acc = MM<T>::zero();
 #pragma unroll
         for (int kk = 0; kk < P / 4; ++kk)
-            acc = MM<T>::mma(wl[kk] * av[kk], bv[kk], acc);
+            acc = MM<T>::mma(aw[kk], bv[kk], acc);
         const int nI = s_nor[ia], nJ = s_nor[ja];
         T *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
 #pragma unroll
@@ -156,11 +164,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
             if (row < nI && li < nJ)
                 o[row * mno + li] = acc[v];
         }
-        for (int s = 0; s < nw; ++s)
-            if (++ja == nb) {
-                ++ia;
-                ja = ia;
-            }
+        tri_advance(ia, ja, nw, nb);
     }
 }
 
