@@ -642,7 +642,14 @@ constexpr int batch_waves() { return MODE == 0 ? 16 : 12; }
 // rho_p = 1/2 sum_I phi_I(p) . T_I(p), since sum_IJ phi_I S2_IJ phi_J = 2 rho_p)
 constexpr int kRho = 0, kForce = 1, kRhoForce = 2;
 
-template <int MODE, typename T, int P>
+// KU (force modes): 0 keeps each atom's T_I in registers only for its own
+// gradient pass (any number of atoms); KU > 0 is the two-phase form for at
+// most KU atoms per wave: T_I of every atom on the matrix cores first (each
+// wave holding the T of its atoms in registers), then T replaces phi in LDS
+// and one thread per (atom, point) evaluates all the atom's orbital
+// gradients there, so that the gradient work is spread evenly over all
+// threads and each radial's spline evaluation serves its 2l + 1 orbitals.
+template <int MODE, typename T, int P, int KU>
 __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
                                                             const double *__restrict__ W, double wscale,
                                                             double *__restrict__ out, double *__restrict__ rho2)
@@ -811,6 +818,137 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                 out[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = v;
             }
         }
+    } else if constexpr (KU > 0) {
+        // ---- phase A: T_I = sum_J S2_IJ phi_J, rho_p = 1/2 sum_I phi_I . T_I ----
+        double rp[NS];
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2)
+            rp[s2] = 0.0;
+        typename MM<T>::acc Tt[KU][NS];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2)
+                Tt[u][s2] = MM<T>::zero();
+            const int ia = wave + kBatchWaves * u;
+            if (ia >= nb)
+                continue;
+            auto load = [&](T (&f4)[4], int y) {
+                const T *f = (ia <= y) ? frag(ia, y, 0) : frag(y, ia, 1);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    f4[c] = f[64 * c];
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            auto block = [&](const T (&f4)[4], int y) {
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) {
+                    const T *pJ = tile(y, s2) + 16 * lk + li;
+                    Tt[u][s2] = MM<T>::mma(f4[0], pJ[0], Tt[u][s2]);
+                    Tt[u][s2] = MM<T>::mma(f4[1], pJ[64], Tt[u][s2]);
+                    Tt[u][s2] = MM<T>::mma(f4[2], pJ[128], Tt[u][s2]);
+                    Tt[u][s2] = MM<T>::mma(f4[3], pJ[192], Tt[u][s2]);
+                }
+            };
+            T fa[4], fb[4];
+            load(fa, 0);
+            for (int ja = 0;; ja += 2) {
+                const bool has_b = ja + 1 < nb;
+                load(fb, has_b ? ja + 1 : ja);
+                block(fa, ja);
+                if (!has_b)
+                    break;
+                const bool has_a = ja + 2 < nb;
+                load(fa, has_a ? ja + 2 : ja + 1);
+                block(fb, ja + 1);
+                if (!has_a)
+                    break;
+            }
+            if (RHO) {
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) {
+                    const T *pI = tile(ia, s2) + li;
+                    double dot = 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        dot += (double)Tt[u][s2][v] * (double)pI[16 * MM<T>::row(lk, v)];
+                    rp[s2] += dot;
+                }
+            }
+        }
+        if (RHO) {
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                double v = rp[s2];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lane < 16)
+                    s_red[wave][16 * s2 + lane] = v;
+            }
+        }
+        __syncthreads();  // every wave is done with phi
+        // T_I replaces phi_I, in the same [tile][orbital][point] layout
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int ia = wave + kBatchWaves * u;
+            if (ia >= nb)
+                continue;
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                T *t = s_phi + (size_t)(ia * NS + s2) * 256 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    t[16 * MM<T>::row(lk, v)] = Tt[u][s2][v];
+            }
+        }
+        __syncthreads();
+        // ---- phase B: dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p) ----
+        // item (atom a, point p) = a P + p: the P items of an atom are P
+        // consecutive lanes of one wave (P divides 64)
+        for (int base = wave * 64; base < nb * P; base += NT) {
+            const int idx = base + lane;
+            const int a = idx / P, p = idx % P;
+            double fx[3] = {0.0, 0.0, 0.0};
+            int n[3];
+            if (idx < nb * P && batch_point(g, ib, p, n)) {
+                const int e = e0 + a;
+                const int atom = s_atom[a];
+                const DevSpecies &S = s_sp[bs.spc[atom]];
+                const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+                const int io = bn.ent_img[e];
+                const int cnt = bn.ent_img[e + 1] - io;
+                double r[3];
+                mesh_cart(g, n, r);
+                grad_dot_all<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
+                                    r, s_phi + (size_t)(a * NS + (p >> 4)) * 256 + (p & 15), s_w[p], fx);
+            }
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                double v = fx[x];
+#pragma unroll
+                for (int o = P / 2; o > 0; o >>= 1)
+                    v += __shfl_xor(v, o);
+                fx[x] = v;
+            }
+            if (idx < nb * P && p == 0) {
+                s_F[a][0] = -fx[0];
+                s_F[a][1] = -fx[1];
+                s_F[a][2] = -fx[2];
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < nb * 3; k += NT)
+            out[(size_t)(e0 + k / 3) * 3 + k % 3] = s_F[k / 3][k % 3];
+        if (RHO)
+            for (int p = tid; p < P; p += NT) {
+                int n[3];
+                if (batch_point(g, ib, p, n)) {
+                    double v = s_red[0][p];
+                    for (int w = 1; w < kBatchWaves; ++w)
+                        v += s_red[w][p];
+                    rho2[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = 0.5 * v;
+                }
+            }
     } else {
         // dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p),  T_I = sum_J S2_IJ phi_J
         double rp[NS];
@@ -932,18 +1070,35 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
 
 size_t batch_lds_bytes(int nbmax, int P, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * P * kMaxOrb; }
 
+template <int MODE, typename T, int P, int KU>
+static hipError_t launch_batch_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                                 const void *pk, const double *W, double wscale, double *out, double *rho2)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
+    hipError_t e = hipFuncSetAttribute((const void *)k_batch<MODE, T, P, KU>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_batch<MODE, T, P, KU>), dim3(xcd_grid(g.nbatch)), dim3(64 * batch_waves<MODE>()), lds, s, g,
+                       bn, b, static_cast<const T *>(pk), W, wscale, out, rho2);
+    return hipGetLastError();
+}
+
+// force modes: the two-phase form while every wave holds at most 3 atoms
 template <int MODE, typename T, int P>
 static hipError_t launch_batch_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                  const void *pk, const double *W, double wscale, double *out, double *rho2)
 {
-    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch<MODE, T, P>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((k_batch<MODE, T, P>), dim3(xcd_grid(g.nbatch)), dim3(64 * batch_waves<MODE>()), lds, s, g, bn, b,
-                       static_cast<const T *>(pk), W, wscale, out, rho2);
-    return hipGetLastError();
+    if constexpr (MODE == kRho)
+        return launch_batch_k<MODE, T, P, 0>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    const int ku = (nbmax + batch_waves<MODE>() - 1) / batch_waves<MODE>();
+    switch (ku) {
+    case 0:
+    case 1: return launch_batch_k<MODE, T, P, 1>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    case 2: return launch_batch_k<MODE, T, P, 2>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    case 3: return launch_batch_k<MODE, T, P, 3>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    default: return launch_batch_k<MODE, T, P, 0>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    }
 }
 
 template <int MODE, typename T>

@@ -229,19 +229,20 @@ __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__r
     }
 }
 
-// Gradients of four orbitals o_v = o0 + step v (v < 4) of one atom at point r
-// (zero for o_v >= norb), summed over the listed images.  orb_rad[o] is the
-// radial (index into rads) owning orbital o, orb_m[o] its m.  Used where
-// each lane needs exactly the orbitals of its MFMA result rows.
-__device__ __forceinline__ void grad4(const Geo &g, const DevRadial *__restrict__ rads,
-                                      const signed char *__restrict__ orb_rad, const signed char *__restrict__ orb_m,
-                                      int norb, double rc, const double *__restrict__ coef, const double *X, int icnt,
-                                      int pk0, int ioff, const int *__restrict__ img, const double *r, int o0,
-                                      int step, double (*gr)[4])
+// fx += sum_o c_o grad_r phit_o(r) over every orbital of one atom at point r
+// (radials k0..k1-1 of its species), summed over the listed images, with
+// c_o = wp * crow[o * ST].  One spline evaluation (value and slope) per
+// radial serves its 2l+1 orbitals:
+//     sum_m c_m grad(f Y_m) = (f' A - l (f/r) A) u + (f/r) G,
+//     A = sum_m c_m Y_m(u),  G = sum_m c_m dY_m/du,
+// (Y_lm is a homogeneous polynomial of degree l in u, so u . dY/du = l Y).
+// At the atom's centre only p orbitals keep a gradient, f'(0) dY/du.
+template <typename T, int ST>
+__device__ __forceinline__ void grad_dot_all(const Geo &g, const DevRadial *__restrict__ rads, int k0, int k1,
+                                             double rc, const double *__restrict__ coef, const double *X, int icnt,
+                                             int pk0, int ioff, const int *__restrict__ img, const double *r,
+                                             const T *crow, double wp, double *fx)
 {
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-        gr[0][v] = gr[1][v] = gr[2][v] = 0.0;
     const double rc2 = rc * rc;
     for (int i = 0; i < icnt; ++i) {
         const int pk = (i == 0) ? pk0 : img[ioff + i];
@@ -261,88 +262,69 @@ __device__ __forceinline__ void grad4(const Geo &g, const DevRadial *__restrict_
             rr = r2 * ir;
         }
         const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
-        double2 c01[4], c23[4];
-        double tt[4];
-        int lv[4], mv[4];
+        for (int kb = k0; kb < k1; kb += 8) {
+            double2 c01[8], c23[8];
+            double tt[8];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int o = o0 + step * v;
-            c01[v] = double2{0.0, 0.0};
-            c23[v] = double2{0.0, 0.0};
-            tt[v] = 0.0;
-            lv[v] = -1;
-            mv[v] = 0;
-            if (o < norb) {
-                const DevRadial R = rads[orb_rad[o]];
-                lv[v] = R.l;
-                mv[v] = orb_m[o];
-                if (rr < R.rc) {
-                    const int iv = spline_interval(R, rr, &tt[v]);
-                    c01[v] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
-                    c23[v] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
+            for (int u = 0; u < 8; ++u) {
+                const int k = kb + u;
+                c01[u] = double2{0.0, 0.0};
+                c23[u] = double2{0.0, 0.0};
+                tt[u] = 0.0;
+                if (k < k1) {
+                    const DevRadial R = rads[k];
+                    if (rr < R.rc) {
+                        const int iv = spline_interval(R, rr, &tt[u]);
+                        c01[u] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
+                        c23[u] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            if (lv[v] < 0)
-                continue;
-            const double t = tt[v];
-            const double f = c01[v].x + t * (c01[v].y + t * (c23[v].x + t * c23[v].y));
-            const double fp = c01[v].y + t * (2.0 * c23[v].x + t * 3.0 * c23[v].y);
-            const int m = mv[v];
-            double Y, G0, G1, G2;
-            if (lv[v] == 0) {
-                Y = Y_C00;
-                G0 = G1 = G2 = 0.0;
-            } else if (lv[v] == 1) {
-                // m = -1, 0, 1 -> y, z, x
-                Y = Y_C1 * (m == -1 ? uy : (m == 0 ? uz : ux));
-                G0 = (m == 1) ? Y_C1 : 0.0;
-                G1 = (m == -1) ? Y_C1 : 0.0;
-                G2 = (m == 0) ? Y_C1 : 0.0;
-            } else {
-                if (m == -2) {
-                    Y = Y_C2 * ux * uy;
-                    G0 = Y_C2 * uy;
-                    G1 = Y_C2 * ux;
-                    G2 = 0.0;
-                } else if (m == -1) {
-                    Y = Y_C2 * uy * uz;
-                    G0 = 0.0;
-                    G1 = Y_C2 * uz;
-                    G2 = Y_C2 * uy;
-                } else if (m == 0) {
-                    Y = Y_C20 * (2.0 * uz * uz - ux * ux - uy * uy);
-                    G0 = -2.0 * Y_C20 * ux;
-                    G1 = -2.0 * Y_C20 * uy;
-                    G2 = 4.0 * Y_C20 * uz;
-                } else if (m == 1) {
-                    Y = Y_C2 * ux * uz;
-                    G0 = Y_C2 * uz;
-                    G1 = 0.0;
-                    G2 = Y_C2 * ux;
+            for (int u = 0; u < 8; ++u) {
+                const int k = kb + u;
+                if (k >= k1)
+                    break;
+                const int l = rads[k].l, o = rads[k].orb0;
+                const double t = tt[u];
+                const double f = c01[u].x + t * (c01[u].y + t * (c23[u].x + t * c23[u].y));
+                const double fp = c01[u].y + t * (2.0 * c23[u].x + t * 3.0 * c23[u].y);
+                double A, G0, G1, G2;
+                if (l == 0) {
+                    A = Y_C00 * wp * (double)crow[o * ST];
+                    G0 = G1 = G2 = 0.0;
+                } else if (l == 1) {
+                    // m = -1, 0, 1 -> y, z, x
+                    const double cy = wp * (double)crow[o * ST], cz = wp * (double)crow[(o + 1) * ST],
+                                 cx = wp * (double)crow[(o + 2) * ST];
+                    G0 = Y_C1 * cx;
+                    G1 = Y_C1 * cy;
+                    G2 = Y_C1 * cz;
+                    A = G0 * ux + G1 * uy + G2 * uz;
                 } else {
-                    Y = Y_C22 * (ux * ux - uy * uy);
-                    G0 = 2.0 * Y_C22 * ux;
-                    G1 = -2.0 * Y_C22 * uy;
-                    G2 = 0.0;
+                    // m = -2 .. 2 -> xy, yz, 2z^2 - x^2 - y^2, xz, x^2 - y^2
+                    const double c0 = wp * (double)crow[o * ST], c1 = wp * (double)crow[(o + 1) * ST],
+                                 c2 = wp * (double)crow[(o + 2) * ST], c3 = wp * (double)crow[(o + 3) * ST],
+                                 c4 = wp * (double)crow[(o + 4) * ST];
+                    G0 = Y_C2 * (c0 * uy + c3 * uz) + ux * (2.0 * Y_C22 * c4 - 2.0 * Y_C20 * c2);
+                    G1 = Y_C2 * (c0 * ux + c1 * uz) - uy * (2.0 * Y_C22 * c4 + 2.0 * Y_C20 * c2);
+                    G2 = Y_C2 * (c1 * uy + c3 * ux) + uz * (4.0 * Y_C20 * c2);
+                    A = 0.5 * (G0 * ux + G1 * uy + G2 * uz);
                 }
-            }
-            if (tiny) {
-                // only p orbitals keep a gradient at the centre: f'(0) C1 e_m
-                if (lv[v] == 1) {
-                    gr[0][v] += fp * G0;
-                    gr[1][v] += fp * G1;
-                    gr[2][v] += fp * G2;
+                if (tiny) {
+                    if (l == 1) {
+                        fx[0] += fp * G0;
+                        fx[1] += fp * G1;
+                        fx[2] += fp * G2;
+                    }
+                    continue;
                 }
-                continue;
+                const double fr = f * ir;
+                const double s = (fp - l * fr) * A;
+                fx[0] += s * ux + fr * G0;
+                fx[1] += s * uy + fr * G1;
+                fx[2] += s * uz + fr * G2;
             }
-            const double fr = f * ir;
-            const double lY = lv[v] * Y;
-            gr[0][v] += fp * Y * ux + fr * (G0 - lY * ux);
-            gr[1][v] += fp * Y * uy + fr * (G1 - lY * uy);
-            gr[2][v] += fp * Y * uz + fr * (G2 - lY * uz);
         }
     }
 }
