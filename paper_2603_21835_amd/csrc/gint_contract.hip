@@ -777,28 +777,26 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                 rp[s2] += half * dot;
             }
         };
-        // (every path issues the same loads; past the end a block's own
-        // fragment is reloaded)
+        // (one exit, no break between a load and its use; past the end a
+        // valid fragment is reloaded)
         T fa[4], fb[4];
         if (wave < nblk) {
             load(fa, ia, ja);
-            for (int k = wave;; k += 2 * kBatchWaves) {
+            int k = wave;
+            for (; k + kBatchWaves < nblk; k += 2 * kBatchWaves) {
                 int ib2 = ia, jb2 = ja;
                 advance(ib2, jb2);
-                const bool has_b = k + kBatchWaves < nblk;
-                load(fb, has_b ? ib2 : ia, has_b ? jb2 : ja);
+                load(fb, ib2, jb2);
                 block(fa, ia, ja);
-                if (!has_b)
-                    break;
                 ia = ib2;
                 ja = jb2;
                 advance(ia, ja);
                 const bool has_a = k + 2 * kBatchWaves < nblk;
                 load(fa, has_a ? ia : ib2, has_a ? ja : jb2);
                 block(fb, ib2, jb2);
-                if (!has_a)
-                    break;
             }
+            if (k < nblk)
+                block(fa, ia, ja);
         }
 #pragma unroll
         for (int s2 = 0; s2 < NS; ++s2) {
@@ -834,7 +832,9 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
             if (ia >= nb)
                 continue;
             auto load = [&](T (&f4)[4], int y) {
-                const T *f = (ia <= y) ? frag(ia, y, 0) : frag(y, ia, 1);
+                // (selects, not branches: the loads stay in one basic block
+                // ahead of the scheduling barrier)
+                const T *f = frag(min(ia, y), max(ia, y), ia <= y ? 0 : 1);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     f4[c] = f[64 * c];
@@ -850,20 +850,19 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                     Tt[u][s2] = MM<T>::mma(f4[3], pJ[192], Tt[u][s2]);
                 }
             };
+            // (one exit, no break between a load and its use: the
+            // accumulators then stay in place instead of being copied)
             T fa[4], fb[4];
             load(fa, 0);
-            for (int ja = 0;; ja += 2) {
-                const bool has_b = ja + 1 < nb;
-                load(fb, has_b ? ja + 1 : ja);
+            int ja = 0;
+            for (; ja + 1 < nb; ja += 2) {
+                load(fb, ja + 1);
                 block(fa, ja);
-                if (!has_b)
-                    break;
-                const bool has_a = ja + 2 < nb;
-                load(fa, has_a ? ja + 2 : ja + 1);
+                load(fa, ja + 2 < nb ? ja + 2 : ja + 1);  // past the end: any valid fragment
                 block(fb, ja + 1);
-                if (!has_a)
-                    break;
             }
+            if (ja < nb)
+                block(fa, ja);
             if (RHO) {
 #pragma unroll
                 for (int s2 = 0; s2 < NS; ++s2) {
@@ -963,7 +962,9 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                 Tt[s2] = MM<T>::zero();
             // T_I over every ja; fragment register sets alternate as in rho
             auto load = [&](T (&f4)[4], int y) {
-                const T *f = (ia <= y) ? frag(ia, y, 0) : frag(y, ia, 1);
+                // (selects, not branches: the loads stay in one basic block
+                // ahead of the scheduling barrier)
+                const T *f = frag(min(ia, y), max(ia, y), ia <= y ? 0 : 1);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     f4[c] = f[64 * c];
@@ -979,20 +980,19 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                     Tt[s2] = MM<T>::mma(f4[3], pJ[192], Tt[s2]);
                 }
             };
+            // (one exit, no break between a load and its use: the
+            // accumulators then stay in place instead of being copied)
             T fa[4], fb[4];
             load(fa, 0);
-            for (int ja = 0;; ja += 2) {
-                const bool has_b = ja + 1 < nb;
-                load(fb, has_b ? ja + 1 : ja);
+            int ja = 0;
+            for (; ja + 1 < nb; ja += 2) {
+                load(fb, ja + 1);
                 block(fa, ja);
-                if (!has_b)
-                    break;
-                const bool has_a = ja + 2 < nb;
-                load(fa, has_a ? ja + 2 : ja + 1);
+                load(fa, ja + 2 < nb ? ja + 2 : ja + 1);  // past the end: any valid fragment
                 block(fb, ja + 1);
-                if (!has_a)
-                    break;
             }
+            if (ja < nb)
+                block(fa, ja);
             // gradients of orbitals row(lk, v) of atom I at point 16 s + li
             const int e = e0 + ia;
             const DevSpecies &S = s_sp[bs.spc[I]];
