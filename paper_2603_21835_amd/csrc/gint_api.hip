@@ -114,6 +114,7 @@ struct gint_plan_s {
     // work buffers
     DevBuf Hpart, S2pk, Fent, sums, readback;
     DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist, lcnt, lptr, blist;
+    DevBuf pown, lsl, slabq;  // owner of each owned pair; slab ranges of its block list
     int npair_owned = 0;          // owned atom pairs (entries of plist)
     std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
@@ -522,6 +523,18 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     p->slab_q.clear();
     for (int b : p->slab)
         p->slab_q.push_back(hboff[b]);
+    {
+        const int ns = (int)p->slab.size() - 1;
+        STCHK(p->slabq.ensure(sizeof(int) * (ns + 1)));
+        STCHK(p->pown.ensure(sizeof(int) * (tpart + 1)));
+        STCHK(p->lsl.ensure(sizeof(int) * ((size_t)tpart * (ns + 1) + 1)));
+        HIPCHK(hipMemcpyAsync(p->slabq.p, p->slab_q.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, s));
+        STCHK(timed(p, GINT_K_BIN, [&] {
+            return launch_pair_slabs(s, na, tpart, p->pptr.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), ns,
+                                     p->slabq.as<int>(), p->pown.as<int>(), p->lsl.as<int>());
+        }));
+        HIPCHK(hipStreamSynchronize(s));  // slab_q (host) outlives the copy
+    }
     if (p->ext_hpart) {
         if (blk_bytes * (size_t)most > p->ext_hpart_bytes)
             return fail(GINT_ENOMEM, "a batch of the cell needs %zu bytes of H partials", blk_bytes * (size_t)most);
@@ -892,9 +905,9 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
                                   p->mno, p->hpart());
         }));
         STCHK(timed(p, GINT_K_H_REDUCE, [&] {
-            return launch_H_pairreduce(p->stream, p->f32(), p->natom, p->npair_owned, p->pptr.as<int>(),
-                                       p->plist.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), B, p->mno, p->norb,
-                                       p->hpart(), p->slab_q[i], p->slab_q[i + 1], i > 0 ? 1 : 0, H);
+            return launch_H_pairreduce(p->stream, p->f32(), p->npair_owned, p->pown.as<int>(), p->plist.as<int>(),
+                                       p->lsl.as<int>(), (int)p->slab.size() - 1, (int)i, p->blist.as<int>(), B,
+                                       p->mno, p->norb, p->hpart(), p->slab_q[i], i > 0 ? 1 : 0, H);
         }));
     }
     return GINT_OK;
@@ -940,7 +953,7 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
         return launch_pack_S2(p->stream, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
     }));
     STCHK(timed(p, rho ? GINT_K_RHO_FORCE : GINT_K_FORCE, [&] {
-        return launch_force_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, p->S2pk.p, W, wscale,
+        return launch_force_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, W, wscale,
                                   p->Fent.as<double>(), rho);
     }));
     STCHK(timed(p, GINT_K_F_REDUCE,

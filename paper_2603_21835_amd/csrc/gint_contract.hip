@@ -436,11 +436,11 @@ struct Vec16<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, const int *__restrict__ pptr,
-                                                      const int *__restrict__ plist, const int *__restrict__ lptr,
-                                                      const int *__restrict__ list, Basis bs, int mno, int norb,
-                                                      const T *__restrict__ part, int q0, int q1, int accumulate,
-                                                      double *__restrict__ H)
+__global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__restrict__ pown,
+                                                      const int *__restrict__ plist, const int *__restrict__ lsl,
+                                                      int nslab1, int si, const int *__restrict__ list, Basis bs,
+                                                      int mno, int norb, const T *__restrict__ part, int q0,
+                                                      int accumulate, double *__restrict__ H)
 {
     typedef typename Vec16<T>::type VT;
     constexpr int V = Vec16<T>::V;
@@ -450,40 +450,8 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
     const int p = blockIdx.x * 4 + wv;
     if (p >= npair)
         return;
-    // owner I of pair p
-    int lo = 0, hi = natom + 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (pptr[mid] <= p)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    const int I = lo - 1, J = plist[p];
-    // the part of the list inside the block range [q0, q1)
     auto qof = [](int c) { return c >= 0 ? c : -c - 1; };
-    int l0 = lptr[p], l1 = lptr[p + 1];
-    {
-        int a = l0, z = l1;
-        while (a < z) {
-            const int mid = (a + z) >> 1;
-            if (qof(list[mid]) < q0)
-                a = mid + 1;
-            else
-                z = mid;
-        }
-        const int s0 = a;
-        z = l1;
-        while (a < z) {
-            const int mid = (a + z) >> 1;
-            if (qof(list[mid]) < q1)
-                a = mid + 1;
-            else
-                z = mid;
-        }
-        l0 = s0;
-        l1 = a;
-    }
+    const int l0 = lsl[(size_t)p * nslab1 + si], l1 = lsl[(size_t)p * nslab1 + si + 1];
     if (accumulate && l0 == l1)
         return;
     const int pitch = block_pitch(mno, sizeof(T));
@@ -493,19 +461,25 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
 #pragma unroll
         for (int i = 0; i < V; ++i)
             up[m][i] = dn[m][i] = 0.0;
-    for (int k0 = l0; k0 < l1; k0 += kRedGroup) {
+    // list entries 64 at a time, one per lane, handed out with readlane:
+    // the block loads of a group do not wait on list loads
+    for (int kc = l0; kc < l1; kc += 64) {
+        const int nc = min(64, l1 - kc);
+        const int lcode = lane < nc ? list[kc + lane] : 0;
+        for (int k0 = 0; k0 < nc; k0 += kRedGroup) {
         VT v[kRedGroup][M];
         bool isup[kRedGroup];
 #pragma unroll
         for (int g = 0; g < kRedGroup; ++g) {
             const int k = k0 + g;
-            const int code = k < l1 ? list[k] : 0;
+            const bool ok = k < nc;
+            const int code = __builtin_amdgcn_readlane(lcode, ok ? k : 0);
             isup[g] = code >= 0;
             const T *blk = part + (size_t)(qof(code) - q0) * pitch;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int e = V * lane + 64 * V * m;
-                v[g][m] = (k < l1 && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
+                v[g][m] = (ok && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
             }
         }
 #pragma unroll
@@ -520,6 +494,7 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
                     else
                         dn[m][i] += x;
                 }
+        }
     }
     // H_IJ(r, c) = up(r mno + c) + dn(c mno + r)
 #pragma unroll
@@ -532,6 +507,7 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
                 s_sum[wv][1][e] = dn[m][i];
             }
         }
+    const int I = pown[p], J = plist[p];
     const int Iin = bs.perm[I], Jin = bs.perm[J];
     const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
     const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
@@ -549,19 +525,19 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int natom, int npair, cons
     }
 }
 
-hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int natom, int npair, const int *pptr, const int *plist,
-                               const int *lptr, const int *list, const Basis &b, int mno, int norb, const void *part,
-                               int q0, int q1, int accumulate, double *H)
+hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *pown, const int *plist, const int *lsl,
+                               int nslab, int si, const int *list, const Basis &b, int mno, int norb,
+                               const void *part, int q0, int accumulate, double *H)
 {
     if (npair <= 0)
         return hipSuccess;
     const unsigned nblk = (unsigned)((npair + 3) / 4);
     if (f32)
-        hipLaunchKernelGGL(k_H_pairreduce<float>, dim3(nblk), dim3(256), 0, s, natom, npair, pptr, plist, lptr, list,
-                           b, mno, norb, static_cast<const float *>(part), q0, q1, accumulate, H);
+        hipLaunchKernelGGL(k_H_pairreduce<float>, dim3(nblk), dim3(256), 0, s, npair, pown, plist, lsl, nslab + 1, si,
+                           list, b, mno, norb, static_cast<const float *>(part), q0, accumulate, H);
     else
-        hipLaunchKernelGGL(k_H_pairreduce<double>, dim3(nblk), dim3(256), 0, s, natom, npair, pptr, plist, lptr,
-                           list, b, mno, norb, static_cast<const double *>(part), q0, q1, accumulate, H);
+        hipLaunchKernelGGL(k_H_pairreduce<double>, dim3(nblk), dim3(256), 0, s, npair, pown, plist, lsl, nslab + 1,
+                           si, list, b, mno, norb, static_cast<const double *>(part), q0, accumulate, H);
     return hipGetLastError();
 }
 
@@ -642,14 +618,7 @@ constexpr int batch_waves() { return MODE == 0 ? 16 : 12; }
 // rho_p = 1/2 sum_I phi_I(p) . T_I(p), since sum_IJ phi_I S2_IJ phi_J = 2 rho_p)
 constexpr int kRho = 0, kForce = 1, kRhoForce = 2;
 
-// KU (force modes): 0 keeps each atom's T_I in registers only for its own
-// gradient pass (any number of atoms); KU > 0 is the two-phase form for at
-// most KU atoms per wave: T_I of every atom on the matrix cores first (each
-// wave holding the T of its atoms in registers), then T replaces phi in LDS
-// and one thread per (atom, point) evaluates all the atom's orbital
-// gradients there, so that the gradient work is spread evenly over all
-// threads and each radial's spline evaluation serves its 2l + 1 orbitals.
-template <int MODE, typename T, int P, int KU>
+template <int MODE, typename T, int P>
 __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
                                                             const double *__restrict__ W, double wscale,
                                                             double *__restrict__ out, double *__restrict__ rho2)
@@ -816,138 +785,6 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
                 out[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = v;
             }
         }
-    } else if constexpr (KU > 0) {
-        // ---- phase A: T_I = sum_J S2_IJ phi_J, rho_p = 1/2 sum_I phi_I . T_I ----
-        double rp[NS];
-#pragma unroll
-        for (int s2 = 0; s2 < NS; ++s2)
-            rp[s2] = 0.0;
-        typename MM<T>::acc Tt[KU][NS];
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {
-#pragma unroll
-            for (int s2 = 0; s2 < NS; ++s2)
-                Tt[u][s2] = MM<T>::zero();
-            const int ia = wave + kBatchWaves * u;
-            if (ia >= nb)
-                continue;
-            auto load = [&](T (&f4)[4], int y) {
-                // (selects, not branches: the loads stay in one basic block
-                // ahead of the scheduling barrier)
-                const T *f = frag(min(ia, y), max(ia, y), ia <= y ? 0 : 1);
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    f4[c] = f[64 * c];
-                __builtin_amdgcn_sched_barrier(0);
-            };
-            auto block = [&](const T (&f4)[4], int y) {
-#pragma unroll
-                for (int s2 = 0; s2 < NS; ++s2) {
-                    const T *pJ = tile(y, s2) + 16 * lk + li;
-                    Tt[u][s2] = MM<T>::mma(f4[0], pJ[0], Tt[u][s2]);
-                    Tt[u][s2] = MM<T>::mma(f4[1], pJ[64], Tt[u][s2]);
-                    Tt[u][s2] = MM<T>::mma(f4[2], pJ[128], Tt[u][s2]);
-                    Tt[u][s2] = MM<T>::mma(f4[3], pJ[192], Tt[u][s2]);
-                }
-            };
-            // (one exit, no break between a load and its use: the
-            // accumulators then stay in place instead of being copied)
-            T fa[4], fb[4];
-            load(fa, 0);
-            int ja = 0;
-            for (; ja + 1 < nb; ja += 2) {
-                load(fb, ja + 1);
-                block(fa, ja);
-                load(fa, ja + 2 < nb ? ja + 2 : ja + 1);  // past the end: any valid fragment
-                block(fb, ja + 1);
-            }
-            if (ja < nb)
-                block(fa, ja);
-            if (RHO) {
-#pragma unroll
-                for (int s2 = 0; s2 < NS; ++s2) {
-                    const T *pI = tile(ia, s2) + li;
-                    double dot = 0.0;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        dot += (double)Tt[u][s2][v] * (double)pI[16 * MM<T>::row(lk, v)];
-                    rp[s2] += dot;
-                }
-            }
-        }
-        if (RHO) {
-#pragma unroll
-            for (int s2 = 0; s2 < NS; ++s2) {
-                double v = rp[s2];
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
-                if (lane < 16)
-                    s_red[wave][16 * s2 + lane] = v;
-            }
-        }
-        __syncthreads();  // every wave is done with phi
-        // T_I replaces phi_I, in the same [tile][orbital][point] layout
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {
-            const int ia = wave + kBatchWaves * u;
-            if (ia >= nb)
-                continue;
-#pragma unroll
-            for (int s2 = 0; s2 < NS; ++s2) {
-                T *t = s_phi + (size_t)(ia * NS + s2) * 256 + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    t[16 * MM<T>::row(lk, v)] = Tt[u][s2][v];
-            }
-        }
-        __syncthreads();
-        // ---- phase B: dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p) ----
-        // item (atom a, point p) = a P + p: the P items of an atom are P
-        // consecutive lanes of one wave (P divides 64)
-        for (int base = wave * 64; base < nb * P; base += NT) {
-            const int idx = base + lane;
-            const int a = idx / P, p = idx % P;
-            double fx[3] = {0.0, 0.0, 0.0};
-            int n[3];
-            if (idx < nb * P && batch_point(g, ib, p, n)) {
-                const int e = e0 + a;
-                const int atom = s_atom[a];
-                const DevSpecies &S = s_sp[bs.spc[atom]];
-                const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
-                const int io = bn.ent_img[e];
-                const int cnt = bn.ent_img[e + 1] - io;
-                double r[3];
-                mesh_cart(g, n, r);
-                grad_dot_all<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
-                                    r, s_phi + (size_t)(a * NS + (p >> 4)) * 256 + (p & 15), s_w[p], fx);
-            }
-#pragma unroll
-            for (int x = 0; x < 3; ++x) {
-                double v = fx[x];
-#pragma unroll
-                for (int o = P / 2; o > 0; o >>= 1)
-                    v += __shfl_xor(v, o);
-                fx[x] = v;
-            }
-            if (idx < nb * P && p == 0) {
-                s_F[a][0] = -fx[0];
-                s_F[a][1] = -fx[1];
-                s_F[a][2] = -fx[2];
-            }
-        }
-        __syncthreads();
-        for (int k = tid; k < nb * 3; k += NT)
-            out[(size_t)(e0 + k / 3) * 3 + k % 3] = s_F[k / 3][k % 3];
-        if (RHO)
-            for (int p = tid; p < P; p += NT) {
-                int n[3];
-                if (batch_point(g, ib, p, n)) {
-                    double v = s_red[0][p];
-                    for (int w = 1; w < kBatchWaves; ++w)
-                        v += s_red[w][p];
-                    rho2[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = 0.5 * v;
-                }
-            }
     } else {
         // dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p),  T_I = sum_J S2_IJ phi_J
         double rp[NS];
@@ -1070,35 +907,18 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
 
 size_t batch_lds_bytes(int nbmax, int P, bool f32) { return (f32 ? 4 : 8) * (size_t)nbmax * P * kMaxOrb; }
 
-template <int MODE, typename T, int P, int KU>
-static hipError_t launch_batch_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                                 const void *pk, const double *W, double wscale, double *out, double *rho2)
-{
-    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch<MODE, T, P, KU>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((k_batch<MODE, T, P, KU>), dim3(xcd_grid(g.nbatch)), dim3(64 * batch_waves<MODE>()), lds, s, g,
-                       bn, b, static_cast<const T *>(pk), W, wscale, out, rho2);
-    return hipGetLastError();
-}
-
-// force modes: the two-phase form while every wave holds at most 3 atoms
 template <int MODE, typename T, int P>
 static hipError_t launch_batch_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                  const void *pk, const double *W, double wscale, double *out, double *rho2)
 {
-    if constexpr (MODE == kRho)
-        return launch_batch_k<MODE, T, P, 0>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
-    const int ku = (nbmax + batch_waves<MODE>() - 1) / batch_waves<MODE>();
-    switch (ku) {
-    case 0:
-    case 1: return launch_batch_k<MODE, T, P, 1>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
-    case 2: return launch_batch_k<MODE, T, P, 2>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
-    case 3: return launch_batch_k<MODE, T, P, 3>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
-    default: return launch_batch_k<MODE, T, P, 0>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
-    }
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
+    hipError_t e = hipFuncSetAttribute((const void *)k_batch<MODE, T, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_batch<MODE, T, P>), dim3(xcd_grid(g.nbatch)), dim3(64 * batch_waves<MODE>()), lds, s, g, bn,
+                       b, static_cast<const T *>(pk), W, wscale, out, rho2);
+    return hipGetLastError();
 }
 
 template <int MODE, typename T>
@@ -1112,6 +932,328 @@ static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, co
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Point-stationary force (and rho) with packed output rows.
+//
+// The orbitals of the atoms reaching a batch are numbered consecutively
+// (atom slot a owns rows off[a] .. off[a] + norb_a - 1), and the output of
+// T_I = sum_J S2_IJ phi_J is tiled over these packed rows, so that the
+// 16-row matrix-core tiles carry no per-atom padding in the output; the
+// contraction runs atom by atom (16 orbital slots, zero beyond norb).
+//   phase A: for every 16-row tile, T over all atoms J; the left operand is
+//            gathered per lane (a tile's rows may belong to several atoms)
+//            from the packed D + D^T blocks, the next atom's values in
+//            flight during the current one; the right operand is phi_J in
+//            LDS.  Each wave keeps the T of its (at most KU) tiles in
+//            registers; rho_p = 1/2 sum_r phi_r(p) T_r(p).
+//   phase B: T replaces phi in LDS; one thread per (atom, point) evaluates
+//            every orbital gradient of its atom there (one spline
+//            evaluation per radial) against w_p T, and the P threads of an
+//            atom sum their dot products.
+// LDS: phi / T as [atom][P / 16 point tiles][16 orbitals][16 points].
+
+constexpr int kForceWaves = 12;
+
+template <bool RHO, typename T, int P, int KU>
+__global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
+                                                                  const double *__restrict__ W, double wscale,
+                                                                  double *__restrict__ out, double *__restrict__ rho2)
+{
+    constexpr int NW = kForceWaves, NT = 64 * NW, NS = P / 16;
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T *s_phi = reinterpret_cast<T *>(s_dyn);
+    __shared__ DevRadial s_rad[kMaxRadTotal];
+    __shared__ DevSpecies s_sp[kMaxSpecies];
+    __shared__ int s_atom[kMaxBatchAtoms], s_spc[kMaxBatchAtoms], s_off[kMaxBatchAtoms + 1];
+    __shared__ int s_grank[kMaxBatchAtoms];
+    __shared__ int s_ptab[kMaxBatchGroups * kMaxBatchGroups];
+    // packed row -> (slot << 16) | (group rank << 8) | (atom % kGroup) << 4 | orbital, or -1
+    __shared__ int s_row[kMaxBatchAtoms * kMaxOrb];
+    __shared__ double s_red[RHO ? NW : 1][kMaxP];
+    __shared__ double s_w[kMaxP];
+    __shared__ double s_F[kMaxBatchAtoms][3];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
+    if (b < 0)
+        return;
+    const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
+    const int g0 = bn.bgptr[b], ngb = bn.bgptr[b + 1] - g0;
+    int ib[3];
+    batch_coords(g, b, ib);
+
+    for (int k = tid; k < g.nrad; k += NT)
+        s_rad[k] = bs.rad[k];
+    for (int k = tid; k < g.nspecies; k += NT)
+        s_sp[k] = bs.sp[k];
+    for (int a = tid; a < nb; a += NT) {
+        const int atom = bn.ent_atom[e0 + a];
+        s_atom[a] = atom;
+        s_spc[a] = bs.spc[atom];
+        s_grank[a] = lower_bound_i(bn.bgrp, g0, g0 + ngb, atom / kGroup) - g0;
+        s_F[a][0] = s_F[a][1] = s_F[a][2] = 0.0;
+    }
+    for (int k = tid; k < ngb * ngb; k += NT) {
+        const int ra = k / ngb, rb = k % ngb;
+        const int ga = bn.bgrp[g0 + ra], gb = bn.bgrp[g0 + rb];
+        s_ptab[k] = (ra <= rb) ? bn.pair_index[(size_t)ga * g.ngroup + gb] : -1;
+    }
+    for (int p = tid; p < P; p += NT) {
+        int n[3];
+        s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
+    }
+    __syncthreads();
+    // row offsets of the atoms: an inclusive scan of their orbital counts (nb <= 64)
+    if (wave == 0) {
+        int v = lane < nb ? s_sp[s_spc[lane]].norb : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(v, o);
+            if (lane >= o)
+                v += t;
+        }
+        if (lane < nb)
+            s_off[lane + 1] = v;
+        if (lane == 0)
+            s_off[0] = 0;
+    }
+    __syncthreads();
+    const int nrow = s_off[nb];
+    const int nrp = (nrow + 15) & ~15;  // packed rows incl. the padding of the last tile
+    for (int r = tid; r < nrp; r += NT) {
+        int code = -1;
+        if (r < nrow) {
+            int lo = 0, hi = nb;  // last a with off[a] <= r
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= r)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            code = (lo << 16) | (s_grank[lo] << 8) | ((s_atom[lo] % kGroup) << 4) | (r - s_off[lo]);
+        }
+        s_row[r] = code;
+    }
+
+    // ---- stage the folded orbitals of every atom at every batch point ----
+    for (int idx = tid; idx < nb * P; idx += NT) {
+        const int a = idx / P, p = idx % P;
+        const int e = e0 + a;
+        const int atom = s_atom[a];
+        // orbital o of this point at row[16 o]
+        T *row = s_phi + (size_t)(a * NS + (p >> 4)) * 256 + (p & 15);
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[s_spc[a]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[16 * o] = (T)0;
+        if (valid) {
+            const int io = bn.ent_img[e];
+            const int cnt = bn.ent_img[e + 1] - io;
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            double r[3];
+            mesh_cart(g, n, r);
+            eval_orbitals<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
+                                 r, row);
+        }
+    }
+    __syncthreads();
+    // tile s2 of atom slot x: element (orbital o, point q) at [16 o + q]
+    auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * 256; };
+
+    // ---- phase A ----
+    const int ntile = nrp >> 4;
+    double rp[NS];
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2)
+        rp[s2] = 0.0;
+    typename MM<T>::acc acc[KU][NS];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2)
+            acc[u][s2] = MM<T>::zero();
+        const int ti = wave + NW * u;
+        if (ti >= ntile)
+            continue;
+        // this lane's output row (x, ox): A[i][k] = S2[row 16 ti + i][(y, 4 j + k)]
+        const int rc = s_row[16 * ti + li];
+        const bool rok = rc >= 0;
+        const int x = rok ? rc >> 16 : 0, gx = rok ? (rc >> 8) & 0xff : 0, sx = rok ? (rc >> 4) & 15 : 0,
+                  ox = rok ? rc & 15 : 0;
+        // the A values of atom y: S2[(x, ox)][(y, 4 j + lk)] sits in the packed
+        // block of the slot-ordered pair (orientation 0 when x <= y) at
+        // 16 (4 j + lk) + ox
+        auto load = [&](T (&a4)[4], int y) {
+            const bool le = x <= y;
+            const int gy = s_grank[y], sy = s_atom[y] % kGroup;
+            const int pr = s_ptab[le ? gx * ngb + gy : gy * ngb + gx];
+            const int blk = le ? sx * 4 + sy : sy * 4 + sx;
+            const T *f = pk + ((size_t)(pr * 16 + blk) * 2 + (le ? 0 : 1)) * 256 + 16 * lk + ox;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T v = f[64 * j];
+                a4[j] = rok ? v : (T)0;
+            }
+        };
+        auto mblock = [&](const T (&a4)[4], int y) {
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                const T *pB = tile(y, s2) + 16 * lk + li;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[u][s2] = MM<T>::mma(a4[j], pB[64 * j], acc[u][s2]);
+            }
+        };
+        T fa[4], fb[4];
+        load(fa, 0);
+        int ja = 0;
+        for (; ja + 1 < nb; ja += 2) {
+            load(fb, ja + 1);
+            mblock(fa, ja);
+            load(fa, ja + 2 < nb ? ja + 2 : ja + 1);  // past the end: any valid atom
+            mblock(fb, ja + 1);
+        }
+        if (ja < nb)
+            mblock(fa, ja);
+        if (RHO) {
+            // phi at the output rows of this lane (zero for padding rows)
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2) {
+                double dot = 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = s_row[16 * ti + MM<T>::row(lk, v)];
+                    const T ph = c >= 0 ? tile(c >> 16, s2)[16 * (c & 15) + li] : (T)0;
+                    dot += (double)acc[u][s2][v] * (double)ph;
+                }
+                rp[s2] += dot;
+            }
+        }
+    }
+    if (RHO) {
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) {
+            double v = rp[s2];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16)
+                s_red[wave][16 * s2 + lane] = v;
+        }
+    }
+    __syncthreads();  // every wave is done with Phi
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+        const int ti = wave + NW * u;
+        if (ti >= ntile)
+            continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = s_row[16 * ti + MM<T>::row(lk, v)];
+            if (c >= 0)
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2)
+                    tile(c >> 16, s2)[16 * (c & 15) + li] = acc[u][s2][v];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase B: dE/dR_I partial = -sum_p w_p grad phi_I(p) . T_I(p) ----
+    // item (atom a, point p) = a P + p: the P items of an atom are P
+    // consecutive lanes of one wave (P divides 64)
+    for (int base = wave * 64; base < nb * P; base += NT) {
+        const int idx = base + lane;
+        const int a = idx / P, p = idx % P;
+        double fx[3] = {0.0, 0.0, 0.0};
+        int n[3];
+        if (idx < nb * P && batch_point(g, ib, p, n)) {
+            const int e = e0 + a;
+            const int atom = s_atom[a];
+            const DevSpecies &S = s_sp[s_spc[a]];
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            const int io = bn.ent_img[e];
+            const int cnt = bn.ent_img[e + 1] - io;
+            double r[3];
+            mesh_cart(g, n, r);
+            grad_dot_all<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
+                                tile(a, p >> 4) + (p & 15), s_w[p], fx);
+        }
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            double v = fx[x];
+#pragma unroll
+            for (int o = P / 2; o > 0; o >>= 1)
+                v += __shfl_xor(v, o);
+            fx[x] = v;
+        }
+        if (idx < nb * P && p == 0) {
+            s_F[a][0] = -fx[0];
+            s_F[a][1] = -fx[1];
+            s_F[a][2] = -fx[2];
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < nb * 3; k += NT)
+        out[(size_t)(e0 + k / 3) * 3 + k % 3] = s_F[k / 3][k % 3];
+    if (RHO)
+        for (int p = tid; p < P; p += NT) {
+            int n[3];
+            if (batch_point(g, ib, p, n)) {
+                double v = s_red[0][p];
+                for (int w = 1; w < NW; ++w)
+                    v += s_red[w][p];
+                rho2[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = 0.5 * v;
+            }
+        }
+}
+
+template <bool RHO, typename T, int P, int KU>
+static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, size_t lds,
+                                  const void *pk, const double *W, double wscale, double *out, double *rho2)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU>), dim3(xcd_grid(g.nbatch)), dim3(64 * kForceWaves), lds, s, g,
+                       bn, b, static_cast<const T *>(pk), W, wscale, out, rho2);
+    return hipGetLastError();
+}
+
+// the packed form while every wave holds at most 3 row tiles (otherwise the
+// per-atom form, whose registers do not grow with the atom count)
+template <bool RHO, typename T, int P>
+static hipError_t launch_force_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int mno,
+                                 const void *pk, const double *W, double wscale, double *out, double *rho2)
+{
+    const int rows = (nbmax * mno + 15) & ~15;
+    const int ku = (rows / 16 + kForceWaves - 1) / kForceWaves;
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
+    if (lds + 20480 > 163840)  // with the kernel's static LDS
+        return launch_batch_p<RHO ? kRhoForce : kForce, T, P>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    switch (ku) {
+    case 0:
+    case 1: return launch_packed_k<RHO, T, P, 1>(s, g, bn, b, lds, pk, W, wscale, out, rho2);
+    case 2: return launch_packed_k<RHO, T, P, 2>(s, g, bn, b, lds, pk, W, wscale, out, rho2);
+    case 3: return launch_packed_k<RHO, T, P, 3>(s, g, bn, b, lds, pk, W, wscale, out, rho2);
+    default: return launch_batch_p<RHO ? kRhoForce : kForce, T, P>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
+    }
+}
+
+template <bool RHO, typename T>
+static hipError_t launch_force_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int mno,
+                                 const void *pk, const double *W, double wscale, double *out, double *rho2)
+{
+    if (g.P == 32)
+        return launch_force_p<RHO, T, 32>(s, g, bn, b, nbmax, mno, pk, W, wscale, out, rho2);
+    if (g.P == 16)
+        return launch_force_p<RHO, T, 16>(s, g, bn, b, nbmax, mno, pk, W, wscale, out, rho2);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                             const void *pk, double *rho)
 {
@@ -1120,13 +1262,13 @@ hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &b
 }
 
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              const void *pk, const double *W, double wscale, double *Fent, double *rho)
+                              int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho)
 {
     if (rho)
-        return f32 ? launch_batch_t<kRhoForce, float>(s, g, bn, b, nbmax, pk, W, wscale, Fent, rho)
-                   : launch_batch_t<kRhoForce, double>(s, g, bn, b, nbmax, pk, W, wscale, Fent, rho);
-    return f32 ? launch_batch_t<kForce, float>(s, g, bn, b, nbmax, pk, W, wscale, Fent, nullptr)
-               : launch_batch_t<kForce, double>(s, g, bn, b, nbmax, pk, W, wscale, Fent, nullptr);
+        return f32 ? launch_force_t<true, float>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho)
+                   : launch_force_t<true, double>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho);
+    return f32 ? launch_force_t<false, float>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, nullptr)
+               : launch_force_t<false, double>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, nullptr);
 }
 
 // dE/dR per atom: fixed-order sum of its per-(batch, atom) partials over the

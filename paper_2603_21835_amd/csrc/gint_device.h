@@ -237,7 +237,9 @@ __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__r
 //     A = sum_m c_m Y_m(u),  G = sum_m c_m dY_m/du,
 // (Y_lm is a homogeneous polynomial of degree l in u, so u . dY/du = l Y).
 // At the atom's centre only p orbitals keep a gradient, f'(0) dY/du.
-template <typename T, int ST>
+// The radial loop is unrolled by U (spline-coefficient loads in flight
+// together).
+template <typename T, int ST, int U = 4>
 __device__ __forceinline__ void grad_dot_all(const Geo &g, const DevRadial *__restrict__ rads, int k0, int k1,
                                              double rc, const double *__restrict__ coef, const double *X, int icnt,
                                              int pk0, int ioff, const int *__restrict__ img, const double *r,
@@ -262,11 +264,11 @@ __device__ __forceinline__ void grad_dot_all(const Geo &g, const DevRadial *__re
             rr = r2 * ir;
         }
         const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
-        for (int kb = k0; kb < k1; kb += 8) {
-            double2 c01[8], c23[8];
-            double tt[8];
+        for (int kb = k0; kb < k1; kb += U) {
+            double2 c01[U], c23[U];
+            double tt[U];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int k = kb + u;
                 c01[u] = double2{0.0, 0.0};
                 c23[u] = double2{0.0, 0.0};
@@ -281,7 +283,7 @@ __device__ __forceinline__ void grad_dot_all(const Geo &g, const DevRadial *__re
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int k = kb + u;
                 if (k >= k1)
                     break;

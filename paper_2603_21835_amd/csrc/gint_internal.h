@@ -132,12 +132,16 @@ __host__ __device__ inline int block_pitch(int mno, int esz)
 constexpr int kModeF64 = 0, kModeF32 = 1, kModeBF16 = 2, kModeF16 = 3, kModeBF16x3 = 4, kModeF16x3 = 5;
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                           int b1, const double *W, double wscale, const int *boff, int mno, void *part);
-hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int natom, int npair, const int *pptr, const int *plist,
-                               const int *lptr, const int *list, const Basis &b, int mno, int norb, const void *part,
-                               int q0, int q1, int accumulate, double *H);
+// H block partials of slab si summed per owned pair (I = pown[p], J = plist[p])
+// over its list entries lsl[p (nslab + 1) + si] .. lsl[... + si + 1]
+hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *pown, const int *plist, const int *lsl,
+                               int nslab, int si, const int *list, const Basis &b, int mno, int norb,
+                               const void *part, int q0, int accumulate, double *H);
 hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
                               const int *abat, const int *bptr, const int *boff, const int *pptr, const int *plist,
                               int *lcnt, const int *lptr, int *list);
+hipError_t launch_pair_slabs(hipStream_t s, int natom, int npair, const int *pptr, const int *lptr, const int *list,
+                             int nslab, const int *slab_q, int *pown, int *lsl);
 hipError_t launch_fill_f64(hipStream_t s, double *p, long long n, double v);
 hipError_t launch_block_count(hipStream_t s, int nbatch, const int *bptr, int *cnt);
 hipError_t launch_atom_count(hipStream_t s, int natom, const int *gptr, const int *gbatch, const int *bptr,
@@ -152,7 +156,7 @@ size_t batch_lds_bytes(int nbmax, int P, bool f32);
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                             const void *pk, double *rho);
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              const void *pk, const double *W, double wscale, double *Fent,
+                              int mno, const void *pk, const double *W, double wscale, double *Fent,
                               double *rho /* NULL, or rho as well */);
 hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
                                const double *Fent, double *dEdR);

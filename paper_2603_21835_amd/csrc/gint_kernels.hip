@@ -914,4 +914,52 @@ hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *ap
     return hipGetLastError();
 }
 
+
+// Owner atom of every owned pair, and where each slab's blocks start in the
+// pair's block list: lsl[p (nslab + 1) + s] = first list entry whose block
+// index is >= slab_q[s] (slab_q[nslab] is past every block).  Lists hold
+// block indices q (or -(q + 1), transposed blocks) in increasing q.
+__global__ __launch_bounds__(256) void k_pair_slabs(int natom, int npair, const int *__restrict__ pptr,
+                                                    const int *__restrict__ lptr, const int *__restrict__ list,
+                                                    int nslab, const int *__restrict__ slab_q, int *__restrict__ pown,
+                                                    int *__restrict__ lsl)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair)
+        return;
+    int lo = 0, hi = natom + 1;  // last atom I with pptr[I] <= p
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (pptr[mid] <= p)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    pown[p] = lo - 1;
+    const int l0 = lptr[p], l1 = lptr[p + 1];
+    for (int si = 0; si <= nslab; ++si) {
+        const int q = slab_q[si];
+        int a = l0, z = l1;
+        while (a < z) {
+            const int mid = (a + z) >> 1;
+            const int c = list[mid];
+            if ((c >= 0 ? c : -c - 1) < q)
+                a = mid + 1;
+            else
+                z = mid;
+        }
+        lsl[(size_t)p * (nslab + 1) + si] = a;
+    }
+}
+
+hipError_t launch_pair_slabs(hipStream_t s, int natom, int npair, const int *pptr, const int *lptr, const int *list,
+                             int nslab, const int *slab_q, int *pown, int *lsl)
+{
+    if (npair <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pair_slabs, dim3((npair + 255) / 256), dim3(256), 0, s, natom, npair, pptr, lptr, list, nslab,
+                       slab_q, pown, lsl);
+    return hipGetLastError();
+}
+
 }  // namespace gint
