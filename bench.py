@@ -54,6 +54,54 @@ def _traffic(kernel: str, workload: str, precision: str):
     return t.get("bytes_per_launch")
 
 
+# device kernel (symbol prefix) behind each timing kind whose traffic is recorded
+KERNEL_SYMBOLS = {"rho_force": "k_force_packed", "H_blocks": "k_H_batch", "H_reduce": "k_H_pairreduce"}
+
+
+def _counter_csv(d: str, counter: str):
+    """(kernel name, value) per dispatch of one counter from a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return rows
+
+
+def write_traffic(args):
+    """HBM bytes per launch of one kernel from FETCH_SIZE / WRITE_SIZE runs
+    (KiB per dispatch), each scaled by what the same counter reads for a plain
+    copy of known size (the largest copy dispatch of the calibration runs)."""
+    d = args.traffic_from
+    sym = KERNEL_SYMBOLS[args.kernel]
+    with open(os.path.join(d, "copy_bytes.json")) as fh:
+        copy_bytes = json.load(fh)["copy_bytes"]
+    out = {"kernel": args.kernel, "symbol": sym, "workload": args.workload, "precision": args.precision,
+           "kernel_sha": _kernel_sha()}
+    total = 0.0
+    for name, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        copy_kib = max(v for _, v in _counter_csv(os.path.join(d, "copy_" + name), counter))
+        factor = copy_bytes / (copy_kib * 1024.0)
+        vals = [v for k, v in _counter_csv(os.path.join(d, name), counter) if sym in k]
+        if not vals:
+            raise SystemExit(f"no {sym} dispatch in {d}/{name}")
+        per = sum(vals) / len(vals) * 1024.0 * factor
+        out[name] = {"counter": counter, "kib_per_dispatch": sum(vals) / len(vals), "dispatches": len(vals),
+                     "copy_kib": copy_kib, "scale": factor, "bytes_per_launch": per}
+        total += per
+    out["bytes_per_launch"] = total
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.kernel}_{args.workload}_{args.precision}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
+
+
 def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -182,13 +230,20 @@ def main():
     ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
-    ap.add_argument("--only", default=None, choices=["H", "rho", "force"],
+    ap.add_argument("--only", default=None, choices=["H", "rho", "force", "rho_force"],
                     help="time one contraction only (short profiler runs)")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (counter calibration)")
+    ap.add_argument("--traffic-from", default=None, metavar="DIR",
+                    help="write profiles/traffic_<kernel>_<workload>_<precision>.json from the rocprofv3 "
+                         "counter CSVs under DIR (fetch/, write/, copy_fetch/, copy_write/) and exit")
+    ap.add_argument("--kernel", default="rho_force", help="timing kind whose traffic --traffic-from records")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -235,7 +290,7 @@ def main():
             plan.set_positions(w.positions)
         if args.only in (None, "H"):
             plan.build_H(V, out=H)
-        if args.only is None and not args.separate:
+        if (args.only is None and not args.separate) or args.only == "rho_force":
             plan.rho_force(V, D, rho=rho, out=F)  # rho from the force pass
         else:
             if args.only in (None, "rho"):
