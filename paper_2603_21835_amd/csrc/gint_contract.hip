@@ -955,13 +955,17 @@ static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, co
 constexpr int kForceWaves = 12;
 
 template <bool RHO, typename T, int P, int KU>
-__global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, const T *__restrict__ pk,
+__global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, int nbmax,
+                                                                  const T *__restrict__ pk,
                                                                   const double *__restrict__ W, double wscale,
                                                                   double *__restrict__ out, double *__restrict__ rho2)
 {
     constexpr int NW = kForceWaves, NT = 64 * NW, NS = P / 16;
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T *s_phi = reinterpret_cast<T *>(s_dyn);
+    // after phi: the packed-fragment block of every slot pair (x, y), in
+    // units of 256 elements: (pair * 16 + block) * 2 + orientation
+    int *s_bb = reinterpret_cast<int *>(s_dyn + sizeof(T) * (size_t)nbmax * NS * 256);
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_spc[kMaxBatchAtoms], s_off[kMaxBatchAtoms + 1];
@@ -1019,6 +1023,13 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             s_off[0] = 0;
     }
     __syncthreads();
+    for (int k = tid; k < nb * nb; k += NT) {
+        const int x = k / nb, y = k % nb;
+        const bool le = x <= y;
+        const int lo = le ? x : y, hi = le ? y : x;
+        const int pr = s_ptab[s_grank[lo] * ngb + s_grank[hi]];
+        s_bb[k] = (pr * 16 + (s_atom[lo] % kGroup) * 4 + s_atom[hi] % kGroup) * 2 + (le ? 0 : 1);
+    }
     const int nrow = s_off[nb];
     const int nrp = (nrow + 15) & ~15;  // packed rows incl. the padding of the last tile
     for (int r = tid; r < nrp; r += NT) {
@@ -1082,22 +1093,18 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         // this lane's output row (x, ox): A[i][k] = S2[row 16 ti + i][(y, 4 j + k)]
         const int rc = s_row[16 * ti + li];
         const bool rok = rc >= 0;
-        const int x = rok ? rc >> 16 : 0, gx = rok ? (rc >> 8) & 0xff : 0, sx = rok ? (rc >> 4) & 15 : 0,
-                  ox = rok ? rc & 15 : 0;
+        const int x = rok ? rc >> 16 : 0, ox = rok ? rc & 15 : 0;
         // the A values of atom y: S2[(x, ox)][(y, 4 j + lk)] sits in the packed
         // block of the slot-ordered pair (orientation 0 when x <= y) at
         // 16 (4 j + lk) + ox
         auto load = [&](T (&a4)[4], int y) {
-            const bool le = x <= y;
-            const int gy = s_grank[y], sy = s_atom[y] % kGroup;
-            const int pr = s_ptab[le ? gx * ngb + gy : gy * ngb + gx];
-            const int blk = le ? sx * 4 + sy : sy * 4 + sx;
-            const T *f = pk + ((size_t)(pr * 16 + blk) * 2 + (le ? 0 : 1)) * 256 + 16 * lk + ox;
+            const T *f = pk + (size_t)s_bb[x * nb + y] * 256 + 16 * lk + ox;
+            // (rows past the last orbital read the finite values of row
+            // (0, 0): their T is discarded; no select here, which would wait
+            // for the loads where they are issued)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const T v = f[64 * j];
-                a4[j] = rok ? v : (T)0;
-            }
+            for (int j = 0; j < 4; ++j)
+                a4[j] = f[64 * j];
         };
         auto mblock = [&](const T (&a4)[4], int y) {
 #pragma unroll
@@ -1108,17 +1115,25 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
                     acc[u][s2] = MM<T>::mma(a4[j], pB[64 * j], acc[u][s2]);
             }
         };
-        T fa[4], fb[4];
+        // three register sets in rotation: an atom's D values are loaded two
+        // atoms ahead of their use (past the end, the last atom is reloaded)
+        auto at = [&](int y) { return y < nb ? y : nb - 1; };
+        T fa[4], fb[4], fc[4];
         load(fa, 0);
+        load(fb, at(1));
         int ja = 0;
-        for (; ja + 1 < nb; ja += 2) {
-            load(fb, ja + 1);
+        for (; ja + 2 < nb; ja += 3) {
+            load(fc, ja + 2);
             mblock(fa, ja);
-            load(fa, ja + 2 < nb ? ja + 2 : ja + 1);  // past the end: any valid atom
+            load(fa, at(ja + 3));
             mblock(fb, ja + 1);
+            load(fb, at(ja + 4));
+            mblock(fc, ja + 2);
         }
         if (ja < nb)
             mblock(fa, ja);
+        if (ja + 1 < nb)
+            mblock(fb, ja + 1);
         if (RHO) {
             // phi at the output rows of this lane (zero for padding rows)
 #pragma unroll
@@ -1211,15 +1226,16 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
 }
 
 template <bool RHO, typename T, int P, int KU>
-static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, size_t lds,
-                                  const void *pk, const double *W, double wscale, double *out, double *rho2)
+static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                                  size_t lds, const void *pk, const double *W, double wscale, double *out,
+                                  double *rho2)
 {
     hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU>), dim3(xcd_grid(g.nbatch)), dim3(64 * kForceWaves), lds, s, g,
-                       bn, b, static_cast<const T *>(pk), W, wscale, out, rho2);
+                       bn, b, nbmax, static_cast<const T *>(pk), W, wscale, out, rho2);
     return hipGetLastError();
 }
 
@@ -1231,14 +1247,14 @@ static hipError_t launch_force_p(hipStream_t s, const Geo &g, const Bins &bn, co
 {
     const int rows = (nbmax * mno + 15) & ~15;
     const int ku = (rows / 16 + kForceWaves - 1) / kForceWaves;
-    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb;
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb + sizeof(int) * (size_t)nbmax * nbmax;
     if (lds + 20480 > 163840)  // with the kernel's static LDS
         return launch_batch_p<RHO ? kRhoForce : kForce, T, P>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
     switch (ku) {
     case 0:
-    case 1: return launch_packed_k<RHO, T, P, 1>(s, g, bn, b, lds, pk, W, wscale, out, rho2);
-    case 2: return launch_packed_k<RHO, T, P, 2>(s, g, bn, b, lds, pk, W, wscale, out, rho2);
-    case 3: return launch_packed_k<RHO, T, P, 3>(s, g, bn, b, lds, pk, W, wscale, out, rho2);
+    case 1: return launch_packed_k<RHO, T, P, 1>(s, g, bn, b, nbmax, lds, pk, W, wscale, out, rho2);
+    case 2: return launch_packed_k<RHO, T, P, 2>(s, g, bn, b, nbmax, lds, pk, W, wscale, out, rho2);
+    case 3: return launch_packed_k<RHO, T, P, 3>(s, g, bn, b, nbmax, lds, pk, W, wscale, out, rho2);
     default: return launch_batch_p<RHO ? kRhoForce : kForce, T, P>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
     }
 }
