@@ -69,7 +69,10 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
     __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms];
     __shared__ double s_w[kMaxP];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    // (the wave index through readfirstlane: known uniform, so that the
+    // block bookkeeping that depends on it stays in scalar registers)
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+              nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int b = xcd_batch(blockIdx.x, b0, b1 - b0);
     if (b < 0)
@@ -242,7 +245,10 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
     __shared__ float s_sw[P];
     __shared__ unsigned s_neg[P];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    // (the wave index through readfirstlane: known uniform, so that the
+    // block bookkeeping that depends on it stays in scalar registers)
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+              nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int b = xcd_batch(blockIdx.x, b0, b1 - b0);
     if (b < 0)
@@ -637,7 +643,7 @@ __global__ __launch_bounds__(64 * batch_waves<MODE>()) void k_batch(Geo g, Bins 
     __shared__ double s_w[kMaxP];
     __shared__ double s_F[FORCE ? kMaxBatchAtoms : 1][3];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
     const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
     if (b < 0)
@@ -977,7 +983,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     __shared__ double s_w[kMaxP];
     __shared__ double s_F[kMaxBatchAtoms][3];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
     const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
     if (b < 0)
