@@ -234,6 +234,9 @@ def main():
                     help="time one contraction only (short profiler runs)")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="H beside the rho + force pass on two streams (gint_H_rho_force); the per-kernel "
+                         "durations (and the roofline) then include the time the kernels share the GPU")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (counter calibration)")
     ap.add_argument("--traffic-from", default=None, metavar="DIR",
@@ -288,6 +291,9 @@ def main():
     def step():
         if args.only is None:
             plan.set_positions(w.positions)
+        if args.only is None and args.concurrent:
+            plan.H_rho_force(V, D, H=H, rho=rho, out=F)  # H beside the rho + force pass
+            return
         if args.only in (None, "H"):
             plan.build_H(V, out=H)
         if (args.only is None and not args.separate) or args.only == "rho_force":
@@ -380,7 +386,9 @@ def main():
         "config": {
             "workload": f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh {'x'.join(map(str, w.grid))}, "
                         "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR"
-                        + (" (rho and dE/dR as two passes)" if args.separate else " (rho from the force pass)"),
+                        + (" (rho and dE/dR as two passes)" if args.separate else
+                           " (rho from the force pass, concurrent with H on a second stream)" if args.concurrent
+                           else " (rho from the force pass)"),
             "batch": list(work["batch"]), "h_slabs": work["nslab"], "group_pairs": work["npair"],
             "sum_ng2": s2, "sum_ng": s1,
         },

@@ -180,6 +180,20 @@ gint_status gint_force_weighted(gint_plan plan, const double *w_dev, const doubl
 gint_status gint_rho_force(gint_plan plan, const double *W_dev, const double *D_dev, double *rho_dev,
                            double *dEdR_dev);
 
+/* H (gint_build_H), rho and the force (gint_rho_force) of one potential V
+ * and density matrix D in one call, the H path on the plan's stream and the
+ * rho / force pass on a second stream of the plan (default priority), which
+ * forks from the plan's stream at the call and joins it before the call's
+ * work is complete on the plan's stream.  The paper runs independent
+ * integration work on several streams (Sec. 3.3.1); H needs only V, the
+ * force pass V and D, and their buffers are disjoint, so the two overlap.
+ * Results are bitwise those of the two separate calls.  Arguments as
+ * gint_build_H and gint_rho_force; H_dev, rho_dev and dEdR_dev must not
+ * overlap.  Errors as the separate calls (GINT_EDEVICE if the second stream
+ * cannot be created). */
+gint_status gint_H_rho_force(gint_plan plan, const double *V_dev, const double *D_dev, double *H_dev,
+                             double *rho_dev, double *dEdR_dev);
+
 /* Kernel classes reported by gint_plan_timing. */
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */

@@ -30,7 +30,7 @@ EXPORTS = (
     "gint_build_H", "gint_build_H_weighted", "gint_build_rho", "gint_force",
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
-    "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force",
+    "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force", "gint_H_rho_force",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).argtypes = [P, P, P, P]
     lib.gint_rho_force.restype = st
     lib.gint_rho_force.argtypes = [P, P, P, P, P]
+    lib.gint_H_rho_force.restype = st
+    lib.gint_H_rho_force.argtypes = [P, P, P, P, P, P]
     lib.gint_plan_sync.restype = st
     lib.gint_plan_sync.argtypes = [P]
     lib.gint_plan_work.restype = st
@@ -343,6 +345,25 @@ class GintPlan:
         op = _dev_ptr(out, self.natom * 3, "dEdR")
         _check(self._lib.gint_rho_force(self._handle(), wp, dp, rp, op))
         return rho, out
+
+    def H_rho_force(self, V, D, H=None, rho=None, out=None):
+        """(H, rho, dE/dR) of one V and D in one call: the H path and the
+        rho / force pass run concurrently on two streams."""
+        import torch
+
+        vp = _dev_ptr(V, self.ngrid, "V")
+        dp = _dev_ptr(D, self.norb * self.norb, "D")
+        if H is None:
+            H = torch.empty((self.norb, self.norb), dtype=torch.float64, device=V.device)
+        if rho is None:
+            rho = torch.empty(self.ngrid, dtype=torch.float64, device=V.device)
+        if out is None:
+            out = torch.empty((self.natom, 3), dtype=torch.float64, device=V.device)
+        hp = _dev_ptr(H, self.norb * self.norb, "H")
+        rp = _dev_ptr(rho, self.ngrid, "rho")
+        op = _dev_ptr(out, self.natom * 3, "dEdR")
+        _check(self._lib.gint_H_rho_force(self._handle(), vp, dp, hp, rp, op))
+        return H, rho, out
 
 
 def build_H(plan: GintPlan, V, out=None):

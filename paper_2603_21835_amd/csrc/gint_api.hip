@@ -88,6 +88,10 @@ struct gint_plan_s {
     unsigned magic = kMagic;
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream of gint_H_rho_force (created on first use) and its
+    // fork / join events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     gint_precision prec = GINT_FP64;
     Geo geo{};
     int natom = 0, norb = 0, nrad = 0, nspecies = 0;
@@ -132,6 +136,14 @@ struct gint_plan_s {
 
     ~gint_plan_s()
     {
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_fork)
+            (void)hipEventDestroy(ev_fork);
+        if (ev_join)
+            (void)hipEventDestroy(ev_join);
         for (auto &m : marks) {
             (void)hipEventDestroy(m.a);
             (void)hipEventDestroy(m.b);
@@ -940,24 +952,28 @@ gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
     return GINT_OK;
 }
 
+// st: the stream the pass runs on (the plan's, or the second stream of
+// gint_H_rho_force)
 static gint_status force_impl(gint_plan p, const double *W, double wscale, const double *D, double *dEdR,
-                              double *rho = nullptr)
+                              double *rho = nullptr, hipStream_t st = nullptr)
 {
     STCHK(check_plan(p));
     if (!W || !D || !dEdR)
         return fail(GINT_EINVAL, "W, D and dEdR must be non-NULL device pointers");
     HIPCHK(hipSetDevice(p->device));
+    if (!st)
+        st = p->stream;
     const Bins bn = p->bins();
     const Basis B = p->basis();
-    STCHK(timed(p, GINT_K_PACK, [&] {
-        return launch_pack_S2(p->stream, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
+    STCHK(timed_on(p, st, GINT_K_PACK, [&] {
+        return launch_pack_S2(st, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
     }));
-    STCHK(timed(p, rho ? GINT_K_RHO_FORCE : GINT_K_FORCE, [&] {
-        return launch_force_batch(p->stream, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, W, wscale,
+    STCHK(timed_on(p, st, rho ? GINT_K_RHO_FORCE : GINT_K_FORCE, [&] {
+        return launch_force_batch(st, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, W, wscale,
                                   p->Fent.as<double>(), rho);
     }));
-    STCHK(timed(p, GINT_K_F_REDUCE,
-                [&] { return launch_force_reduce(p->stream, p->geo, bn, B, p->Fent.as<double>(), dEdR); }));
+    STCHK(timed_on(p, st, GINT_K_F_REDUCE,
+                   [&] { return launch_force_reduce(st, p->geo, bn, B, p->Fent.as<double>(), dEdR); }));
     return GINT_OK;
 }
 
@@ -978,6 +994,30 @@ gint_status gint_rho_force(gint_plan p, const double *W_dev, const double *D_dev
     if (!rho_dev)
         return fail(GINT_EINVAL, "rho must be a non-NULL device pointer");
     return force_impl(p, W_dev, p->dV, D_dev, dEdR_dev, rho_dev);
+}
+
+gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_dev, double *H_dev, double *rho_dev,
+                             double *dEdR_dev)
+{
+    STCHK(check_plan(p));
+    if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
+        return fail(GINT_EINVAL, "V, D, H, rho and dEdR must be non-NULL device pointers");
+    HIPCHK(hipSetDevice(p->device));
+    if (!p->aux) {
+        // default priority, like every stream of the library
+        HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    }
+    // fork: rho and the force on the second stream, H on the plan's stream;
+    // join: the plan's stream waits for both
+    HIPCHK(hipEventRecord(p->ev_fork, p->stream));
+    HIPCHK(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+    STCHK(force_impl(p, V_dev, p->dV, D_dev, dEdR_dev, rho_dev, p->aux));
+    STCHK(build_H_impl(p, V_dev, p->dV, H_dev));
+    HIPCHK(hipEventRecord(p->ev_join, p->aux));
+    HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join, 0));
+    return GINT_OK;
 }
 
 gint_status gint_plan_sync(gint_plan p)

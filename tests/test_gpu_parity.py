@@ -258,3 +258,28 @@ def test_rho_force_si512_sampled(oracle_mod, torch_dev):
     er = _rel_l2(rho.cpu().numpy()[idx], o.rho(w.D, idx))
     _say(f"  rho sampled: {er:.2e}")
     assert er <= TOL
+
+
+@pytest.mark.parametrize("make", [_triclinic_two_species, gi.si64_dzp], ids=["triclinic", "si64"])
+def test_H_rho_force_two_streams(oracle_mod, torch_dev, make):
+    # gint_H_rho_force (H beside the rho + force pass on a second stream):
+    # bitwise the separate calls, twice in a row (the second reuses the
+    # plan's second stream), and against the oracle on sampled points
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = make()
+    _say(f"case H_rho_force {make.__name__}")
+    plan = g.GintPlan.from_workload(w)
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    H1, rho1, F1 = (t.cpu().numpy() for t in plan.H_rho_force(V, D))
+    H2, rho2, F2 = (t.cpu().numpy() for t in plan.H_rho_force(V, D))
+    Hs = plan.build_H(V).cpu().numpy()
+    rs, Fs = (t.cpu().numpy() for t in plan.rho_force(V, D))
+    for a, b2, c in ((H1, H2, Hs), (rho1, rho2, rs), (F1, F2, Fs)):
+        assert np.array_equal(a, b2) and np.array_equal(a, c)
+    o = oracle_mod.Oracle.from_workload(w)
+    idx = np.random.default_rng(3).choice(w.ngrid, min(w.ngrid, 4000), replace=False)
+    er = _rel_l2(rho1[idx], o.rho(w.D, idx))
+    _say(f"  rho sampled {er:.2e}")
+    assert er <= TOL
