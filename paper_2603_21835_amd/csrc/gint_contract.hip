@@ -1001,7 +1001,6 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         const int atom = bn.ent_atom[e0 + a];
         s_atom[a] = atom;
         s_spc[a] = bs.spc[atom];
-        s_grank[a] = lower_bound_i(bn.bgrp, g0, g0 + ngb, atom / kGroup) - g0;
         s_F[a][0] = s_F[a][1] = s_F[a][2] = 0.0;
     }
     for (int k = tid; k < ngb * ngb; k += NT) {
@@ -1014,17 +1013,24 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
     }
     __syncthreads();
-    // row offsets of the atoms: an inclusive scan of their orbital counts (nb <= 64)
+    // row offsets of the atoms (an inclusive scan of their orbital counts) and
+    // their group ranks (atoms are increasing, so the rank of an atom's group
+    // among the batch's groups counts the group changes before it); nb <= 64
     if (wave == 0) {
         int v = lane < nb ? s_sp[s_spc[lane]].norb : 0;
+        int c = (lane > 0 && lane < nb && s_atom[lane] / kGroup != s_atom[lane - 1] / kGroup) ? 1 : 0;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(v, o);
-            if (lane >= o)
+            const int t = __shfl_up(v, o), tc = __shfl_up(c, o);
+            if (lane >= o) {
                 v += t;
+                c += tc;
+            }
         }
-        if (lane < nb)
+        if (lane < nb) {
             s_off[lane + 1] = v;
+            s_grank[lane] = c;
+        }
         if (lane == 0)
             s_off[0] = 0;
     }
