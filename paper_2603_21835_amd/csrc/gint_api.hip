@@ -119,6 +119,7 @@ struct gint_plan_s {
     DevBuf Hpart, S2pk, Fent, sums, readback;
     DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist, lcnt, lptr, blist;
     DevBuf pown, lsl, slabq;  // owner of each owned pair; slab ranges of its block list
+    DevBuf scan_tmp;          // tile sums of the list scans
     int npair_owned = 0;          // owned atom pairs (entries of plist)
     std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
@@ -337,6 +338,14 @@ gint_status timed(gint_plan p, int kind, F launch)
     return timed_on(p, p->stream, kind, launch);
 }
 
+// exclusive scan of n ints on stream st (out: n + 1 ints)
+gint_status scan_i32(gint_plan p, hipStream_t st, const int *in, long long n, int *out)
+{
+    STCHK(p->scan_tmp.ensure(sizeof(int) * (size_t)scan_tmp_ints(n)));
+    HIPCHK(launch_scan_i32(st, in, n, out, p->scan_tmp.as<int>()));
+    return GINT_OK;
+}
+
 template <typename T>
 gint_status read_scalar(gint_plan p, const T *dev, T *host)
 {
@@ -369,9 +378,9 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_bin_count(s, g, B, p->cnt_e.as<int>(), p->cnt_i.as<int>(), p->cnt_g.as<int>());
     }));
-    HIPCHK(launch_scan_i32(s, p->cnt_e.as<int>(), nb, p->bptr.as<int>()));
-    HIPCHK(launch_scan_i32(s, p->cnt_i.as<int>(), nb, p->iptr.as<int>()));
-    HIPCHK(launch_scan_i32(s, p->cnt_g.as<int>(), nb, p->bgptr.as<int>()));
+    STCHK(scan_i32(p, s, p->cnt_e.as<int>(), nb, p->bptr.as<int>()));
+    STCHK(scan_i32(p, s, p->cnt_i.as<int>(), nb, p->iptr.as<int>()));
+    STCHK(scan_i32(p, s, p->cnt_g.as<int>(), nb, p->bgptr.as<int>()));
     // totals (counts are far below 2^31 for any mesh this library accepts,
     // but the image total is checked explicitly)
     int tot[5];
@@ -418,7 +427,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->gptr.ensure(sizeof(int) * (ng + 1)));
     STCHK(timed(p, GINT_K_BIN,
                 [&] { return launch_group_count(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->gcnt.as<int>()); }));
-    HIPCHK(launch_scan_i32(s, p->gcnt.as<int>(), ngc, p->gcoff.as<int>()));
+    STCHK(scan_i32(p, s, p->gcnt.as<int>(), ngc, p->gcoff.as<int>()));
     int tg = 0;
     STCHK(read_scalar(p, p->gcoff.as<int>() + ngc, &tg));
     if (tg < 0)
@@ -438,7 +447,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     HIPCHK(launch_fill_i32(s, p->mark.as<int>(), nn, 0));
     STCHK(timed(p, GINT_K_BIN,
                 [&] { return launch_pair_mark(s, g, p->bgptr.as<int>(), p->bgrp.as<int>(), p->mark.as<int>()); }));
-    HIPCHK(launch_scan_i32(s, p->mark.as<int>(), nn, p->mscan.as<int>()));
+    STCHK(scan_i32(p, s, p->mark.as<int>(), nn, p->mscan.as<int>()));
     int tp = 0;
     STCHK(read_scalar(p, p->mscan.as<int>() + nn, &tp));
     p->npair = tp;
@@ -453,7 +462,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->cnt_blk.ensure(sizeof(int) * nb));
     STCHK(p->boff.ensure(sizeof(int) * (nb + 1)));
     HIPCHK(launch_block_count(s, g.nbatch, p->bptr.as<int>(), p->cnt_blk.as<int>()));
-    HIPCHK(launch_scan_i32(s, p->cnt_blk.as<int>(), nb, p->boff.as<int>()));
+    STCHK(scan_i32(p, s, p->cnt_blk.as<int>(), nb, p->boff.as<int>()));
     // (na: atom count, set above)
     STCHK(p->acnt.ensure(sizeof(int) * na));
     STCHK(p->aptr.ensure(sizeof(int) * (na + 1)));
@@ -463,7 +472,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
         return launch_atom_count(s, na, p->gptr.as<int>(), p->gbatch.as<int>(), p->bptr.as<int>(),
                                  p->ent_atom.as<int>(), p->acnt.as<int>());
     }));
-    HIPCHK(launch_scan_i32(s, p->acnt.as<int>(), na, p->aptr.as<int>()));
+    STCHK(scan_i32(p, s, p->acnt.as<int>(), na, p->aptr.as<int>()));
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_atom_fill(s, na, p->gptr.as<int>(), p->gbatch.as<int>(), p->bptr.as<int>(),
                                 p->ent_atom.as<int>(), p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>());
@@ -472,7 +481,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(p->pptr.ensure(sizeof(int) * (na + 1)));
     const Basis B2 = p->basis();
     STCHK(timed(p, GINT_K_BIN, [&] { return launch_partners(s, g, B2, p->brad, nullptr, p->pcnt.as<int>(), nullptr); }));
-    HIPCHK(launch_scan_i32(s, p->pcnt.as<int>(), na, p->pptr.as<int>()));
+    STCHK(scan_i32(p, s, p->pcnt.as<int>(), na, p->pptr.as<int>()));
     std::vector<int> hboff(nb + 1);
     int tpart = 0;
     HIPCHK(hipMemcpyAsync(hboff.data(), p->boff.p, sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, s));
@@ -494,7 +503,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
                                   p->bptr.as<int>(), p->boff.as<int>(), p->pptr.as<int>(), p->plist.as<int>(),
                                   p->lcnt.as<int>(), nullptr, nullptr);
     }));
-    HIPCHK(launch_scan_i32(s, p->lcnt.as<int>(), tpart, p->lptr.as<int>()));
+    STCHK(scan_i32(p, s, p->lcnt.as<int>(), tpart, p->lptr.as<int>()));
     int tlist = 0;
     HIPCHK(hipMemcpyAsync(&tlist, p->lptr.as<int>() + tpart, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

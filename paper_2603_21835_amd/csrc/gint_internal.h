@@ -104,8 +104,9 @@ hipError_t launch_bin_count(hipStream_t s, const Geo &g, const Basis &b, int *cn
 hipError_t launch_bin_fill(hipStream_t s, const Geo &g, const Basis &b, const int *bptr,
                            const int *iptr, const int *bgptr, int *ent_atom, int *ent_img, int *img,
                            int *bgrp);
-hipError_t launch_scan_i32(hipStream_t s, const int *in, long long n, int *out);
-hipError_t launch_scan_i64(hipStream_t s, const long long *in, long long n, long long *out);
+// exclusive scan (out: n + 1 ints, out[n] = total); tmp: scan_tmp_ints(n) ints
+int scan_tmp_ints(long long n);
+hipError_t launch_scan_i32(hipStream_t s, const int *in, long long n, int *out, int *tmp);
 int group_chunks(const Geo &g);  // chunks of the per-group batch list construction
 hipError_t launch_group_count(hipStream_t s, const Geo &g, const int *bgptr, const int *bgrp,
                               int *cnt /* ngroup * group_chunks */);

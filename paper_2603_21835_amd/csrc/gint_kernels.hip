@@ -363,47 +363,110 @@ hipError_t launch_bin_fill(hipStream_t s, const Geo &g, const Basis &b, const in
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan, one workgroup: out[i] = sum_{j<i} in[j], out[n] = total.
+// Exclusive scan out[i] = sum_{j<i} in[j], out[n] = total, in three passes
+// over tiles of kScanTile elements (1024 threads x 4 consecutive elements):
+// tile sums; an exclusive scan of the tile sums (one workgroup); each tile
+// scanned and offset by its tile's sum.  tmp holds the tile sums
+// (ceil(n / kScanTile) ints).
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_scan(const T *__restrict__ in, long long n, T *__restrict__ out)
+constexpr int kScanTile = 4096;
+
+// inclusive scan over the 1024 threads of a workgroup; returns the exclusive
+// prefix of this thread, *total the workgroup's sum
+__device__ __forceinline__ int block_scan_excl(int v, int *s_w, int *total)
 {
-    __shared__ T part[1024];
-    const int t = threadIdx.x;
-    const long long per = (n + 1023) / 1024;
-    const long long lo = t * per;
-    const long long hi = (lo + per < n) ? lo + per : n;
-    T s = 0;
-    for (long long i = lo; i < hi; ++i)
-        s += in[i];
-    part[t] = s;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        s_w[w] = x;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        T v = (t >= off) ? part[t - off] : (T)0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    if (w == 0) {
+        int u = lane < 16 ? s_w[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(u, o);
+            if (lane >= o)
+                u += y;
+        }
+        if (lane < 16)
+            s_w[16 + lane] = u;  // inclusive prefix of the wave sums
     }
-    T run = (t == 0) ? (T)0 : part[t - 1];
-    for (long long i = lo; i < hi; ++i) {
-        const T v = in[i];
-        out[i] = run;
-        run += v;
-    }
-    if (t == 1023)
-        out[n] = part[1023];
+    __syncthreads();
+    *total = s_w[31];
+    const int before = w > 0 ? s_w[16 + w - 1] : 0;
+    return before + x - v;
 }
 
-hipError_t launch_scan_i32(hipStream_t s, const int *in, long long n, int *out)
+__global__ __launch_bounds__(1024) void k_scan_tiles(const int *__restrict__ in, long long n, int *__restrict__ tsum)
 {
-    hipLaunchKernelGGL(k_scan<int>, dim3(1), dim3(1024), 0, s, in, n, out);
-    return hipGetLastError();
+    __shared__ int s_w[32];
+    const long long base = (long long)blockIdx.x * kScanTile + 4 * (long long)threadIdx.x;
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n)
+            v += in[base + k];
+    int total;
+    (void)block_scan_excl(v, s_w, &total);
+    if (threadIdx.x == 0)
+        tsum[blockIdx.x] = total;
 }
 
-hipError_t launch_scan_i64(hipStream_t s, const long long *in, long long n, long long *out)
+__global__ __launch_bounds__(1024) void k_scan_top(int *__restrict__ tsum, int ntile, int *__restrict__ total_out)
 {
-    hipLaunchKernelGGL(k_scan<long long>, dim3(1), dim3(1024), 0, s, in, n, out);
+    __shared__ int s_w[32];
+    int carry = 0;
+    for (int c = 0; c < ntile; c += 1024) {
+        const int i = c + threadIdx.x;
+        const int v = i < ntile ? tsum[i] : 0;
+        int total;
+        const int ex = block_scan_excl(v, s_w, &total);
+        if (i < ntile)
+            tsum[i] = carry + ex;
+        carry += total;
+        __syncthreads();  // s_w reused by the next chunk
+    }
+    if (threadIdx.x == 0)
+        *total_out = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(const int *__restrict__ in, long long n,
+                                                     const int *__restrict__ toff, int *__restrict__ out)
+{
+    __shared__ int s_w[32];
+    const long long base = (long long)blockIdx.x * kScanTile + 4 * (long long)threadIdx.x;
+    int v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int total;
+    int run = toff[blockIdx.x] + block_scan_excl(sum, s_w, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) {
+            out[base + k] = run;
+            run += v[k];
+        }
+}
+
+int scan_tmp_ints(long long n) { return (int)((n + kScanTile - 1) / kScanTile) + 1; }
+
+hipError_t launch_scan_i32(hipStream_t s, const int *in, long long n, int *out, int *tmp)
+{
+    const long long nt = (n + kScanTile - 1) / kScanTile;
+    if (nt == 0)
+        return launch_fill_i32(s, out, 1, 0);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(1024), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, (int)nt, out + n);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(1024), 0, s, in, n, tmp, out);
     return hipGetLastError();
 }
 
