@@ -959,6 +959,10 @@ static hipError_t launch_batch_t(hipStream_t s, const Geo &g, const Bins &bn, co
 // LDS: phi / T as [atom][P / 16 point tiles][16 orbitals][16 points].
 
 constexpr int kForceWaves = 12;
+// 16 x 16 (orbital x point) tiles with a row pitch of 17 elements: operand
+// reads along points (the force's right operand, T) and along orbitals (the
+// H operands) are both free of bank conflicts
+constexpr int kPitch = 17, kTile = 16 * kPitch;
 
 template <bool RHO, typename T, int P, int KU>
 __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, int nbmax,
@@ -971,7 +975,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     T *s_phi = reinterpret_cast<T *>(s_dyn);
     // after phi: the packed-fragment block of every slot pair (x, y), in
     // units of 256 elements: (pair * 16 + block) * 2 + orientation
-    int *s_bb = reinterpret_cast<int *>(s_dyn + sizeof(T) * (size_t)nbmax * NS * 256);
+    int *s_bb = reinterpret_cast<int *>(s_dyn + sizeof(T) * (size_t)nbmax * NS * kTile);
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_spc[kMaxBatchAtoms], s_off[kMaxBatchAtoms + 1];
@@ -1065,27 +1069,27 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         const int a = idx / P, p = idx % P;
         const int e = e0 + a;
         const int atom = s_atom[a];
-        // orbital o of this point at row[16 o]
-        T *row = s_phi + (size_t)(a * NS + (p >> 4)) * 256 + (p & 15);
+        // orbital o of this point at row[kPitch o]
+        T *row = s_phi + (size_t)(a * NS + (p >> 4)) * kTile + (p & 15);
         int n[3];
         const bool valid = batch_point(g, ib, p, n);
         const DevSpecies &S = s_sp[s_spc[a]];
         const int zlo = valid ? S.norb : 0;
         for (int o = zlo; o < kMaxOrb; ++o)
-            row[16 * o] = (T)0;
+            row[kPitch * o] = (T)0;
         if (valid) {
             const int io = bn.ent_img[e];
             const int cnt = bn.ent_img[e + 1] - io;
             const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
             double r[3];
             mesh_cart(g, n, r);
-            eval_orbitals<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
-                                 r, row);
+            eval_orbitals<T, kPitch>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io,
+                                     bn.img, r, row);
         }
     }
     __syncthreads();
-    // tile s2 of atom slot x: element (orbital o, point q) at [16 o + q]
-    auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * 256; };
+    // tile s2 of atom slot x: element (orbital o, point q) at [kPitch o + q]
+    auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * kTile; };
 
     // ---- phase A ----
     const int ntile = nrp >> 4;
@@ -1121,10 +1125,10 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         auto mblock = [&](const T (&a4)[4], int y) {
 #pragma unroll
             for (int s2 = 0; s2 < NS; ++s2) {
-                const T *pB = tile(y, s2) + 16 * lk + li;
+                const T *pB = tile(y, s2) + kPitch * lk + li;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[u][s2] = MM<T>::mma(a4[j], pB[64 * j], acc[u][s2]);
+                    acc[u][s2] = MM<T>::mma(a4[j], pB[4 * kPitch * j], acc[u][s2]);
             }
         };
         // three register sets in rotation: an atom's D values are loaded two
@@ -1154,7 +1158,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int c = s_row[16 * ti + MM<T>::row(lk, v)];
-                    const T ph = c >= 0 ? tile(c >> 16, s2)[16 * (c & 15) + li] : (T)0;
+                    const T ph = c >= 0 ? tile(c >> 16, s2)[kPitch * (c & 15) + li] : (T)0;
                     dot += (double)acc[u][s2][v] * (double)ph;
                 }
                 rp[s2] += dot;
@@ -1183,7 +1187,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             if (c >= 0)
 #pragma unroll
                 for (int s2 = 0; s2 < NS; ++s2)
-                    tile(c >> 16, s2)[16 * (c & 15) + li] = acc[u][s2][v];
+                    tile(c >> 16, s2)[kPitch * (c & 15) + li] = acc[u][s2][v];
         }
     }
     __syncthreads();
@@ -1205,8 +1209,8 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             const int cnt = bn.ent_img[e + 1] - io;
             double r[3];
             mesh_cart(g, n, r);
-            grad_dot_all<T, 16>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r,
-                                tile(a, p >> 4) + (p & 15), s_w[p], fx);
+            grad_dot_all<T, kPitch>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io,
+                                    bn.img, r, tile(a, p >> 4) + (p & 15), s_w[p], fx);
         }
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
@@ -1259,7 +1263,7 @@ static hipError_t launch_force_p(hipStream_t s, const Geo &g, const Bins &bn, co
 {
     const int rows = (nbmax * mno + 15) & ~15;
     const int ku = (rows / 16 + kForceWaves - 1) / kForceWaves;
-    const size_t lds = sizeof(T) * (size_t)nbmax * P * kMaxOrb + sizeof(int) * (size_t)nbmax * nbmax;
+    const size_t lds = sizeof(T) * (size_t)nbmax * (P / 16) * kTile + sizeof(int) * (size_t)nbmax * nbmax;
     if (lds + 20480 > 163840)  // with the kernel's static LDS
         return launch_batch_p<RHO ? kRhoForce : kForce, T, P>(s, g, bn, b, nbmax, pk, W, wscale, out, rho2);
     switch (ku) {
