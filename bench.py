@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -55,7 +56,8 @@ def _traffic(kernel: str, workload: str, precision: str):
 
 
 # device kernel (symbol prefix) behind each timing kind whose traffic is recorded
-KERNEL_SYMBOLS = {"rho_force": "k_force_packed", "H_blocks": "k_H_batch", "H_reduce": "k_H_pairreduce"}
+KERNEL_SYMBOLS = {"rho_force": r"k_force_packed<[^>]*, false>", "H_rho_force": r"k_force_packed<[^>]*, true>",
+                  "H_blocks": r"k_H_batch<", "H_reduce": r"k_H_pairreduce<"}
 
 
 def _counter_csv(d: str, counter: str):
@@ -88,7 +90,7 @@ def write_traffic(args):
     for name, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
         copy_kib = max(v for _, v in _counter_csv(os.path.join(d, "copy_" + name), counter))
         factor = copy_bytes / (copy_kib * 1024.0)
-        vals = [v for k, v in _counter_csv(os.path.join(d, name), counter) if sym in k]
+        vals = [v for k, v in _counter_csv(os.path.join(d, name), counter) if re.search(sym, k)]
         if not vals:
             raise SystemExit(f"no {sym} dispatch in {d}/{name}")
         per = sum(vals) / len(vals) * 1024.0 * factor
@@ -230,13 +232,13 @@ def main():
     ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
-    ap.add_argument("--only", default=None, choices=["H", "rho", "force", "rho_force"],
+    ap.add_argument("--only", default=None, choices=["H", "rho", "force", "rho_force", "H_rho_force"],
                     help="time one contraction only (short profiler runs)")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
-    ap.add_argument("--concurrent", action="store_true",
-                    help="H beside the rho + force pass on two streams (gint_H_rho_force); the per-kernel "
-                         "durations (and the roofline) then include the time the kernels share the GPU")
+    ap.add_argument("--serial", action="store_true",
+                    help="H and the rho + force pass as two calls (gint_build_H + gint_rho_force) instead of "
+                         "gint_H_rho_force")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (counter calibration)")
     ap.add_argument("--traffic-from", default=None, metavar="DIR",
@@ -291,8 +293,8 @@ def main():
     def step():
         if args.only is None:
             plan.set_positions(w.positions)
-        if args.only is None and args.concurrent:
-            plan.H_rho_force(V, D, H=H, rho=rho, out=F)  # H beside the rho + force pass
+        if (args.only is None and not args.serial and not args.separate) or args.only == "H_rho_force":
+            plan.H_rho_force(V, D, H=H, rho=rho, out=F)  # H, rho and dE/dR in one call
             return
         if args.only in (None, "H"):
             plan.build_H(V, out=H)
@@ -325,7 +327,7 @@ def main():
     s1, s2 = work["sum_ng"], work["sum_ng2"]
     # algorithmic work per step (per unit: one mesh point with n_g orbitals)
     flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1,
-             "rho_force": 2 * s2 + 8 * s1}
+             "rho_force": 2 * s2 + 8 * s1, "H_rho_force": 4 * s2 + 8 * s1}
     # the H reduction moves every block partial once and writes H's blocks
     hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
               "H_fill": 8 * plan.norb ** 2}
@@ -386,9 +388,10 @@ def main():
         "config": {
             "workload": f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh {'x'.join(map(str, w.grid))}, "
                         "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR"
-                        + (" (rho and dE/dR as two passes)" if args.separate else
-                           " (rho from the force pass, concurrent with H on a second stream)" if args.concurrent
-                           else " (rho from the force pass)"),
+                        + (" (H, rho and dE/dR as three passes)" if args.separate else
+                           " (H, then rho from the force pass)" if args.serial else
+                           " (gint_H_rho_force: one pass per batch for H, rho and dE/dR in FP64 / FP32, H beside "
+                           "the rho + force pass on a second stream in the 16-bit modes)"),
             "batch": list(work["batch"]), "h_slabs": work["nslab"], "group_pairs": work["npair"],
             "sum_ng2": s2, "sum_ng": s1,
         },

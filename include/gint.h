@@ -181,16 +181,17 @@ gint_status gint_rho_force(gint_plan plan, const double *W_dev, const double *D_
                            double *dEdR_dev);
 
 /* H (gint_build_H), rho and the force (gint_rho_force) of one potential V
- * and density matrix D in one call, the H path on the plan's stream and the
- * rho / force pass on a second stream of the plan (default priority), which
- * forks from the plan's stream at the call and joins it before the call's
- * work is complete on the plan's stream.  The paper runs independent
- * integration work on several streams (Sec. 3.3.1); H needs only V, the
- * force pass V and D, and their buffers are disjoint, so the two overlap.
- * Results are bitwise those of the two separate calls.  Arguments as
- * gint_build_H and gint_rho_force; H_dev, rho_dev and dEdR_dev must not
- * overlap.  Errors as the separate calls (GINT_EDEVICE if the second stream
- * cannot be created). */
+ * and density matrix D in one call; results are bitwise those of the two
+ * separate calls.  In the FP64 and FP32 modes one pass per mesh batch
+ * evaluates the orbital tiles once for the H blocks, rho and the force (the
+ * three integrals of Sec. 3.3.1 share the orbital values of a batch); in the
+ * 16-bit modes, or when a batch holds too many orbitals for that pass, the H
+ * path runs on the plan's stream beside the rho / force pass on a second
+ * stream of the plan (default priority), forked from and joined back into the
+ * plan's stream within the call (the paper runs independent integration work
+ * on several streams).  Arguments as gint_build_H and gint_rho_force; H_dev,
+ * rho_dev and dEdR_dev must not overlap.  Errors as the separate calls
+ * (GINT_EDEVICE if the second stream cannot be created). */
 gint_status gint_H_rho_force(gint_plan plan, const double *V_dev, const double *D_dev, double *H_dev,
                              double *rho_dev, double *dEdR_dev);
 
@@ -205,7 +206,8 @@ enum {
     GINT_K_F_REDUCE = 6,  /* force reduction per atom                               */
     GINT_K_H_FILL = 7,    /* zero fill of dense H                                   */
     GINT_K_RHO_FORCE = 8, /* rho and force contraction in one pass                  */
-    GINT_NKERNEL = 9
+    GINT_K_H_RHO_FORCE = 9, /* H blocks, rho and force in one pass (gint_H_rho_force) */
+    GINT_NKERNEL = 10
 };
 
 /* Enable (1) or disable (0) timing: each kernel launch of later calls is

@@ -34,7 +34,8 @@ EXPORTS = (
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
-KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force")
+KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
+           "H_rho_force")
 
 
 class GintError(RuntimeError):
@@ -347,8 +348,8 @@ class GintPlan:
         return rho, out
 
     def H_rho_force(self, V, D, H=None, rho=None, out=None):
-        """(H, rho, dE/dR) of one V and D in one call: the H path and the
-        rho / force pass run concurrently on two streams."""
+        """(H, rho, dE/dR) of one V and D in one call (one pass over the mesh
+        batches for all three in the FP64 / FP32 modes)."""
         import torch
 
         vp = _dev_ptr(V, self.ngrid, "V")

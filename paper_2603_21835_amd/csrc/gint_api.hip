@@ -1012,6 +1012,35 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
     if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
         return fail(GINT_EINVAL, "V, D, H, rho and dEdR must be non-NULL device pointers");
     HIPCHK(hipSetDevice(p->device));
+    if ((p->prec == GINT_FP64 || p->prec == GINT_FP32) && H_rho_force_fits(p->f32(), p->geo.P, p->nbmax, p->mno)) {
+        // one pass per H slab evaluates each batch's orbital tiles once for
+        // the H blocks, rho and the force partials
+        const Bins bn = p->bins();
+        const Basis B = p->basis();
+        const hipStream_t st = p->stream;
+        STCHK(timed(p, GINT_K_H_FILL,
+                    [&] { return launch_fill_f64(st, H_dev, (long long)p->norb * p->norb, 0.0); }));
+        STCHK(timed(p, GINT_K_PACK, [&] {
+            return launch_pack_S2(st, p->f32(), p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.p);
+        }));
+        for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
+            const int b0 = p->slab[i], b1 = p->slab[i + 1];
+            STCHK(timed(p, GINT_K_H_RHO_FORCE, [&] {
+                return launch_H_rho_force(st, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, V_dev, p->dV,
+                                          p->Fent.as<double>(), rho_dev, b0, b1, p->boff.as<int>(), p->hpart());
+            }));
+            STCHK(timed(p, GINT_K_H_REDUCE, [&] {
+                return launch_H_pairreduce(st, p->f32(), p->npair_owned, p->pown.as<int>(), p->plist.as<int>(),
+                                           p->lsl.as<int>(), (int)p->slab.size() - 1, (int)i, p->blist.as<int>(), B,
+                                           p->mno, p->norb, p->hpart(), p->slab_q[i], i > 0 ? 1 : 0, H_dev);
+            }));
+        }
+        STCHK(timed(p, GINT_K_F_REDUCE,
+                    [&] { return launch_force_reduce(st, p->geo, bn, B, p->Fent.as<double>(), dEdR_dev); }));
+        return GINT_OK;
+    }
+    // 16-bit H modes (or batches too large for the fused pass): H beside the
+    // rho + force pass on a second stream
     if (!p->aux) {
         // default priority, like every stream of the library
         HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));

@@ -964,11 +964,17 @@ constexpr int kForceWaves = 12;
 // H operands) are both free of bank conflicts
 constexpr int kPitch = 17, kTile = 16 * kPitch;
 
-template <bool RHO, typename T, int P, int KU>
+// HB: the H blocks of the batch as well (batches b0 .. b1 - 1, one H slab),
+// from the same orbital tiles, before phase A: block (ia <= ja) as in
+// k_H_batch (same operands, same order: the same bits), written to part at
+// block offset boff[b] - boff[b0] + k.
+template <bool RHO, typename T, int P, int KU, bool HB>
 __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, int nbmax,
                                                                   const T *__restrict__ pk,
                                                                   const double *__restrict__ W, double wscale,
-                                                                  double *__restrict__ out, double *__restrict__ rho2)
+                                                                  double *__restrict__ out, double *__restrict__ rho2,
+                                                                  int b0, int b1, const int *__restrict__ boff,
+                                                                  int mno, T *__restrict__ part)
 {
     constexpr int NW = kForceWaves, NT = 64 * NW, NS = P / 16;
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -989,7 +995,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
 
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
-    const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
+    const int b = HB ? xcd_batch(blockIdx.x, b0, b1 - b0) : xcd_batch(blockIdx.x, 0, g.nbatch);
     if (b < 0)
         return;
     const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
@@ -1090,6 +1096,53 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     __syncthreads();
     // tile s2 of atom slot x: element (orbital o, point q) at [kPitch o + q]
     auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * kTile; };
+
+    if constexpr (HB) {
+        // ---- H blocks (ia <= ja), round-robin over the waves ----
+        const int nblk = nb * (nb + 1) / 2;
+        int ia = 0, ja = 0;
+        tri_advance(ia, ja, wave, nb);
+        const size_t mm = (size_t)block_pitch(mno, sizeof(T));
+        // this lane's points 4 kk + lk: weights, and where (orbital li, point)
+        // sits in an atom's tiles
+        T wl[P / 4];
+        int off[P / 4];
+#pragma unroll
+        for (int kk = 0; kk < P / 4; ++kk) {
+            const int p = 4 * kk + lk;
+            wl[kk] = (T)s_w[p];
+            off[kk] = (p >> 4) * kTile + kPitch * li + (p & 15);
+        }
+        int cur = -1;
+        T aw[P / 4];
+        for (int k = wave; k < nblk; k += NW) {
+            if (ia != cur) {
+                const T *pI = tile(ia, 0);
+#pragma unroll
+                for (int kk = 0; kk < P / 4; ++kk)
+                    aw[kk] = wl[kk] * pI[off[kk]];
+                cur = ia;
+            }
+            const T *pJ = tile(ja, 0);
+            T bv[P / 4];
+#pragma unroll
+            for (int kk = 0; kk < P / 4; ++kk)
+                bv[kk] = pJ[off[kk]];
+            typename MM<T>::acc hc = MM<T>::zero();
+#pragma unroll
+            for (int kk = 0; kk < P / 4; ++kk)
+                hc = MM<T>::mma(aw[kk], bv[kk], hc);
+            const int nI = s_sp[s_spc[ia]].norb, nJ = s_sp[s_spc[ja]].norb;
+            T *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = MM<T>::row(lk, v);
+                if (row < nI && li < nJ)
+                    o[row * mno + li] = hc[v];
+            }
+            tri_advance(ia, ja, NW, nb);
+        }
+    }
 
     // ---- phase A ----
     const int ntile = nrp >> 4;
@@ -1241,17 +1294,20 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         }
 }
 
-template <bool RHO, typename T, int P, int KU>
+template <bool RHO, typename T, int P, int KU, bool HB = false>
 static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                   size_t lds, const void *pk, const double *W, double wscale, double *out,
-                                  double *rho2)
+                                  double *rho2, int b0 = 0, int b1 = 0, const int *boff = nullptr, int mno = 0,
+                                  void *part = nullptr)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU, HB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU>), dim3(xcd_grid(g.nbatch)), dim3(64 * kForceWaves), lds, s, g,
-                       bn, b, nbmax, static_cast<const T *>(pk), W, wscale, out, rho2);
+    const int nbat = HB ? b1 - b0 : g.nbatch;
+    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU, HB>), dim3(xcd_grid(nbat)), dim3(64 * kForceWaves), lds, s,
+                       g, bn, b, nbmax, static_cast<const T *>(pk), W, wscale, out, rho2, b0, b1, boff, mno,
+                       static_cast<T *>(part));
     return hipGetLastError();
 }
 
@@ -1291,6 +1347,56 @@ hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &b
 {
     return f32 ? launch_batch_t<kRho, float>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho, nullptr)
                : launch_batch_t<kRho, double>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho, nullptr);
+}
+
+// the packed form's LDS and row tiles per wave for this plan, or 0 if it
+// does not apply
+template <typename T, int P>
+static int packed_ku(int nbmax, int mno, size_t *lds)
+{
+    const int rows = (nbmax * mno + 15) & ~15;
+    const int ku = (rows / 16 + kForceWaves - 1) / kForceWaves;
+    *lds = sizeof(T) * (size_t)nbmax * (P / 16) * kTile + sizeof(int) * (size_t)nbmax * nbmax;
+    return (*lds + 24576 > 163840 || ku > 3) ? 0 : (ku < 1 ? 1 : ku);
+}
+
+template <typename T, int P>
+static hipError_t launch_hrf_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int mno,
+                               const void *pk, const double *W, double wscale, double *Fent, double *rho, int b0,
+                               int b1, const int *boff, void *part)
+{
+    size_t lds = 0;
+    switch (packed_ku<T, P>(nbmax, mno, &lds)) {
+    case 1: return launch_packed_k<true, T, P, 1, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
+    case 2: return launch_packed_k<true, T, P, 2, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
+    case 3: return launch_packed_k<true, T, P, 3, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
+    default: return hipErrorNotSupported;
+    }
+}
+
+bool H_rho_force_fits(bool f32, int P, int nbmax, int mno)
+{
+    size_t lds = 0;
+    if (P != 32 && P != 16)
+        return false;
+    if (f32)
+        return (P == 32 ? packed_ku<float, 32>(nbmax, mno, &lds) : packed_ku<float, 16>(nbmax, mno, &lds)) > 0;
+    return (P == 32 ? packed_ku<double, 32>(nbmax, mno, &lds) : packed_ku<double, 16>(nbmax, mno, &lds)) > 0;
+}
+
+hipError_t launch_H_rho_force(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                              int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho,
+                              int b0, int b1, const int *boff, void *part)
+{
+    if (b1 <= b0)
+        return hipSuccess;
+    if (g.P == 32)
+        return f32 ? launch_hrf_p<float, 32>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part)
+                   : launch_hrf_p<double, 32>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part);
+    if (g.P == 16)
+        return f32 ? launch_hrf_p<float, 16>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part)
+                   : launch_hrf_p<double, 16>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
