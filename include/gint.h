@@ -134,7 +134,7 @@ gint_status gint_plan_set_positions(gint_plan plan, const double *positions);
 
 /* Batch shape (mesh points per batch along each axis; product 16 or 32) and
  * the device-memory budget (bytes) of the H path's per-batch block partials
- * (0 = automatic: min(16 GiB, a third of free memory)); a smaller budget
+ * (0 = automatic: min(64 GiB, a third of free memory)); a smaller budget
  * splits H into more batch ranges.  Rebuilds the lists; synchronises the
  * stream. */
 gint_status gint_plan_tune(gint_plan plan, const int batch[3], long long h_budget_bytes);

@@ -517,7 +517,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     }));
     const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
     const size_t blk_bytes = esz * (size_t)block_pitch(p->mno, (int)esz);
-    size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)16 << 30;
+    size_t budget = p->hbudget_req > 0 ? (size_t)p->hbudget_req : (size_t)64 << 30;
     if (p->ext_hpart)
         budget = p->ext_hpart_bytes;
     else if (p->hbudget_req <= 0) {

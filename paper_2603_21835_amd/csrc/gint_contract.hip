@@ -421,7 +421,7 @@ hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn,
 // stored as H_JI separately, each in list order; the two sums meet through
 // LDS.  It writes H_IJ and its mirror H_JI (for J = I only the upper
 // triangle, mirrored).
-constexpr int kRedGroup = 8;  // list entries whose loads are in flight together
+constexpr int kRedGroup = 16;  // list entries whose loads are in flight together
 
 template <typename T>
 struct Vec16;
