@@ -123,10 +123,13 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
     }
     __syncthreads();
 
-    // ---- every block (ia <= ja), round-robin over the waves ----
+    // ---- every block (ia <= ja), in contiguous ranges over the waves ----
     const int nblk = nb * (nb + 1) / 2;
     int ia = 0, ja = 0;
-    tri_advance(ia, ja, wave, nb);
+    // a contiguous range of blocks per wave (triangle order): the left
+    // operand changes only at the end of a row
+    const int k0 = wave * nblk / nw, k1 = (wave + 1) * nblk / nw;
+    tri_advance(ia, ja, k0, nb);
     const size_t mm = (size_t)block_pitch(mno, sizeof(T));
     // this lane's points are 4 kk + lk: their weights stay in registers
     // and the (swizzled) offsets of (point 4 kk + lk, orbital li)
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
     // w phi_I stays in registers until ia changes
     int cur = -1;
     T aw[P / 4];
-    for (int k = wave; k < nblk; k += nw) {
+    for (int k = k0; k < k1; ++k) {
         if (ia != cur) {
             const T *pI = s_phi + (size_t)(ia * P) * kRow;
 #pragma unroll
@@ -167,7 +170,10 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
             if (row < nI && li < nJ)
                 o[row * mno + li] = acc[v];
         }
-        tri_advance(ia, ja, nw, nb);
+        if (++ja == nb) {
+            ++ia;
+            ja = ia;
+        }
     }
 }
 
@@ -1098,10 +1104,13 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * kTile; };
 
     if constexpr (HB) {
-        // ---- H blocks (ia <= ja), round-robin over the waves ----
+        // ---- H blocks (ia <= ja), in contiguous ranges over the waves ----
         const int nblk = nb * (nb + 1) / 2;
         int ia = 0, ja = 0;
-        tri_advance(ia, ja, wave, nb);
+        // a contiguous range of blocks per wave (triangle order): the left
+        // operand changes only at the end of a row
+        const int k0 = wave * nblk / NW, k1 = (wave + 1) * nblk / NW;
+        tri_advance(ia, ja, k0, nb);
         const size_t mm = (size_t)block_pitch(mno, sizeof(T));
         // this lane's points 4 kk + lk: weights, and where (orbital li, point)
         // sits in an atom's tiles
@@ -1115,7 +1124,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         }
         int cur = -1;
         T aw[P / 4];
-        for (int k = wave; k < nblk; k += NW) {
+        for (int k = k0; k < k1; ++k) {
             if (ia != cur) {
                 const T *pI = tile(ia, 0);
 #pragma unroll
@@ -1140,7 +1149,10 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
                 if (row < nI && li < nJ)
                     o[row * mno + li] = hc[v];
             }
-            tri_advance(ia, ja, NW, nb);
+            if (++ja == nb) {
+                ++ia;
+                ja = ia;
+            }
         }
     }
 
