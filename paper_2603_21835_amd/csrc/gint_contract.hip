@@ -1104,54 +1104,71 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * kTile; };
 
     if constexpr (HB) {
-        // ---- H blocks (ia <= ja), in contiguous ranges over the waves ----
-        const int nblk = nb * (nb + 1) / 2;
-        int ia = 0, ja = 0;
-        // a contiguous range of blocks per wave (triangle order): the left
-        // operand changes only at the end of a row
-        const int k0 = wave * nblk / NW, k1 = (wave + 1) * nblk / NW;
-        tri_advance(ia, ja, k0, nb);
-        const size_t mm = (size_t)block_pitch(mno, sizeof(T));
-        // this lane's points 4 kk + lk: weights, and where (orbital li, point)
-        // sits in an atom's tiles
+        // ---- H over the packed rows: tile pairs (ti <= tj) of 16 packed
+        // rows, in contiguous ranges over the waves.  Output element (packed
+        // row r, packed column c) is element (ox, oy) of atom-pair block
+        // (x, y); it is stored when x < y, or x == y and ox <= oy (the upper
+        // triangle of a diagonal block, the part the reduction reads), at the
+        // block's partial.  Each element is the same 32-point dot product as
+        // in k_H_batch, accumulated in the same order. ----
+        const int ntile = nrp >> 4;
+        const int npr = ntile * (ntile + 1) / 2;
+        const int k0 = wave * npr / NW, k1 = (wave + 1) * npr / NW;
+        int ti = 0, tj = 0;
+        tri_advance(ti, tj, k0, ntile);
+        const int mm = block_pitch(mno, sizeof(T));
+        T *pb = part + (size_t)(boff[b] - boff[b0]) * mm;  // this batch's block partials
+        // this lane's points 4 kk + lk: weight, and the point's place in a tile row
         T wl[P / 4];
-        int off[P / 4];
+        int po[P / 4];
 #pragma unroll
         for (int kk = 0; kk < P / 4; ++kk) {
             const int p = 4 * kk + lk;
             wl[kk] = (T)s_w[p];
-            off[kk] = (p >> 4) * kTile + kPitch * li + (p & 15);
+            po[kk] = (p >> 4) * kTile + (p & 15);
         }
+        // operand row li of tile t: phi of packed row 16 t + li (zero past the last row)
+        auto oprow = [&](int t, T (&v8)[P / 4], bool weighted) {
+            const int c = s_row[16 * t + li];
+            const T *pr = tile(c >= 0 ? c >> 16 : 0, 0) + kPitch * (c & 15);
+#pragma unroll
+            for (int kk = 0; kk < P / 4; ++kk) {
+                const T f = c >= 0 ? pr[po[kk]] : (T)0;
+                v8[kk] = weighted ? wl[kk] * f : f;
+            }
+        };
         int cur = -1;
         T aw[P / 4];
+        int rkey[4], rb[4];  // per output row of this lane: 16 x + ox (or -1), partial offset
         for (int k = k0; k < k1; ++k) {
-            if (ia != cur) {
-                const T *pI = tile(ia, 0);
+            if (ti != cur) {
+                oprow(ti, aw, true);
 #pragma unroll
-                for (int kk = 0; kk < P / 4; ++kk)
-                    aw[kk] = wl[kk] * pI[off[kk]];
-                cur = ia;
+                for (int v = 0; v < 4; ++v) {
+                    const int c = s_row[16 * ti + MM<T>::row(lk, v)];
+                    const int x = c >> 16, ox = c & 15;
+                    rkey[v] = c >= 0 ? 16 * x + ox : -1;
+                    // block (x, y) is number x nb - x (x - 1) / 2 + (y - x) of the triangle
+                    rb[v] = (x * nb - x * (x - 1) / 2 - x) * mm + ox * mno;
+                }
+                cur = ti;
             }
-            const T *pJ = tile(ja, 0);
             T bv[P / 4];
-#pragma unroll
-            for (int kk = 0; kk < P / 4; ++kk)
-                bv[kk] = pJ[off[kk]];
+            oprow(tj, bv, false);
             typename MM<T>::acc hc = MM<T>::zero();
 #pragma unroll
             for (int kk = 0; kk < P / 4; ++kk)
                 hc = MM<T>::mma(aw[kk], bv[kk], hc);
-            const int nI = s_sp[s_spc[ia]].norb, nJ = s_sp[s_spc[ja]].norb;
-            T *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
+            const int cc = s_row[16 * tj + li];
+            const int ckey = cc >= 0 ? 16 * (cc >> 16) + (cc & 15) : -1;
+            const int cb = (cc >> 16) * mm + (cc & 15);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = MM<T>::row(lk, v);
-                if (row < nI && li < nJ)
-                    o[row * mno + li] = hc[v];
-            }
-            if (++ja == nb) {
-                ++ia;
-                ja = ia;
+            for (int v = 0; v < 4; ++v)
+                if (rkey[v] >= 0 && ckey >= 0 && rkey[v] <= ckey)
+                    pb[rb[v] + cb] = hc[v];
+            if (++tj == ntile) {
+                ++ti;
+                tj = ti;
             }
         }
     }
