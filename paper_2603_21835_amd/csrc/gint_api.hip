@@ -1012,7 +1012,7 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
     if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
         return fail(GINT_EINVAL, "V, D, H, rho and dEdR must be non-NULL device pointers");
     HIPCHK(hipSetDevice(p->device));
-    if ((p->prec == GINT_FP64 || p->prec == GINT_FP32) && H_rho_force_fits(p->f32(), p->geo.P, p->nbmax, p->mno)) {
+    if (H_rho_force_fits((int)p->prec, p->geo.P, p->nbmax, p->mno)) {
         // one pass per H slab evaluates each batch's orbital tiles once for
         // the H blocks, rho and the force partials
         const Bins bn = p->bins();
@@ -1026,7 +1026,7 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
         for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
             const int b0 = p->slab[i], b1 = p->slab[i + 1];
             STCHK(timed(p, GINT_K_H_RHO_FORCE, [&] {
-                return launch_H_rho_force(st, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, V_dev, p->dV,
+                return launch_H_rho_force(st, (int)p->prec, p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, V_dev, p->dV,
                                           p->Fent.as<double>(), rho_dev, b0, b1, p->boff.as<int>(), p->hpart());
             }));
             STCHK(timed(p, GINT_K_H_REDUCE, [&] {
@@ -1039,8 +1039,8 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
                     [&] { return launch_force_reduce(st, p->geo, bn, B, p->Fent.as<double>(), dEdR_dev); }));
         return GINT_OK;
     }
-    // 16-bit H modes (or batches too large for the fused pass): H beside the
-    // rho + force pass on a second stream
+    // batches too large for the fused pass: H beside the rho + force pass on
+    // a second stream
     if (!p->aux) {
         // default priority, like every stream of the library
         HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));

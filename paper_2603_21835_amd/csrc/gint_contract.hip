@@ -970,11 +970,20 @@ constexpr int kForceWaves = 12;
 // H operands) are both free of bank conflicts
 constexpr int kPitch = 17, kTile = 16 * kPitch;
 
-// HB: the H blocks of the batch as well (batches b0 .. b1 - 1, one H slab),
-// from the same orbital tiles, before phase A: block (ia <= ja) as in
-// k_H_batch (same operands, same order: the same bits), written to part at
-// block offset boff[b] - boff[b0] + k.
-template <bool RHO, typename T, int P, int KU, bool HB>
+// bytes of the phi / T tiles and the slot-pair table of k_force_packed, i.e.
+// where the 16-bit H planes start (16-byte aligned)
+__host__ __device__ inline size_t h16_plane_offset(size_t esz, int nbmax, int P)
+{
+    const size_t b = esz * (size_t)nbmax * (P / 16) * kTile + sizeof(int) * (size_t)nbmax * nbmax;
+    return (b + 15) & ~(size_t)15;
+}
+
+// HB (an arithmetic mode of the H kernels, kModeF64 + 1 .. kModeF16x3 + 1;
+// 0: no H): the H blocks of the batch as well (batches b0 .. b1 - 1, one H
+// slab), from the same orbital tiles, before phase A; the same operands and
+// order as k_H_batch / k_H_batch16 (the same bits), written to part at block
+// offset boff[b] - boff[b0] + k.
+template <bool RHO, typename T, int P, int KU, int HB>
 __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, int nbmax,
                                                                   const T *__restrict__ pk,
                                                                   const double *__restrict__ W, double wscale,
@@ -1001,6 +1010,8 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
 
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
+    constexpr int HMODE = HB - 1;  // arithmetic mode of the H blocks
+    constexpr bool H16 = HB > kModeF32 + 1;
     const int b = HB ? xcd_batch(blockIdx.x, b0, b1 - b0) : xcd_batch(blockIdx.x, 0, g.nbatch);
     if (b < 0)
         return;
@@ -1103,7 +1114,68 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     // tile s2 of atom slot x: element (orbital o, point q) at [kPitch o + q]
     auto tile = [&](int x, int s2) -> T * { return s_phi + (size_t)(x * NS + s2) * kTile; };
 
-    if constexpr (HB) {
+    if constexpr (H16) {
+        // ---- 16-bit H (as k_H_batch16): per atom the hi (and lo) planes of
+        // psi = sqrt|w| phi, then every block (ia <= ja) in contiguous ranges
+        // over the waves, the sign of w a bit flip of the left operand ----
+        constexpr bool F16 = HMODE == kModeF16 || HMODE == kModeF16x3;
+        constexpr bool SPLIT = HMODE == kModeBF16x3 || HMODE == kModeF16x3;
+        constexpr float kScale = F16 ? 256.0f : 1.0f;
+        constexpr float kUnscale = 1.0f / (kScale * kScale);
+        u4v *s_pl = reinterpret_cast<u4v *>(s_dyn + h16_plane_offset(sizeof(T), nbmax, P));  // [atom][hi, lo][lane]
+        for (int a = wave; a < nb; a += NW) {
+            const float *ta = reinterpret_cast<const float *>(tile(a, 0));
+            unsigned hi[8], lo[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int p = 8 * lk + j;
+                const float sw = (float)(sqrt(fabs(s_w[p])) * (double)kScale);
+                split16<F16>(ta[(p >> 4) * kTile + kPitch * li + (p & 15)] * sw, hi[j], lo[j]);
+            }
+            u4v H, L;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                H[d] = hi[2 * d] | (hi[2 * d + 1] << 16);
+                L[d] = lo[2 * d] | (lo[2 * d + 1] << 16);
+            }
+            s_pl[(2 * a) * 64 + lane] = H;
+            s_pl[(2 * a + 1) * 64 + lane] = L;
+        }
+        u4v neg;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            neg[d] = ((s_w[8 * lk + 2 * d] < 0.0 ? 1u : 0u) << 15) | ((s_w[8 * lk + 2 * d + 1] < 0.0 ? 1u : 0u) << 31);
+        __syncthreads();
+        const int nblk = nb * (nb + 1) / 2;
+        const int k0 = wave * nblk / NW, k1 = (wave + 1) * nblk / NW;
+        int ia = 0, ja = 0;
+        tri_advance(ia, ja, k0, nb);
+        const size_t mm = (size_t)block_pitch(mno, sizeof(float));
+        for (int k = k0; k < k1; ++k) {
+            const u4v aH = s_pl[(2 * ia) * 64 + lane] ^ neg;
+            const u4v bH = s_pl[(2 * ja) * 64 + lane];
+            f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mma16<F16>(aH, bH, acc);
+            if (SPLIT) {
+                const u4v aL = s_pl[(2 * ia + 1) * 64 + lane] ^ neg;
+                const u4v bL = s_pl[(2 * ja + 1) * 64 + lane];
+                acc = mma16<F16>(aH, bL, acc);
+                acc = mma16<F16>(aL, bH, acc);
+            }
+            const int nI = s_sp[s_spc[ia]].norb, nJ = s_sp[s_spc[ja]].norb;
+            float *o = reinterpret_cast<float *>(part) + (size_t)(boff[b] - boff[b0] + k) * mm;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 4 * lk + v;
+                if (row < nI && li < nJ)
+                    o[row * mno + li] = acc[v] * kUnscale;
+            }
+            if (++ja == nb) {
+                ++ia;
+                ja = ia;
+            }
+        }
+    } else if constexpr (HB) {
         // ---- H over the packed rows: tile pairs (ti <= tj) of 16 packed
         // rows, in contiguous ranges over the waves.  Output element (packed
         // row r, packed column c) is element (ox, oy) of atom-pair block
@@ -1323,7 +1395,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         }
 }
 
-template <bool RHO, typename T, int P, int KU, bool HB = false>
+template <bool RHO, typename T, int P, int KU, int HB = 0>
 static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                   size_t lds, const void *pk, const double *W, double wscale, double *out,
                                   double *rho2, int b0 = 0, int b1 = 0, const int *boff = nullptr, int mno = 0,
@@ -1378,53 +1450,72 @@ hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &b
                : launch_batch_t<kRho, double>(s, g, bn, b, nbmax, pk, nullptr, 0.0, rho, nullptr);
 }
 
-// the packed form's LDS and row tiles per wave for this plan, or 0 if it
-// does not apply
+// the fused pass's LDS and row tiles per wave for this plan and H mode, or 0
+// if it does not apply (16-bit H: 32-point batches, FP32 tiles)
 template <typename T, int P>
-static int packed_ku(int nbmax, int mno, size_t *lds)
+static int packed_ku(int nbmax, int mno, int mode, size_t *lds)
 {
     const int rows = (nbmax * mno + 15) & ~15;
     const int ku = (rows / 16 + kForceWaves - 1) / kForceWaves;
     *lds = sizeof(T) * (size_t)nbmax * (P / 16) * kTile + sizeof(int) * (size_t)nbmax * nbmax;
+    if (mode > kModeF32) {
+        if (P != 32)
+            return 0;
+        *lds = h16_plane_offset(sizeof(T), nbmax, P) + 2 * 64 * 16 * (size_t)nbmax;
+    }
     return (*lds + 24576 > 163840 || ku > 3) ? 0 : (ku < 1 ? 1 : ku);
 }
 
-template <typename T, int P>
-static hipError_t launch_hrf_p(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int mno,
+template <typename T, int P, int HB>
+static hipError_t launch_hrf_m(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int mno,
                                const void *pk, const double *W, double wscale, double *Fent, double *rho, int b0,
                                int b1, const int *boff, void *part)
 {
     size_t lds = 0;
-    switch (packed_ku<T, P>(nbmax, mno, &lds)) {
-    case 1: return launch_packed_k<true, T, P, 1, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
-    case 2: return launch_packed_k<true, T, P, 2, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
-    case 3: return launch_packed_k<true, T, P, 3, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
+    switch (packed_ku<T, P>(nbmax, mno, HB - 1, &lds)) {
+    case 1: return launch_packed_k<true, T, P, 1, HB>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
+    case 2: return launch_packed_k<true, T, P, 2, HB>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
+    case 3: return launch_packed_k<true, T, P, 3, HB>(s, g, bn, b, nbmax, lds, pk, W, wscale, Fent, rho, b0, b1, boff, mno, part);
     default: return hipErrorNotSupported;
     }
 }
 
-bool H_rho_force_fits(bool f32, int P, int nbmax, int mno)
+bool H_rho_force_fits(int mode, int P, int nbmax, int mno)
 {
     size_t lds = 0;
     if (P != 32 && P != 16)
         return false;
-    if (f32)
-        return (P == 32 ? packed_ku<float, 32>(nbmax, mno, &lds) : packed_ku<float, 16>(nbmax, mno, &lds)) > 0;
-    return (P == 32 ? packed_ku<double, 32>(nbmax, mno, &lds) : packed_ku<double, 16>(nbmax, mno, &lds)) > 0;
+    if (mode != kModeF64)
+        return (P == 32 ? packed_ku<float, 32>(nbmax, mno, mode, &lds) : packed_ku<float, 16>(nbmax, mno, mode, &lds)) > 0;
+    return (P == 32 ? packed_ku<double, 32>(nbmax, mno, mode, &lds) : packed_ku<double, 16>(nbmax, mno, mode, &lds)) > 0;
 }
 
-hipError_t launch_H_rho_force(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+hipError_t launch_H_rho_force(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                               int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho,
                               int b0, int b1, const int *boff, void *part)
 {
     if (b1 <= b0)
         return hipSuccess;
-    if (g.P == 32)
-        return f32 ? launch_hrf_p<float, 32>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part)
-                   : launch_hrf_p<double, 32>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part);
-    if (g.P == 16)
-        return f32 ? launch_hrf_p<float, 16>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part)
-                   : launch_hrf_p<double, 16>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part);
+#define GINT_HRF(T, P, HB) launch_hrf_m<T, P, HB>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho, b0, b1, boff, part)
+    if (g.P == 32) {
+        switch (mode) {
+        case kModeF64: return GINT_HRF(double, 32, kModeF64 + 1);
+        case kModeF32: return GINT_HRF(float, 32, kModeF32 + 1);
+        case kModeBF16: return GINT_HRF(float, 32, kModeBF16 + 1);
+        case kModeF16: return GINT_HRF(float, 32, kModeF16 + 1);
+        case kModeBF16x3: return GINT_HRF(float, 32, kModeBF16x3 + 1);
+        case kModeF16x3: return GINT_HRF(float, 32, kModeF16x3 + 1);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (g.P == 16) {
+        switch (mode) {
+        case kModeF64: return GINT_HRF(double, 16, kModeF64 + 1);
+        case kModeF32: return GINT_HRF(float, 16, kModeF32 + 1);
+        default: return hipErrorNotSupported;
+        }
+    }
+#undef GINT_HRF
     return hipErrorNotSupported;
 }
 

@@ -161,10 +161,10 @@ hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins 
                               double *rho /* NULL, or rho as well */);
 // H blocks of batches b0 .. b1 - 1 (into part, as launch_H_batch) together
 // with rho and the force partials of the same batches, from one evaluation of
-// the orbital tiles (FP64 / FP32 modes); H_rho_force_fits says whether the
-// plan's batches fit the fused pass
-bool H_rho_force_fits(bool f32, int P, int nbmax, int mno);
-hipError_t launch_H_rho_force(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+// the orbital tiles (mode: the H arithmetic, kModeF64 .. kModeF16x3);
+// H_rho_force_fits says whether the plan's batches fit the fused pass
+bool H_rho_force_fits(int mode, int P, int nbmax, int mno);
+hipError_t launch_H_rho_force(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                               int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho,
                               int b0, int b1, const int *boff, void *part);
 hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
