@@ -56,7 +56,7 @@ def _traffic(kernel: str, workload: str, precision: str):
 
 
 # device kernel (symbol prefix) behind each timing kind whose traffic is recorded
-KERNEL_SYMBOLS = {"rho_force": r"k_force_packed<[^>]*, false>", "H_rho_force": r"k_force_packed<[^>]*, true>",
+KERNEL_SYMBOLS = {"rho_force": r"k_force_packed<[^>]*, 0>", "H_rho_force": r"k_force_packed<[^>]*, [1-6]>",
                   "H_blocks": r"k_H_batch<", "H_reduce": r"k_H_pairreduce<"}
 
 
