@@ -7,7 +7,9 @@ library: it has its own spline, spherical harmonics, image search and loops
 
 Functions follow Sec. 3.3.1 ("Uniform Grid Integration for Usual
 Quantities") of the paper: the rho(r_g) equation, the H^loc equation and the
-F^{loc,Pulay} equation, at the Gamma point, on the basis of Sec. 2.1.
+F^{loc,Pulay} equation, at the Gamma point, on the basis of Sec. 2.1; and
+the lattice-vector blocks H^loc(R) of the same H^loc equation (``HR``),
+whose phase sum is the H(k) equation of Sec. 2.1.
 """
 from __future__ import annotations
 
@@ -60,6 +62,8 @@ def _load():
     lib.oracle_ylm.argtypes = [ctypes.c_int, dp, dp]
     lib.oracle_phi.argtypes = [P, dp, dp, dp]
     lib.oracle_H_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, lp, dp]
+    lib.oracle_HR_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp]
+    lib.oracle_HR_rows.restype = ctypes.c_int
     lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
     lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, ctypes.c_long, lp, dp]
     lib.oracle_set_positions.argtypes = [P, dp]
@@ -183,6 +187,22 @@ class Oracle:
 
     def H(self, V) -> np.ndarray:
         return self.H_rows(V, 0, self.natom)
+
+    def HR(self, V, R, I0: int = 0, I1: Optional[int] = None) -> np.ndarray:
+        """Lattice-vector blocks H(R) for the lattice multiples ``R`` (n x 3
+        ints), rows of atoms I0..I1-1: an array [n][rows][norb].  Positions
+        are taken as given (not wrapped); contributions to R outside the
+        list are dropped."""
+        I1 = self.natom if I1 is None else I1
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        assert V.size == self.ngrid
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        n = int(self.atom_orb0[I1] - self.atom_orb0[I0])
+        out = np.zeros((Rl.shape[0], n, self.norb))
+        rc = self._lib.oracle_HR_rows(self._ctx, _dp(V), int(I0), int(I1), int(Rl.shape[0]), _ip(Rl), _dp(out))
+        if rc != 0:
+            raise RuntimeError("a mesh point sees too many images of one atom")
+        return out
 
     def rho(self, D, idx: Optional[Sequence[int]] = None) -> np.ndarray:
         D = np.ascontiguousarray(D, dtype=np.float64)

@@ -536,6 +536,139 @@ void oracle_H_rows(void *p, const double *V, int I0, int I1, long npts, const lo
 }
 
 /*
+ * Orbitals of atom I at point r, one set per lattice vector T with
+ * |r - tau_I - T| < rc (not summed): image k has lattice multiples
+ * nvec[3k..3k+2] and values phi[k*norb(I) + o].  At most maximg images are
+ * stored; returns how many there are (the caller checks it against maximg).
+ */
+static int atom_image_phi(const octx *c, int I, const double *r, int maximg, int *nvec, double *phi)
+{
+    const int s = c->spc[I];
+    const int no = c->sp_norb[s];
+    const int o0 = c->sp_orb0[s];
+    const double rc = c->atom_rc[I];
+    double dd[3];
+    for (int k = 0; k < 3; ++k)
+        dd[k] = r[k] - c->pos[3 * I + k];
+    int lo[3], hi[3];
+    for (int i = 0; i < 3; ++i) {
+        const double f = dd[0] * c->rec[3 * i] + dd[1] * c->rec[3 * i + 1] + dd[2] * c->rec[3 * i + 2];
+        const double bn = sqrt(c->rec[3 * i] * c->rec[3 * i] + c->rec[3 * i + 1] * c->rec[3 * i + 1] +
+                               c->rec[3 * i + 2] * c->rec[3 * i + 2]);
+        lo[i] = (int)floor(f - rc * bn);
+        hi[i] = (int)ceil(f + rc * bn);
+    }
+    int nimg = 0;
+    for (int n1 = lo[0]; n1 <= hi[0]; ++n1)
+        for (int n2 = lo[1]; n2 <= hi[1]; ++n2)
+            for (int n3 = lo[2]; n3 <= hi[2]; ++n3) {
+                double d[3];
+                for (int k = 0; k < 3; ++k)
+                    d[k] = dd[k] - (n1 * c->lat[k] + n2 * c->lat[3 + k] + n3 * c->lat[6 + k]);
+                const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (!(rr < rc))
+                    continue;
+                if (nimg < maximg) {
+                    nvec[3 * nimg] = n1;
+                    nvec[3 * nimg + 1] = n2;
+                    nvec[3 * nimg + 2] = n3;
+                    double *ph = phi + (size_t)nimg * no;
+                    for (int o = 0; o < no; ++o) {
+                        const orad *R = &c->rad[c->orb_rad[o0 + o]];
+                        ph[o] = 0.0;
+                        if (rr < R->rc)
+                            orbital_value(R, c->orb_m[o0 + o], d, &ph[o], NULL);
+                    }
+                }
+                ++nimg;
+            }
+    return nimg;
+}
+
+#define MAX_IMG 64
+
+/*
+ * Lattice-vector blocks of H^loc (Sec. 3.3.1, H^loc_{mu nu}(R) equation):
+ *   H_mu,nu(R) = dV sum over the mesh points g of the whole crystal of
+ *                phi_mu(r_g - tau_I) V(r_g) phi_nu(r_g - tau_J - R),
+ * with tau the positions as given (not wrapped into the cell) and
+ * R = n1 a1 + n2 a2 + n3 a3.  A crystal point is a cell point r_g shifted
+ * by a lattice vector -T; V and the mesh are periodic, so the sum runs over
+ * the cell's points and the images T of atom I reaching each:
+ *   H_mu,nu(R) = dV sum_{g in cell} sum_T V_g phi_mu(r_g - tau_I - T)
+ *                                         phi_nu(r_g - tau_J - T - R).
+ * out is [nR][orb rows of I0..I1-1][norb], overwritten; R lists the nR
+ * lattice multiples (n1, n2, n3); contributions to unlisted R are dropped.
+ * The sum over R of H(R) is the Gamma-point H of oracle_H_rows.  Returns
+ * -1 if some point sees more than MAX_IMG images of one atom, else 0.
+ * Parallel over atom rows.
+ */
+int oracle_HR_rows(void *p, const double *V, int I0, int I1, int nR, const int *R, double *out)
+{
+    const octx *c = (const octx *)p;
+    const int norb = c->norb;
+    const int row0 = c->atom_orb0[I0];
+    const size_t nrow = (size_t)(c->atom_orb0[I1] - row0);
+    memset(out, 0, sizeof(double) * (size_t)nR * nrow * norb);
+    int bad = 0;
+#pragma omp parallel reduction(| : bad)
+    {
+        double *phiI = (double *)malloc(sizeof(double) * MAX_IMG * 64);
+        double *phiJ = (double *)malloc(sizeof(double) * MAX_IMG * 64);
+        int nI_vec[3 * MAX_IMG], nJ_vec[3 * MAX_IMG];
+#pragma omp for schedule(dynamic, 1)
+        for (int I = I0; I < I1; ++I) {
+            const int nI = c->sp_norb[c->spc[I]];
+            const size_t rI = (size_t)(c->atom_orb0[I] - row0);
+            for (long g = 0; g < c->ng; ++g) {
+                double r[3];
+                mesh_point(c, g, r);
+                const int kI = atom_image_phi(c, I, r, MAX_IMG, nI_vec, phiI);
+                if (kI == 0)
+                    continue;
+                if (kI > MAX_IMG) {
+                    bad = 1;
+                    continue;
+                }
+                const double w = c->dV * V[g];
+                for (int J = 0; J < c->natom; ++J) {
+                    const int kJ = atom_image_phi(c, J, r, MAX_IMG, nJ_vec, phiJ);
+                    if (kJ > MAX_IMG) {
+                        bad = 1;
+                        continue;
+                    }
+                    const int nJ = c->sp_norb[c->spc[J]];
+                    const int j0 = c->atom_orb0[J];
+                    /* T is image a of I; T + R is image b of J */
+                    for (int a = 0; a < kI; ++a)
+                        for (int b = 0; b < kJ; ++b) {
+                            int ir = -1;
+                            for (int q = 0; q < nR; ++q)
+                                if (R[3 * q] == nJ_vec[3 * b] - nI_vec[3 * a] &&
+                                    R[3 * q + 1] == nJ_vec[3 * b + 1] - nI_vec[3 * a + 1] &&
+                                    R[3 * q + 2] == nJ_vec[3 * b + 2] - nI_vec[3 * a + 2]) {
+                                    ir = q;
+                                    break;
+                                }
+                            if (ir < 0)
+                                continue;
+                            double *blk = out + ((size_t)ir * nrow + rI) * norb + j0;
+                            for (int x = 0; x < nI; ++x) {
+                                const double wa = w * phiI[(size_t)a * nI + x];
+                                for (int y = 0; y < nJ; ++y)
+                                    blk[(size_t)x * norb + y] += wa * phiJ[(size_t)b * nJ + y];
+                            }
+                        }
+                }
+            }
+        }
+        free(phiI);
+        free(phiJ);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
  * rho at mesh points idx[0..npts) (or at g = 0..npts-1 when idx == NULL).
  * Parallel over points.
  */

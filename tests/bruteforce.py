@@ -9,7 +9,9 @@ or the GPU library:
 * angular: real harmonics assembled from ``scipy.special.sph_harm_y``
   (complex, Condon-Shortley phase), not from the closed forms;
 * images: every lattice vector in [-n, n]^3, n = ceil(rc / L_min) + 1;
-* the sums of Sec. 3.3.1 (rho(r_g), H^loc) as explicit loops.
+* the sums of Sec. 3.3.1 (rho(r_g), H^loc) as explicit loops;
+* H^loc(R): the crystal's mesh enumerated as the cell's points shifted by
+  every lattice vector of a cube, with unfolded (per-image) orbitals.
 """
 from __future__ import annotations
 
@@ -83,6 +85,52 @@ class BruteCell:
                             vals[:, k] += f * Y
             cols.append(vals)
         return np.concatenate(cols, axis=1)
+
+    def phi_image(self, n, positions=None):
+        """Unfolded orbital values phi_mu(r_g - tau_I - T), T = n . (a1, a2, a3),
+        at the cell's mesh points: shape (ngrid, norb)."""
+        w = self.w
+        pos = np.asarray(w.positions if positions is None else positions, dtype=np.float64)
+        T = n[0] * self.lat[0] + n[1] * self.lat[1] + n[2] * self.lat[2]
+        cols = []
+        for I, s in enumerate(w.species_of_atom):
+            d = self.points - pos[I] - T
+            r = np.sqrt(np.sum(d * d, axis=1))
+            safe = np.where(r > 0, r, 1.0)
+            u = d / safe[:, None]
+            vals = np.zeros((len(self.points), len(self.orbs[s])))
+            for k, (cs, rc, l, m) in enumerate(self.orbs[s]):
+                f = np.where(r < rc, cs(np.minimum(r, rc)), 0.0)
+                if l == 0:
+                    Y = real_ylm(0, 0, u)
+                else:
+                    Y = np.where(r > 1e-12, real_ylm(l, m, u), 0.0)
+                vals[:, k] = f * Y
+            cols.append(vals)
+        return np.concatenate(cols, axis=1)
+
+    def HR(self, V, Rlist):
+        """H(R)_mu,nu = dV sum over crystal points r of phi_mu(r - tau_I) V(r)
+        phi_nu(r - tau_J - R): crystal points r = r_g - T for every T of a
+        cube big enough that no orbital pair is missed.  Returns [n][norb][norb]."""
+        rcmax = max(o[1] for lst in self.orbs for o in lst)
+        nimg = int(math.ceil(rcmax / np.min(np.linalg.norm(self.lat, axis=1)))) + 1
+        cache = {}
+
+        def img(n):
+            if n not in cache:
+                cache[n] = self.phi_image(n)
+            return cache[n]
+
+        out = np.zeros((len(Rlist), self.w.norb, self.w.norb))
+        rng = range(-nimg, nimg + 1)
+        for T in [(a, b, c) for a in rng for b in rng for c in rng]:
+            A = img(T) * V[:, None]
+            if not np.any(A):
+                continue
+            for q, R in enumerate(Rlist):
+                out[q] += self.dV * A.T @ img((T[0] + R[0], T[1] + R[1], T[2] + R[2]))
+        return out
 
     def H(self, V, phi=None):
         phi = self.phi_all() if phi is None else phi
