@@ -232,8 +232,9 @@ def main():
     ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
-    ap.add_argument("--only", default=None, choices=["H", "rho", "force", "rho_force", "H_rho_force"],
-                    help="time one contraction only (short profiler runs)")
+    ap.add_argument("--only", default=None, choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR"],
+                    help="time one contraction only (short profiler runs); HR: the lattice-vector blocks "
+                         "H(R) for every R of gint_HR_lattice")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--serial", action="store_true",
@@ -289,8 +290,14 @@ def main():
     rho = torch.empty(plan.ngrid, dtype=torch.float64, device=dev)
     F = torch.empty((plan.natom, 3), dtype=torch.float64, device=dev)
     work = plan.work()
+    if args.only == "HR":
+        R_list = plan.HR_lattice()
+        HRbuf = torch.empty((len(R_list), plan.norb, plan.norb), dtype=torch.float64, device=dev)
 
     def step():
+        if args.only == "HR":
+            plan.build_HR(V, R_list, out=HRbuf)
+            return
         if args.only is None:
             plan.set_positions(w.positions)
         if (args.only is None and not args.serial and not args.separate) or args.only == "H_rho_force":
@@ -327,10 +334,10 @@ def main():
     s1, s2 = work["sum_ng"], work["sum_ng2"]
     # algorithmic work per step (per unit: one mesh point with n_g orbitals)
     flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1,
-             "rho_force": 2 * s2 + 8 * s1, "H_rho_force": 4 * s2 + 8 * s1}
+             "rho_force": 2 * s2 + 8 * s1, "H_rho_force": 4 * s2 + 8 * s1, "HR": 2 * s2}
     # the H reduction moves every block partial once and writes H's blocks
     hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
-              "H_fill": 8 * plan.norb ** 2}
+              "H_fill": 8 * plan.norb ** 2 * (len(R_list) if args.only == "HR" else 1)}
     kernels = {}
     for k, (ms, n) in timing.items():
         if n == 0:
@@ -390,8 +397,7 @@ def main():
                         "DZP rc=8 bohr, one step = re-binning + H + rho + dE/dR"
                         + (" (H, rho and dE/dR as three passes)" if args.separate else
                            " (H, then rho from the force pass)" if args.serial else
-                           " (gint_H_rho_force: one pass per batch for H, rho and dE/dR in FP64 / FP32, H beside "
-                           "the rho + force pass on a second stream in the 16-bit modes)"),
+                           " (gint_H_rho_force: one pass per batch for H, rho and dE/dR)"),
             "batch": list(work["batch"]), "h_slabs": work["nslab"], "group_pairs": work["npair"],
             "sum_ng2": s2, "sum_ng": s1,
         },
@@ -415,6 +421,11 @@ def main():
         ref.close()
     if args.only is not None:
         out["only"] = args.only
+    if args.only == "HR":
+        out["config"]["workload"] = (f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh "
+                                     f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the lattice-vector "
+                                     f"blocks H(R) of {len(R_list)} lattice vectors (gint_build_HR)")
+        out["config"]["n_R"] = len(R_list)
     if not args.no_cpu_baseline and args.only is None:
         _progress("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -195,6 +195,35 @@ gint_status gint_rho_force(gint_plan plan, const double *W_dev, const double *D_
 gint_status gint_H_rho_force(gint_plan plan, const double *V_dev, const double *D_dev, double *H_dev,
                              double *rho_dev, double *dEdR_dev);
 
+/* Lattice-vector blocks of H^loc (Sec. 3.3.1, H^loc(R) equation; the sum
+ * over g runs over the mesh points of the whole crystal):
+ *   H_mu,nu(R) = dV sum_g phi_mu(r_g - tau_I) V(r_g) phi_nu(r_g - tau_J - R),
+ * R = n1 a1 + n2 a2 + n3 a3, tau the positions as given to the plan (not
+ * wrapped into the cell).  sum_R e^{ik.R} H(R) is H(k) of Sec. 2.1; the sum
+ * over all R is gint_build_H's Gamma-point H.
+ *   V_dev   device, N1*N2*N3 doubles (Ha)
+ *   nR, R   host, nR >= 1 distinct lattice multiples (n1, n2, n3) as 3*nR
+ *           ints, each |n_k| <= 31
+ *   HR_dev  device, nR*norb*norb doubles: block q (row-major norb x norb)
+ *           is H(R_q); overwritten.  Contributions to R not in the list
+ *           are dropped; gint_HR_lattice lists the R that can have any.
+ * Blocks are accumulated with FP64 atomics, so the last bits can differ
+ * between calls.  FP64 plans evaluate orbitals in FP64, the other
+ * precisions in FP32 (FP32 matrix-core products); sums are FP64.
+ * GINT_EINVAL for bad arguments (outputs untouched); GINT_EUNSUPPORTED if
+ * too many atom images reach one mesh batch. */
+gint_status gint_build_HR(gint_plan plan, const double *V_dev, int nR, const int *R, double *HR_dev);
+
+/* The lattice vectors R = T_b - T_a over every pair of atom images (a, b)
+ * that reach a common mesh batch, for the current positions: every R with
+ * a non-zero H(R) block is among them (a superset; |n_k| <= 31 only).
+ * Sorted by (n1, n2, n3).
+ *   cap   room in R (host, 3*cap ints); cap = 0 (R may be NULL) only counts
+ *   nR    host, receives the count
+ * GINT_EINVAL (with *nR set) when the count exceeds cap.  Synchronises the
+ * stream once. */
+gint_status gint_HR_lattice(gint_plan plan, int cap, int *nR, int *R);
+
 /* Kernel classes reported by gint_plan_timing. */
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
@@ -207,7 +236,8 @@ enum {
     GINT_K_H_FILL = 7,    /* zero fill of dense H                                   */
     GINT_K_RHO_FORCE = 8, /* rho and force contraction in one pass                  */
     GINT_K_H_RHO_FORCE = 9, /* H blocks, rho and force in one pass (gint_H_rho_force) */
-    GINT_NKERNEL = 10
+    GINT_K_HR = 10,       /* lattice-vector blocks H(R) (gint_build_HR)            */
+    GINT_NKERNEL = 11
 };
 
 /* Enable (1) or disable (0) timing: each kernel launch of later calls is

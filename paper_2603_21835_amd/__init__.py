@@ -31,11 +31,12 @@ EXPORTS = (
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force", "gint_H_rho_force",
+    "gint_build_HR", "gint_HR_lattice",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
 KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
-           "H_rho_force")
+           "H_rho_force", "HR")
 
 
 class GintError(RuntimeError):
@@ -102,6 +103,10 @@ def load_library(path: str = LIB_PATH):
     lib.gint_H_rho_force.restype = st
     lib.gint_H_rho_force.argtypes = [P, P, P, P, P, P]
     lib.gint_plan_sync.restype = st
+    lib.gint_build_HR.argtypes = [P, P, ctypes.c_int, ip, P]
+    lib.gint_build_HR.restype = ctypes.c_int
+    lib.gint_HR_lattice.argtypes = [P, ctypes.c_int, ip, ip]
+    lib.gint_HR_lattice.restype = ctypes.c_int
     lib.gint_plan_sync.argtypes = [P]
     lib.gint_plan_work.restype = st
     lib.gint_plan_work.argtypes = [P, ctypes.POINTER(Work)]
@@ -308,6 +313,37 @@ class GintPlan:
         fn = self._lib.gint_build_H_weighted if weighted else self._lib.gint_build_H
         _check(fn(self._handle(), vp, op))
         return out
+
+    def HR_lattice(self):
+        """Lattice multiples (n x 3 ints) of every R that can carry a non-zero
+        H(R) block (pairs of atom images sharing a mesh batch)."""
+        import numpy as np
+
+        n = ctypes.c_int(0)
+        self._lib.gint_HR_lattice(self._handle(), 0, ctypes.byref(n), None)
+        R = np.zeros((max(n.value, 1), 3), dtype=np.int32)
+        _check(self._lib.gint_HR_lattice(self._handle(), n.value, ctypes.byref(n),
+                                         R.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return R[: n.value]
+
+    def build_HR(self, V, R=None, out=None):
+        """Lattice-vector blocks H(R) (nR x norb x norb) for the lattice
+        multiples R (nR x 3 ints; default: HR_lattice()).
+        Returns (R, HR)."""
+        import numpy as np
+        import torch
+
+        if R is None:
+            R = self.HR_lattice()
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        nR = int(Rl.shape[0])
+        vp = _dev_ptr(V, self.ngrid, "V")
+        if out is None:
+            out = torch.empty((nR, self.norb, self.norb), dtype=torch.float64, device=V.device)
+        op = _dev_ptr(out, nR * self.norb * self.norb, "HR")
+        _check(self._lib.gint_build_HR(self._handle(), vp, nR,
+                                       Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), op))
+        return Rl, out
 
     def build_rho(self, D, out=None):
         import torch

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgint.so")
-SOURCES = ["gint_api.hip", "gint_kernels.hip", "gint_contract.hip"]
+SOURCES = ["gint_api.hip", "gint_kernels.hip", "gint_contract.hip", "gint_hr.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -120,6 +120,13 @@ struct gint_plan_s {
     DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist, lcnt, lptr, blist;
     DevBuf pown, lsl, slabq;  // owner of each owned pair; slab ranges of its block list
     DevBuf scan_tmp;          // tile sums of the list scans
+    // H(R) blocks: internal atom of each image, wrap shift of each atom,
+    // the caller's R list as a box map (rebuilt when the lists or the list
+    // change)
+    DevBuf img_atom, wsh, rmap;
+    long long hr_gen = -1;
+    int nbmax_img = 0;
+    std::vector<int> hr_key;
     int npair_owned = 0;          // owned atom pairs (entries of plist)
     std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
@@ -1055,6 +1062,121 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
     STCHK(build_H_impl(p, V_dev, p->dV, H_dev));
     HIPCHK(hipEventRecord(p->ev_join, p->aux));
     HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join, 0));
+    return GINT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+constexpr int kMaxHRExt = 31;  // |n_k| of the lattice vectors of gint_build_HR
+
+// per-image atoms, wrap shifts and the most images in one batch, once per
+// list generation
+gint_status hr_prepare(gint_plan p)
+{
+    if (p->hr_gen == p->gen)
+        return GINT_OK;
+    const hipStream_t st = p->stream;
+    STCHK(p->img_atom.ensure(sizeof(int) * (size_t)(p->nimg + 1)));
+    STCHK(p->wsh.ensure(sizeof(int) * 3 * (size_t)p->natom));
+    HIPCHK(launch_HR_prep(st, p->geo, p->nent, p->ent_atom.as<int>(), p->ent_img.as<int>(), p->img_atom.as<int>(),
+                          p->perm.as<int>(), p->pos_in.as<double>(), p->xw.as<double>(), p->wsh.as<int>()));
+    STCHK(p->maxv.ensure(2 * sizeof(int)));
+    HIPCHK(launch_max_i32(st, p->cnt_i.as<int>(), p->geo.nbatch, p->maxv.as<int>()));
+    int most = 0;
+    STCHK(read_scalar(p, p->maxv.as<int>(), &most));
+    p->nbmax_img = most;
+    p->hr_gen = p->gen;
+    return GINT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gint_status gint_HR_lattice(gint_plan p, int cap, int *nR, int *R)
+{
+    STCHK(check_plan(p));
+    if (!nR || cap < 0 || (cap > 0 && !R))
+        return fail(GINT_EINVAL, "nR must be non-NULL, cap >= 0, and R non-NULL when cap > 0");
+    HIPCHK(hipSetDevice(p->device));
+    STCHK(hr_prepare(p));
+    const int M = kMaxHRExt, w = 2 * M + 1;
+    const size_t nbox = (size_t)w * w * w;
+    STCHK(p->rmap.ensure(sizeof(int) * nbox));
+    p->hr_key.clear();  // the R map buffer is reused here
+    HIPCHK(launch_fill_i32(p->stream, p->rmap.as<int>(), (long long)nbox, 0));
+    HIPCHK(launch_HR_mark(p->stream, p->geo, p->iptr.as<int>(), p->img_atom.as<int>(), p->img.as<int>(),
+                          p->wsh.as<int>(), M, p->rmap.as<int>()));
+    std::vector<int> mark(nbox);
+    HIPCHK(hipMemcpyAsync(mark.data(), p->rmap.p, sizeof(int) * nbox, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    int n = 0;
+    for (size_t i = 0; i < nbox; ++i)
+        if (mark[i]) {
+            if (n < cap) {
+                R[3 * n] = (int)(i / ((size_t)w * w)) - M;
+                R[3 * n + 1] = (int)((i / w) % w) - M;
+                R[3 * n + 2] = (int)(i % w) - M;
+            }
+            ++n;
+        }
+    *nR = n;
+    if (n > cap)
+        return fail(GINT_EINVAL, "%d lattice vectors, room for %d (nR holds the count)", n, cap);
+    return GINT_OK;
+}
+
+gint_status gint_build_HR(gint_plan p, const double *V_dev, int nR, const int *R, double *HR_dev)
+{
+    constexpr int kMaxExt = kMaxHRExt;
+    STCHK(check_plan(p));
+    if (!V_dev || !HR_dev || !R)
+        return fail(GINT_EINVAL, "V and HR must be non-NULL device pointers and R a non-NULL host array");
+    if (nR < 1)
+        return fail(GINT_EINVAL, "nR = %d must be >= 1", nR);
+    int ext[3] = {0, 0, 0};
+    for (int q = 0; q < nR; ++q)
+        for (int k = 0; k < 3; ++k) {
+            if (R[3 * q + k] < -kMaxExt || R[3 * q + k] > kMaxExt)
+                return fail(GINT_EINVAL, "R[%d] has a component %d outside [-%d, %d]", q, R[3 * q + k], kMaxExt,
+                            kMaxExt);
+            ext[k] = std::max(ext[k], std::abs(R[3 * q + k]));
+        }
+    const size_t nbox = (size_t)(2 * ext[0] + 1) * (2 * ext[1] + 1) * (2 * ext[2] + 1);
+    std::vector<int> map(nbox, -1);
+    for (int q = 0; q < nR; ++q) {
+        const size_t i = ((size_t)(R[3 * q] + ext[0]) * (2 * ext[1] + 1) + R[3 * q + 1] + ext[1]) * (2 * ext[2] + 1) +
+                         R[3 * q + 2] + ext[2];
+        if (map[i] >= 0)
+            return fail(GINT_EINVAL, "R[%d] repeats R[%d]", q, map[i]);
+        map[i] = q;
+    }
+    HIPCHK(hipSetDevice(p->device));
+    const hipStream_t st = p->stream;
+    STCHK(hr_prepare(p));
+    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
+    if (p->nbmax_img > kMaxBatchAtoms || esz * (size_t)p->nbmax_img * p->geo.P * kRow + 16384 > 163840)
+        return fail(GINT_EUNSUPPORTED, "%d atom images reach one %d-point batch; use a smaller batch", p->nbmax_img,
+                    p->geo.P);
+    std::vector<int> key(map);
+    key.insert(key.end(), ext, ext + 3);
+    if (key != p->hr_key) {
+        STCHK(p->rmap.ensure(sizeof(int) * nbox));
+        HIPCHK(hipMemcpyAsync(p->rmap.p, map.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // map (host) outlives the copy
+        p->hr_key.swap(key);
+    }
+    HRMap m;
+    m.rmap = p->rmap.as<int>();
+    for (int k = 0; k < 3; ++k)
+        m.ext[k] = ext[k];
+    STCHK(timed(p, GINT_K_H_FILL,
+                [&] { return launch_fill_f64(st, HR_dev, (long long)nR * p->norb * p->norb, 0.0); }));
+    const Basis B = p->basis();
+    STCHK(timed(p, GINT_K_HR, [&] {
+        return launch_HR_batch(st, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(), p->img_atom.as<int>(),
+                               p->img.as<int>(), B, p->wsh.as<int>(), V_dev, p->dV, m, p->norb, HR_dev);
+    }));
     return GINT_OK;
 }
 

@@ -1,0 +1,255 @@
+// gint_hr.hip -- lattice-vector blocks of the local Hamiltonian,
+//     H_mu,nu(R) = dV sum_g phi_mu(r_g - tau_I) V(r_g) phi_nu(r_g - tau_J - R)
+// (Sec. 3.3.1, H^loc(R) equation; the sum runs over the mesh points of the
+// whole crystal), the per-R storage from which H(k) = sum_R e^{ik.R} H(R)
+// of Sec. 2.1 is assembled.  tau are the positions as the caller gave them.
+//
+// Point-stationary like the Gamma-point H kernels, with the images of each
+// atom kept apart instead of folded: a workgroup owns a mesh batch,
+// evaluates every (atom, image) that reaches it into LDS once, and forms
+// every block of two of them (ia <= ja) on the matrix cores.  With image T_a
+// of atom I and T_b of atom J, a block is the contribution of the crystal
+// points r_g - T_a to H_IJ(T_b - T_a); its transpose goes to
+// H_JI(T_a - T_b).  Blocks are added into the dense per-R output with FP64
+// atomics (the order of the additions is not fixed).
+#include <hip/hip_runtime.h>
+
+#include "gint_device.h"
+
+namespace gint {
+
+// internal atom of every image (image i belongs to the entry e with
+// ent_img[e] <= i < ent_img[e + 1])
+__global__ void k_image_atoms(long long nent, const int *__restrict__ ent_atom, const int *__restrict__ ent_img,
+                              int *__restrict__ img_atom)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nent)
+        return;
+    const int a = ent_atom[e];
+    for (int i = ent_img[e]; i < ent_img[e + 1]; ++i)
+        img_atom[i] = a;
+}
+
+// lattice multiples W of each internal atom: the position as given is the
+// wrapped one plus W . (a1, a2, a3)
+__global__ void k_wrap_shift(Geo g, const int *__restrict__ perm, const double *__restrict__ pos_in,
+                             const double *__restrict__ xw, int *__restrict__ wsh)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= g.natom)
+        return;
+    const int q = perm[a];
+    const double x[3] = {pos_in[3 * q], pos_in[3 * q + 1], pos_in[3 * q + 2]};
+    const double y[3] = {xw[3 * a], xw[3 * a + 1], xw[3 * a + 2]};
+    double s[3], t[3];
+    frac_of(g, x, s);
+    frac_of(g, y, t);
+    for (int k = 0; k < 3; ++k)
+        wsh[3 * a + k] = (int)rint(s[k] - t[k]);
+}
+
+hipError_t launch_HR_prep(hipStream_t s, const Geo &g, long long nent, const int *ent_atom, const int *ent_img,
+                          int *img_atom, const int *perm, const double *pos_in, const double *xw, int *wsh)
+{
+    if (nent > 0)
+        hipLaunchKernelGGL(k_image_atoms, dim3((unsigned)((nent + 255) / 256)), dim3(256), 0, s, nent, ent_atom,
+                           ent_img, img_atom);
+    hipLaunchKernelGGL(k_wrap_shift, dim3((g.natom + 255) / 256), dim3(256), 0, s, g, perm, pos_in, xw, wsh);
+    return hipGetLastError();
+}
+
+// Lattice vectors R = T_c - T_a over every ordered pair of atom images (a, c)
+// reaching one batch: a superset of the R with a non-zero block.  mark is
+// the box |n_k| <= M (row-major, n3 fastest); entries are set to 1.
+__global__ __launch_bounds__(256) void k_HR_mark(Geo g, const int *__restrict__ iptr, const int *__restrict__ img_atom,
+                                                 const int *__restrict__ img, const int *__restrict__ wsh, int M,
+                                                 int *__restrict__ mark)
+{
+    const int b = blockIdx.x;
+    const int i0 = iptr[b], nb = iptr[b + 1] - i0;
+    const int w = 2 * M + 1;
+    for (int q = threadIdx.x; q < nb * nb; q += blockDim.x) {
+        const int a = q / nb, c = q - a * nb;
+        int na[3], nc[3];
+        unpack_image(img[i0 + a], na);
+        unpack_image(img[i0 + c], nc);
+        const int A = img_atom[i0 + a], C = img_atom[i0 + c];
+        int R[3];
+        bool in = true;
+        for (int k = 0; k < 3; ++k) {
+            R[k] = (nc[k] - wsh[3 * C + k]) - (na[k] - wsh[3 * A + k]);
+            in = in && R[k] >= -M && R[k] <= M;
+        }
+        if (in)
+            mark[((R[0] + M) * w + R[1] + M) * w + R[2] + M] = 1;
+    }
+}
+
+hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const int *img_atom, const int *img,
+                          const int *wsh, int M, int *mark)
+{
+    hipLaunchKernelGGL(k_HR_mark, dim3((unsigned)g.nbatch), dim3(256), 0, s, g, iptr, img_atom, img, wsh, M, mark);
+    return hipGetLastError();
+}
+
+constexpr int kHRWaves = 16;
+
+// index of R = (n1, n2, n3) in the caller's list, -1 if absent
+__device__ __forceinline__ int hr_lookup(const HRMap &m, int n1, int n2, int n3)
+{
+    if (n1 < -m.ext[0] || n1 > m.ext[0] || n2 < -m.ext[1] || n2 > m.ext[1] || n3 < -m.ext[2] || n3 > m.ext[2])
+        return -1;
+    return m.rmap[((n1 + m.ext[0]) * (2 * m.ext[1] + 1) + n2 + m.ext[1]) * (2 * m.ext[2] + 1) + n3 + m.ext[2]];
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64 * kHRWaves) void k_HR_batch(Geo g, const int *__restrict__ iptr,
+                                                   const int *__restrict__ img_atom, const int *__restrict__ img,
+                                                   Basis bs, const int *__restrict__ wsh,
+                                                   const double *__restrict__ W, double wscale, HRMap m, int norb,
+                                                   double *__restrict__ HR)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
+    __shared__ DevRadial s_rad[kMaxRadTotal];
+    __shared__ DevSpecies s_sp[kMaxSpecies];
+    __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms], s_mu0[kMaxBatchAtoms];
+    __shared__ int s_T[kMaxBatchAtoms][3];
+    __shared__ double s_w[kMaxP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+              nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
+    if (b < 0)
+        return;
+    const int i0 = iptr[b], nb = iptr[b + 1] - i0;
+    int ib[3];
+    batch_coords(g, b, ib);
+
+    for (int k = tid; k < g.nrad; k += blockDim.x)
+        s_rad[k] = bs.rad[k];
+    for (int k = tid; k < g.nspecies; k += blockDim.x)
+        s_sp[k] = bs.sp[k];
+    for (int a = tid; a < nb; a += blockDim.x) {
+        const int atom = img_atom[i0 + a];
+        s_atom[a] = atom;
+        s_nor[a] = bs.sp[bs.spc[atom]].norb;
+        s_mu0[a] = bs.orb0[bs.perm[atom]];
+        // image of the wrapped atom, as a lattice vector from the position
+        // the caller gave
+        int n[3];
+        unpack_image(img[i0 + a], n);
+        for (int k = 0; k < 3; ++k)
+            s_T[a][k] = n[k] - wsh[3 * atom + k];
+    }
+    for (int p = tid; p < P; p += blockDim.x) {
+        int n[3];
+        s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
+    }
+    __syncthreads();
+
+    // ---- one image of one atom per LDS slot, every batch point ----
+    for (int idx = tid; idx < nb * P; idx += blockDim.x) {
+        const int a = idx / P, p = idx % P;
+        const int atom = s_atom[a];
+        T *row = s_phi + (size_t)(a * P + p) * kRow;
+        const int swz = p & 15;
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[o ^ swz] = (T)0;
+        if (valid) {
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            double r[3];
+            mesh_cart(g, n, r);
+            eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, 1, img[i0 + a], i0 + a, img, r,
+                             row, swz);
+        }
+    }
+    __syncthreads();
+
+    const int nblk = nb * (nb + 1) / 2;
+    const int k0 = wave * nblk / nw, k1 = (wave + 1) * nblk / nw;
+    int ia = 0, ja = 0;
+    {
+        // (ia, ja) of block k0 in the row-major order of ia <= ja < nb
+        int k = k0;
+        while (ia < nb && k >= nb - ia) {
+            k -= nb - ia;
+            ++ia;
+        }
+        ja = ia + k;
+    }
+    T wl[P / 4];
+    int off[P / 4];
+#pragma unroll
+    for (int kk = 0; kk < P / 4; ++kk) {
+        const int p = 4 * kk + lk;
+        wl[kk] = (T)s_w[p];
+        off[kk] = p * kRow + (li ^ (p & 15));
+    }
+    const size_t nn = (size_t)norb * norb;
+    for (int k = k0; k < k1; ++k) {
+        const int Rx = s_T[ja][0] - s_T[ia][0], Ry = s_T[ja][1] - s_T[ia][1], Rz = s_T[ja][2] - s_T[ia][2];
+        const int rp = hr_lookup(m, Rx, Ry, Rz);
+        const int rn = ia != ja ? hr_lookup(m, -Rx, -Ry, -Rz) : -1;
+        if (rp >= 0 || rn >= 0) {
+            const T *pI = s_phi + (size_t)(ia * P) * kRow;
+            const T *pJ = s_phi + (size_t)(ja * P) * kRow;
+            typename MM<T>::acc acc = MM<T>::zero();
+#pragma unroll
+            for (int kk = 0; kk < P / 4; ++kk)
+                acc = MM<T>::mma(wl[kk] * pI[off[kk]], pJ[off[kk]], acc);
+            const int nI = s_nor[ia], nJ = s_nor[ja], mI = s_mu0[ia], mJ = s_mu0[ja];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = MM<T>::row(lk, v);
+                if (row < nI && li < nJ) {
+                    const double x = (double)acc[v];
+                    if (rp >= 0)
+                        unsafeAtomicAdd(HR + rp * nn + (size_t)(mI + row) * norb + mJ + li, x);
+                    if (rn >= 0)
+                        unsafeAtomicAdd(HR + rn * nn + (size_t)(mJ + li) * norb + mI + row, x);
+                }
+            }
+        }
+        if (++ja == nb) {
+            ++ia;
+            ja = ia;
+        }
+    }
+}
+
+template <typename T, int P>
+static hipError_t launch_HR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                              const int *img, const Basis &b, const int *wsh, const double *W, double wscale,
+                              const HRMap &m, int norb, double *HR)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow;
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_HR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_HR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
+                       dim3(64 * kHRWaves), lds, s, g, iptr, img_atom, img, b, wsh, W, wscale, m, norb, HR);
+    return hipGetLastError();
+}
+
+hipError_t launch_HR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                           const int *img, const Basis &b, const int *wsh, const double *W, double wscale,
+                           const HRMap &m, int norb, double *HR)
+{
+    if (g.P == 32)
+        return f32 ? launch_HR_p<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, W, wscale, m, norb, HR)
+                   : launch_HR_p<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, W, wscale, m, norb, HR);
+    if (g.P == 16)
+        return f32 ? launch_HR_p<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, W, wscale, m, norb, HR)
+                   : launch_HR_p<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, W, wscale, m, norb, HR);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gint

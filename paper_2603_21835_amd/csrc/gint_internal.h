@@ -70,6 +70,13 @@ struct Bins {
 };
 
 // Per-atom lists for the point-stationary H path.
+// Caller's list of lattice vectors for the H(R) blocks: rmap over the box
+// |n_k| <= ext[k] gives the list index of R = (n1, n2, n3), or -1.
+struct HRMap {
+    const int *rmap;
+    int ext[3];
+};
+
 struct AtomLists {
     const int *aptr;   // natom+1: entries of each atom
     const int *aent;   // entry indices, increasing (= increasing batch)
@@ -131,6 +138,15 @@ __host__ __device__ inline int block_pitch(int mno, int esz)
 }
 // arithmetic modes of the H kernel (values of gint_precision)
 constexpr int kModeF64 = 0, kModeF32 = 1, kModeBF16 = 2, kModeF16 = 3, kModeBF16x3 = 4, kModeF16x3 = 5;
+// H(R) blocks (gint_hr.hip): per-image atom and wrap-shift tables, then the
+// per-batch kernel adding into HR[nR][norb][norb]
+hipError_t launch_HR_prep(hipStream_t s, const Geo &g, long long nent, const int *ent_atom, const int *ent_img,
+                          int *img_atom, const int *perm, const double *pos_in, const double *xw, int *wsh);
+hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const int *img_atom, const int *img,
+                          const int *wsh, int M, int *mark);
+hipError_t launch_HR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                           const int *img, const Basis &b, const int *wsh, const double *W, double wscale,
+                           const HRMap &m, int norb, double *HR);
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                           int b1, const double *W, double wscale, const int *boff, int mno, void *part);
 // H block partials of slab si summed per owned pair (I = pown[p], J = plist[p])

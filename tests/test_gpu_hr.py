@@ -1,0 +1,158 @@
+"""GPU parity of the lattice-vector blocks H(R) (gint_build_HR) against the
+oracle's H(R) (Sec. 3.3.1, H^loc(R) equation).
+
+FP64 bar: max|dH(R)| / max|H(R)| <= 1e-10 over all listed R (the blocks are
+accumulated with FP64 atomics, so only the order of additions differs).
+FP32 plans: max|dH(R)| <= 1e-6 Ha (the mixed-precision target of the H path).
+Cells cover several images of one atom per batch (cutoff above half the
+cell), a triclinic cell, a ragged mesh, empty batches, positions given
+outside the cell, and the 64-atom DZP cell at full size (sampled rows).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gint_inputs as gi
+from tests.test_gpu_parity import (TOL, _dev, _long_range_tiny, _ragged_five_atoms, _rel_max,
+                                   _triclinic_two_species, _vacuum_single_atom)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_21835_amd as g
+
+    g.load_library()
+    return torch, torch.device("cuda:0")
+
+
+def _box(e):
+    return np.array([(a, b, c) for a in range(-e[0], e[0] + 1) for b in range(-e[1], e[1] + 1)
+                     for c in range(-e[2], e[2] + 1)], dtype=np.int32)
+
+
+def _gpu_HR(torch, dev, w, R=None, precision="fp64", positions=None):
+    import paper_2603_21835_amd as g
+
+    plan = g.GintPlan.from_workload(w, precision)
+    if positions is not None:
+        plan.set_positions(positions)
+    V = _dev(torch, dev, w.V)
+    R, HR = plan.build_HR(V, R)
+    H = plan.build_H(V).cpu().numpy()
+    out = HR.cpu().numpy()
+    plan.sync()
+    return plan, R, out, H
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _triclinic_two_species, _long_range_tiny, _ragged_five_atoms,
+                                  _vacuum_single_atom])
+def test_hr_full(oracle_mod, torch_dev, make):
+    torch, dev = torch_dev
+    w = make()
+    _say(f"case HR {w.name} grid {w.grid} natom {w.natom}")
+    plan, R, HR, H = _gpu_HR(torch, dev, w)
+    o = oracle_mod.Oracle.from_workload(w)
+    HRo = o.HR(w.V, R)
+    e = _rel_max(HR, HRo)
+    _say(f"  {len(R)} R, max|H(R)| {np.abs(HRo).max():.3e}: rel {e:.2e}")
+    assert e <= TOL
+    # the listed R are the only ones with a non-zero block: the oracle over
+    # a box around them finds nothing elsewhere
+    m = int(np.abs(R).max()) + 1
+    big = _box((m, m, m))
+    listed = {tuple(int(x) for x in r) for r in R}
+    rest = np.array([r for r in big if tuple(int(x) for x in r) not in listed])
+    assert np.abs(o.HR(w.V, rest)).max() == 0.0
+    # the sum over R is the Gamma-point H of gint_build_H
+    assert _rel_max(HR.sum(0), H) <= 1e-12
+
+
+def test_hr_subset_and_order(oracle_mod, torch_dev):
+    # a shuffled subset of R: each block equals the oracle's, the dropped R
+    # contribute nothing
+    torch, dev = torch_dev
+    w = _triclinic_two_species()
+    import paper_2603_21835_amd as g
+
+    plan = g.GintPlan.from_workload(w)
+    full = plan.HR_lattice()
+    rng = np.random.default_rng(4)
+    sub = full[rng.permutation(len(full))[: len(full) // 3]]
+    V = _dev(torch, dev, w.V)
+    _, HR = plan.build_HR(V, sub)
+    HR = HR.cpu().numpy()
+    o = oracle_mod.Oracle.from_workload(w)
+    HRo = o.HR(w.V, sub)
+    assert _rel_max(HR, HRo) <= TOL
+    # and a second list right after (the cached R map is replaced)
+    sub2 = full[: 5]
+    _, HR2 = plan.build_HR(V, sub2)
+    assert _rel_max(HR2.cpu().numpy(), o.HR(w.V, sub2)) <= TOL
+
+
+def test_hr_positions_outside_cell(oracle_mod, torch_dev):
+    # positions given shifted by lattice vectors: R is taken from the
+    # positions as given, like the oracle's
+    torch, dev = torch_dev
+    w = _triclinic_two_species()
+    lat = np.asarray(w.lattice)
+    shift = np.array([[1, 0, -1], [0, -2, 0], [3, 1, 1]])
+    pos = np.asarray(w.positions) + shift @ lat
+    plan, R, HR, H = _gpu_HR(torch, dev, w, positions=pos)
+    o = oracle_mod.Oracle.from_workload(w)
+    o.set_positions(pos)
+    HRo = o.HR(w.V, R)
+    assert np.abs(HRo).max() > 0
+    e = _rel_max(HR, HRo)
+    _say(f"  shifted positions: {len(R)} R, rel {e:.2e}")
+    assert e <= TOL
+
+
+def test_hr_fp32(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    w = gi.si8_sz()
+    plan, R, HR, H = _gpu_HR(torch, dev, w, precision="fp32")
+    HRo = oracle_mod.Oracle.from_workload(w).HR(w.V, R)
+    dH = np.abs(HR - HRo).max()
+    _say(f"  fp32 si8 H(R): max|dH| {dH:.2e} Ha")
+    assert dH <= 1e-6
+
+
+def test_hr_si64_sampled(oracle_mod, torch_dev):
+    # full-size 64-atom DZP cell: rows of two atoms against the oracle
+    torch, dev = torch_dev
+    w = gi.si64_dzp()
+    _say(f"case HR si64_dzp grid {w.grid}")
+    plan, R, HR, H = _gpu_HR(torch, dev, w)
+    assert _rel_max(HR.sum(0), H) <= 1e-12
+    o = oracle_mod.Oracle.from_workload(w)
+    for I in (0, 42):
+        rows = o.HR(w.V, R, I, I + 1)
+        r0, r1 = o.atom_orb0[I], o.atom_orb0[I + 1]
+        e = _rel_max(HR[:, r0:r1], rows)
+        _say(f"  H(R) rows atom {I}: {e:.2e}")
+        assert e <= TOL
+
+
+def test_hr_errors(torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si8_sz()
+    plan = g.GintPlan.from_workload(w)
+    V = _dev(torch, dev, w.V)
+    with pytest.raises(g.GintError):
+        plan.build_HR(V, [(0, 0, 0), (1, 0, 0), (0, 0, 0)])  # repeated R
+    with pytest.raises(g.GintError):
+        plan.build_HR(V, [(0, 0, 32)])  # outside the supported range
