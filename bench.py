@@ -338,6 +338,13 @@ def main():
     # the H reduction moves every block partial once and writes H's blocks
     hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
               "H_fill": 8 * plan.norb ** 2 * (len(R_list) if args.only == "HR" else 1)}
+    if args.only == "HR":
+        work_hr = plan.work()
+        if work_hr["nblock_hr"] > 0:
+            # the fixed-order H(R) reduction moves every unfolded block partial once
+            hbytes["HR"] = work_hr["nblock_hr"] * work["mno"] ** 2 * work["partial_bytes"]
+            flops.pop("HR")
+            work["nblock_hr"] = work_hr["nblock_hr"]
     kernels = {}
     for k, (ms, n) in timing.items():
         if n == 0:

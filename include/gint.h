@@ -108,6 +108,9 @@ typedef struct {
     long long nblock;      /* H atom-pair block partials over all batches         */
     int mno;               /* block partial edge (most orbitals of one atom)      */
     int partial_bytes;     /* bytes per block partial element (8 FP64, 4 else)    */
+    long long nblock_hr;   /* block partials of the unfolded atom images (H(R)),
+                              -1 before the first gint_build_HR / gint_HR_lattice
+                              call of the current geometry                      */
 } gint_work;
 
 typedef struct gint_plan_s *gint_plan;

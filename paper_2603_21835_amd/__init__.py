@@ -65,7 +65,7 @@ class Work(ctypes.Structure):
                 ("nentry", ctypes.c_longlong), ("npair", ctypes.c_longlong),
                 ("sum_ng", ctypes.c_double), ("sum_ng2", ctypes.c_double),
                 ("batch", ctypes.c_int * 3), ("nslab", ctypes.c_int), ("nblock", ctypes.c_longlong),
-                ("mno", ctypes.c_int), ("partial_bytes", ctypes.c_int)]
+                ("mno", ctypes.c_int), ("partial_bytes", ctypes.c_int), ("nblock_hr", ctypes.c_longlong)]
 
 
 _lib = None
@@ -289,7 +289,7 @@ class GintPlan:
         _check(self._lib.gint_plan_work(self._handle(), ctypes.byref(w)))
         return {"ngrid": w.ngrid, "nbatch": w.nbatch, "nentry": w.nentry, "npair": w.npair,
                 "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nslab": w.nslab,
-                "nblock": w.nblock, "mno": w.mno, "partial_bytes": w.partial_bytes}
+                "nblock": w.nblock, "mno": w.mno, "partial_bytes": w.partial_bytes, "nblock_hr": w.nblock_hr}
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.gint_plan_set_timing(self._handle(), 1 if enable else 0))

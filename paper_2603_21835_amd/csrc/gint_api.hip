@@ -127,6 +127,13 @@ struct gint_plan_s {
     long long hr_gen = -1;
     int nbmax_img = 0;
     std::vector<int> hr_key;
+    // fixed-order H(R): per-image identity entries, per-batch block offsets
+    // of the unfolded images, sorted triple keys and their runs
+    DevBuf img_id, cnt_u, boff_u, hkey, hkey2, hcode, hcode2, hflag, hfscan, tstart, tkey, sort_tmp, hbad;
+    long long nblock_u = 0;
+    int ntri = 0;
+    bool hr_fixed = false;  // the partials fit the budget: sorted-triple path
+    size_t hbudget_eff = 0;  // partial-buffer budget of the last list build
     int npair_owned = 0;          // owned atom pairs (entries of plist)
     std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
@@ -532,6 +539,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr / 3 < budget)
             budget = fr / 3;
     }
+    p->hbudget_eff = budget;
     // a range holds at least one whole batch
     long long per_slab = (long long)(budget / blk_bytes);
     for (int b = 0; b < nb; ++b)
@@ -1071,21 +1079,80 @@ namespace {
 constexpr int kMaxHRExt = 31;  // |n_k| of the lattice vectors of gint_build_HR
 
 // per-image atoms, wrap shifts and the most images in one batch, once per
-// list generation
+// list generation; and, when the block partials of the unfolded images fit
+// the partial-buffer budget, the sorted canonical triples of the fixed-order
+// reduction
 gint_status hr_prepare(gint_plan p)
 {
     if (p->hr_gen == p->gen)
         return GINT_OK;
     const hipStream_t st = p->stream;
+    const long long nb = p->geo.nbatch;
     STCHK(p->img_atom.ensure(sizeof(int) * (size_t)(p->nimg + 1)));
     STCHK(p->wsh.ensure(sizeof(int) * 3 * (size_t)p->natom));
     HIPCHK(launch_HR_prep(st, p->geo, p->nent, p->ent_atom.as<int>(), p->ent_img.as<int>(), p->img_atom.as<int>(),
                           p->perm.as<int>(), p->pos_in.as<double>(), p->xw.as<double>(), p->wsh.as<int>()));
     STCHK(p->maxv.ensure(2 * sizeof(int)));
-    HIPCHK(launch_max_i32(st, p->cnt_i.as<int>(), p->geo.nbatch, p->maxv.as<int>()));
+    HIPCHK(launch_max_i32(st, p->cnt_i.as<int>(), nb, p->maxv.as<int>()));
     int most = 0;
     STCHK(read_scalar(p, p->maxv.as<int>(), &most));
     p->nbmax_img = most;
+
+    // block offsets of the unfolded images
+    STCHK(p->img_id.ensure(sizeof(int) * (size_t)(p->nimg + 1)));
+    HIPCHK(launch_iota(st, p->nimg + 1, p->img_id.as<int>()));
+    STCHK(p->cnt_u.ensure(sizeof(int) * nb));
+    STCHK(p->boff_u.ensure(sizeof(int) * (nb + 1)));
+    HIPCHK(launch_block_count(st, (int)nb, p->iptr.as<int>(), p->cnt_u.as<int>()));
+    STCHK(scan_i32(p, st, p->cnt_u.as<int>(), nb, p->boff_u.as<int>()));
+    int nbu = 0;
+    STCHK(read_scalar(p, p->boff_u.as<int>() + nb, &nbu));
+    if (nbu < 0)
+        return fail(GINT_EUNSUPPORTED, "H(R) block lists exceed 2^31 entries");
+    p->nblock_u = nbu;
+    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
+    const size_t blk_bytes = esz * (size_t)block_pitch(p->mno, (int)esz);
+    p->hr_fixed = !p->ext_hpart && blk_bytes * (size_t)std::max(nbu, 1) <= std::max(p->hbudget_eff, p->Hpart.bytes);
+    p->ntri = 0;
+    if (p->hr_fixed && nbu > 0) {
+        const size_t n = (size_t)nbu;
+        STCHK(p->hkey.ensure(sizeof(unsigned long long) * n));
+        STCHK(p->hkey2.ensure(sizeof(unsigned long long) * n));
+        STCHK(p->hcode.ensure(sizeof(int) * n));
+        STCHK(p->hcode2.ensure(sizeof(int) * n));
+        STCHK(p->hbad.ensure(sizeof(int)));
+        HIPCHK(launch_fill_i32(st, p->hbad.as<int>(), 1, 0));
+        HIPCHK(launch_HR_keys(st, (int)nb, p->iptr.as<int>(), p->boff_u.as<int>(), p->img_atom.as<int>(),
+                              p->img.as<int>(), p->perm.as<int>(), p->wsh.as<int>(), p->natom,
+                              p->hkey.as<unsigned long long>(), p->hcode.as<int>(), p->hbad.as<int>()));
+        int bad = 0;
+        STCHK(read_scalar(p, p->hbad.as<int>(), &bad));
+        if (bad)
+            return fail(GINT_EUNSUPPORTED, "an atom-image pair spans more than %d cells along an axis", kHRBox);
+        int end_bit = 18;
+        while (end_bit < 64 && ((unsigned long long)p->natom * p->natom) >> (end_bit - 18))
+            ++end_bit;
+        size_t tb = 0;
+        HIPCHK(sort_HR_keys(st, nullptr, tb, p->hkey.as<unsigned long long>(), p->hkey2.as<unsigned long long>(),
+                            p->hcode.as<int>(), p->hcode2.as<int>(), nbu, end_bit));
+        STCHK(p->sort_tmp.ensure(tb));
+        HIPCHK(sort_HR_keys(st, p->sort_tmp.p, tb, p->hkey.as<unsigned long long>(),
+                            p->hkey2.as<unsigned long long>(), p->hcode.as<int>(), p->hcode2.as<int>(), nbu,
+                            end_bit));
+        STCHK(p->hflag.ensure(sizeof(int) * n));
+        STCHK(p->hfscan.ensure(sizeof(int) * (n + 1)));
+        HIPCHK(launch_seg(st, nbu, p->hkey2.as<unsigned long long>(), p->hflag.as<int>(), nullptr, nullptr, nullptr,
+                          false));
+        STCHK(scan_i32(p, st, p->hflag.as<int>(), nbu, p->hfscan.as<int>()));
+        int ntri = 0;
+        STCHK(read_scalar(p, p->hfscan.as<int>() + nbu, &ntri));
+        STCHK(p->tstart.ensure(sizeof(int) * ((size_t)ntri + 1)));
+        STCHK(p->tkey.ensure(sizeof(unsigned long long) * ((size_t)ntri + 1)));
+        HIPCHK(launch_seg(st, nbu, p->hkey2.as<unsigned long long>(), nullptr, p->hfscan.as<int>(),
+                          p->tstart.as<int>(), p->tkey.as<unsigned long long>(), true));
+        p->ntri = ntri;
+        STCHK(p->Hpart.ensure(blk_bytes * n));
+    }
     p->hr_gen = p->gen;
     return GINT_OK;
 }
@@ -1173,6 +1240,23 @@ gint_status gint_build_HR(gint_plan p, const double *V_dev, int nR, const int *R
     STCHK(timed(p, GINT_K_H_FILL,
                 [&] { return launch_fill_f64(st, HR_dev, (long long)nR * p->norb * p->norb, 0.0); }));
     const Basis B = p->basis();
+    if (p->hr_fixed) {
+        // the Gamma-point H block kernel over the unfolded images (one image
+        // per entry), then the fixed-order sums per canonical triple
+        Bins bu = p->bins();
+        bu.bptr = p->iptr.as<int>();
+        bu.ent_atom = p->img_atom.as<int>();
+        bu.ent_img = p->img_id.as<int>();
+        STCHK(timed(p, GINT_K_H, [&] {
+            return launch_H_batch(st, (int)p->prec, p->geo, bu, B, p->nbmax_img, 0, p->geo.nbatch, V_dev, p->dV,
+                                  p->boff_u.as<int>(), p->mno, p->Hpart.p);
+        }));
+        STCHK(timed(p, GINT_K_HR, [&] {
+            return launch_HR_reduce(st, p->f32(), p->ntri, p->tkey.as<unsigned long long>(), p->tstart.as<int>(),
+                                    p->hcode2.as<int>(), p->natom, m, B, p->mno, p->norb, p->Hpart.p, HR_dev);
+        }));
+        return GINT_OK;
+    }
     STCHK(timed(p, GINT_K_HR, [&] {
         return launch_HR_batch(st, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(), p->img_atom.as<int>(),
                                p->img.as<int>(), B, p->wsh.as<int>(), V_dev, p->dV, m, p->norb, HR_dev);
@@ -1218,6 +1302,7 @@ gint_status gint_plan_work(gint_plan p, gint_work *out)
     out->nblock = p->nblock;
     out->mno = p->mno;
     out->partial_bytes = p->f32() ? 4 : 8;
+    out->nblock_hr = p->hr_gen == p->gen ? p->nblock_u : -1;
     return GINT_OK;
 }
 

@@ -553,6 +553,123 @@ hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *po
     return hipGetLastError();
 }
 
+// H(R): one wave per canonical triple (I, J, R) (key of k_HR_keys) sums the
+// triple's block partials in their sorted (batch) order, streaming each
+// block whole like k_H_pairreduce, and writes H_IJ(R) and its transpose
+// H_JI(-R) for the listed R (for I = J and R = 0 the upper triangle,
+// mirrored).
+template <typename T>
+__global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long long *__restrict__ tkey,
+                                                   const int *__restrict__ tstart, const int *__restrict__ list,
+                                                   int natom, HRMap hm, Basis bs, int mno, int norb,
+                                                   const T *__restrict__ part, double *__restrict__ HR)
+{
+    typedef typename Vec16<T>::type VT;
+    constexpr int V = Vec16<T>::V;
+    constexpr int M = (kMaxOrb * kMaxOrb + 64 * V - 1) / (64 * V);  // vectors per lane
+    constexpr int B = kHRBox, w = 2 * kHRBox + 1;
+    __shared__ double s_sum[4][2][kMaxOrb * kMaxOrb];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int t = blockIdx.x * 4 + wv;
+    if (t >= ntri)
+        return;
+    const unsigned long long key = tkey[t];
+    const int ridx = (int)(key & 0x3ffffULL);
+    const long long ij = (long long)(key >> 18);
+    const int I = (int)(ij / natom), J = (int)(ij - (long long)I * natom);
+    const int R0 = ridx / (w * w) - B, R1 = (ridx / w) % w - B, R2 = ridx % w - B;
+    const bool self = I == J && R0 == 0 && R1 == 0 && R2 == 0;
+    const int qo = hr_lookup(hm, R0, R1, R2);
+    const int qm = self ? -1 : hr_lookup(hm, -R0, -R1, -R2);
+    if (qo < 0 && qm < 0)
+        return;
+    auto qof = [](int c) { return c >= 0 ? c : -c - 1; };
+    const int l0 = tstart[t], l1 = tstart[t + 1];
+    const int pitch = block_pitch(mno, sizeof(T));
+    double up[M][V], dn[M][V];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            up[m][i] = dn[m][i] = 0.0;
+    for (int kc = l0; kc < l1; kc += 64) {
+        const int nc = min(64, l1 - kc);
+        const int lcode = lane < nc ? list[kc + lane] : 0;
+        for (int k0 = 0; k0 < nc; k0 += kRedGroup) {
+            VT v[kRedGroup][M];
+            bool isup[kRedGroup];
+#pragma unroll
+            for (int g = 0; g < kRedGroup; ++g) {
+                const int k = k0 + g;
+                const bool ok = k < nc;
+                const int code = __builtin_amdgcn_readlane(lcode, ok ? k : 0);
+                isup[g] = code >= 0;
+                const T *blk = part + (size_t)qof(code) * pitch;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int e = V * lane + 64 * V * m;
+                    v[g][m] = (ok && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kRedGroup; ++g)
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+#pragma unroll
+                    for (int i = 0; i < V; ++i) {
+                        const double x = Vec16<T>::at(v[g][m], i);
+                        if (isup[g])
+                            up[m][i] += x;
+                        else
+                            dn[m][i] += x;
+                    }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const int e = V * lane + 64 * V * m + i;
+            if (e < kMaxOrb * kMaxOrb) {
+                s_sum[wv][0][e] = up[m][i];
+                s_sum[wv][1][e] = dn[m][i];
+            }
+        }
+    const int mu0 = bs.orb0[I], nI = bs.orb0[I + 1] - mu0;
+    const int nu0 = bs.orb0[J], nJ = bs.orb0[J + 1] - nu0;
+    const size_t nn = (size_t)norb * norb;
+    const int mm = mno * mno;
+    for (int e = lane; e < mm; e += 64) {
+        const int r = e / mno, c = e - r * mno;
+        if (r < nI && c < nJ && !(self && c < r)) {
+            const double sum = s_sum[wv][0][e] + s_sum[wv][1][c * mno + r];
+            if (qo >= 0) {
+                HR[qo * nn + (size_t)(mu0 + r) * norb + nu0 + c] = sum;
+                if (self)
+                    HR[qo * nn + (size_t)(nu0 + c) * norb + mu0 + r] = sum;
+            }
+            if (qm >= 0)
+                HR[qm * nn + (size_t)(nu0 + c) * norb + mu0 + r] = sum;
+        }
+    }
+}
+
+hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const unsigned long long *tkey, const int *tstart,
+                            const int *list, int natom, const HRMap &m, const Basis &b, int mno, int norb,
+                            const void *part, double *HR)
+{
+    if (ntri <= 0)
+        return hipSuccess;
+    const unsigned nblk = (unsigned)((ntri + 3) / 4);
+    if (f32)
+        hipLaunchKernelGGL(k_HR_reduce<float>, dim3(nblk), dim3(256), 0, s, ntri, tkey, tstart, list, natom, m, b, mno,
+                           norb, static_cast<const float *>(part), HR);
+    else
+        hipLaunchKernelGGL(k_HR_reduce<double>, dim3(nblk), dim3(256), 0, s, ntri, tkey, tstart, list, natom, m, b,
+                           mno, norb, static_cast<const double *>(part), HR);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_f64(double *p, long long n, double v)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -126,6 +126,15 @@ __device__ __forceinline__ int lower_bound_i(const int *__restrict__ a, int lo, 
     return lo;
 }
 
+// index of R = (n1, n2, n3) in a caller's list of lattice vectors, -1 if
+// absent
+__device__ __forceinline__ int hr_lookup(const HRMap &m, int n1, int n2, int n3)
+{
+    if (n1 < -m.ext[0] || n1 > m.ext[0] || n2 < -m.ext[1] || n2 > m.ext[1] || n3 < -m.ext[2] || n3 > m.ext[2])
+        return -1;
+    return m.rmap[((n1 + m.ext[0]) * (2 * m.ext[1] + 1) + n2 + m.ext[1]) * (2 * m.ext[2] + 1) + n3 + m.ext[2]];
+}
+
 __device__ __forceinline__ void unpack_image(int pk, int *n)
 {
     n[0] = (int)(signed char)(pk & 0xff);

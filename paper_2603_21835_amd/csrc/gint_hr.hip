@@ -10,9 +10,19 @@
 // every block of two of them (ia <= ja) on the matrix cores.  With image T_a
 // of atom I and T_b of atom J, a block is the contribution of the crystal
 // points r_g - T_a to H_IJ(T_b - T_a); its transpose goes to
-// H_JI(T_a - T_b).  Blocks are added into the dense per-R output with FP64
-// atomics (the order of the additions is not fixed).
+// H_JI(T_a - T_b).
+//
+// Default (fixed order): the per-batch kernels of the Gamma-point H write
+// the blocks of the unfolded images as partials; every block gets the key
+// of its canonical triple (I, J, R) (I < J, or I = J and R >= 0 in
+// lexicographic order; the block or its transpose), the keys are sorted
+// once per geometry (stable: batch order inside a triple), and one wave per
+// triple sums its blocks in that order and writes H_IJ(R) and H_JI(-R)
+// (k_HR_reduce).  When the partials exceed the partial-buffer budget, the
+// blocks are added into the output with FP64 atomics instead (k_HR_batch;
+// the order of the additions is then not fixed).
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include "gint_device.h"
 
@@ -93,15 +103,119 @@ hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const in
     return hipGetLastError();
 }
 
-constexpr int kHRWaves = 16;
-
-// index of R = (n1, n2, n3) in the caller's list, -1 if absent
-__device__ __forceinline__ int hr_lookup(const HRMap &m, int n1, int n2, int n3)
+// 0, 1, ..., n - 1
+__global__ void k_iota(long long n, int *__restrict__ a)
 {
-    if (n1 < -m.ext[0] || n1 > m.ext[0] || n2 < -m.ext[1] || n2 > m.ext[1] || n3 < -m.ext[2] || n3 > m.ext[2])
-        return -1;
-    return m.rmap[((n1 + m.ext[0]) * (2 * m.ext[1] + 1) + n2 + m.ext[1]) * (2 * m.ext[2] + 1) + n3 + m.ext[2]];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        a[i] = (int)i;
 }
+
+// Canonical triple of every unfolded block: key = (I n_atom + J) 2^18 +
+// index of R in the box |n_k| <= kHRBox, I, J input atom ids; code = the
+// block's partial index q (stored as H_IJ) or -q - 1 (stored as H_JI).
+// *bad is set when some R falls outside the box (the key then sorts last).
+__global__ __launch_bounds__(256) void k_HR_keys(const int *__restrict__ iptr, const int *__restrict__ boff,
+                                                 const int *__restrict__ img_atom, const int *__restrict__ img,
+                                                 const int *__restrict__ perm, const int *__restrict__ wsh, int natom,
+                                                 unsigned long long *__restrict__ key, int *__restrict__ code,
+                                                 int *__restrict__ bad)
+{
+    const int b = blockIdx.x;
+    const int i0 = iptr[b], nb = iptr[b + 1] - i0, q0 = boff[b];
+    const int nblk = nb * (nb + 1) / 2;
+    constexpr int M = kHRBox, w = 2 * kHRBox + 1;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+        int ia = 0, r = k;
+        while (r >= nb - ia) {
+            r -= nb - ia;
+            ++ia;
+        }
+        const int ja = ia + r;
+        const int A = img_atom[i0 + ia], C = img_atom[i0 + ja];
+        int na[3], nc[3], R[3];
+        unpack_image(img[i0 + ia], na);
+        unpack_image(img[i0 + ja], nc);
+        for (int d = 0; d < 3; ++d)
+            R[d] = (nc[d] - wsh[3 * C + d]) - (na[d] - wsh[3 * A + d]);
+        const int Ii = perm[A], Ji = perm[C];
+        const bool Rnonneg = R[0] > 0 || (R[0] == 0 && (R[1] > 0 || (R[1] == 0 && R[2] >= 0)));
+        const bool up = Ii < Ji || (Ii == Ji && Rnonneg);
+        const int I = up ? Ii : Ji, J = up ? Ji : Ii, s = up ? 1 : -1;
+        bool in = true;
+        for (int d = 0; d < 3; ++d)
+            in = in && s * R[d] >= -M && s * R[d] <= M;
+        const int q = q0 + k;
+        if (in) {
+            const int ridx = ((s * R[0] + M) * w + s * R[1] + M) * w + s * R[2] + M;
+            key[q] = (((unsigned long long)I * natom + J) << 18) | (unsigned long long)ridx;
+        } else {
+            key[q] = ~0ULL;
+            *bad = 1;
+        }
+        code[q] = up ? q : -q - 1;
+    }
+}
+
+// first position of every run of equal sorted keys: flag, then (after an
+// exclusive scan of the flags) start and key of each run
+__global__ void k_seg_flag(long long n, const unsigned long long *__restrict__ key, int *__restrict__ flag)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_seg_fill(long long n, const unsigned long long *__restrict__ key, const int *__restrict__ fscan,
+                           int *__restrict__ tstart, unsigned long long *__restrict__ tkey)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    if (i == 0 || key[i] != key[i - 1]) {
+        tstart[fscan[i]] = (int)i;
+        tkey[fscan[i]] = key[i];
+    }
+    if (i == n - 1)
+        tstart[fscan[n]] = (int)n;
+}
+
+hipError_t launch_iota(hipStream_t s, long long n, int *a)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_HR_keys(hipStream_t s, int nbatch, const int *iptr, const int *boff, const int *img_atom,
+                          const int *img, const int *perm, const int *wsh, int natom, unsigned long long *key,
+                          int *code, int *bad)
+{
+    hipLaunchKernelGGL(k_HR_keys, dim3((unsigned)nbatch), dim3(256), 0, s, iptr, boff, img_atom, img, perm, wsh, natom,
+                       key, code, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg(hipStream_t s, long long n, const unsigned long long *key, int *flag, int *fscan, int *tstart,
+                      unsigned long long *tkey, bool fill)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (fill)
+        hipLaunchKernelGGL(k_seg_fill, dim3(nb), dim3(256), 0, s, n, key, fscan, tstart, tkey);
+    else
+        hipLaunchKernelGGL(k_seg_flag, dim3(nb), dim3(256), 0, s, n, key, flag);
+    return hipGetLastError();
+}
+
+hipError_t sort_HR_keys(hipStream_t s, void *tmp, size_t &tmp_bytes, const unsigned long long *key_in,
+                        unsigned long long *key_out, const int *code_in, int *code_out, int n, int end_bit)
+{
+    return hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, code_in, code_out, n, 0, end_bit, s);
+}
+
+constexpr int kHRWaves = 16;
 
 template <typename T, int P>
 __global__ __launch_bounds__(64 * kHRWaves) void k_HR_batch(Geo g, const int *__restrict__ iptr,

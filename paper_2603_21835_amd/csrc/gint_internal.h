@@ -76,6 +76,7 @@ struct HRMap {
     const int *rmap;
     int ext[3];
 };
+constexpr int kHRBox = 31;  // |n_k| of the lattice vectors of the H(R) blocks
 
 struct AtomLists {
     const int *aptr;   // natom+1: entries of each atom
@@ -142,6 +143,18 @@ constexpr int kModeF64 = 0, kModeF32 = 1, kModeBF16 = 2, kModeF16 = 3, kModeBF16
 // per-batch kernel adding into HR[nR][norb][norb]
 hipError_t launch_HR_prep(hipStream_t s, const Geo &g, long long nent, const int *ent_atom, const int *ent_img,
                           int *img_atom, const int *perm, const double *pos_in, const double *xw, int *wsh);
+hipError_t launch_iota(hipStream_t s, long long n, int *a);
+hipError_t launch_HR_keys(hipStream_t s, int nbatch, const int *iptr, const int *boff, const int *img_atom,
+                          const int *img, const int *perm, const int *wsh, int natom, unsigned long long *key,
+                          int *code, int *bad);
+hipError_t launch_seg(hipStream_t s, long long n, const unsigned long long *key, int *flag, int *fscan, int *tstart,
+                      unsigned long long *tkey, bool fill);
+hipError_t sort_HR_keys(hipStream_t s, void *tmp, size_t &tmp_bytes, const unsigned long long *key_in,
+                        unsigned long long *key_out, const int *code_in, int *code_out, int n, int end_bit);
+// fixed-order sums of the H(R) block partials, one wave per canonical triple
+hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const unsigned long long *tkey, const int *tstart,
+                            const int *list, int natom, const HRMap &m, const Basis &b, int mno, int norb,
+                            const void *part, double *HR);
 hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const int *img_atom, const int *img,
                           const int *wsh, int M, int *mark);
 hipError_t launch_HR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,

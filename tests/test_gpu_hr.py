@@ -156,3 +156,36 @@ def test_hr_errors(torch_dev):
         plan.build_HR(V, [(0, 0, 0), (1, 0, 0), (0, 0, 0)])  # repeated R
     with pytest.raises(g.GintError):
         plan.build_HR(V, [(0, 0, 32)])  # outside the supported range
+
+
+def test_hr_fixed_order_repeatable(torch_dev):
+    # the default path sums each triple's blocks in a fixed order: two calls
+    # give identical bits
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _triclinic_two_species()
+    plan = g.GintPlan.from_workload(w)
+    V = _dev(torch, dev, w.V)
+    R, a = plan.build_HR(V)
+    a = a.cpu().numpy()
+    _, b = plan.build_HR(V, R)
+    assert plan.work()["nblock_hr"] > 0
+    assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_hr_atomic_fallback(oracle_mod, torch_dev):
+    # a partial-buffer budget below the unfolded blocks' size: the blocks
+    # are added into the output with atomics; same values to roundoff
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _triclinic_two_species()
+    plan = g.GintPlan.from_workload(w)
+    plan.tune((4, 4, 2), 1)
+    V = _dev(torch, dev, w.V)
+    R, HR = plan.build_HR(V)
+    HRo = oracle_mod.Oracle.from_workload(w).HR(w.V, R)
+    e = _rel_max(HR.cpu().numpy(), HRo)
+    _say(f"  atomic fallback: {len(R)} R, rel {e:.2e}")
+    assert e <= TOL
