@@ -9,7 +9,9 @@ Functions follow Sec. 3.3.1 ("Uniform Grid Integration for Usual
 Quantities") of the paper: the rho(r_g) equation, the H^loc equation and the
 F^{loc,Pulay} equation, at the Gamma point, on the basis of Sec. 2.1; and
 the lattice-vector blocks H^loc(R) of the same H^loc equation (``HR``),
-whose phase sum is the H(k) equation of Sec. 2.1.
+whose phase sum is the H(k) equation of Sec. 2.1, and rho from
+lattice-vector density-matrix blocks (``rhoR``, the rho(r_g) equation with
+its sums over R and R').
 """
 from __future__ import annotations
 
@@ -64,6 +66,8 @@ def _load():
     lib.oracle_H_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, lp, dp]
     lib.oracle_HR_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp]
     lib.oracle_HR_rows.restype = ctypes.c_int
+    lib.oracle_rhoR.argtypes = [P, ctypes.c_int, ip, dp, ctypes.c_long, lp, dp]
+    lib.oracle_rhoR.restype = ctypes.c_int
     lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
     lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, ctypes.c_long, lp, dp]
     lib.oracle_set_positions.argtypes = [P, dp]
@@ -200,6 +204,24 @@ class Oracle:
         n = int(self.atom_orb0[I1] - self.atom_orb0[I0])
         out = np.zeros((Rl.shape[0], n, self.norb))
         rc = self._lib.oracle_HR_rows(self._ctx, _dp(V), int(I0), int(I1), int(Rl.shape[0]), _ip(Rl), _dp(out))
+        if rc != 0:
+            raise RuntimeError("a mesh point sees too many images of one atom")
+        return out
+
+    def rhoR(self, R, DR, idx: Optional[Sequence[int]] = None) -> np.ndarray:
+        """rho from lattice-vector density-matrix blocks DR [n][norb][norb]
+        for the lattice multiples R (n x 3), at mesh points ``idx`` (all when
+        None)."""
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        DR = np.ascontiguousarray(DR, dtype=np.float64)
+        assert DR.shape == (Rl.shape[0], self.norb, self.norb)
+        if idx is None:
+            n, ip_ = self.ngrid, None
+        else:
+            keep = np.ascontiguousarray(idx, dtype=np.int64)
+            n, ip_ = keep.size, keep.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+        out = np.zeros(n)
+        rc = self._lib.oracle_rhoR(self._ctx, int(Rl.shape[0]), _ip(Rl), _dp(DR), n, ip_, _dp(out))
         if rc != 0:
             raise RuntimeError("a mesh point sees too many images of one atom")
         return out

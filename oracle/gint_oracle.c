@@ -669,6 +669,83 @@ int oracle_HR_rows(void *p, const double *V, int I0, int I1, int nR, const int *
 }
 
 /*
+ * Density from lattice-vector density-matrix blocks (Sec. 3.3.1, rho(r_g)
+ * equation with its sums over R and R'):
+ *   rho(r_g) = sum_{R, R'} sum_{mu nu} D_mu,nu(R) phi_mu(r_g - tau_I - R')
+ *                                              phi_nu(r_g - tau_J - R - R'),
+ * tau the positions as given.  With image T_a = R' of atom I and T_b of
+ * atom J reaching r_g, the term is the block D_IJ(T_b - T_a).  DR is
+ * [nR][norb][norb] for the nR lattice multiples R (blocks of unlisted R are
+ * zero).  rho at mesh points idx[0..npts) (all when idx == NULL).  Returns
+ * -1 if some point sees more than MAX_IMG images of one atom, else 0.
+ * Parallel over points.
+ */
+int oracle_rhoR(void *p, int nR, const int *R, const double *DR, long npts, const long *idx, double *rho)
+{
+    const octx *c = (const octx *)p;
+    const int norb = c->norb;
+    const long nq = idx ? npts : c->ng;
+    int bad = 0;
+#pragma omp parallel reduction(| : bad)
+    {
+        /* per atom: its images at the point and their orbital values */
+        int *kimg = (int *)malloc(sizeof(int) * c->natom);
+        int *nvec = (int *)malloc(sizeof(int) * 3 * MAX_IMG * c->natom);
+        double *ph = (double *)malloc(sizeof(double) * MAX_IMG * 64 * c->natom);
+#pragma omp for schedule(dynamic, 64)
+        for (long q = 0; q < nq; ++q) {
+            const long g = idx ? idx[q] : q;
+            double r[3];
+            mesh_point(c, g, r);
+            for (int I = 0; I < c->natom; ++I) {
+                kimg[I] = atom_image_phi(c, I, r, MAX_IMG, nvec + 3 * MAX_IMG * I, ph + (size_t)MAX_IMG * 64 * I);
+                if (kimg[I] > MAX_IMG) {
+                    bad = 1;
+                    kimg[I] = 0;
+                }
+            }
+            double acc = 0.0;
+            for (int I = 0; I < c->natom; ++I) {
+                const int nI = c->sp_norb[c->spc[I]];
+                const int i0 = c->atom_orb0[I];
+                for (int J = 0; J < c->natom; ++J) {
+                    const int nJ = c->sp_norb[c->spc[J]];
+                    const int j0 = c->atom_orb0[J];
+                    for (int a = 0; a < kimg[I]; ++a)
+                        for (int b = 0; b < kimg[J]; ++b) {
+                            const int *Ta = nvec + 3 * MAX_IMG * I + 3 * a;
+                            const int *Tb = nvec + 3 * MAX_IMG * J + 3 * b;
+                            int ir = -1;
+                            for (int k = 0; k < nR; ++k)
+                                if (R[3 * k] == Tb[0] - Ta[0] && R[3 * k + 1] == Tb[1] - Ta[1] &&
+                                    R[3 * k + 2] == Tb[2] - Ta[2]) {
+                                    ir = k;
+                                    break;
+                                }
+                            if (ir < 0)
+                                continue;
+                            const double *pa = ph + (size_t)MAX_IMG * 64 * I + (size_t)a * nI;
+                            const double *pb = ph + (size_t)MAX_IMG * 64 * J + (size_t)b * nJ;
+                            const double *Dblk = DR + ((size_t)ir * norb + i0) * norb + j0;
+                            for (int x = 0; x < nI; ++x) {
+                                double t = 0.0;
+                                for (int y = 0; y < nJ; ++y)
+                                    t += Dblk[(size_t)x * norb + y] * pb[y];
+                                acc += pa[x] * t;
+                            }
+                        }
+                }
+            }
+            rho[q] = acc;
+        }
+        free(kimg);
+        free(nvec);
+        free(ph);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
  * rho at mesh points idx[0..npts) (or at g = 0..npts-1 when idx == NULL).
  * Parallel over points.
  */

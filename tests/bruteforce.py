@@ -132,6 +132,30 @@ class BruteCell:
                 out[q] += self.dV * A.T @ img((T[0] + R[0], T[1] + R[1], T[2] + R[2]))
         return out
 
+    def rhoR(self, Rlist, DR):
+        """rho(r_g) = sum_T sum_q phi_T(r_g)^T DR[q] phi_{T + R_q}(r_g): the
+        sums over R' (= T) and R of the rho(r_g) equation, T over a cube big
+        enough that no orbital pair is missed."""
+        rcmax = max(o[1] for lst in self.orbs for o in lst)
+        nimg = int(math.ceil(rcmax / np.min(np.linalg.norm(self.lat, axis=1)))) + 1
+        cache = {}
+
+        def img(n):
+            if n not in cache:
+                cache[n] = self.phi_image(n)
+            return cache[n]
+
+        out = np.zeros(len(self.points))
+        rng = range(-nimg, nimg + 1)
+        for T in [(a, b, c) for a in rng for b in rng for c in rng]:
+            A = img(T)
+            if not np.any(A):
+                continue
+            for q, R in enumerate(Rlist):
+                B = img((T[0] + R[0], T[1] + R[1], T[2] + R[2]))
+                out += np.einsum("gm,mn,gn->g", A, DR[q], B)
+        return out
+
     def H(self, V, phi=None):
         phi = self.phi_all() if phi is None else phi
         return self.dV * (phi * V[:, None]).T @ phi

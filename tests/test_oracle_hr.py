@@ -1,5 +1,6 @@
 """Pins of the oracle's lattice-vector blocks H(R) (Sec. 3.3.1, H^loc(R)
-equation; Sec. 2.1, H(k) equation).
+equation; Sec. 2.1, H(k) equation) and of rho from lattice-vector density
+matrices D(R) (Sec. 3.3.1, rho(r_g) equation with its sums over R, R').
 
 * brute force: every crystal mesh point enumerated as a cell point shifted by
   a lattice vector, unfolded orbitals from scipy's spline and harmonics;
@@ -9,7 +10,10 @@ equation; Sec. 2.1, H(k) equation).
   copy c2 of atom J are the sum of H(R) over n1 = c2 - c1 mod 3 and all
   n2, n3 (the supercell runs through the folded Gamma path);
 * Hermiticity H(R)_IJ = H(-R)_JI^T, and the lattice-translation rule for
-  positions given outside the cell.
+  positions given outside the cell;
+* rho(D(R)): brute force; D(R) = D for every R gives the folded Gamma-point
+  rho of D; the energy identity dV sum_g V_g rho_g = sum_R <D(R), H(R)>
+  against the oracle's H(R) (random, non-symmetric D(R)).
 """
 import numpy as np
 import pytest
@@ -120,3 +124,41 @@ def test_hr_supercell(oracle_mod):
             want = sum(HR[i] for i, r in enumerate(R) if (int(r[0]) - (c2 - c1)) % 3 == 0)
             got = H_sc[c1 * nb:(c1 + 1) * nb, c2 * nb:(c2 + 1) * nb]
             assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max())
+
+
+def _random_DR(rng, nR, norb):
+    return rng.normal(size=(nR, norb, norb)) / norb
+
+
+@pytest.mark.parametrize("make", [_two_atom_dzp, _tiny_long_range])
+def test_rhoR_bruteforce(oracle_mod, make):
+    w = make()
+    o = oracle_mod.Oracle.from_workload(w)
+    R = _box(2)
+    DR = _random_DR(np.random.default_rng(1), len(R), o.norb)
+    rho = o.rhoR(R, DR)
+    bf = BruteCell(w).rhoR([tuple(r) for r in R], DR)
+    assert np.abs(bf).max() > 1e-3
+    assert np.abs(rho - bf).max() <= 1e-13 * max(1.0, np.abs(bf).max())
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _two_atom_dzp, _tiny_long_range])
+def test_rhoR_constant_is_gamma(oracle_mod, make):
+    w = make()
+    o = oracle_mod.Oracle.from_workload(w)
+    R = _box(4)
+    DR = np.broadcast_to(w.D, (len(R),) + w.D.shape).copy()
+    rho = o.rhoR(R, DR)
+    ref = o.rho(w.D)
+    assert np.abs(rho - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _two_atom_dzp])
+def test_rhoR_energy_identity(oracle_mod, make):
+    w = make()
+    o = oracle_mod.Oracle.from_workload(w)
+    R = _box(3)
+    DR = _random_DR(np.random.default_rng(2), len(R), o.norb)
+    E1 = o.dV * float(np.dot(w.V, o.rhoR(R, DR)))
+    E2 = float(np.sum(DR * o.HR(w.V, R)))
+    assert abs(E1 - E2) <= 1e-12 * max(1.0, np.sum(np.abs(DR * o.HR(w.V, R))))
