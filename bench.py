@@ -232,9 +232,11 @@ def main():
     ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
-    ap.add_argument("--only", default=None, choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR"],
+    ap.add_argument("--only", default=None,
+                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR"],
                     help="time one contraction only (short profiler runs); HR: the lattice-vector blocks "
-                         "H(R) for every R of gint_HR_lattice")
+                         "H(R) for every R of gint_HR_lattice; rhoR: rho from random lattice-vector density "
+                         "matrices D(R) over the same R")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--serial", action="store_true",
@@ -290,13 +292,22 @@ def main():
     rho = torch.empty(plan.ngrid, dtype=torch.float64, device=dev)
     F = torch.empty((plan.natom, 3), dtype=torch.float64, device=dev)
     work = plan.work()
-    if args.only == "HR":
+    if args.only in ("HR", "rhoR"):
         R_list = plan.HR_lattice()
+    if args.only == "HR":
         HRbuf = torch.empty((len(R_list), plan.norb, plan.norb), dtype=torch.float64, device=dev)
+    if args.only == "rhoR":
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(12)
+        DRbuf = torch.randn((len(R_list), plan.norb, plan.norb), dtype=torch.float64, device=dev,
+                            generator=gen) / plan.norb
 
     def step():
         if args.only == "HR":
             plan.build_HR(V, R_list, out=HRbuf)
+            return
+        if args.only == "rhoR":
+            plan.build_rhoR(R_list, DRbuf, out=rho)
             return
         if args.only is None:
             plan.set_positions(w.positions)
@@ -432,6 +443,12 @@ def main():
         out["config"]["workload"] = (f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh "
                                      f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the lattice-vector "
                                      f"blocks H(R) of {len(R_list)} lattice vectors (gint_build_HR)")
+        out["config"]["n_R"] = len(R_list)
+    if args.only == "rhoR":
+        out["config"]["workload"] = (f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh "
+                                     f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = rho from random "
+                                     f"density-matrix blocks D(R) of {len(R_list)} lattice vectors "
+                                     f"(gint_build_rhoR)")
         out["config"]["n_R"] = len(R_list)
     if not args.no_cpu_baseline and args.only is None:
         _progress("cpu baseline (oracle sample)")

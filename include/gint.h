@@ -217,6 +217,21 @@ gint_status gint_H_rho_force(gint_plan plan, const double *V_dev, const double *
  * too many atom images reach one mesh batch. */
 gint_status gint_build_HR(gint_plan plan, const double *V_dev, int nR, const int *R, double *HR_dev);
 
+/* rho from lattice-vector blocks of the density matrix (Sec. 3.3.1, rho(r_g)
+ * equation with its sums over R and R'):
+ *   rho(r_g) = sum_{R, R'} sum_{mu nu} D_mu,nu(R) phi_mu(r_g - tau_I - R')
+ *                                                phi_nu(r_g - tau_J - R - R'),
+ * tau the positions as given (as gint_build_HR).
+ *   nR, R    host, nR >= 1 distinct lattice multiples as in gint_build_HR
+ *   DR_dev   device, nR*norb*norb doubles: block q is D(R_q), row-major, used
+ *            as given (blocks of unlisted R are zero)
+ *   rho_dev  device, N1*N2*N3 doubles, overwritten; each point written once
+ *            by one workgroup (fixed order, repeatable bits).
+ * FP64 plans evaluate orbitals and products in FP64, the other precisions in
+ * FP32 (FP32 matrix-core products); sums are FP64.  Errors as gint_build_HR.
+ * With D(R) = D for every R of gint_HR_lattice, rho is gint_build_rho's. */
+gint_status gint_build_rhoR(gint_plan plan, int nR, const int *R, const double *DR_dev, double *rho_dev);
+
 /* The lattice vectors R = T_b - T_a over every pair of atom images (a, b)
  * that reach a common mesh batch, for the current positions: every R with
  * a non-zero H(R) block is among them (a superset; |n_k| <= 31 only).

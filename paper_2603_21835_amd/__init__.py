@@ -31,7 +31,7 @@ EXPORTS = (
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force", "gint_H_rho_force",
-    "gint_build_HR", "gint_HR_lattice",
+    "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_sync.restype = st
     lib.gint_build_HR.argtypes = [P, P, ctypes.c_int, ip, P]
     lib.gint_build_HR.restype = ctypes.c_int
+    lib.gint_build_rhoR.argtypes = [P, ctypes.c_int, ip, P, P]
+    lib.gint_build_rhoR.restype = ctypes.c_int
     lib.gint_HR_lattice.argtypes = [P, ctypes.c_int, ip, ip]
     lib.gint_HR_lattice.restype = ctypes.c_int
     lib.gint_plan_sync.argtypes = [P]
@@ -344,6 +346,22 @@ class GintPlan:
         _check(self._lib.gint_build_HR(self._handle(), vp, nR,
                                        Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), op))
         return Rl, out
+
+    def build_rhoR(self, R, DR, out=None):
+        """rho (N1*N2*N3) from lattice-vector density-matrix blocks DR
+        (nR x norb x norb, device) for the lattice multiples R (nR x 3)."""
+        import numpy as np
+        import torch
+
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        nR = int(Rl.shape[0])
+        dp = _dev_ptr(DR, nR * self.norb * self.norb, "DR")
+        if out is None:
+            out = torch.empty(self.ngrid, dtype=torch.float64, device=DR.device)
+        op = _dev_ptr(out, self.ngrid, "rho")
+        _check(self._lib.gint_build_rhoR(self._handle(), nR, Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                         dp, op))
+        return out
 
     def build_rho(self, D, out=None):
         import torch

@@ -124,7 +124,8 @@ struct gint_plan_s {
     // the caller's R list as a box map (rebuilt when the lists or the list
     // change)
     DevBuf img_atom, wsh, rmap;
-    long long hr_gen = -1;
+    long long hr_gen = -1;     // list generation of img_atom / wsh / nbmax_img
+    long long hrfix_gen = -1;  // list generation of the sorted triples
     int nbmax_img = 0;
     std::vector<int> hr_key;
     // fixed-order H(R): per-image identity entries, per-batch block offsets
@@ -1076,13 +1077,11 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
 }  // extern "C"
 
 namespace {
-constexpr int kMaxHRExt = 31;  // |n_k| of the lattice vectors of gint_build_HR
+constexpr int kMaxHRExt = kHRBox;  // |n_k| of the lattice vectors of the H(R) / rho(R) calls
 
 // per-image atoms, wrap shifts and the most images in one batch, once per
-// list generation; and, when the block partials of the unfolded images fit
-// the partial-buffer budget, the sorted canonical triples of the fixed-order
-// reduction
-gint_status hr_prepare(gint_plan p)
+// list generation
+gint_status hr_images(gint_plan p)
 {
     if (p->hr_gen == p->gen)
         return GINT_OK;
@@ -1097,6 +1096,20 @@ gint_status hr_prepare(gint_plan p)
     int most = 0;
     STCHK(read_scalar(p, p->maxv.as<int>(), &most));
     p->nbmax_img = most;
+    p->hr_gen = p->gen;
+    return GINT_OK;
+}
+
+// when the block partials of the unfolded images fit the partial-buffer
+// budget, the sorted canonical triples of the fixed-order H(R) reduction,
+// once per list generation
+gint_status hr_prepare(gint_plan p)
+{
+    STCHK(hr_images(p));
+    if (p->hrfix_gen == p->gen)
+        return GINT_OK;
+    const hipStream_t st = p->stream;
+    const long long nb = p->geo.nbatch;
 
     // block offsets of the unfolded images
     STCHK(p->img_id.ensure(sizeof(int) * (size_t)(p->nimg + 1)));
@@ -1153,7 +1166,49 @@ gint_status hr_prepare(gint_plan p)
         p->ntri = ntri;
         STCHK(p->Hpart.ensure(blk_bytes * n));
     }
-    p->hr_gen = p->gen;
+    p->hrfix_gen = p->gen;
+    return GINT_OK;
+}
+
+// Validate a caller's list of lattice vectors and upload its box map (kept
+// while the list is unchanged); also checks that the unfolded images of a
+// batch fit the LDS of the per-batch kernels.
+gint_status hr_map(gint_plan p, int nR, const int *R, HRMap *m)
+{
+    int ext[3] = {0, 0, 0};
+    for (int q = 0; q < nR; ++q)
+        for (int k = 0; k < 3; ++k) {
+            if (R[3 * q + k] < -kMaxHRExt || R[3 * q + k] > kMaxHRExt)
+                return fail(GINT_EINVAL, "R[%d] has a component %d outside [-%d, %d]", q, R[3 * q + k], kMaxHRExt,
+                            kMaxHRExt);
+            ext[k] = std::max(ext[k], std::abs(R[3 * q + k]));
+        }
+    const size_t nbox = (size_t)(2 * ext[0] + 1) * (2 * ext[1] + 1) * (2 * ext[2] + 1);
+    std::vector<int> map(nbox, -1);
+    for (int q = 0; q < nR; ++q) {
+        const size_t i = ((size_t)(R[3 * q] + ext[0]) * (2 * ext[1] + 1) + R[3 * q + 1] + ext[1]) * (2 * ext[2] + 1) +
+                         R[3 * q + 2] + ext[2];
+        if (map[i] >= 0)
+            return fail(GINT_EINVAL, "R[%d] repeats R[%d]", q, map[i]);
+        map[i] = q;
+    }
+    HIPCHK(hipSetDevice(p->device));
+    STCHK(hr_images(p));
+    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
+    if (p->nbmax_img > kMaxBatchAtoms || esz * (size_t)p->nbmax_img * p->geo.P * kRow + 16384 > 163840)
+        return fail(GINT_EUNSUPPORTED, "%d atom images reach one %d-point batch; use a smaller batch", p->nbmax_img,
+                    p->geo.P);
+    std::vector<int> key(map);
+    key.insert(key.end(), ext, ext + 3);
+    if (key != p->hr_key) {
+        STCHK(p->rmap.ensure(sizeof(int) * nbox));
+        HIPCHK(hipMemcpyAsync(p->rmap.p, map.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));  // map (host) outlives the copy
+        p->hr_key.swap(key);
+    }
+    m->rmap = p->rmap.as<int>();
+    for (int k = 0; k < 3; ++k)
+        m->ext[k] = ext[k];
     return GINT_OK;
 }
 }  // namespace
@@ -1166,7 +1221,7 @@ gint_status gint_HR_lattice(gint_plan p, int cap, int *nR, int *R)
     if (!nR || cap < 0 || (cap > 0 && !R))
         return fail(GINT_EINVAL, "nR must be non-NULL, cap >= 0, and R non-NULL when cap > 0");
     HIPCHK(hipSetDevice(p->device));
-    STCHK(hr_prepare(p));
+    STCHK(hr_images(p));
     const int M = kMaxHRExt, w = 2 * M + 1;
     const size_t nbox = (size_t)w * w * w;
     STCHK(p->rmap.ensure(sizeof(int) * nbox));
@@ -1195,48 +1250,15 @@ gint_status gint_HR_lattice(gint_plan p, int cap, int *nR, int *R)
 
 gint_status gint_build_HR(gint_plan p, const double *V_dev, int nR, const int *R, double *HR_dev)
 {
-    constexpr int kMaxExt = kMaxHRExt;
     STCHK(check_plan(p));
     if (!V_dev || !HR_dev || !R)
         return fail(GINT_EINVAL, "V and HR must be non-NULL device pointers and R a non-NULL host array");
     if (nR < 1)
         return fail(GINT_EINVAL, "nR = %d must be >= 1", nR);
-    int ext[3] = {0, 0, 0};
-    for (int q = 0; q < nR; ++q)
-        for (int k = 0; k < 3; ++k) {
-            if (R[3 * q + k] < -kMaxExt || R[3 * q + k] > kMaxExt)
-                return fail(GINT_EINVAL, "R[%d] has a component %d outside [-%d, %d]", q, R[3 * q + k], kMaxExt,
-                            kMaxExt);
-            ext[k] = std::max(ext[k], std::abs(R[3 * q + k]));
-        }
-    const size_t nbox = (size_t)(2 * ext[0] + 1) * (2 * ext[1] + 1) * (2 * ext[2] + 1);
-    std::vector<int> map(nbox, -1);
-    for (int q = 0; q < nR; ++q) {
-        const size_t i = ((size_t)(R[3 * q] + ext[0]) * (2 * ext[1] + 1) + R[3 * q + 1] + ext[1]) * (2 * ext[2] + 1) +
-                         R[3 * q + 2] + ext[2];
-        if (map[i] >= 0)
-            return fail(GINT_EINVAL, "R[%d] repeats R[%d]", q, map[i]);
-        map[i] = q;
-    }
-    HIPCHK(hipSetDevice(p->device));
-    const hipStream_t st = p->stream;
-    STCHK(hr_prepare(p));
-    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
-    if (p->nbmax_img > kMaxBatchAtoms || esz * (size_t)p->nbmax_img * p->geo.P * kRow + 16384 > 163840)
-        return fail(GINT_EUNSUPPORTED, "%d atom images reach one %d-point batch; use a smaller batch", p->nbmax_img,
-                    p->geo.P);
-    std::vector<int> key(map);
-    key.insert(key.end(), ext, ext + 3);
-    if (key != p->hr_key) {
-        STCHK(p->rmap.ensure(sizeof(int) * nbox));
-        HIPCHK(hipMemcpyAsync(p->rmap.p, map.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));  // map (host) outlives the copy
-        p->hr_key.swap(key);
-    }
     HRMap m;
-    m.rmap = p->rmap.as<int>();
-    for (int k = 0; k < 3; ++k)
-        m.ext[k] = ext[k];
+    STCHK(hr_map(p, nR, R, &m));
+    STCHK(hr_prepare(p));
+    const hipStream_t st = p->stream;
     STCHK(timed(p, GINT_K_H_FILL,
                 [&] { return launch_fill_f64(st, HR_dev, (long long)nR * p->norb * p->norb, 0.0); }));
     const Basis B = p->basis();
@@ -1260,6 +1282,23 @@ gint_status gint_build_HR(gint_plan p, const double *V_dev, int nR, const int *R
     STCHK(timed(p, GINT_K_HR, [&] {
         return launch_HR_batch(st, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(), p->img_atom.as<int>(),
                                p->img.as<int>(), B, p->wsh.as<int>(), V_dev, p->dV, m, p->norb, HR_dev);
+    }));
+    return GINT_OK;
+}
+
+gint_status gint_build_rhoR(gint_plan p, int nR, const int *R, const double *DR_dev, double *rho_dev)
+{
+    STCHK(check_plan(p));
+    if (!DR_dev || !rho_dev || !R)
+        return fail(GINT_EINVAL, "DR and rho must be non-NULL device pointers and R a non-NULL host array");
+    if (nR < 1)
+        return fail(GINT_EINVAL, "nR = %d must be >= 1", nR);
+    HRMap m;
+    STCHK(hr_map(p, nR, R, &m));
+    const Basis B = p->basis();
+    STCHK(timed(p, GINT_K_RHO, [&] {
+        return launch_rhoR_batch(p->stream, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(), p->img_atom.as<int>(),
+                                 p->img.as<int>(), B, p->wsh.as<int>(), m, p->norb, DR_dev, rho_dev);
     }));
     return GINT_OK;
 }
@@ -1302,7 +1341,7 @@ gint_status gint_plan_work(gint_plan p, gint_work *out)
     out->nblock = p->nblock;
     out->mno = p->mno;
     out->partial_bytes = p->f32() ? 4 : 8;
-    out->nblock_hr = p->hr_gen == p->gen ? p->nblock_u : -1;
+    out->nblock_hr = p->hrfix_gen == p->gen ? p->nblock_u : -1;
     return GINT_OK;
 }
 

@@ -338,6 +338,186 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_HR_batch(Geo g, const int *__
     }
 }
 
+// rho from lattice-vector density-matrix blocks (Sec. 3.3.1, rho(r_g)
+// equation with its sums over R and R'): with the images of the batch
+// unfolded as above,
+//     rho_p = sum_{a <= c} phi_a(p)^T S_ac phi_c(p),
+//     S_ac = D_{I_a I_c}(T_c - T_a) + D_{I_c I_a}(T_a - T_c)^T  (a < c),
+//     S_aa = D_{I_a I_a}(0),
+// D blocks of unlisted R being zero.  Per block, T = S_ac phi_c on the
+// matrix cores (16 points per product), dotted with phi_a in the result
+// registers; lanes and waves are summed in a fixed order.  Each point is
+// written once.
+template <typename T, int P>
+__global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *__restrict__ iptr,
+                                                     const int *__restrict__ img_atom, const int *__restrict__ img,
+                                                     Basis bs, const int *__restrict__ wsh, HRMap m, int norb,
+                                                     const double *__restrict__ DR, double *__restrict__ rho)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
+    __shared__ DevRadial s_rad[kMaxRadTotal];
+    __shared__ DevSpecies s_sp[kMaxSpecies];
+    __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms], s_mu0[kMaxBatchAtoms];
+    __shared__ int s_T[kMaxBatchAtoms][3];
+    __shared__ double s_part[kHRWaves][kMaxP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+              nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
+    if (b < 0)
+        return;
+    const int i0 = iptr[b], nb = iptr[b + 1] - i0;
+    int ib[3];
+    batch_coords(g, b, ib);
+
+    for (int k = tid; k < g.nrad; k += blockDim.x)
+        s_rad[k] = bs.rad[k];
+    for (int k = tid; k < g.nspecies; k += blockDim.x)
+        s_sp[k] = bs.sp[k];
+    for (int a = tid; a < nb; a += blockDim.x) {
+        const int atom = img_atom[i0 + a];
+        s_atom[a] = atom;
+        s_nor[a] = bs.sp[bs.spc[atom]].norb;
+        s_mu0[a] = bs.orb0[bs.perm[atom]];
+        int n[3];
+        unpack_image(img[i0 + a], n);
+        for (int k = 0; k < 3; ++k)
+            s_T[a][k] = n[k] - wsh[3 * atom + k];
+    }
+    __syncthreads();
+
+    for (int idx = tid; idx < nb * P; idx += blockDim.x) {
+        const int a = idx / P, p = idx % P;
+        const int atom = s_atom[a];
+        T *row = s_phi + (size_t)(a * P + p) * kRow;
+        const int swz = p & 15;
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[o ^ swz] = (T)0;
+        if (valid) {
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            double r[3];
+            mesh_cart(g, n, r);
+            eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, 1, img[i0 + a], i0 + a, img, r,
+                             row, swz);
+        }
+    }
+    __syncthreads();
+
+    constexpr int NT = P / 16;  // 16-point tiles
+    double racc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        racc[t] = 0.0;
+    const int nblk = nb * (nb + 1) / 2;
+    const int k0 = wave * nblk / nw, k1 = (wave + 1) * nblk / nw;
+    int ia = 0, ja = 0;
+    {
+        int k = k0;
+        while (ia < nb && k >= nb - ia) {
+            k -= nb - ia;
+            ++ia;
+        }
+        ja = ia + k;
+    }
+    const size_t nn = (size_t)norb * norb;
+    for (int k = k0; k < k1; ++k) {
+        const int Rx = s_T[ja][0] - s_T[ia][0], Ry = s_T[ja][1] - s_T[ia][1], Rz = s_T[ja][2] - s_T[ia][2];
+        const int qp = hr_lookup(m, Rx, Ry, Rz);
+        const int qn = ia != ja ? hr_lookup(m, -Rx, -Ry, -Rz) : -1;
+        if (qp >= 0 || qn >= 0) {
+            const int nI = s_nor[ia], nJ = s_nor[ja], mI = s_mu0[ia], mJ = s_mu0[ja];
+            // A operand: S[i = li][k = lk + 4 s]
+            T aS[4];
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int kc = lk + 4 * st;
+                double x = 0.0;
+                if (li < nI && kc < nJ) {
+                    if (qp >= 0)
+                        x += DR[qp * nn + (size_t)(mI + li) * norb + mJ + kc];
+                    if (qn >= 0)
+                        x += DR[qn * nn + (size_t)(mJ + kc) * norb + mI + li];
+                }
+                aS[st] = (T)x;
+            }
+            const T *pA = s_phi + (size_t)(ia * P) * kRow;
+            const T *pC = s_phi + (size_t)(ja * P) * kRow;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int p = 16 * t + li;  // this lane's point (B and result column)
+                typename MM<T>::acc acc = MM<T>::zero();
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    acc = MM<T>::mma(aS[st], pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc);
+                double d = 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = MM<T>::row(lk, v);
+                    d += (double)pA[p * kRow + (i ^ (p & 15))] * (double)acc[v];
+                }
+                racc[t] += d;
+            }
+        }
+        if (++ja == nb) {
+            ++ia;
+            ja = ia;
+        }
+    }
+    // lanes li, li + 16, li + 32, li + 48 hold the same point
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double x = racc[t];
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 32);
+        if (lk == 0)
+            s_part[wave][16 * t + li] = x;
+    }
+    __syncthreads();
+    for (int p = tid; p < P; p += blockDim.x) {
+        int n[3];
+        if (!batch_point(g, ib, p, n))
+            continue;
+        double x = 0.0;
+        for (int w = 0; w < nw; ++w)
+            x += s_part[w][p];
+        rho[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] = x;
+    }
+}
+
+template <typename T, int P>
+static hipError_t launch_rhoR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                                const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
+                                const double *DR, double *rho)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow;
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_rhoR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_rhoR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
+                       dim3(64 * kHRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                             const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
+                             const double *DR, double *rho)
+{
+    if (g.P == 32)
+        return f32 ? launch_rhoR_p<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho)
+                   : launch_rhoR_p<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho);
+    if (g.P == 16)
+        return f32 ? launch_rhoR_p<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho)
+                   : launch_rhoR_p<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho);
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int P>
 static hipError_t launch_HR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                               const int *img, const Basis &b, const int *wsh, const double *W, double wscale,

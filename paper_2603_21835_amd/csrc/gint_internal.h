@@ -155,6 +155,9 @@ hipError_t sort_HR_keys(hipStream_t s, void *tmp, size_t &tmp_bytes, const unsig
 hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const unsigned long long *tkey, const int *tstart,
                             const int *list, int natom, const HRMap &m, const Basis &b, int mno, int norb,
                             const void *part, double *HR);
+hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                             const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
+                             const double *DR, double *rho);
 hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const int *img_atom, const int *img,
                           const int *wsh, int M, int *mark);
 hipError_t launch_HR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,

@@ -189,3 +189,111 @@ def test_hr_atomic_fallback(oracle_mod, torch_dev):
     e = _rel_max(HR.cpu().numpy(), HRo)
     _say(f"  atomic fallback: {len(R)} R, rel {e:.2e}")
     assert e <= TOL
+
+
+# ---- rho from lattice-vector density matrices D(R) (gint_build_rhoR) ----
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _random_DR(n, norb, seed):
+    return np.random.default_rng(seed).normal(size=(n, norb, norb)) / norb
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _triclinic_two_species, _long_range_tiny, _ragged_five_atoms,
+                                  _vacuum_single_atom])
+def test_rhoR_full(oracle_mod, torch_dev, make):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = make()
+    _say(f"case rhoR {w.name} grid {w.grid} natom {w.natom}")
+    plan = g.GintPlan.from_workload(w)
+    R = plan.HR_lattice()
+    DR = _random_DR(len(R), plan.norb, 3)
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    ref = oracle_mod.Oracle.from_workload(w).rhoR(R, DR)
+    e = _rel_l2(rho, ref)
+    _say(f"  {len(R)} R: rel-L2 {e:.2e}")
+    assert e <= TOL
+    # repeatable bits
+    rho2 = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    assert np.array_equal(rho, rho2)
+
+
+def test_rhoR_constant_is_gamma(torch_dev):
+    # D(R) = D for every R of the lattice list: the Gamma-point rho of D
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _triclinic_two_species()
+    plan = g.GintPlan.from_workload(w)
+    R = plan.HR_lattice()
+    DR = np.broadcast_to(w.D, (len(R),) + w.D.shape).copy()
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    ref = plan.build_rho(_dev(torch, dev, w.D)).cpu().numpy()
+    assert _rel_l2(rho, ref) <= 1e-12
+
+
+def test_rhoR_energy_identity(torch_dev):
+    # dV sum_g V_g rho_g(D(R)) = sum_R <D(R), H(R)>, both sides on the GPU
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _ragged_five_atoms()
+    plan = g.GintPlan.from_workload(w)
+    V = _dev(torch, dev, w.V)
+    R, HR = plan.build_HR(V)
+    DR = _random_DR(len(R), plan.norb, 5)
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    E1 = plan.dV * float(np.dot(w.V, rho))
+    prod = DR * HR.cpu().numpy()
+    assert abs(E1 - prod.sum()) <= 1e-11 * np.abs(prod).sum()
+
+
+def test_rhoR_positions_outside_cell(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _triclinic_two_species()
+    pos = np.asarray(w.positions) + np.array([[2, 0, -1], [0, 1, 0], [-1, -1, 3]]) @ np.asarray(w.lattice)
+    plan = g.GintPlan.from_workload(w)
+    plan.set_positions(pos)
+    R = plan.HR_lattice()
+    DR = _random_DR(len(R), plan.norb, 6)
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    o = oracle_mod.Oracle.from_workload(w)
+    o.set_positions(pos)
+    e = _rel_l2(rho, o.rhoR(R, DR))
+    _say(f"  shifted positions rhoR: rel-L2 {e:.2e}")
+    assert e <= TOL
+
+
+def test_rhoR_fp32(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si8_sz()
+    plan = g.GintPlan.from_workload(w, "fp32")
+    R = plan.HR_lattice()
+    DR = _random_DR(len(R), plan.norb, 7)
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    e = _rel_l2(rho, oracle_mod.Oracle.from_workload(w).rhoR(R, DR))
+    _say(f"  fp32 si8 rhoR: rel-L2 {e:.2e}")
+    assert e <= 1e-5
+
+
+def test_rhoR_si64_sampled(oracle_mod, torch_dev):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si64_dzp()
+    plan = g.GintPlan.from_workload(w)
+    R = plan.HR_lattice()
+    DR = _random_DR(len(R), plan.norb, 8)
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    idx = np.random.default_rng(9).choice(w.ngrid, 4000, replace=False)
+    e = _rel_l2(rho[idx], oracle_mod.Oracle.from_workload(w).rhoR(R, DR, idx))
+    _say(f"  si64 rhoR sampled: rel-L2 {e:.2e}")
+    assert e <= TOL
