@@ -94,6 +94,20 @@ def ylm(l: int, u) -> np.ndarray:
     return out
 
 
+def Hk_from_HR(R, HR, kfrac) -> np.ndarray:
+    """Bloch sum of Sec. 2.1's H(k) equation: H(k) = sum_R e^{i k.R} H(R),
+    k.R = 2 pi kappa . n for fractional reciprocal coordinates kappa and
+    lattice multiples n.  Returns complex [nk][norb][norb]."""
+    R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+    kf = np.asarray(kfrac, dtype=np.float64).reshape(-1, 3)
+    HR = np.asarray(HR, dtype=np.float64)
+    out = np.zeros((kf.shape[0],) + HR.shape[1:], dtype=np.complex128)
+    for i, k in enumerate(kf):
+        for q in range(R.shape[0]):
+            out[i] += np.exp(2j * np.pi * float(k @ R[q])) * HR[q]
+    return out
+
+
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
 

@@ -162,3 +162,37 @@ def test_rhoR_energy_identity(oracle_mod, make):
     E1 = o.dV * float(np.dot(w.V, o.rhoR(R, DR)))
     E2 = float(np.sum(DR * o.HR(w.V, R)))
     assert abs(E1 - E2) <= 1e-12 * max(1.0, np.sum(np.abs(DR * o.HR(w.V, R))))
+
+
+def test_hk_pins(oracle_mod):
+    # H(k) of Sec. 2.1 from the oracle's H(R): k = 0 is the Gamma-point H,
+    # H(k + G) = H(k), H(k) Hermitian, and the 3x1x1 supercell's Gamma-point
+    # blocks are (1/3) sum_m e^{-i 2 pi m c / 3} H(k_m), k_m = (m/3, 0, 0)
+    w = _two_atom_dzp()
+    o = oracle_mod.Oracle.from_workload(w)
+    R = _box(4)
+    HR = o.HR(w.V, R)
+    H = o.H(w.V)
+    ks = np.array([[0.0, 0.0, 0.0], [0.25, -0.1, 0.4], [1.25, 0.9, -0.6], [1 / 3, 0, 0], [2 / 3, 0, 0]])
+    Hk = oracle_mod.Hk_from_HR(R, HR, ks)
+    scale = np.abs(H).max()
+    assert np.abs(Hk[0] - H).max() <= 1e-13 * scale
+    assert np.abs(Hk[1] - Hk[2]).max() <= 1e-12 * scale
+    for h in Hk:
+        assert np.abs(h - h.conj().T).max() <= 1e-13 * scale
+    lat = np.asarray(w.lattice, dtype=np.float64)
+    N = w.grid
+    pos_sc = np.concatenate([np.asarray(w.positions) + c * lat[0] for c in range(3)])
+    lat_sc = lat.copy()
+    lat_sc[0] *= 3
+    V_sc = np.concatenate([np.asarray(w.V).reshape(N)] * 3, axis=0).reshape(-1)
+    o_sc = oracle_mod.Oracle(lat_sc, (3 * N[0], N[1], N[2]), w.species,
+                             np.concatenate([w.species_of_atom] * 3), pos_sc)
+    H_sc = o_sc.H(V_sc)
+    nb = o.norb
+    km = [Hk[0], Hk[3], Hk[4]]
+    for c in range(3):
+        want = sum(np.exp(-2j * np.pi * m * c / 3) * km[m] for m in range(3)) / 3
+        got = H_sc[0:nb, c * nb:(c + 1) * nb]
+        assert np.abs(want.imag).max() <= 1e-12 * scale
+        assert np.abs(got - want.real).max() <= 1e-12 * scale
