@@ -232,6 +232,21 @@ gint_status gint_build_HR(gint_plan plan, const double *V_dev, int nR, const int
  * With D(R) = D for every R of gint_HR_lattice, rho is gint_build_rho's. */
 gint_status gint_build_rhoR(gint_plan plan, int nR, const int *R, const double *DR_dev, double *rho_dev);
 
+/* Bloch sum of lattice-vector blocks (Sec. 2.1, H(k) equation):
+ *   H(k) = sum_q e^{i k.R_q} H(R_q),  k.R_q = 2 pi (kappa . n_q),
+ * kappa the fractional coordinates of k in the reciprocal basis (b_i with
+ * a_i . b_j = delta_ij).  Works for any blocks of this plan's size (H(R) of
+ * gint_build_HR, or S(R), ...).
+ *   nR, R     host, the lattice multiples of the blocks (3*nR ints)
+ *   HR_dev    device, nR*norb*norb doubles
+ *   nk, kfrac host, 3*nk doubles
+ *   Hk_dev    device, nk*norb*norb complex values as (re, im) double pairs,
+ *             row-major per k; overwritten
+ * Phases are formed in FP64 on the host; sums are FP64.  Synchronises the
+ * stream once. */
+gint_status gint_HR_to_Hk(gint_plan plan, int nR, const int *R, const double *HR_dev, int nk, const double *kfrac,
+                          double *Hk_dev);
+
 /* The lattice vectors R = T_b - T_a over every pair of atom images (a, b)
  * that reach a common mesh batch, for the current positions: every R with
  * a non-zero H(R) block is among them (a superset; |n_k| <= 31 only).

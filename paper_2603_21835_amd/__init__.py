@@ -31,7 +31,7 @@ EXPORTS = (
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force", "gint_H_rho_force",
-    "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR",
+    "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_sync.restype = st
     lib.gint_build_HR.argtypes = [P, P, ctypes.c_int, ip, P]
     lib.gint_build_HR.restype = ctypes.c_int
+    lib.gint_HR_to_Hk.argtypes = [P, ctypes.c_int, ip, P, ctypes.c_int, dp, P]
+    lib.gint_HR_to_Hk.restype = ctypes.c_int
     lib.gint_build_rhoR.argtypes = [P, ctypes.c_int, ip, P, P]
     lib.gint_build_rhoR.restype = ctypes.c_int
     lib.gint_HR_lattice.argtypes = [P, ctypes.c_int, ip, ip]
@@ -346,6 +348,25 @@ class GintPlan:
         _check(self._lib.gint_build_HR(self._handle(), vp, nR,
                                        Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), op))
         return Rl, out
+
+    def HR_to_Hk(self, R, HR, kfrac, out=None):
+        """H(k) = sum_q e^{i 2 pi kappa.n_q} H(R_q) for fractional k-points
+        kfrac (nk x 3): a complex128 tensor (nk x norb x norb)."""
+        import numpy as np
+        import torch
+
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        kf = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, 3))
+        nR, nk = int(Rl.shape[0]), int(kf.shape[0])
+        hp = _dev_ptr(HR, nR * self.norb * self.norb, "HR")
+        if out is None:
+            out = torch.empty((nk, self.norb, self.norb), dtype=torch.complex128, device=HR.device)
+        if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() != nk * self.norb * self.norb:
+            raise TypeError("out must be a contiguous complex128 tensor of nk*norb*norb elements")
+        _check(self._lib.gint_HR_to_Hk(self._handle(), nR, Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), hp, nk,
+                                       kf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def build_rhoR(self, R, DR, out=None):
         """rho (N1*N2*N3) from lattice-vector density-matrix blocks DR

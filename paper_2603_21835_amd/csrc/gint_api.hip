@@ -130,6 +130,7 @@ struct gint_plan_s {
     std::vector<int> hr_key;
     // fixed-order H(R): per-image identity entries, per-batch block offsets
     // of the unfolded images, sorted triple keys and their runs
+    DevBuf hk_phase;  // (cos, sin) phases of gint_HR_to_Hk
     DevBuf img_id, cnt_u, boff_u, hkey, hkey2, hcode, hcode2, hflag, hfscan, tstart, tkey, sort_tmp, hbad;
     long long nblock_u = 0;
     int ntri = 0;
@@ -1300,6 +1301,40 @@ gint_status gint_build_rhoR(gint_plan p, int nR, const int *R, const double *DR_
         return launch_rhoR_batch(p->stream, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(), p->img_atom.as<int>(),
                                  p->img.as<int>(), B, p->wsh.as<int>(), m, p->norb, DR_dev, rho_dev);
     }));
+    return GINT_OK;
+}
+
+gint_status gint_HR_to_Hk(gint_plan p, int nR, const int *R, const double *HR_dev, int nk, const double *kfrac,
+                          double *Hk_dev)
+{
+    STCHK(check_plan(p));
+    if (!R || !kfrac || !HR_dev || !Hk_dev)
+        return fail(GINT_EINVAL, "R and kfrac must be non-NULL host arrays, HR and Hk non-NULL device pointers");
+    if (nR < 1 || nk < 1)
+        return fail(GINT_EINVAL, "nR = %d and nk = %d must be >= 1", nR, nk);
+    for (int i = 0; i < 3 * nk; ++i)
+        if (!std::isfinite(kfrac[i]))
+            return fail(GINT_EINVAL, "kfrac has non-finite entries");
+    HIPCHK(hipSetDevice(p->device));
+    // phases in FP64 on the host: 2 pi kappa . n reduced to [0, 1) turns first
+    std::vector<double> ph((size_t)2 * nk * nR);
+    for (int k = 0; k < nk; ++k)
+        for (int q = 0; q < nR; ++q) {
+            double t = 0.0;
+            for (int d = 0; d < 3; ++d)
+                t += kfrac[3 * k + d] * (double)R[3 * q + d];
+            t -= std::floor(t);
+            const double a = 2.0 * M_PI * t;
+            ph[2 * ((size_t)k * nR + q)] = std::cos(a);
+            ph[2 * ((size_t)k * nR + q) + 1] = std::sin(a);
+        }
+    STCHK(p->hk_phase.ensure(sizeof(double) * ph.size()));
+    HIPCHK(hipMemcpyAsync(p->hk_phase.p, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice, p->stream));
+    const long long nel = (long long)p->norb * p->norb;
+    STCHK(timed(p, GINT_K_HR, [&] {
+        return launch_Hk(p->stream, nel, nR, nk, p->hk_phase.as<double>(), HR_dev, Hk_dev);
+    }));
+    HIPCHK(hipStreamSynchronize(p->stream));  // ph (host) outlives the copy
     return GINT_OK;
 }
 

@@ -518,6 +518,52 @@ hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, c
     return hipErrorInvalidValue;
 }
 
+// H(k) = sum_q e^{i 2 pi kappa . n_q} H(R_q) (Sec. 2.1, H(k) equation), with
+// kappa the fractional reciprocal coordinates of k and n_q the lattice
+// multiples of R_q; ph holds (cos, sin) of the phase for every (k, q).  One
+// thread per matrix element reads each H(R) value once per chunk of kHkChunk
+// k-points; Hk is [nk][norb*norb] of (re, im) pairs.
+constexpr int kHkChunk = 8;
+
+__global__ __launch_bounds__(256) void k_Hk(long long nel, int nR, int nk, const double *__restrict__ ph,
+                                            const double *__restrict__ HR, double *__restrict__ Hk)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nel)
+        return;
+    for (int k0 = 0; k0 < nk; k0 += kHkChunk) {
+        double re[kHkChunk], im[kHkChunk];
+#pragma unroll
+        for (int j = 0; j < kHkChunk; ++j)
+            re[j] = im[j] = 0.0;
+        for (int q = 0; q < nR; ++q) {
+            const double h = HR[(size_t)q * nel + e];
+#pragma unroll
+            for (int j = 0; j < kHkChunk; ++j) {
+                if (k0 + j < nk) {
+                    const double *c = ph + 2 * ((size_t)(k0 + j) * nR + q);
+                    re[j] = fma(c[0], h, re[j]);
+                    im[j] = fma(c[1], h, im[j]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kHkChunk; ++j)
+            if (k0 + j < nk) {
+                double2 *o = reinterpret_cast<double2 *>(Hk) + (size_t)(k0 + j) * nel + e;
+                *o = double2{re[j], im[j]};
+            }
+    }
+}
+
+hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double *ph, const double *HR, double *Hk)
+{
+    if (nel <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_Hk, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s, nel, nR, nk, ph, HR, Hk);
+    return hipGetLastError();
+}
+
 template <typename T, int P>
 static hipError_t launch_HR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                               const int *img, const Basis &b, const int *wsh, const double *W, double wscale,

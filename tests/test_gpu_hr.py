@@ -297,3 +297,24 @@ def test_rhoR_si64_sampled(oracle_mod, torch_dev):
     e = _rel_l2(rho[idx], oracle_mod.Oracle.from_workload(w).rhoR(R, DR, idx))
     _say(f"  si64 rhoR sampled: rel-L2 {e:.2e}")
     assert e <= TOL
+
+
+def test_hk_bloch_sum(oracle_mod, torch_dev):
+    # H(k) from the GPU's H(R) against the oracle's Bloch sum of the oracle's
+    # H(R); 11 k-points (more than one chunk of 8, ragged)
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _triclinic_two_species()
+    plan = g.GintPlan.from_workload(w)
+    V = _dev(torch, dev, w.V)
+    R, HR = plan.build_HR(V)
+    ks = np.random.default_rng(13).uniform(-1, 1, (11, 3))
+    ks[0] = 0.0
+    Hk = plan.HR_to_Hk(R, HR, ks).cpu().numpy()
+    o = oracle_mod.Oracle.from_workload(w)
+    ref = oracle_mod.Hk_from_HR(R, o.HR(w.V, R), ks)
+    e = float(np.abs(Hk - ref).max() / np.abs(ref).max())
+    _say(f"  H(k) at 11 k: rel {e:.2e}")
+    assert e <= TOL
+    assert _rel_max(Hk[0].real, plan.build_H(V).cpu().numpy()) <= 1e-12
