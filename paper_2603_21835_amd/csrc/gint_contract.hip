@@ -168,7 +168,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
         for (int v = 0; v < 4; ++v) {
             const int row = MM<T>::row(lk, v);
             if (row < nI && li < nJ)
-                o[row * mno + li] = acc[v];
+                __builtin_nontemporal_store(acc[v], o + row * mno + li);  // read once, by the reduction
         }
         if (++ja == nb) {
             ++ia;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * lk + v;
             if (row < nI && li < nJ)
-                o[row * mno + li] = acc[v] * kUnscale;
+                __builtin_nontemporal_store(acc[v] * kUnscale, o + row * mno + li);
         }
         tri_advance(ia, ja, nw, nb);
     }
@@ -431,19 +431,32 @@ constexpr int kRedGroup = 16;  // list entries whose loads are in flight togethe
 
 template <typename T>
 struct Vec16;
+// (partials are read once: loads marked non-temporal)
 template <>
 struct Vec16<double> {
     typedef double2 type;
+    typedef double nt_type __attribute__((ext_vector_type(2)));
     static constexpr int V = 2;
     static __device__ __forceinline__ double at(const double2 &x, int i) { return i ? x.y : x.x; }
+    static __device__ __forceinline__ double2 load(const double *p)
+    {
+        const nt_type x = __builtin_nontemporal_load(reinterpret_cast<const nt_type *>(p));
+        return double2{x[0], x[1]};
+    }
 };
 template <>
 struct Vec16<float> {
     typedef float4 type;
+    typedef float nt_type __attribute__((ext_vector_type(4)));
     static constexpr int V = 4;
     static __device__ __forceinline__ double at(const float4 &x, int i)
     {
         return (double)(i == 0 ? x.x : (i == 1 ? x.y : (i == 2 ? x.z : x.w)));
+    }
+    static __device__ __forceinline__ float4 load(const float *p)
+    {
+        const nt_type x = __builtin_nontemporal_load(reinterpret_cast<const nt_type *>(p));
+        return float4{x[0], x[1], x[2], x[3]};
     }
 };
 
@@ -491,7 +504,7 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__re
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int e = V * lane + 64 * V * m;
-                v[g][m] = (ok && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
+                v[g][m] = (ok && e < pitch) ? Vec16<T>::load(blk + e) : VT{};
             }
         }
 #pragma unroll
@@ -608,7 +621,7 @@ __global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const int e = V * lane + 64 * V * m;
-                    v[g][m] = (ok && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
+                    v[g][m] = (ok && e < pitch) ? Vec16<T>::load(blk + e) : VT{};
                 }
             }
 #pragma unroll
@@ -1285,7 +1298,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             for (int v = 0; v < 4; ++v) {
                 const int row = 4 * lk + v;
                 if (row < nI && li < nJ)
-                    o[row * mno + li] = acc[v] * kUnscale;
+                    __builtin_nontemporal_store(acc[v] * kUnscale, o + row * mno + li);
             }
             if (++ja == nb) {
                 ++ia;
@@ -1354,7 +1367,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (rkey[v] >= 0 && ckey >= 0 && rkey[v] <= ckey)
-                    pb[rb[v] + cb] = hc[v];
+                    __builtin_nontemporal_store(hc[v], pb + rb[v] + cb);
             if (++tj == ntile) {
                 ++ti;
                 tj = ti;
