@@ -210,9 +210,13 @@ gint_status gint_H_rho_force(gint_plan plan, const double *V_dev, const double *
  *   HR_dev  device, nR*norb*norb doubles: block q (row-major norb x norb)
  *           is H(R_q); overwritten.  Contributions to R not in the list
  *           are dropped; gint_HR_lattice lists the R that can have any.
- * Blocks are accumulated with FP64 atomics, so the last bits can differ
- * between calls.  FP64 plans evaluate orbitals in FP64, the other
- * precisions in FP32 (FP32 matrix-core products); sums are FP64.
+ * The blocks of each (I, J, R) are summed in a fixed order (repeatable
+ * bits) when the block partials of the unfolded atom images fit the
+ * partial-buffer budget (gint_plan_tune); otherwise they are added into
+ * HR_dev with FP64 atomics (the last bits can then differ between calls).
+ * The matrix-core products follow the plan's precision as in gint_build_H
+ * (the atomic fallback uses FP32 tiles for every non-FP64 precision); sums
+ * across batches are FP64.
  * GINT_EINVAL for bad arguments (outputs untouched); GINT_EUNSUPPORTED if
  * too many atom images reach one mesh batch. */
 gint_status gint_build_HR(gint_plan plan, const double *V_dev, int nR, const int *R, double *HR_dev);

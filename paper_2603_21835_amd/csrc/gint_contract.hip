@@ -29,6 +29,18 @@ namespace gint {
 // workgroups for n batches dispatched XCD-contiguously (xcd_batch)
 static unsigned xcd_grid(int n) { return (unsigned)(kXcd * ((n + kXcd - 1) / kXcd)); }
 
+// One element of an H block partial.  FP64 partials are streamed out with
+// non-temporal stores (each is read once, by the reduction, which measured
+// faster that way); FP32 partials use ordinary stores.
+template <typename T>
+__device__ __forceinline__ void store_partial(T *p, T x)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_nontemporal_store(x, p);
+    else
+        *p = x;
+}
+
 // Advance (ia, ja) by st places in the row-major order of the pairs
 // ia <= ja < nb (row ia holds ja = ia .. nb-1).
 __device__ __forceinline__ void tri_advance(int &ia, int &ja, int st, int nb)
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch(Geo g, Bins bn, Basis 
         for (int v = 0; v < 4; ++v) {
             const int row = MM<T>::row(lk, v);
             if (row < nI && li < nJ)
-                __builtin_nontemporal_store(acc[v], o + row * mno + li);  // read once, by the reduction
+                store_partial(o + row * mno + li, acc[v]);
         }
         if (++ja == nb) {
             ++ia;
@@ -356,7 +368,7 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * lk + v;
             if (row < nI && li < nJ)
-                __builtin_nontemporal_store(acc[v] * kUnscale, o + row * mno + li);
+                o[row * mno + li] = acc[v] * kUnscale;
         }
         tri_advance(ia, ja, nw, nb);
     }
@@ -431,7 +443,9 @@ constexpr int kRedGroup = 16;  // list entries whose loads are in flight togethe
 
 template <typename T>
 struct Vec16;
-// (partials are read once: loads marked non-temporal)
+// FP64 partials are read once: their loads are marked non-temporal (and
+// their stores too, see store_partial).  FP32 partials keep ordinary loads
+// and stores, which measured faster for them.
 template <>
 struct Vec16<double> {
     typedef double2 type;
@@ -447,16 +461,10 @@ struct Vec16<double> {
 template <>
 struct Vec16<float> {
     typedef float4 type;
-    typedef float nt_type __attribute__((ext_vector_type(4)));
     static constexpr int V = 4;
     static __device__ __forceinline__ double at(const float4 &x, int i)
     {
         return (double)(i == 0 ? x.x : (i == 1 ? x.y : (i == 2 ? x.z : x.w)));
-    }
-    static __device__ __forceinline__ float4 load(const float *p)
-    {
-        const nt_type x = __builtin_nontemporal_load(reinterpret_cast<const nt_type *>(p));
-        return float4{x[0], x[1], x[2], x[3]};
     }
 };
 
@@ -504,7 +512,10 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__re
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int e = V * lane + 64 * V * m;
-                v[g][m] = (ok && e < pitch) ? Vec16<T>::load(blk + e) : VT{};
+                if constexpr (sizeof(T) == 8)
+                    v[g][m] = (ok && e < pitch) ? Vec16<T>::load(blk + e) : VT{};
+                else
+                    v[g][m] = (ok && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
             }
         }
 #pragma unroll
@@ -621,7 +632,10 @@ __global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const int e = V * lane + 64 * V * m;
-                    v[g][m] = (ok && e < pitch) ? Vec16<T>::load(blk + e) : VT{};
+                    if constexpr (sizeof(T) == 8)
+                        v[g][m] = (ok && e < pitch) ? Vec16<T>::load(blk + e) : VT{};
+                    else
+                        v[g][m] = (ok && e < pitch) ? *reinterpret_cast<const VT *>(blk + e) : VT{};
                 }
             }
 #pragma unroll
@@ -1298,7 +1312,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             for (int v = 0; v < 4; ++v) {
                 const int row = 4 * lk + v;
                 if (row < nI && li < nJ)
-                    __builtin_nontemporal_store(acc[v] * kUnscale, o + row * mno + li);
+                    o[row * mno + li] = acc[v] * kUnscale;
             }
             if (++ja == nb) {
                 ++ia;
@@ -1367,7 +1381,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (rkey[v] >= 0 && ckey >= 0 && rkey[v] <= ckey)
-                    __builtin_nontemporal_store(hc[v], pb + rb[v] + cb);
+                    store_partial(pb + rb[v] + cb, hc[v]);
             if (++tj == ntile) {
                 ++ti;
                 tj = ti;

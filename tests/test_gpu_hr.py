@@ -129,6 +129,20 @@ def test_hr_fp32(oracle_mod, torch_dev):
     assert dH <= 1e-6
 
 
+@pytest.mark.parametrize("prec,tol", [("fp16x3", 1e-6), ("bf16", 2e-3)])
+def test_hr_16bit_si64_sampled(oracle_mod, torch_dev, prec, tol):
+    # the fixed-order path runs the plan's 16-bit matrix-core mode; the
+    # error bounds are those of the Gamma-point H in the same modes
+    torch, dev = torch_dev
+    w = gi.si64_dzp()
+    _say(f"case HR {prec} si64")
+    plan, R, HR, H = _gpu_HR(torch, dev, w, precision=prec)
+    rows = oracle_mod.Oracle.from_workload(w).HR(w.V, R, 0, 1)
+    dH = float(np.abs(HR[:, 0:rows.shape[1]] - rows).max())
+    _say(f"  {prec} H(R) rows atom 0: max|dH| {dH:.2e} Ha")
+    assert dH <= tol
+
+
 def test_hr_si64_sampled(oracle_mod, torch_dev):
     # full-size 64-atom DZP cell: rows of two atoms against the oracle
     torch, dev = torch_dev
