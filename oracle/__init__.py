@@ -66,6 +66,8 @@ def _load():
     lib.oracle_H_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, lp, dp]
     lib.oracle_HR_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp]
     lib.oracle_HR_rows.restype = ctypes.c_int
+    lib.oracle_forceR.argtypes = [P, dp, ctypes.c_int, ip, dp, ctypes.c_int, ip, dp]
+    lib.oracle_forceR.restype = ctypes.c_int
     lib.oracle_rhoR.argtypes = [P, ctypes.c_int, ip, dp, ctypes.c_long, lp, dp]
     lib.oracle_rhoR.restype = ctypes.c_int
     lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
@@ -236,6 +238,21 @@ class Oracle:
             n, ip_ = keep.size, keep.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
         out = np.zeros(n)
         rc = self._lib.oracle_rhoR(self._ctx, int(Rl.shape[0]), _ip(Rl), _dp(DR), n, ip_, _dp(out))
+        if rc != 0:
+            raise RuntimeError("a mesh point sees too many images of one atom")
+        return out
+
+    def forceR(self, V, R, DR, atoms: Optional[Sequence[int]] = None) -> np.ndarray:
+        """dE/dR_I (not the force) for E = dV sum V rho(D(R)), rho as in
+        ``rhoR``, for the chosen atoms."""
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        DR = np.ascontiguousarray(DR, dtype=np.float64)
+        assert DR.shape == (Rl.shape[0], self.norb, self.norb)
+        sel = np.arange(self.natom, dtype=np.int32) if atoms is None else np.ascontiguousarray(atoms, dtype=np.int32)
+        out = np.zeros((sel.size, 3))
+        rc = self._lib.oracle_forceR(self._ctx, _dp(V), int(Rl.shape[0]), _ip(Rl), _dp(DR), int(sel.size), _ip(sel),
+                                     _dp(out))
         if rc != 0:
             raise RuntimeError("a mesh point sees too many images of one atom")
         return out

@@ -538,10 +538,12 @@ void oracle_H_rows(void *p, const double *V, int I0, int I1, long npts, const lo
 /*
  * Orbitals of atom I at point r, one set per lattice vector T with
  * |r - tau_I - T| < rc (not summed): image k has lattice multiples
- * nvec[3k..3k+2] and values phi[k*norb(I) + o].  At most maximg images are
- * stored; returns how many there are (the caller checks it against maximg).
+ * nvec[3k..3k+2] and values phi[k*norb(I) + o] (gradients with respect to r
+ * in grad[3(k*norb(I) + o) ..] when grad != NULL).  At most maximg images
+ * are stored; returns how many there are (the caller checks it against
+ * maximg).
  */
-static int atom_image_phi(const octx *c, int I, const double *r, int maximg, int *nvec, double *phi)
+static int atom_image_phi(const octx *c, int I, const double *r, int maximg, int *nvec, double *phi, double *grad)
 {
     const int s = c->spc[I];
     const int no = c->sp_norb[s];
@@ -575,9 +577,12 @@ static int atom_image_phi(const octx *c, int I, const double *r, int maximg, int
                     double *ph = phi + (size_t)nimg * no;
                     for (int o = 0; o < no; ++o) {
                         const orad *R = &c->rad[c->orb_rad[o0 + o]];
+                        double *gr = grad ? grad + 3 * ((size_t)nimg * no + o) : NULL;
                         ph[o] = 0.0;
+                        if (gr)
+                            gr[0] = gr[1] = gr[2] = 0.0;
                         if (rr < R->rc)
-                            orbital_value(R, c->orb_m[o0 + o], d, &ph[o], NULL);
+                            orbital_value(R, c->orb_m[o0 + o], d, &ph[o], gr);
                     }
                 }
                 ++nimg;
@@ -623,7 +628,7 @@ int oracle_HR_rows(void *p, const double *V, int I0, int I1, int nR, const int *
             for (long g = 0; g < c->ng; ++g) {
                 double r[3];
                 mesh_point(c, g, r);
-                const int kI = atom_image_phi(c, I, r, MAX_IMG, nI_vec, phiI);
+                const int kI = atom_image_phi(c, I, r, MAX_IMG, nI_vec, phiI, NULL);
                 if (kI == 0)
                     continue;
                 if (kI > MAX_IMG) {
@@ -632,7 +637,7 @@ int oracle_HR_rows(void *p, const double *V, int I0, int I1, int nR, const int *
                 }
                 const double w = c->dV * V[g];
                 for (int J = 0; J < c->natom; ++J) {
-                    const int kJ = atom_image_phi(c, J, r, MAX_IMG, nJ_vec, phiJ);
+                    const int kJ = atom_image_phi(c, J, r, MAX_IMG, nJ_vec, phiJ, NULL);
                     if (kJ > MAX_IMG) {
                         bad = 1;
                         continue;
@@ -698,7 +703,7 @@ int oracle_rhoR(void *p, int nR, const int *R, const double *DR, long npts, cons
             double r[3];
             mesh_point(c, g, r);
             for (int I = 0; I < c->natom; ++I) {
-                kimg[I] = atom_image_phi(c, I, r, MAX_IMG, nvec + 3 * MAX_IMG * I, ph + (size_t)MAX_IMG * 64 * I);
+                kimg[I] = atom_image_phi(c, I, r, MAX_IMG, nvec + 3 * MAX_IMG * I, ph + (size_t)MAX_IMG * 64 * I, NULL);
                 if (kimg[I] > MAX_IMG) {
                     bad = 1;
                     kimg[I] = 0;
@@ -741,6 +746,100 @@ int oracle_rhoR(void *p, int nR, const int *R, const double *DR, long npts, cons
         free(kimg);
         free(nvec);
         free(ph);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
+ * dE/dR for E = dV sum_g V_g rho_g with rho from lattice-vector density
+ * blocks (oracle_rhoR; Sec. 3.3.1, F^{loc,Pulay} equation with its sum over
+ * R): moving atom I moves all its images, so
+ *   dE/dR_I = -dV sum_g V_g sum_{images a of I} sum_o grad phi_{a,o}(r_g) t_{a,o},
+ *   t_a = sum_{atoms J, images c of J} [D_IJ(T_c - T_a) + D_JI(T_a - T_c)^T] phi_c,
+ * D blocks of unlisted R being zero.  out is nsel x 3 for the atoms sel[];
+ * the mesh sum runs over all points.  Returns -1 if some point sees more
+ * than MAX_IMG images of one atom, else 0.  Parallel over the selected
+ * atoms.
+ */
+static int find_R(int nR, const int *R, int n1, int n2, int n3)
+{
+    for (int k = 0; k < nR; ++k)
+        if (R[3 * k] == n1 && R[3 * k + 1] == n2 && R[3 * k + 2] == n3)
+            return k;
+    return -1;
+}
+
+int oracle_forceR(void *p, const double *V, int nR, const int *R, const double *DR, int nsel, const int *sel,
+                  double *out)
+{
+    const octx *c = (const octx *)p;
+    const int norb = c->norb;
+    int bad = 0;
+#pragma omp parallel reduction(| : bad)
+    {
+        double *phiI = (double *)malloc(sizeof(double) * MAX_IMG * 64);
+        double *gI = (double *)malloc(sizeof(double) * 3 * MAX_IMG * 64);
+        double *phiJ = (double *)malloc(sizeof(double) * MAX_IMG * 64);
+        double *t = (double *)malloc(sizeof(double) * 64);
+        int nI_vec[3 * MAX_IMG], nJ_vec[3 * MAX_IMG];
+#pragma omp for schedule(dynamic, 1)
+        for (int s = 0; s < nsel; ++s) {
+            const int I = sel[s];
+            const int nI = c->sp_norb[c->spc[I]];
+            const int i0 = c->atom_orb0[I];
+            double f[3] = {0.0, 0.0, 0.0};
+            for (long g = 0; g < c->ng; ++g) {
+                double r[3];
+                mesh_point(c, g, r);
+                const int kI = atom_image_phi(c, I, r, MAX_IMG, nI_vec, phiI, gI);
+                if (kI == 0)
+                    continue;
+                if (kI > MAX_IMG) {
+                    bad = 1;
+                    continue;
+                }
+                const double w = c->dV * V[g];
+                for (int a = 0; a < kI; ++a) {
+                    const int *Ta = nI_vec + 3 * a;
+                    for (int x = 0; x < nI; ++x)
+                        t[x] = 0.0;
+                    for (int J = 0; J < c->natom; ++J) {
+                        const int kJ = atom_image_phi(c, J, r, MAX_IMG, nJ_vec, phiJ, NULL);
+                        if (kJ > MAX_IMG) {
+                            bad = 1;
+                            continue;
+                        }
+                        const int nJ = c->sp_norb[c->spc[J]];
+                        const int j0 = c->atom_orb0[J];
+                        for (int b = 0; b < kJ; ++b) {
+                            const int *Tb = nJ_vec + 3 * b;
+                            const double *pb = phiJ + (size_t)b * nJ;
+                            const int qp = find_R(nR, R, Tb[0] - Ta[0], Tb[1] - Ta[1], Tb[2] - Ta[2]);
+                            const int qn = find_R(nR, R, Ta[0] - Tb[0], Ta[1] - Tb[1], Ta[2] - Tb[2]);
+                            for (int x = 0; x < nI; ++x)
+                                for (int y = 0; y < nJ; ++y) {
+                                    double sxy = 0.0;
+                                    if (qp >= 0)
+                                        sxy += DR[((size_t)qp * norb + i0 + x) * norb + j0 + y];
+                                    if (qn >= 0)
+                                        sxy += DR[((size_t)qn * norb + j0 + y) * norb + i0 + x];
+                                    t[x] += sxy * pb[y];
+                                }
+                        }
+                    }
+                    for (int x = 0; x < nI; ++x)
+                        for (int k = 0; k < 3; ++k)
+                            f[k] += w * gI[3 * ((size_t)a * nI + x) + k] * t[x];
+                }
+            }
+            out[3 * s] = -f[0];
+            out[3 * s + 1] = -f[1];
+            out[3 * s + 2] = -f[2];
+        }
+        free(phiI);
+        free(gI);
+        free(phiJ);
+        free(t);
     }
     return bad ? -1 : 0;
 }

@@ -13,7 +13,9 @@ matrices D(R) (Sec. 3.3.1, rho(r_g) equation with its sums over R, R').
   positions given outside the cell;
 * rho(D(R)): brute force; D(R) = D for every R gives the folded Gamma-point
   rho of D; the energy identity dV sum_g V_g rho_g = sum_R <D(R), H(R)>
-  against the oracle's H(R) (random, non-symmetric D(R)).
+  against the oracle's H(R) (random, non-symmetric D(R));
+* dE/dR for D(R): central differences of that energy, and the Gamma-point
+  force for D(R) = D.
 """
 import numpy as np
 import pytest
@@ -196,3 +198,38 @@ def test_hk_pins(oracle_mod):
         got = H_sc[0:nb, c * nb:(c + 1) * nb]
         assert np.abs(want.imag).max() <= 1e-12 * scale
         assert np.abs(got - want.real).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("make", [_two_atom_dzp, _tiny_long_range])
+def test_forceR_by_differences(oracle_mod, make):
+    # dE/dR of E = dV sum V rho(D(R)) against central differences of E
+    # computed with rhoR (positions as given; R fixed)
+    w = make()
+    o = oracle_mod.Oracle.from_workload(w)
+    R = _box(3)
+    DR = _random_DR(np.random.default_rng(3), len(R), o.norb)
+    F = o.forceR(w.V, R, DR)
+    pos0 = np.array(w.positions, dtype=np.float64)
+    h = 1e-4
+    for I in range(len(pos0)):
+        for k in range(3):
+            e = []
+            for sgn in (1, -1):
+                pos = pos0.copy()
+                pos[I, k] += sgn * h
+                o.set_positions(pos)
+                e.append(o.dV * float(np.dot(w.V, o.rhoR(R, DR))))
+            fd = (e[0] - e[1]) / (2 * h)
+            assert abs(F[I, k] - fd) <= 1e-6 * max(1.0, np.abs(F).max()), (I, k, F[I, k], fd)
+    o.set_positions(pos0)
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _two_atom_dzp])
+def test_forceR_constant_is_gamma(oracle_mod, make):
+    w = make()
+    o = oracle_mod.Oracle.from_workload(w)
+    R = _box(4)
+    DR = np.broadcast_to(w.D, (len(R),) + w.D.shape).copy()
+    F = o.forceR(w.V, R, DR)
+    ref = o.force(w.V, w.D)
+    assert np.abs(F - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
