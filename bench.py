@@ -233,10 +233,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
     ap.add_argument("--only", default=None,
-                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR"],
+                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR", "forceR"],
                     help="time one contraction only (short profiler runs); HR: the lattice-vector blocks "
                          "H(R) for every R of gint_HR_lattice; rhoR: rho from random lattice-vector density "
-                         "matrices D(R) over the same R")
+                         "matrices D(R) over the same R; forceR: dE/dR for those D(R)")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--serial", action="store_true",
@@ -292,11 +292,11 @@ def main():
     rho = torch.empty(plan.ngrid, dtype=torch.float64, device=dev)
     F = torch.empty((plan.natom, 3), dtype=torch.float64, device=dev)
     work = plan.work()
-    if args.only in ("HR", "rhoR"):
+    if args.only in ("HR", "rhoR", "forceR"):
         R_list = plan.HR_lattice()
     if args.only == "HR":
         HRbuf = torch.empty((len(R_list), plan.norb, plan.norb), dtype=torch.float64, device=dev)
-    if args.only == "rhoR":
+    if args.only in ("rhoR", "forceR"):
         gen = torch.Generator(device=dev)
         gen.manual_seed(12)
         DRbuf = torch.randn((len(R_list), plan.norb, plan.norb), dtype=torch.float64, device=dev,
@@ -308,6 +308,9 @@ def main():
             return
         if args.only == "rhoR":
             plan.build_rhoR(R_list, DRbuf, out=rho)
+            return
+        if args.only == "forceR":
+            plan.forceR(V, R_list, DRbuf, out=F)
             return
         if args.only is None:
             plan.set_positions(w.positions)
@@ -444,11 +447,12 @@ def main():
                                      f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the lattice-vector "
                                      f"blocks H(R) of {len(R_list)} lattice vectors (gint_build_HR)")
         out["config"]["n_R"] = len(R_list)
-    if args.only == "rhoR":
+    if args.only in ("rhoR", "forceR"):
+        what = "rho" if args.only == "rhoR" else "dE/dR"
+        call = "gint_build_rhoR" if args.only == "rhoR" else "gint_forceR"
         out["config"]["workload"] = (f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh "
-                                     f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = rho from random "
-                                     f"density-matrix blocks D(R) of {len(R_list)} lattice vectors "
-                                     f"(gint_build_rhoR)")
+                                     f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = {what} from random "
+                                     f"density-matrix blocks D(R) of {len(R_list)} lattice vectors ({call})")
         out["config"]["n_R"] = len(R_list)
     if not args.no_cpu_baseline and args.only is None:
         _progress("cpu baseline (oracle sample)")

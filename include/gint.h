@@ -236,6 +236,21 @@ gint_status gint_build_HR(gint_plan plan, const double *V_dev, int nR, const int
  * With D(R) = D for every R of gint_HR_lattice, rho is gint_build_rho's. */
 gint_status gint_build_rhoR(gint_plan plan, int nR, const int *R, const double *DR_dev, double *rho_dev);
 
+/* dE/dR for E = dV sum_g V_g rho_g with rho from lattice-vector density
+ * blocks as in gint_build_rhoR (Sec. 3.3.1, F^{loc,Pulay} equation with its
+ * sum over R): moving an atom moves all its images, and
+ *   dE/dR_I = -dV sum_g V_g sum_{images a of I} grad phi_a . t_a,
+ *   t_a = sum_{images c} [D_{I J_c}(T_c - T_a) + D_{J_c I}(T_a - T_c)^T] phi_c.
+ *   V_dev     device, N1*N2*N3 doubles (Ha)
+ *   nR, R     host lattice multiples as in gint_build_HR
+ *   DR_dev    device, nR*norb*norb doubles, used as given
+ *   dEdR_dev  device, natom*3 doubles, input atom order, overwritten
+ * Per-(batch, image) partials summed per atom in a fixed order (repeatable
+ * bits).  Precision and errors as gint_build_rhoR.  With D(R) = D for every
+ * R of gint_HR_lattice this is gint_force's dE/dR. */
+gint_status gint_forceR(gint_plan plan, const double *V_dev, int nR, const int *R, const double *DR_dev,
+                        double *dEdR_dev);
+
 /* Bloch sum of lattice-vector blocks (Sec. 2.1, H(k) equation):
  *   H(k) = sum_q e^{i k.R_q} H(R_q),  k.R_q = 2 pi (kappa . n_q),
  * kappa the fractional coordinates of k in the reciprocal basis (b_i with

@@ -31,7 +31,7 @@ EXPORTS = (
     "gint_force_weighted", "gint_plan_sync", "gint_plan_work", "gint_norb", "gint_natom",
     "gint_dV", "gint_status_string", "gint_last_error", "gint_plan_destroy",
     "gint_plan_set_timing", "gint_plan_timing", "gint_rho_force", "gint_H_rho_force",
-    "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk",
+    "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk", "gint_forceR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
 )
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_sync.restype = st
     lib.gint_build_HR.argtypes = [P, P, ctypes.c_int, ip, P]
     lib.gint_build_HR.restype = ctypes.c_int
+    lib.gint_forceR.argtypes = [P, P, ctypes.c_int, ip, P, P]
+    lib.gint_forceR.restype = ctypes.c_int
     lib.gint_HR_to_Hk.argtypes = [P, ctypes.c_int, ip, P, ctypes.c_int, dp, P]
     lib.gint_HR_to_Hk.restype = ctypes.c_int
     lib.gint_build_rhoR.argtypes = [P, ctypes.c_int, ip, P, P]
@@ -348,6 +350,22 @@ class GintPlan:
         _check(self._lib.gint_build_HR(self._handle(), vp, nR,
                                        Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), op))
         return Rl, out
+
+    def forceR(self, V, R, DR, out=None):
+        """dE/dR (natom x 3) for E = dV sum V rho(D(R)), D(R) blocks DR
+        (nR x norb x norb, device) for the lattice multiples R (nR x 3)."""
+        import numpy as np
+        import torch
+
+        Rl = np.ascontiguousarray(np.asarray(R, dtype=np.int32).reshape(-1, 3))
+        nR = int(Rl.shape[0])
+        vp = _dev_ptr(V, self.ngrid, "V")
+        dp = _dev_ptr(DR, nR * self.norb * self.norb, "DR")
+        if out is None:
+            out = torch.empty((self.natom, 3), dtype=torch.float64, device=V.device)
+        op = _dev_ptr(out, self.natom * 3, "dEdR")
+        _check(self._lib.gint_forceR(self._handle(), vp, nR, Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dp, op))
+        return out
 
     def HR_to_Hk(self, R, HR, kfrac, out=None):
         """H(k) = sum_q e^{i 2 pi kappa.n_q} H(R_q) for fractional k-points

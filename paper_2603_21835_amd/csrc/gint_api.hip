@@ -131,6 +131,7 @@ struct gint_plan_s {
     // fixed-order H(R): per-image identity entries, per-batch block offsets
     // of the unfolded images, sorted triple keys and their runs
     DevBuf hk_phase;  // (cos, sin) phases of gint_HR_to_Hk
+    DevBuf Fimg;      // per-(batch, image) force partials of gint_forceR
     DevBuf img_id, cnt_u, boff_u, hkey, hkey2, hcode, hcode2, hflag, hfscan, tstart, tkey, sort_tmp, hbad;
     long long nblock_u = 0;
     int ntri = 0;
@@ -1335,6 +1336,30 @@ gint_status gint_HR_to_Hk(gint_plan p, int nR, const int *R, const double *HR_de
         return launch_Hk(p->stream, nel, nR, nk, p->hk_phase.as<double>(), HR_dev, Hk_dev);
     }));
     HIPCHK(hipStreamSynchronize(p->stream));  // ph (host) outlives the copy
+    return GINT_OK;
+}
+
+gint_status gint_forceR(gint_plan p, const double *V_dev, int nR, const int *R, const double *DR_dev,
+                        double *dEdR_dev)
+{
+    STCHK(check_plan(p));
+    if (!V_dev || !DR_dev || !dEdR_dev || !R)
+        return fail(GINT_EINVAL, "V, DR and dEdR must be non-NULL device pointers and R a non-NULL host array");
+    if (nR < 1)
+        return fail(GINT_EINVAL, "nR = %d must be >= 1", nR);
+    HRMap m;
+    STCHK(hr_map(p, nR, R, &m));
+    STCHK(p->Fimg.ensure(sizeof(double) * 3 * (size_t)(p->nimg + 1)));
+    const Basis B = p->basis();
+    STCHK(timed(p, GINT_K_FORCE, [&] {
+        return launch_forceR_batch(p->stream, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(),
+                                   p->img_atom.as<int>(), p->img.as<int>(), B, p->wsh.as<int>(), m, p->norb, DR_dev,
+                                   V_dev, p->dV, p->Fimg.as<double>());
+    }));
+    STCHK(timed(p, GINT_K_F_REDUCE, [&] {
+        return launch_forceR_reduce(p->stream, p->natom, p->aptr.as<int>(), p->aent.as<int>(), p->ent_img.as<int>(),
+                                    p->perm.as<int>(), p->Fimg.as<double>(), dEdR_dev);
+    }));
     return GINT_OK;
 }
 

@@ -490,6 +490,217 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
     }
 }
 
+// dE/dR for E = dV sum_g V_g rho_g with rho from D(R) (Sec. 3.3.1,
+// F^{loc,Pulay} equation with its sum over R): per unfolded image a of the
+// batch, T_a = sum_c S'_ac phi_c on the matrix cores with
+// S'_ac = D_{I_a I_c}(T_c - T_a) + D_{I_c I_a}(T_a - T_c)^T over every image
+// c (c = a included), held in the MFMA result registers; then each lane
+// dots the gradients of its four orbitals at its point with w T_a
+// (grad4_dot) and the wave sums the lanes.  One partial per (batch, image),
+// summed per atom in batch order by k_forceR_reduce.
+constexpr int kFRWaves = 8;  // (T_a of a whole image stays in registers)
+
+template <typename T, int P>
+__global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int *__restrict__ iptr,
+                                                       const int *__restrict__ img_atom,
+                                                       const int *__restrict__ img, Basis bs,
+                                                       const int *__restrict__ wsh, HRMap m, int norb,
+                                                       const double *__restrict__ DR, const double *__restrict__ W,
+                                                       double wscale, double *__restrict__ Fimg)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
+    __shared__ DevRadial s_rad[kMaxRadTotal];
+    __shared__ DevSpecies s_sp[kMaxSpecies];
+    __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms], s_mu0[kMaxBatchAtoms];
+    __shared__ int s_T[kMaxBatchAtoms][3];
+    __shared__ double s_w[kMaxP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6),
+              nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = xcd_batch(blockIdx.x, 0, g.nbatch);
+    if (b < 0)
+        return;
+    const int i0 = iptr[b], nb = iptr[b + 1] - i0;
+    int ib[3];
+    batch_coords(g, b, ib);
+
+    for (int k = tid; k < g.nrad; k += blockDim.x)
+        s_rad[k] = bs.rad[k];
+    for (int k = tid; k < g.nspecies; k += blockDim.x)
+        s_sp[k] = bs.sp[k];
+    for (int a = tid; a < nb; a += blockDim.x) {
+        const int atom = img_atom[i0 + a];
+        s_atom[a] = atom;
+        s_nor[a] = bs.sp[bs.spc[atom]].norb;
+        s_mu0[a] = bs.orb0[bs.perm[atom]];
+        int n[3];
+        unpack_image(img[i0 + a], n);
+        for (int k = 0; k < 3; ++k)
+            s_T[a][k] = n[k] - wsh[3 * atom + k];
+    }
+    for (int p = tid; p < P; p += blockDim.x) {
+        int n[3];
+        s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
+    }
+    __syncthreads();
+
+    for (int idx = tid; idx < nb * P; idx += blockDim.x) {
+        const int a = idx / P, p = idx % P;
+        const int atom = s_atom[a];
+        T *row = s_phi + (size_t)(a * P + p) * kRow;
+        const int swz = p & 15;
+        int n[3];
+        const bool valid = batch_point(g, ib, p, n);
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const int zlo = valid ? S.norb : 0;
+        for (int o = zlo; o < kMaxOrb; ++o)
+            row[o ^ swz] = (T)0;
+        if (valid) {
+            const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+            double r[3];
+            mesh_cart(g, n, r);
+            eval_orbitals<T>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, 1, img[i0 + a], i0 + a, img, r,
+                             row, swz);
+        }
+    }
+    __syncthreads();
+
+    constexpr int NT = P / 16;
+    const size_t nn = (size_t)norb * norb;
+    for (int a = wave; a < nb; a += nw) {
+        const int nI = s_nor[a], mI = s_mu0[a];
+        typename MM<T>::acc acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            acc[t] = MM<T>::zero();
+        for (int c = 0; c < nb; ++c) {
+            const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
+            const int qp = hr_lookup(m, Rx, Ry, Rz);
+            const int qn = hr_lookup(m, -Rx, -Ry, -Rz);
+            if (qp < 0 && qn < 0)
+                continue;
+            const int nJ = s_nor[c], mJ = s_mu0[c];
+            T aS[4];
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int kc = lk + 4 * st;
+                double x = 0.0;
+                if (li < nI && kc < nJ) {
+                    if (qp >= 0)
+                        x += DR[qp * nn + (size_t)(mI + li) * norb + mJ + kc];
+                    if (qn >= 0)
+                        x += DR[qn * nn + (size_t)(mJ + kc) * norb + mI + li];
+                }
+                aS[st] = (T)x;
+            }
+            const T *pC = s_phi + (size_t)(c * P) * kRow;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int p = 16 * t + li;
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    acc[t] = MM<T>::mma(aS[st], pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
+            }
+        }
+        // gradients of this lane's four orbitals of image a at its point
+        const int atom = s_atom[a];
+        const DevSpecies &S = s_sp[bs.spc[atom]];
+        const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
+        double fx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int p = 16 * t + li;
+            int n[3];
+            const bool valid = batch_point(g, ib, p, n);
+            double r[3];
+            mesh_cart(g, n, r);
+            const double wp = s_w[p];
+            const double wv[4] = {wp * (double)acc[t][0], wp * (double)acc[t][1], wp * (double)acc[t][2],
+                                  wp * (double)acc[t][3]};
+            grad4_dot(g, s_rad, S.orb_rad, S.orb_m, S.norb, S.rc, bs.coef, X, valid ? 1 : 0, img[i0 + a], i0 + a,
+                      img, r, MM<T>::row(lk, 0), MM<T>::row(lk, 1) - MM<T>::row(lk, 0), wv, fx);
+        }
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            double v = fx[x];
+            for (int o = 32; o > 0; o >>= 1)
+                v += __shfl_xor(v, o);
+            fx[x] = v;
+        }
+        if (lane == 0)
+            for (int x = 0; x < 3; ++x)
+                Fimg[3 * (size_t)(i0 + a) + x] = -fx[x];
+    }
+}
+
+// per internal atom: its image partials in batch order (entries of the atom
+// in batch order, images of each entry in order), tree-summed in a fixed
+// order; written at the atom's input index
+__global__ __launch_bounds__(256) void k_forceR_reduce(const int *__restrict__ aptr, const int *__restrict__ aent,
+                                                       const int *__restrict__ ent_img, const int *__restrict__ perm,
+                                                       const double *__restrict__ Fimg, double *__restrict__ dEdR)
+{
+    __shared__ double red[3][256];
+    const int a = blockIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = aptr[a] + threadIdx.x; k < aptr[a + 1]; k += 256) {
+        const int e = aent[k];
+        for (int i = ent_img[e]; i < ent_img[e + 1]; ++i)
+            for (int x = 0; x < 3; ++x)
+                v[x] += Fimg[3 * (size_t)i + x];
+    }
+    for (int x = 0; x < 3; ++x)
+        red[x][threadIdx.x] = v[x];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int x = 0; x < 3; ++x)
+                red[x][threadIdx.x] += red[x][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3)
+        dEdR[3 * perm[a] + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <typename T, int P>
+static hipError_t launch_forceR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                                  const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
+                                  const double *DR, const double *W, double wscale, double *Fimg)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow;
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_forceR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_forceR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
+                       dim3(64 * kFRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, Fimg);
+    return hipGetLastError();
+}
+
+hipError_t launch_forceR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr,
+                               const int *img_atom, const int *img, const Basis &b, const int *wsh, const HRMap &m,
+                               int norb, const double *DR, const double *W, double wscale, double *Fimg)
+{
+    if (g.P == 32)
+        return f32 ? launch_forceR_p<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, Fimg)
+                   : launch_forceR_p<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale,
+                                                 Fimg);
+    if (g.P == 16)
+        return f32 ? launch_forceR_p<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, Fimg)
+                   : launch_forceR_p<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale,
+                                                 Fimg);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_forceR_reduce(hipStream_t s, int natom, const int *aptr, const int *aent, const int *ent_img,
+                                const int *perm, const double *Fimg, double *dEdR)
+{
+    hipLaunchKernelGGL(k_forceR_reduce, dim3((unsigned)natom), dim3(256), 0, s, aptr, aent, ent_img, perm, Fimg, dEdR);
+    return hipGetLastError();
+}
+
 template <typename T, int P>
 static hipError_t launch_rhoR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                                 const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,

@@ -159,6 +159,11 @@ hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, c
                              const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
                              const double *DR, double *rho);
 hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double *ph, const double *HR, double *Hk);
+hipError_t launch_forceR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr,
+                               const int *img_atom, const int *img, const Basis &b, const int *wsh, const HRMap &m,
+                               int norb, const double *DR, const double *W, double wscale, double *Fimg);
+hipError_t launch_forceR_reduce(hipStream_t s, int natom, const int *aptr, const int *aent, const int *ent_img,
+                                const int *perm, const double *Fimg, double *dEdR);
 hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const int *img_atom, const int *img,
                           const int *wsh, int M, int *mark);
 hipError_t launch_HR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
