@@ -1331,11 +1331,11 @@ gint_status gint_HR_to_Hk(gint_plan p, int nR, const int *R, const double *HR_de
         }
     STCHK(p->hk_phase.ensure(sizeof(double) * ph.size()));
     HIPCHK(hipMemcpyAsync(p->hk_phase.p, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));  // ph (host) outlives the copy on every path
     const long long nel = (long long)p->norb * p->norb;
     STCHK(timed(p, GINT_K_HR, [&] {
         return launch_Hk(p->stream, nel, nR, nk, p->hk_phase.as<double>(), HR_dev, Hk_dev);
     }));
-    HIPCHK(hipStreamSynchronize(p->stream));  // ph (host) outlives the copy
     return GINT_OK;
 }
 
