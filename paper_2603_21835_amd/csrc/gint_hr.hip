@@ -426,7 +426,35 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
         ja = ia + k;
     }
     const size_t nn = (size_t)norb * norb;
+    // a wave's blocks are consecutive in row-major order: T_a = sum_c S_ac
+    // phi_c accumulates in the result registers over the blocks of one row
+    // a, and is dotted with phi_a once per row (at a row change and at the
+    // end)
+    typename MM<T>::acc acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        acc[t] = MM<T>::zero();
+    int cur = ia;
+    auto flush = [&](int a) {
+        const T *pA = s_phi + (size_t)(a * P) * kRow;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int p = 16 * t + li;
+            double d = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = MM<T>::row(lk, v);
+                d += (double)pA[p * kRow + (i ^ (p & 15))] * (double)acc[t][v];
+            }
+            racc[t] += d;
+            acc[t] = MM<T>::zero();
+        }
+    };
     for (int k = k0; k < k1; ++k) {
+        if (ia != cur) {
+            flush(cur);
+            cur = ia;
+        }
         const int Rx = s_T[ja][0] - s_T[ia][0], Ry = s_T[ja][1] - s_T[ia][1], Rz = s_T[ja][2] - s_T[ia][2];
         const int qp = hr_lookup(m, Rx, Ry, Rz);
         const int qn = ia != ja ? hr_lookup(m, -Rx, -Ry, -Rz) : -1;
@@ -446,22 +474,13 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
                 }
                 aS[st] = (T)x;
             }
-            const T *pA = s_phi + (size_t)(ia * P) * kRow;
             const T *pC = s_phi + (size_t)(ja * P) * kRow;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int p = 16 * t + li;  // this lane's point (B and result column)
-                typename MM<T>::acc acc = MM<T>::zero();
 #pragma unroll
                 for (int st = 0; st < 4; ++st)
-                    acc = MM<T>::mma(aS[st], pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc);
-                double d = 0.0;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = MM<T>::row(lk, v);
-                    d += (double)pA[p * kRow + (i ^ (p & 15))] * (double)acc[v];
-                }
-                racc[t] += d;
+                    acc[t] = MM<T>::mma(aS[st], pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
             }
         }
         if (++ja == nb) {
@@ -469,6 +488,8 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
             ja = ia;
         }
     }
+    if (k0 < k1)
+        flush(cur);
     // lanes li, li + 16, li + 32, li + 48 hold the same point
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
