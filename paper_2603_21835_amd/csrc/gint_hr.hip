@@ -344,10 +344,10 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_HR_batch(Geo g, const int *__
 //     rho_p = sum_{a <= c} phi_a(p)^T S_ac phi_c(p),
 //     S_ac = D_{I_a I_c}(T_c - T_a) + D_{I_c I_a}(T_a - T_c)^T  (a < c),
 //     S_aa = D_{I_a I_a}(0),
-// D blocks of unlisted R being zero.  Per block, T = S_ac phi_c on the
-// matrix cores (16 points per product), dotted with phi_a in the result
-// registers; lanes and waves are summed in a fixed order.  Each point is
-// written once.
+// D blocks of unlisted R being zero.  Per block, S_ac phi_c on the matrix
+// cores (16 points per product) is added to T_a in the result registers,
+// which is dotted with phi_a once per row of blocks; lanes and waves are
+// summed in a fixed order.  Each point is written once.
 template <typename T, int P>
 __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *__restrict__ iptr,
                                                      const int *__restrict__ img_atom, const int *__restrict__ img,
