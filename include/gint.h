@@ -365,6 +365,22 @@ int gint_batch_ncell(gint_batch batch);
 gint_plan gint_batch_cell(gint_batch batch, int i);
 void gint_batch_destroy(gint_batch batch);
 
+/* The order the plan processes the atoms in (a Morton curve through the
+ * cell, recomputed at plan creation): order[i] is the input index of the
+ * i-th atom in that order.  order: host, natom ints.  Synchronises the
+ * stream.  For tests and diagnostics; results never depend on it beyond
+ * rounding. */
+gint_status gint_plan_atom_order(gint_plan plan, int *order);
+
+/* Failure injection for tests of the error paths: the next n list rebuilds
+ * (plan creation, gint_plan_set_positions, gint_plan_tune) of any plan fail
+ * with GINT_ENOMEM before enqueuing anything.  n = 0 disarms it.  Not
+ * thread-safe.  When gint_plan_tune fails and restoring the previous batch
+ * shape fails too, the plan is left unusable: every call but
+ * gint_plan_destroy then returns GINT_ESTATE, and gint_plan_destroy still
+ * releases it. */
+gint_status gint_test_fail_rebuilds(int n);
+
 int gint_norb(gint_plan plan);   /* total orbitals, or -1 for an invalid plan */
 int gint_natom(gint_plan plan);  /* atoms, or -1                               */
 double gint_dV(gint_plan plan);  /* mesh volume element, or -1                 */

@@ -72,6 +72,7 @@ def _load():
     lib.oracle_rhoR.restype = ctypes.c_int
     lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
     lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, ctypes.c_long, lp, dp]
+    lib.oracle_DK_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, lp, dp]
     lib.oracle_set_positions.argtypes = [P, dp]
     lib.oracle_support_stats.argtypes = [P, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -281,6 +282,25 @@ class Oracle:
         npts, ip_, keep = self._points(points)
         self._lib.oracle_force(self._ctx, _dp(V), _dp(D), int(sel.size), _ip(sel), npts, ip_, _dp(out))
         return out
+
+    def DK_rows(self, W, I0: int, I1: int, points: Optional[Sequence[int]] = None) -> np.ndarray:
+        """Rows of the moving-basis matrix (Sec. 2.3, D_K equation, Gamma
+        point) for the orbitals of atoms I0..I1-1:
+        out[c, mu, nu] = <phit_mu | W | d phit_nu / d tau_K>_c with K the
+        atom of nu, i.e. -dV sum_g W_g phit_mu d_c phit_nu (W None: W = 1)."""
+        Wp = None
+        if W is not None:
+            W = np.ascontiguousarray(W, dtype=np.float64)
+            Wp = _dp(W)
+        nrow = int(self.atom_orb0[I1] - self.atom_orb0[I0])
+        out = np.zeros((3, nrow, self.norb))
+        npts, ip_, keep = self._points(points)
+        self._lib.oracle_DK_rows(self._ctx, Wp, int(I0), int(I1), npts, ip_, _dp(out))
+        return out
+
+    def DK(self, W=None) -> np.ndarray:
+        """The whole 3 x norb x norb moving-basis matrix (see DK_rows)."""
+        return self.DK_rows(W, 0, self.natom)
 
     def energy(self, V, D) -> float:
         return float(self.dV * np.dot(np.asarray(V, dtype=np.float64), self.rho(D)))

@@ -944,6 +944,69 @@ void oracle_force(void *p, const double *V, const double *D, int nsel, const int
     }
 }
 
+/*
+ * Moving-basis matrix of Sec. 2.3 (Ehrenfest dynamics, D_K equation) at the
+ * Gamma point, on the mesh, with an optional weight W:
+ *
+ *   DK_c,mu,nu = < phit_mu | W | d phit_nu / d tau_K >_c ,  K = atom of nu,
+ *              = -dV sum_g W_g phit_mu(r_g) d/dr_c phit_nu(r_g),
+ *
+ * since an orbital centred on tau_K depends on tau_K only through
+ * r - tau_K (d/dtau_K = -grad_r); the sum over R of the D_K equation at
+ * k = 0 is the folded orbital.  D_K,mu,nu vanishes unless nu belongs to K,
+ * so one 3 x norb x norb array holds every D_K.  W == NULL means W = 1 (the
+ * plain overlap derivative: dS_mu,nu/dtau_K = D_K,nu,mu [mu in K] +
+ * D_K,mu,nu [nu in K]).
+ * Rows mu of atoms I0..I1-1 over the points idx[0..npts) (all when idx is
+ * NULL): out[c][row][nu], c = x, y, z, rows = orbitals of I0..I1-1 in order.
+ * Parallel over the row atoms; each thread owns its rows.
+ */
+void oracle_DK_rows(void *p, const double *W, int I0, int I1, long npts, const long *idx, double *out)
+{
+    const octx *c = (const octx *)p;
+    const int norb = c->norb;
+    const int row0 = c->atom_orb0[I0];
+    const size_t nrow = (size_t)(c->atom_orb0[I1] - row0);
+    memset(out, 0, sizeof(double) * 3 * nrow * norb);
+#pragma omp parallel
+    {
+        double *phiI = (double *)malloc(sizeof(double) * 64);
+        double *phiJ = (double *)malloc(sizeof(double) * 64);
+        double *gJ = (double *)malloc(sizeof(double) * 3 * 64);
+#pragma omp for schedule(dynamic, 1)
+        for (int I = I0; I < I1; ++I) {
+            const int nI = c->sp_norb[c->spc[I]];
+            const size_t r0 = (size_t)(c->atom_orb0[I] - row0);
+            const long nq = idx ? npts : c->ng;
+            for (long q = 0; q < nq; ++q) {
+                const long g = idx ? idx[q] : q;
+                double r[3];
+                mesh_point(c, g, r);
+                if (atom_phi(c, I, r, phiI, NULL) == 0)
+                    continue;
+                const double w = c->dV * (W ? W[g] : 1.0);
+                for (int J = 0; J < c->natom; ++J) {
+                    if (atom_phi(c, J, r, phiJ, gJ) == 0)
+                        continue;
+                    const int nJ = c->sp_norb[c->spc[J]];
+                    const int j0 = c->atom_orb0[J];
+                    for (int a = 0; a < nI; ++a) {
+                        const double wa = w * phiI[a];
+                        for (int k = 0; k < 3; ++k) {
+                            double *row = out + ((size_t)k * nrow + r0 + a) * norb + j0;
+                            for (int b = 0; b < nJ; ++b)
+                                row[b] -= wa * gJ[3 * b + k];
+                        }
+                    }
+                }
+            }
+        }
+        free(phiI);
+        free(phiJ);
+        free(gJ);
+    }
+}
+
 /* Move atoms (for finite differences and symmetry pins). */
 void oracle_set_positions(void *p, const double *pos)
 {

@@ -34,6 +34,7 @@ EXPORTS = (
     "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk", "gint_forceR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
+    "gint_plan_atom_order", "gint_test_fail_rebuilds",
 )
 KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
            "H_rho_force", "HR")
@@ -132,6 +133,10 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_timing.argtypes = [P, dp, ip]
     lib.gint_plan_destroy.restype = None
     lib.gint_plan_destroy.argtypes = [P]
+    lib.gint_plan_atom_order.restype = st
+    lib.gint_plan_atom_order.argtypes = [P, ip]
+    lib.gint_test_fail_rebuilds.restype = st
+    lib.gint_test_fail_rebuilds.argtypes = [ctypes.c_int]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.gint_batch_create.restype = st
     lib.gint_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_Cell), ctypes.c_int, ctypes.POINTER(_Species),
@@ -296,6 +301,12 @@ class GintPlan:
         return {"ngrid": w.ngrid, "nbatch": w.nbatch, "nentry": w.nentry, "npair": w.npair,
                 "sum_ng": w.sum_ng, "sum_ng2": w.sum_ng2, "batch": tuple(w.batch), "nslab": w.nslab,
                 "nblock": w.nblock, "mno": w.mno, "partial_bytes": w.partial_bytes, "nblock_hr": w.nblock_hr}
+
+    def atom_order(self) -> np.ndarray:
+        """Input indices of the atoms in the plan's processing order."""
+        order = np.zeros(self.natom, dtype=np.int32)
+        _check(self._lib.gint_plan_atom_order(self._handle(), _iptr(order)))
+        return order
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.gint_plan_set_timing(self._handle(), 1 if enable else 0))

@@ -21,6 +21,9 @@ namespace {
 
 constexpr unsigned kMagic = 0x47494e54u;  // "GINT"
 thread_local std::string g_last_error;
+// failure injection for tests of the error paths: the next n list rebuilds
+// fail with GINT_ENOMEM before touching the device (gint_test_fail_rebuilds)
+int g_fail_rebuilds = 0;
 
 gint_status fail(gint_status s, const char *fmt, ...)
 {
@@ -86,6 +89,9 @@ struct DevBuf {
 
 struct gint_plan_s {
     unsigned magic = kMagic;
+    // set when a failed re-tune could not restore the previous lists: every
+    // call but gint_plan_destroy then returns GINT_ESTATE
+    bool broken = false;
     int device = 0;
     hipStream_t stream = nullptr;
     // second stream of gint_H_rho_force (created on first use) and its
@@ -230,6 +236,8 @@ gint_status check_plan(gint_plan p)
         return fail(GINT_EINVAL, "plan is NULL");
     if (p->magic != kMagic)
         return fail(GINT_ESTATE, "plan is destroyed or corrupted");
+    if (p->broken)
+        return fail(GINT_ESTATE, "plan lost its lists in a failed gint_plan_tune; only gint_plan_destroy is valid");
     return GINT_OK;
 }
 
@@ -374,6 +382,10 @@ gint_status read_scalar(gint_plan p, const T *dev, T *host)
 // Rebuild every list that depends on the atom positions (GintInfo).
 gint_status rebuild_lists(gint_plan p, bool resort)
 {
+    if (g_fail_rebuilds > 0) {
+        --g_fail_rebuilds;
+        return fail(GINT_ENOMEM, "list rebuild failed (injected by gint_test_fail_rebuilds)");
+    }
     Geo &g = p->geo;
     hipStream_t s = p->stream;
     const int na = p->natom;
@@ -913,8 +925,11 @@ gint_status gint_plan_tune(gint_plan p, const int batch[3], long long h_budget_b
         p->geo = g_old;
         p->brad = brad_old;
         p->hbudget_req = hb_old;
-        if (rebuild_lists(p, false) != GINT_OK)
-            p->magic = 0;
+        if (rebuild_lists(p, false) != GINT_OK) {
+            p->broken = true;
+            return fail(st, "%s (and restoring the previous batch shape failed: the plan is unusable)",
+                        why.c_str());
+        }
         return fail(st, "%s", why.c_str());
     }
     return GINT_OK;
@@ -1429,6 +1444,25 @@ gint_status gint_plan_timing(gint_plan p, double *ms, int *launches)
         ms[k] = p->timed_ms[k];
         launches[k] = p->timed_n[k];
     }
+    return GINT_OK;
+}
+
+gint_status gint_plan_atom_order(gint_plan p, int *order)
+{
+    STCHK(check_plan(p));
+    if (!order)
+        return fail(GINT_EINVAL, "order is NULL");
+    HIPCHK(hipSetDevice(p->device));
+    HIPCHK(hipMemcpyAsync(order, p->perm.p, sizeof(int) * p->natom, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return GINT_OK;
+}
+
+gint_status gint_test_fail_rebuilds(int n)
+{
+    if (n < 0)
+        return fail(GINT_EINVAL, "n = %d must be >= 0", n);
+    g_fail_rebuilds = n;
     return GINT_OK;
 }
 

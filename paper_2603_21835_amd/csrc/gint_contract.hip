@@ -543,6 +543,10 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__re
                 s_sum[wv][1][e] = dn[m][i];
             }
         }
+    // the sums of other lanes of this wave are read below: order the LDS
+    // stores before those loads (a wave-level barrier; the per-wave early
+    // exits rule out a workgroup barrier)
+    wave_lds_sync();
     const int I = pown[p], J = plist[p];
     const int Iin = bs.perm[I], Jin = bs.perm[J];
     const int mu0 = bs.orb0[Iin], nI = bs.orb0[Iin + 1] - mu0;
@@ -662,6 +666,7 @@ __global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long
                 s_sum[wv][1][e] = dn[m][i];
             }
         }
+    wave_lds_sync();  // other lanes' sums are read below
     const int mu0 = bs.orb0[I], nI = bs.orb0[I + 1] - mu0;
     const int nu0 = bs.orb0[J], nJ = bs.orb0[J + 1] - nu0;
     const size_t nn = (size_t)norb * norb;

@@ -40,6 +40,16 @@ struct MM<float> {
     static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
 };
 
+// Make this wave's LDS stores visible to its other lanes' later LDS loads:
+// release fence, wave barrier, acquire fence (for exchanges inside one wave
+// where some waves of the workgroup may already have exited).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // real spherical harmonics (no Condon-Shortley phase)
 #define Y_C00 0.28209479177387814
 #define Y_C1 0.4886025119029199

@@ -167,3 +167,24 @@ class BruteCell:
     def energy(self, V, D, positions=None):
         phi = self.phi_all(positions)
         return self.dV * float(np.dot(V, self.rho(D, phi)))
+
+    def support_stats(self):
+        """sum_g n_g and sum_g n_g^2, n_g = orbitals of the atoms with at
+        least one image strictly inside the atom's cutoff (its largest
+        radial cutoff) at mesh point g: every lattice vector of a cube."""
+        w = self.w
+        pos = np.asarray(w.positions, dtype=np.float64)
+        rcmax = max(o[1] for lst in self.orbs for o in lst)
+        nimg = int(math.ceil(rcmax / np.min(np.linalg.norm(self.lat, axis=1)))) + 1
+        n = np.zeros(len(self.points), dtype=np.int64)
+        for I, s in enumerate(w.species_of_atom):
+            rc = max(o[1] for o in self.orbs[s])
+            hit = np.zeros(len(self.points), dtype=bool)
+            for n1 in range(-nimg, nimg + 1):
+                for n2 in range(-nimg, nimg + 1):
+                    for n3 in range(-nimg, nimg + 1):
+                        T = n1 * self.lat[0] + n2 * self.lat[1] + n3 * self.lat[2]
+                        d = self.points - pos[I] - T
+                        hit |= np.sqrt(np.sum(d * d, axis=1)) < rc
+            n += hit * len(self.orbs[s])
+        return float(n.sum()), float((n * n).sum())

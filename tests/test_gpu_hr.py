@@ -399,3 +399,53 @@ def test_forceR_si64_sampled(oracle_mod, torch_dev):
     e = _rel_max(F[atoms], ref)
     _say(f"  si64 forceR atoms {atoms}: rel {e:.2e}")
     assert e <= TOL
+
+
+def _subset_dropping_partners(full, seed):
+    # a shuffled subset of the lattice list in which some R keep their -R
+    # partner and some do not (and R = 0 may be missing): the blocks of
+    # every unlisted R count as zero on both sides
+    rng = np.random.default_rng(seed)
+    sub = full[rng.permutation(len(full))[: (2 * len(full)) // 3]]
+    keys = {tuple(r) for r in sub}
+    lone = sum(1 for r in sub if tuple(-r) not in keys)
+    paired = sum(1 for r in sub if tuple(-r) in keys and any(r))
+    return sub, lone, paired
+
+
+@pytest.mark.parametrize("make", [_triclinic_two_species, _long_range_tiny])
+def test_rhoR_forceR_partner_subset(oracle_mod, torch_dev, make):
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = make()
+    plan = g.GintPlan.from_workload(w)
+    sub, lone, paired = _subset_dropping_partners(plan.HR_lattice(), 21)
+    _say(f"case rhoR/forceR subset {w.name}: {len(sub)} R, {lone} without -R, {paired} with it")
+    assert lone > 0 and paired > 0
+    DR = _random_DR(len(sub), plan.norb, 22)
+    o = oracle_mod.Oracle.from_workload(w)
+    rho = plan.build_rhoR(sub, _dev(torch, dev, DR)).cpu().numpy()
+    er = _rel_l2(rho, o.rhoR(sub, DR))
+    V = _dev(torch, dev, w.V)
+    F = plan.forceR(V, sub, _dev(torch, dev, DR)).cpu().numpy()
+    eF = _rel_max(F, o.forceR(w.V, sub, DR))
+    _say(f"  rho rel-L2 {er:.2e}  dE/dR rel {eF:.2e}")
+    assert er <= TOL and eF <= TOL
+
+
+def test_rhoR_fp32_si64_sampled(oracle_mod, torch_dev):
+    # FP32 plan at realistic atoms per batch: T_a accumulates over a whole
+    # row of blocks on the FP32 matrix cores
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si64_dzp()
+    plan = g.GintPlan.from_workload(w, "fp32")
+    R = plan.HR_lattice()
+    DR = _random_DR(len(R), plan.norb, 23)
+    rho = plan.build_rhoR(R, _dev(torch, dev, DR)).cpu().numpy()
+    idx = np.random.default_rng(24).choice(w.ngrid, 4000, replace=False)
+    e = _rel_l2(rho[idx], oracle_mod.Oracle.from_workload(w).rhoR(R, DR, idx))
+    _say(f"  fp32 si64 rhoR sampled: rel-L2 {e:.2e}")
+    assert e <= 1e-5

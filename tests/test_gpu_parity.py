@@ -286,3 +286,85 @@ def test_H_rho_force_one_call(oracle_mod, torch_dev, make, precision):
     er = _rel_l2(rho1[idx], o.rho(w.D, idx))
     _say(f"  rho sampled {er:.2e}")
     assert er <= (TOL if precision == "fp64" else 1e-6)
+
+
+def test_H_rho_force_multislab(oracle_mod, torch_dev):
+    # the fused call with a tiny H partial budget: one fused pass per H slab,
+    # each reduction after the first adds into H; bitwise the separate calls
+    # (which split H the same way) and within 1e-10 of the oracle
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _triclinic_two_species()
+    plan = g.GintPlan.from_workload(w)
+    plan.tune((4, 4, 2), 1)
+    nslab = plan.work()["nslab"]
+    _say(f"case H_rho_force multi-slab: {nslab} slabs")
+    assert nslab > 1
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    H, rho, F = (t.cpu().numpy() for t in plan.H_rho_force(V, D))
+    Hs = plan.build_H(V).cpu().numpy()
+    rs, Fs = (t.cpu().numpy() for t in plan.rho_force(V, D))
+    assert np.array_equal(H, Hs) and np.array_equal(rho, rs) and np.array_equal(F, Fs)
+    _compare_full(oracle_mod, w, H, rho, F)
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _triclinic_two_species, gi.si64_dzp])
+def test_support_counts_match_oracle(oracle_mod, torch_dev, make):
+    # the roofline's work counts: the GPU's sum_g n_g and sum_g n_g^2 (from
+    # its batch lists) equal the oracle's per-point count exactly
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = make()
+    plan = g.GintPlan.from_workload(w)
+    wk = plan.work()
+    s1, s2 = oracle_mod.Oracle.from_workload(w).support_stats()
+    _say(f"case support counts {w.name}: GPU {wk['sum_ng']:.0f} {wk['sum_ng2']:.0f} oracle {s1:.0f} {s2:.0f}")
+    assert wk["sum_ng"] == s1 and wk["sum_ng2"] == s2
+
+
+def test_broken_plan_after_failed_retune(torch_dev):
+    # a re-tune that fails and whose restore fails too leaves the plan
+    # unusable: calls return GINT_ESTATE, destroy still releases it
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si8_sz()
+    plan = g.GintPlan.from_workload(w)
+    lib = g.load_library()
+    assert lib.gint_test_fail_rebuilds(2) == 0
+    try:
+        with pytest.raises(g.GintError) as e:
+            plan.tune((4, 2, 4))
+        assert e.value.status == g.GINT_ENOMEM
+    finally:
+        lib.gint_test_fail_rebuilds(0)
+    V = _dev(torch, dev, w.V)
+    with pytest.raises(g.GintError) as e2:
+        plan.build_H(V)
+    assert e2.value.status == g.GINT_ESTATE
+    assert "gint_plan_tune" in lib.gint_last_error().decode()
+    plan.close()  # gint_plan_destroy on a broken plan frees it
+
+
+def test_failed_retune_keeps_plan_usable(oracle_mod, torch_dev):
+    # one injected failure: the re-tune fails, the previous shape is restored
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = gi.si8_sz()
+    plan = g.GintPlan.from_workload(w)
+    before = plan.work()["batch"]
+    lib = g.load_library()
+    assert lib.gint_test_fail_rebuilds(1) == 0
+    try:
+        with pytest.raises(g.GintError):
+            plan.tune((4, 2, 4))
+    finally:
+        lib.gint_test_fail_rebuilds(0)
+    assert plan.work()["batch"] == before
+    V = _dev(torch, dev, w.V)
+    H = plan.build_H(V).cpu().numpy()
+    o = oracle_mod.Oracle.from_workload(w)
+    assert _rel_max(H, o.H(w.V)) <= TOL

@@ -70,3 +70,13 @@ def test_bruteforce_force_by_differences(oracle_mod, make):
             p2[I, k] -= h
             fd = (bf.energy(w.V, w.D, p1) - bf.energy(w.V, w.D, p2)) / (2 * h)
             assert abs(F[I, k] - fd) <= 1e-7 * max(1.0, np.max(np.abs(F)))
+
+
+@pytest.mark.parametrize("make", [_two_atom_dzp, _tiny_long_range, _si8_coarse])
+def test_support_stats_bruteforce(oracle_mod, make):
+    # the work counts behind the roofline (sum_g n_g, sum_g n_g^2) are exact
+    # integers: the oracle's count equals the brute-force count
+    w = make()
+    s1, s2 = oracle_mod.Oracle.from_workload(w).support_stats()
+    b1, b2 = BruteCell(w).support_stats()
+    assert (s1, s2) == (b1, b2)
