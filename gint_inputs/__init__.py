@@ -151,6 +151,35 @@ def dzp_species(rc: float = 8.0, dr: float = 0.01) -> Species:
     )
 
 
+def si_projector_species(rb: float = 2.2, gamma: float = 0.9, dr: float = 0.01) -> Species:
+    """Synthetic nonlocal projectors of one Si atom: one radial each for
+    l = 0, 1, 2, b_l(r) = r^l exp(-gamma r^2) (1 - (r/rb)^2)^2 for r < rb
+    (9 projectors per atom), in the same tabulated form as the orbitals."""
+    return Species([nao_like_radial(l, gamma, rb, dr) for l in (0, 1, 2)])
+
+
+def lebedev_110() -> np.ndarray:
+    """The 110-point Lebedev-Laikov rule on the unit sphere (degree 17),
+    from SciPy: rows (x, y, z, w), weights summing to 4 pi."""
+    from scipy.integrate import lebedev_rule
+
+    x, w = lebedev_rule(17)
+    out = np.ascontiguousarray(np.concatenate([x.T, w[:, None]], axis=1), dtype=np.float64)
+    assert out.shape == (110, 4)
+    return out
+
+
+def gauss_legendre_01(n: int = 140) -> np.ndarray:
+    """n-point Gauss-Legendre rule mapped to [0, 1]: rows (x, q)."""
+    t, w = np.polynomial.legendre.leggauss(n)
+    return np.ascontiguousarray(np.stack([(t + 1.0) / 2.0, w / 2.0], axis=1), dtype=np.float64)
+
+
+def vector_potential(seed: int = 6, scale: float = 0.5) -> np.ndarray:
+    """A seeded vector potential A (bohr^-1), components U(-scale, scale)."""
+    return np.random.default_rng(seed).uniform(-scale, scale, 3)
+
+
 # --------------------------------------------------------------------------
 # cells
 

@@ -73,6 +73,12 @@ def _load():
     lib.oracle_rho.argtypes = [P, dp, ctypes.c_long, lp, dp]
     lib.oracle_force.argtypes = [P, dp, dp, ctypes.c_int, ip, ctypes.c_long, lp, dp]
     lib.oracle_DK_rows.argtypes = [P, dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, lp, dp]
+    lib.oracle_proj_create.restype = P
+    lib.oracle_proj_create.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp, dp, ctypes.c_int, ip]
+    lib.oracle_proj_destroy.argtypes = [P]
+    lib.oracle_proj_row0.restype = ctypes.c_int
+    lib.oracle_proj_row0.argtypes = [P, P, ctypes.c_int]
+    lib.oracle_psibeta.argtypes = [P, P, ctypes.c_int, dp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_int, dp]
     lib.oracle_set_positions.argtypes = [P, dp]
     lib.oracle_support_stats.argtypes = [P, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -301,6 +307,42 @@ class Oracle:
     def DK(self, W=None) -> np.ndarray:
         """The whole 3 x norb x norb moving-basis matrix (see DK_rows)."""
         return self.DK_rows(W, 0, self.natom)
+
+    def psibeta(self, proj_species, ang, rq, A, I0: int = 0, I1: Optional[int] = None) -> np.ndarray:
+        """Spherical-grid projector overlaps (Sec. 3.3.2) for the projectors
+        of atoms I0..I1-1: Q[p, mu] = <phit_mu | e^{-i A.r} | beta_p> on the
+        product grid (angular rule ``ang`` rows (x, y, z, w); radial rule
+        ``rq`` rows (x, q) on [0, 1]) centred on each projector's atom.
+        ``proj_species``: one Species of projector radials per orbital
+        species (may be empty).  Complex (rows, norb)."""
+        I1 = self.natom if I1 is None else I1
+        l, nr, dr, d0, drc, fs, begin = [], [], [], [], [], [], [0]
+        for sp in proj_species:
+            for r in sp.radials:
+                l.append(r.l)
+                nr.append(r.nr)
+                dr.append(r.dr)
+                d0.append(r.dfdr0)
+                drc.append(r.dfdrc)
+                fs.append(np.asarray(r.f, dtype=np.float64))
+            begin.append(len(l))
+        k = [np.asarray(l, dtype=np.int32), np.asarray(nr, dtype=np.int32), np.asarray(dr, dtype=np.float64),
+             np.concatenate(fs) if fs else np.zeros(1), np.asarray(d0, dtype=np.float64),
+             np.asarray(drc, dtype=np.float64), np.asarray(begin, dtype=np.int32)]
+        pp = self._lib.oracle_proj_create(len(l), _ip(k[0]), _ip(k[1]), _dp(k[2]), _dp(k[3]), _dp(k[4]),
+                                          _dp(k[5]), len(proj_species), _ip(k[6]))
+        try:
+            r0 = self._lib.oracle_proj_row0(self._ctx, pp, int(I0))
+            r1 = self._lib.oracle_proj_row0(self._ctx, pp, int(I1))
+            ang = np.ascontiguousarray(ang, dtype=np.float64)
+            rq = np.ascontiguousarray(rq, dtype=np.float64)
+            A = np.ascontiguousarray(A, dtype=np.float64)
+            out = np.zeros((r1 - r0, self.norb, 2))
+            self._lib.oracle_psibeta(self._ctx, pp, int(ang.shape[0]), _dp(ang), int(rq.shape[0]), _dp(rq), _dp(A),
+                                     int(I0), int(I1), _dp(out))
+        finally:
+            self._lib.oracle_proj_destroy(pp)
+        return out[..., 0] + 1j * out[..., 1]
 
     def energy(self, V, D) -> float:
         return float(self.dV * np.dot(np.asarray(V, dtype=np.float64), self.rho(D)))

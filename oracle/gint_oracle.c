@@ -1007,6 +1007,159 @@ void oracle_DK_rows(void *p, const double *W, int I0, int I1, long npts, const l
     }
 }
 
+/* ---------------------------------------------------------------------- */
+/* Spherical-grid projector overlaps (Sec. 3.3.2, "Spherical Grid          */
+/* Integration for Nonlocal Potentials"; the velocity-gauge projector      */
+/* overlap of the nonlocal pseudopotential, Sec. 2.2):                     */
+/*                                                                         */
+/*   Q_{p,mu}(A) = < phit_mu | e^{-i A.r} | beta_p >                       */
+/*              ~= sum_{i,j} W_ij phit_mu(tau_I + x_ij) e^{-i A.(tau_I + x_ij)} */
+/*                 beta_p(x_ij),                                           */
+/*                                                                         */
+/* on the product grid centred on the projector's atom I: x_ij = r_i u_j,  */
+/* r_i = rb x_i, W_ij = rb q_i r_i^2 w_j, with (u_j, w_j) the caller's     */
+/* angular rule on the unit sphere, (x_i, q_i) its radial rule on [0, 1]   */
+/* and rb the largest projector cutoff of atom I's species.  beta_p(x) =   */
+/* b(|x|) Y_lm(x/|x|), b the clamped cubic spline of the projector table   */
+/* (strict cutoff, r = 0 limits as for the orbitals); phit is the orbital  */
+/* folded over lattice images; tau_I the position as given.                */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int nrad;
+    orad *rad;
+    int nspecies;
+    int *sp_begin; /* projector radials of species s: sp_begin[s] .. sp_begin[s+1]-1 */
+    int *sp_nproj; /* projectors per species */
+    double *sp_rb; /* largest projector cutoff per species */
+} oproj;
+
+void *oracle_proj_create(int nrad, const int *rad_l, const int *rad_nr, const double *rad_dr, const double *rad_f,
+                         const double *rad_d0, const double *rad_drc, int nspecies, const int *sp_rad_begin)
+{
+    oproj *P = (oproj *)calloc(1, sizeof(oproj));
+    P->nrad = nrad;
+    P->rad = (orad *)calloc(nrad > 0 ? nrad : 1, sizeof(orad));
+    long off = 0;
+    for (int k = 0; k < nrad; ++k) {
+        orad *R = &P->rad[k];
+        R->l = rad_l[k];
+        R->nr = rad_nr[k];
+        R->dr = rad_dr[k];
+        R->rc = (R->nr - 1) * R->dr;
+        R->y = (double *)malloc(sizeof(double) * R->nr);
+        R->m2 = (double *)malloc(sizeof(double) * R->nr);
+        memcpy(R->y, rad_f + off, sizeof(double) * R->nr);
+        spline_moments(R->nr, R->dr, R->y, rad_d0[k], rad_drc[k], R->m2);
+        off += R->nr;
+    }
+    P->nspecies = nspecies;
+    P->sp_begin = (int *)malloc(sizeof(int) * (nspecies + 1));
+    P->sp_nproj = (int *)calloc(nspecies, sizeof(int));
+    P->sp_rb = (double *)calloc(nspecies, sizeof(double));
+    memcpy(P->sp_begin, sp_rad_begin, sizeof(int) * (nspecies + 1));
+    for (int s = 0; s < nspecies; ++s)
+        for (int k = sp_rad_begin[s]; k < sp_rad_begin[s + 1]; ++k) {
+            P->sp_nproj[s] += 2 * rad_l[k] + 1;
+            if (P->rad[k].rc > P->sp_rb[s])
+                P->sp_rb[s] = P->rad[k].rc;
+        }
+    return P;
+}
+
+void oracle_proj_destroy(void *p)
+{
+    oproj *P = (oproj *)p;
+    if (!P)
+        return;
+    for (int k = 0; k < P->nrad; ++k) {
+        free(P->rad[k].y);
+        free(P->rad[k].m2);
+    }
+    free(P->rad);
+    free(P->sp_begin);
+    free(P->sp_nproj);
+    free(P->sp_rb);
+    free(P);
+}
+
+/* projectors of the atoms before I (row offset of atom I in Q) */
+int oracle_proj_row0(void *pc, void *pp, int I)
+{
+    const octx *c = (const octx *)pc;
+    const oproj *P = (const oproj *)pp;
+    int n = 0;
+    for (int J = 0; J < I; ++J)
+        n += P->sp_nproj[c->spc[J]];
+    return n;
+}
+
+/* Rows of Q for the projectors of atoms I0..I1-1 (atoms in input order,
+   within an atom the projector radials by increasing l, stable, then m):
+   out is (rows) x norb complex values as (re, im) pairs, overwritten.
+   Parallel over the projector atoms. */
+void oracle_psibeta(void *pc, void *pp, int nang, const double *ang, int nrq, const double *rq, const double *A,
+                    int I0, int I1, double *out)
+{
+    const octx *c = (const octx *)pc;
+    const oproj *P = (const oproj *)pp;
+    const int norb = c->norb;
+    const int row0 = oracle_proj_row0(pc, pp, I0);
+    const int nrow = oracle_proj_row0(pc, pp, I1) - row0;
+    memset(out, 0, sizeof(double) * 2 * (size_t)nrow * norb);
+#pragma omp parallel
+    {
+        double *phi = (double *)malloc(sizeof(double) * (norb > 0 ? norb : 1));
+        double *beta = (double *)malloc(sizeof(double) * 64);
+#pragma omp for schedule(dynamic, 1)
+        for (int I = I0; I < I1; ++I) {
+            const int s = c->spc[I];
+            const int np = P->sp_nproj[s];
+            if (np == 0)
+                continue;
+            const double rb = P->sp_rb[s];
+            double *rows = out + 2 * (size_t)(oracle_proj_row0(pc, pp, I) - row0) * norb;
+            for (int i = 0; i < nrq; ++i) {
+                const double r = rb * rq[2 * i];
+                const double wr = rb * rq[2 * i + 1] * r * r;
+                for (int j = 0; j < nang; ++j) {
+                    const double x[3] = {r * ang[4 * j], r * ang[4 * j + 1], r * ang[4 * j + 2]};
+                    const double W = wr * ang[4 * j + 3];
+                    double pt[3];
+                    for (int k = 0; k < 3; ++k)
+                        pt[k] = c->pos[3 * I + k] + x[k];
+                    const double th = -(A[0] * pt[0] + A[1] * pt[1] + A[2] * pt[2]);
+                    const double cr = W * cos(th), ci = W * sin(th);
+                    /* projectors at x, in projector order */
+                    int q = 0;
+                    for (int l = 0; l <= 2; ++l)
+                        for (int k = P->sp_begin[s]; k < P->sp_begin[s + 1]; ++k) {
+                            if (P->rad[k].l != l)
+                                continue;
+                            for (int m = -l; m <= l; ++m)
+                                orbital_value(&P->rad[k], m, x, &beta[q++], NULL);
+                        }
+                    /* every folded orbital at the point (zero where no image reaches) */
+                    for (int J = 0; J < c->natom; ++J)
+                        (void)atom_phi(c, J, pt, phi + c->atom_orb0[J], NULL);
+                    for (int a = 0; a < np; ++a) {
+                        if (beta[a] == 0.0)
+                            continue;
+                        double *row = rows + 2 * (size_t)a * norb;
+                        const double br = cr * beta[a], bi = ci * beta[a];
+                        for (int mu = 0; mu < norb; ++mu) {
+                            row[2 * mu] += br * phi[mu];
+                            row[2 * mu + 1] += bi * phi[mu];
+                        }
+                    }
+                }
+            }
+        }
+        free(phi);
+        free(beta);
+    }
+}
+
 /* Move atoms (for finite differences and symmetry pins). */
 void oracle_set_positions(void *p, const double *pos)
 {
