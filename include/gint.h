@@ -266,6 +266,22 @@ gint_status gint_forceR(gint_plan plan, const double *V_dev, int nR, const int *
 gint_status gint_HR_to_Hk(gint_plan plan, int nR, const int *R, const double *HR_dev, int nk, const double *kfrac,
                           double *Hk_dev);
 
+/* gint_HR_to_Hk for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, output and conventions, and no device allocation in
+ * the call.  Its workspace (the phase table and the staged R and kfrac) is
+ * a fixed device array of the library, about 1.3 MiB, that each GPU holds
+ * from the first call on it until the process ends; the phases are formed
+ * on the device (FP64 sincospi) instead of the host, so results agree with
+ * gint_HR_to_Hk to rounding.  Limits: nR <= 8192, nk <= 8192 and
+ * nR * nk <= 65536, else GINT_EINVAL (nothing enqueued).  Every call on a
+ * GPU shares that GPU's workspace: calls that overlap on one GPU (several
+ * streams or threads) race and must be serialised by the caller.
+ * Synchronises the plan's stream once (after staging R and kfrac), then
+ * enqueues the sums and returns. */
+gint_status gint_HR_to_Hk_noalloc(gint_plan plan, int nR, const int *R, const double *HR_dev, int nk,
+                                  const double *kfrac, double *Hk_dev);
+
 /* The lattice vectors R = T_b - T_a over every pair of atom images (a, b)
  * that reach a common mesh batch, for the current positions: every R with
  * a non-zero H(R) block is among them (a superset; |n_k| <= 31 only).

@@ -34,7 +34,7 @@ EXPORTS = (
     "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk", "gint_forceR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
-    "gint_plan_atom_order", "gint_test_fail_rebuilds",
+    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_HR_to_Hk_noalloc",
 )
 KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
            "H_rho_force", "HR")
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     lib.gint_forceR.restype = ctypes.c_int
     lib.gint_HR_to_Hk.argtypes = [P, ctypes.c_int, ip, P, ctypes.c_int, dp, P]
     lib.gint_HR_to_Hk.restype = ctypes.c_int
+    lib.gint_HR_to_Hk_noalloc.argtypes = [P, ctypes.c_int, ip, P, ctypes.c_int, dp, P]
+    lib.gint_HR_to_Hk_noalloc.restype = ctypes.c_int
     lib.gint_build_rhoR.argtypes = [P, ctypes.c_int, ip, P, P]
     lib.gint_build_rhoR.restype = ctypes.c_int
     lib.gint_HR_lattice.argtypes = [P, ctypes.c_int, ip, ip]
@@ -378,9 +380,11 @@ class GintPlan:
         _check(self._lib.gint_forceR(self._handle(), vp, nR, Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), dp, op))
         return out
 
-    def HR_to_Hk(self, R, HR, kfrac, out=None):
+    def HR_to_Hk(self, R, HR, kfrac, out=None, noalloc: bool = False):
         """H(k) = sum_q e^{i 2 pi kappa.n_q} H(R_q) for fractional k-points
-        kfrac (nk x 3): a complex128 tensor (nk x norb x norb)."""
+        kfrac (nk x 3): a complex128 tensor (nk x norb x norb).  noalloc:
+        call gint_HR_to_Hk_noalloc (no device allocation in the library;
+        ``out`` should then be given)."""
         import numpy as np
         import torch
 
@@ -392,9 +396,9 @@ class GintPlan:
             out = torch.empty((nk, self.norb, self.norb), dtype=torch.complex128, device=HR.device)
         if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() != nk * self.norb * self.norb:
             raise TypeError("out must be a contiguous complex128 tensor of nk*norb*norb elements")
-        _check(self._lib.gint_HR_to_Hk(self._handle(), nR, Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), hp, nk,
-                                       kf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                       ctypes.c_void_p(out.data_ptr())))
+        fn = self._lib.gint_HR_to_Hk_noalloc if noalloc else self._lib.gint_HR_to_Hk
+        _check(fn(self._handle(), nR, Rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), hp, nk,
+                  kf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(out.data_ptr())))
         return out
 
     def build_rhoR(self, R, DR, out=None):

@@ -1354,6 +1354,27 @@ gint_status gint_HR_to_Hk(gint_plan p, int nR, const int *R, const double *HR_de
     return GINT_OK;
 }
 
+gint_status gint_HR_to_Hk_noalloc(gint_plan p, int nR, const int *R, const double *HR_dev, int nk,
+                                  const double *kfrac, double *Hk_dev)
+{
+    STCHK(check_plan(p));
+    if (!R || !kfrac || !HR_dev || !Hk_dev)
+        return fail(GINT_EINVAL, "R and kfrac must be non-NULL host arrays, HR and Hk non-NULL device pointers");
+    if (nR < 1 || nk < 1)
+        return fail(GINT_EINVAL, "nR = %d and nk = %d must be >= 1", nR, nk);
+    if (nR > kHkNaMaxR || nk > kHkNaMaxK || (long long)nR * nk > kHkNaMaxPhase)
+        return fail(GINT_EINVAL,
+                    "gint_HR_to_Hk_noalloc: nR = %d, nk = %d exceed its fixed workspace (nR <= %d, nk <= %d, "
+                    "nR * nk <= %d); use gint_HR_to_Hk",
+                    nR, nk, kHkNaMaxR, kHkNaMaxK, kHkNaMaxPhase);
+    for (int i = 0; i < 3 * nk; ++i)
+        if (!std::isfinite(kfrac[i]))
+            return fail(GINT_EINVAL, "kfrac has non-finite entries");
+    HIPCHK(hipSetDevice(p->device));
+    HIPCHK(Hk_noalloc(p->stream, p->device, (long long)p->norb * p->norb, nR, R, nk, kfrac, HR_dev, Hk_dev));
+    return GINT_OK;
+}
+
 gint_status gint_forceR(gint_plan p, const double *V_dev, int nR, const int *R, const double *DR_dev,
                         double *dEdR_dev)
 {

@@ -22,7 +22,9 @@
 // blocks are added into the output with FP64 atomics instead (k_HR_batch;
 // the order of the additions is then not fixed).
 #include <hip/hip_runtime.h>
+
 #include <hipcub/hipcub.hpp>
+#include <mutex>
 
 #include "gint_device.h"
 
@@ -794,6 +796,78 @@ hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double 
         return hipSuccess;
     hipLaunchKernelGGL(k_Hk, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s, nel, nR, nk, ph, HR, Hk);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// H(k) without device allocations (gint_HR_to_Hk_noalloc).  The phase table
+// and the staged inputs (kappa, n) live in one file-scope device array, one
+// copy per GPU.  Host code never uses the array's name as an address: the
+// address of each device's copy comes from hipGetSymbolAddress, looked up
+// once per device (with that device current) and kept in g_scratch_ptr.
+// Layout: [phases: 2 kHkNaMaxPhase doubles][kappa: 3 kHkNaMaxK doubles]
+//         [n: 3 kHkNaMaxR ints].  Every call overwrites what it reads, so
+// nothing needs clearing; calls that overlap on one GPU race on the array.
+constexpr size_t kScrPh = 0, kScrKf = kScrPh + sizeof(double) * 2 * kHkNaMaxPhase,
+                 kScrR = kScrKf + sizeof(double) * 3 * kHkNaMaxK, kScrBytes = kScrR + sizeof(int) * 3 * kHkNaMaxR;
+static __device__ __align__(256) unsigned char scratch[kScrBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// (cos, sin) of 2 pi (kappa_k . n_q) reduced to [0, 1) turns, for every (k, q)
+__global__ __launch_bounds__(256) void k_Hk_phases(int nk, int nR, const double *__restrict__ kf,
+                                                   const int *__restrict__ n, double *__restrict__ ph)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nk * nR)
+        return;
+    const int k = i / nR, q = i - k * nR;
+    double t = 0.0;
+    for (int d = 0; d < 3; ++d)
+        t += kf[3 * k + d] * (double)n[3 * q + d];
+    t -= floor(t);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    ph[2 * (size_t)i] = cs;
+    ph[2 * (size_t)i + 1] = sn;
+}
+
+hipError_t Hk_noalloc(hipStream_t s, int device, long long nel, int nR, const int *R, int nk, const double *kfrac,
+                      const double *HR, double *Hk)
+{
+    if (device < 0 || device >= kMaxScratchDevices || nR > kHkNaMaxR || nk > kHkNaMaxK ||
+        (long long)nR * nk > kHkNaMaxPhase)
+        return hipErrorInvalidValue;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            // the caller made `device` current
+            const hipError_t e = hipGetSymbolAddress((void **)&g_scratch_ptr[device], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                g_scratch_ptr[device] = nullptr;
+                return e;
+            }
+        }
+        base = g_scratch_ptr[device];
+    }
+    double *ph = reinterpret_cast<double *>(base + kScrPh);
+    double *kf = reinterpret_cast<double *>(base + kScrKf);
+    int *n = reinterpret_cast<int *>(base + kScrR);
+    hipError_t e = hipMemcpyAsync(kf, kfrac, sizeof(double) * 3 * nk, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(n, R, sizeof(int) * 3 * nR, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // the caller's host arrays outlive the copies
+    if (e != hipSuccess)
+        return e;
+    const int np = nk * nR;
+    hipLaunchKernelGGL(k_Hk_phases, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, nk, nR, kf, n, ph);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_Hk(s, nel, nR, nk, ph, HR, Hk);
 }
 
 template <typename T, int P>

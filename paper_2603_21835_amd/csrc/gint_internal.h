@@ -159,6 +159,13 @@ hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, c
                              const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
                              const double *DR, double *rho);
 hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double *ph, const double *HR, double *Hk);
+// limits of the allocation-free H(k) (its workspace is a fixed device array)
+constexpr int kHkNaMaxPhase = 65536, kHkNaMaxK = 8192, kHkNaMaxR = 8192;
+// H(k) with the phases and staged inputs in the device array of gint_hr.hip
+// (no device allocation; synchronises s once after staging R and kfrac);
+// hipErrorInvalidValue beyond the limits above
+hipError_t Hk_noalloc(hipStream_t s, int device, long long nel, int nR, const int *R, int nk, const double *kfrac,
+                      const double *HR, double *Hk);
 hipError_t launch_forceR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr,
                                const int *img_atom, const int *img, const Basis &b, const int *wsh, const HRMap &m,
                                int norb, const double *DR, const double *W, double wscale, double *Fimg);
