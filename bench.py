@@ -233,10 +233,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
     ap.add_argument("--only", default=None,
-                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR", "forceR"],
+                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR", "forceR", "DK"],
                     help="time one contraction only (short profiler runs); HR: the lattice-vector blocks "
                          "H(R) for every R of gint_HR_lattice; rhoR: rho from random lattice-vector density "
-                         "matrices D(R) over the same R; forceR: dE/dR for those D(R)")
+                         "matrices D(R) over the same R; forceR: dE/dR for those D(R); DK: the moving-basis "
+                         "matrix <phi_mu|V|d phi_nu/d tau_K> (gint_build_DK)")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--serial", action="store_true",
@@ -302,7 +303,13 @@ def main():
         DRbuf = torch.randn((len(R_list), plan.norb, plan.norb), dtype=torch.float64, device=dev,
                             generator=gen) / plan.norb
 
+    if args.only == "DK":
+        DKbuf = torch.empty((3, plan.norb, plan.norb), dtype=torch.float64, device=dev)
+
     def step():
+        if args.only == "DK":
+            plan.build_DK(V, out=DKbuf)
+            return
         if args.only == "HR":
             plan.build_HR(V, R_list, out=HRbuf)
             return
@@ -348,7 +355,9 @@ def main():
     s1, s2 = work["sum_ng"], work["sum_ng2"]
     # algorithmic work per step (per unit: one mesh point with n_g orbitals)
     flops = {"H_blocks": 2 * s2, "rho": 2 * s2 + 2 * s1, "force": 2 * s2 + 6 * s1,
-             "rho_force": 2 * s2 + 8 * s1, "H_rho_force": 4 * s2 + 8 * s1, "HR": 2 * s2}
+             "rho_force": 2 * s2 + 8 * s1, "H_rho_force": 4 * s2 + 8 * s1, "HR": 2 * s2,
+             # three non-symmetric products phi (d_c phi)^T over the supported orbitals
+             "DK": 6 * s2}
     # the H reduction moves every block partial once and writes H's blocks
     hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
               "H_fill": 8 * plan.norb ** 2 * (len(R_list) if args.only == "HR" else 1)}
@@ -447,6 +456,10 @@ def main():
                                      f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the lattice-vector "
                                      f"blocks H(R) of {len(R_list)} lattice vectors (gint_build_HR)")
         out["config"]["n_R"] = len(R_list)
+    if args.only == "DK":
+        out["config"]["workload"] = (f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh "
+                                     f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the moving-basis "
+                                     "matrix DK[c][mu][nu] = <phi_mu|V|d phi_nu/d tau_K> (gint_build_DK)")
     if args.only in ("rhoR", "forceR"):
         what = "rho" if args.only == "rhoR" else "dE/dR"
         call = "gint_build_rhoR" if args.only == "rhoR" else "gint_forceR"

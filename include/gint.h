@@ -156,6 +156,28 @@ gint_status gint_build_H(gint_plan plan, const double *V_dev, double *H_dev);
  * derivative of sum_g w_g rho_g with respect to D. */
 gint_status gint_build_H_weighted(gint_plan plan, const double *w_dev, double *H_dev);
 
+/* Moving-basis matrix of Sec. 2.3 (Ehrenfest dynamics, D_K equation) at the
+ * Gamma point, on the mesh, with an optional weight W:
+ *   DK_c,mu,nu = < phit_mu | W | d phit_nu / d tau_K >_c,  K = atom of nu,
+ *              = -dV sum_g W_g phit_mu(r_g) d/dr_c phit_nu(r_g),  c = x, y, z
+ * (an orbital depends on its centre tau_K only through r - tau_K; at k = 0
+ * the lattice sum of the D_K equation folds the orbital).  D_K,mu,nu is zero
+ * unless nu is on K, so one array holds every D_K.  With W = 1 the mesh
+ * overlap S_grid (gint_build_H_weighted with w = dV) has the derivatives
+ *   dS_mu,nu / dtau_K = DK[.][nu][mu] (mu on K) + DK[.][mu][nu] (nu on K),
+ * and P_mu,nu = -i sum_K tau_dot_K . D_K,mu,nu is the P matrix of the TDKS
+ * equation with moving orbitals.  With W = V,
+ *   dE/dR_I = sum_{mu on I} sum_nu (D + D^T)_mu,nu DK[.][nu][mu]
+ * for E = dV sum_g V_g rho_g (gint_force).
+ *   W_dev   device, N1*N2*N3 doubles, or NULL for W = 1
+ *   DK_dev  device, 3*norb*norb doubles: DK[c][mu][nu] at
+ *           (c*norb + mu)*norb + nu, input orbital order; overwritten.
+ * One workgroup per atom pair within reach of each other walks the mesh
+ * batches the two share in batch order and keeps the pair's sums on the
+ * FP64 matrix cores; the plan's precision does not apply (FP64 always);
+ * repeatable bits. */
+gint_status gint_build_DK(gint_plan plan, const double *W_dev, double *DK_dev);
+
 /* rho(r_g) of Sec. 3.3.1 (Gamma point, images folded):
  *   D_dev    device, norb*norb doubles, row-major, used as given (a
  *            non-symmetric D acts through its symmetric part)
@@ -305,7 +327,8 @@ enum {
     GINT_K_RHO_FORCE = 8, /* rho and force contraction in one pass                  */
     GINT_K_H_RHO_FORCE = 9, /* H blocks, rho and force in one pass (gint_H_rho_force) */
     GINT_K_HR = 10,       /* lattice-vector blocks H(R) (gint_build_HR)            */
-    GINT_NKERNEL = 11
+    GINT_K_DK = 11,       /* moving-basis matrix (gint_build_DK)                    */
+    GINT_NKERNEL = 12
 };
 
 /* Enable (1) or disable (0) timing: each kernel launch of later calls is

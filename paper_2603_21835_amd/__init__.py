@@ -34,10 +34,10 @@ EXPORTS = (
     "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk", "gint_forceR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
-    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_HR_to_Hk_noalloc",
+    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_build_DK", "gint_HR_to_Hk_noalloc",
 )
 KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
-           "H_rho_force", "HR")
+           "H_rho_force", "HR", "DK")
 
 
 class GintError(RuntimeError):
@@ -93,7 +93,7 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_tune.argtypes = [P, ip, ctypes.c_longlong]
     lib.gint_plan_set_stream.restype = st
     lib.gint_plan_set_stream.argtypes = [P, P]
-    for name in ("gint_build_H", "gint_build_H_weighted", "gint_build_rho"):
+    for name in ("gint_build_H", "gint_build_H_weighted", "gint_build_rho", "gint_build_DK"):
         getattr(lib, name).restype = st
         getattr(lib, name).argtypes = [P, P, P]
     for name in ("gint_force", "gint_force_weighted"):
@@ -331,6 +331,20 @@ class GintPlan:
         op = _dev_ptr(out, self.norb * self.norb, "H")
         fn = self._lib.gint_build_H_weighted if weighted else self._lib.gint_build_H
         _check(fn(self._handle(), vp, op))
+        return out
+
+    def build_DK(self, W=None, out=None):
+        """Moving-basis matrix DK[c, mu, nu] = <phit_mu|W|d phit_nu/d tau_K>_c
+        (K the atom of nu; W None: W = 1), a (3, norb, norb) tensor."""
+        import torch
+
+        n = self.norb
+        wp = ctypes.c_void_p(None) if W is None else _dev_ptr(W, self.ngrid, "W")
+        if out is None:
+            dev = W.device if W is not None else torch.device("cuda", torch.cuda.current_device())
+            out = torch.empty((3, n, n), dtype=torch.float64, device=dev)
+        op = _dev_ptr(out, 3 * n * n, "DK")
+        _check(self._lib.gint_build_DK(self._handle(), wp, op))
         return out
 
     def HR_lattice(self):

@@ -978,6 +978,26 @@ gint_status gint_build_H_weighted(gint_plan p, const double *w_dev, double *H_de
     return build_H_impl(p, w_dev, 1.0, H_dev);
 }
 
+gint_status gint_build_DK(gint_plan p, const double *W_dev, double *DK_dev)
+{
+    STCHK(check_plan(p));
+    if (!DK_dev)
+        return fail(GINT_EINVAL, "DK must be a non-NULL device pointer");
+    if (p->geo.P != 16 && p->geo.P != 32)
+        return fail(GINT_EUNSUPPORTED, "batch of %d points", p->geo.P);
+    HIPCHK(hipSetDevice(p->device));
+    const Bins bn = p->bins();
+    const Basis B = p->basis();
+    STCHK(timed(p, GINT_K_H_FILL,
+                [&] { return launch_fill_f64(p->stream, DK_dev, 3LL * p->norb * p->norb, 0.0); }));
+    STCHK(timed(p, GINT_K_DK, [&] {
+        return launch_DK_pairs(p->stream, p->geo, bn, B, W_dev, p->dV, p->npair_owned, p->pown.as<int>(),
+                               p->plist.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), p->boff.as<int>(), p->norb,
+                               DK_dev);
+    }));
+    return GINT_OK;
+}
+
 gint_status gint_build_rho(gint_plan p, const double *D_dev, double *rho_dev)
 {
     STCHK(check_plan(p));

@@ -159,6 +159,12 @@ hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, c
                              const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
                              const double *DR, double *rho);
 hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double *ph, const double *HR, double *Hk);
+// moving-basis matrix DK (gint_dphi.hip): one workgroup per owned atom pair
+// over the pair's block list; DK must be zero beforehand
+size_t DK_pairs_lds(int P);
+hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *W, double wscale,
+                           int npair, const int *pown, const int *plist, const int *lptr, const int *list,
+                           const int *boff, int norb, double *DK);
 // limits of the allocation-free H(k) (its workspace is a fixed device array)
 constexpr int kHkNaMaxPhase = 65536, kHkNaMaxK = 8192, kHkNaMaxR = 8192;
 // H(k) with the phases and staged inputs in the device array of gint_hr.hip
