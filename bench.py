@@ -108,12 +108,39 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _host_cpu():
+    """CPU model and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = "unknown", set()
+    try:
+        phys = core = None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model == "unknown":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None and core is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return model, len(cores) or None
+
+
 def cpu_baseline(w):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
     workload and extrapolate to one full step: H rows and dE/dR of one atom
     per oracle thread (the oracle is parallel over atoms for both) summed
     over a random half of the mesh points, and rho at 40000 mesh points
-    (parallel over points): about 10 s of host time."""
+    (parallel over points): about 10 s of host time.  A single-thread run of
+    one atom's H rows and dE/dR over 1/16 of the mesh gives the one-core
+    rate (a few seconds)."""
     import oracle
 
     o = oracle.Oracle.from_workload(w)
@@ -136,17 +163,94 @@ def cpu_baseline(w):
     o.rho(w.D, idx)
     tR = time.perf_counter() - t
     t_step = (tH + tF) * (w.natom / na) * (w.ngrid / nsub) + tR * w.ngrid / npts
+    # one thread: H rows and dE/dR of one atom over 1/16 of the mesh
+    n1 = max(1, w.ngrid // 16)
+    sub1 = np.sort(rng.choice(w.ngrid, n1, replace=False))
+    oracle.set_threads(1)
+    try:
+        t = time.perf_counter()
+        o.H_rows(w.V, lo, lo + 1, points=sub1)
+        o.force(w.V, w.D, atoms[:1], points=sub1)
+        t1 = time.perf_counter() - t
+    finally:
+        oracle.set_threads(nthr)
+    t_step1 = t1 * w.natom * (w.ngrid / n1) + tR * nthr * w.ngrid / npts
+    model, phys = _host_cpu()
     return {
         "value": w.ngrid / t_step,
         "unit": "grid pts/s",
         "cores": int(nthr),
+        "physical_cores": phys,
+        "logical_cpus": os.cpu_count(),
+        "cpu_model": model,
+        "single_thread_value": w.ngrid / t_step1,
         "kind": "oracle",
         "sample": (f"{w.name}: H rows of atoms {lo}..{lo + na - 1} ({tH:.1f} s) and dE/dR of the same "
                    f"{na} atoms ({tF:.1f} s), both over {nsub} random mesh points; rho at {npts} random "
                    f"mesh points ({tR:.1f} s); "
                    f"extrapolated linearly to all {w.natom} atoms and {w.ngrid} points = "
-                   f"{t_step:.0f} s per step"),
+                   f"{t_step:.0f} s per step on {nthr} threads; one thread: one atom's H rows and dE/dR over "
+                   f"{n1} points ({t1:.1f} s), rho as above scaled by {nthr} threads, = {t_step1:.0f} s per step"),
     }
+
+
+def mixed_leg(args, w, V, D, H64, rho64, F64, torch, g, dev, ms_fp64):
+    """The same step (re-binning + gint_H_rho_force) in the FP16 hi/lo mode
+    (H on FP16 matrix cores with 3 products, rho and the force on FP32
+    tiles, FP64 sums across batches), timed like the FP64 step, with its
+    error against the FP64 GPU outputs of the same inputs."""
+    prec = "fp16x3"
+    plan = g.GintPlan.from_workload(w, precision=prec)
+    H = torch.empty((plan.norb, plan.norb), dtype=torch.float64, device=dev)
+    rho = torch.empty(plan.ngrid, dtype=torch.float64, device=dev)
+    F = torch.empty((plan.natom, 3), dtype=torch.float64, device=dev)
+
+    def step():
+        plan.set_positions(w.positions)
+        plan.H_rho_force(V, D, H=H, rho=rho, out=F)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = plan.timing()
+    plan.set_timing(False)
+    work = plan.work()
+    ms = (t1 - t0) * 1e3 / args.steps
+    s1, s2 = work["sum_ng"], work["sum_ng2"]
+    kernels = {k: {"avg_ms": round(t / n, 4), "launches": n} for k, (t, n) in timing.items() if n}
+    dom = max(kernels, key=lambda k: timing[k][0])
+    roof = None
+    if dom == "H_rho_force":
+        per = (4 * s2 + 8 * s1) / (timing[dom][1] / args.steps)
+        ach = per / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                "note": "fused pass: T = (D + D^T) phi on FP32 matrix cores (the larger share), H on FP16 ones; "
+                        "priced at the FP32 peak"}
+    out = {
+        "precision": prec,
+        "dtype": DTYPES[prec],
+        "ms_per_step": ms,
+        "value": w.ngrid / (ms * 1e-3),
+        "unit": "grid pts/s",
+        "speedup_vs_fp64": ms_fp64 / ms,
+        "max_abs_dH_Ha": float((H - H64).abs().max()),
+        "meets_1e-6_Ha": bool(float((H - H64).abs().max()) <= 1e-6),
+        "rho_rel_l2": float(torch.linalg.norm(rho - rho64) / torch.linalg.norm(rho64)),
+        "force_rel_max": float((F - F64).abs().max() / F64.abs().max()),
+        "error_reference": "the FP64 GPU path on the same inputs (itself within 1e-10 of the FP64 oracle)",
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    plan.close()
+    return out
 
 
 def run_batched(args, torch, gi, g, dev):
@@ -231,13 +335,17 @@ def main():
     ap.add_argument("--workload", default="si512", choices=["si512", "si64", "si8", "batched"])
     ap.add_argument("--cells", type=int, default=256, help="number of cells of the batched workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP16 hi/lo leg of the default FP64 line")
     ap.add_argument("--precision", default="fp64", choices=list(DTYPES))
     ap.add_argument("--only", default=None,
-                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR", "forceR", "DK"],
+                    choices=["H", "rho", "force", "rho_force", "H_rho_force", "HR", "rhoR", "forceR", "DK",
+                             "psibeta"],
                     help="time one contraction only (short profiler runs); HR: the lattice-vector blocks "
                          "H(R) for every R of gint_HR_lattice; rhoR: rho from random lattice-vector density "
                          "matrices D(R) over the same R; forceR: dE/dR for those D(R); DK: the moving-basis "
-                         "matrix <phi_mu|V|d phi_nu/d tau_K> (gint_build_DK)")
+                         "matrix <phi_mu|V|d phi_nu/d tau_K> (gint_build_DK); psibeta: the spherical-grid projector "
+                         "overlaps <phi_mu|e^{-iA.r}|beta_p> (110 x 140 points per atom, gint_psibeta_overlap)")
     ap.add_argument("--separate", action="store_true",
                     help="rho and the force as two passes (gint_build_rho + gint_force) instead of gint_rho_force")
     ap.add_argument("--serial", action="store_true",
@@ -305,8 +413,17 @@ def main():
 
     if args.only == "DK":
         DKbuf = torch.empty((3, plan.norb, plan.norb), dtype=torch.float64, device=dev)
+    if args.only == "psibeta":
+        proj = [gi.si_projector_species()]
+        ang, rq = gi.lebedev_110(), gi.gauss_legendre_01(140)
+        pb = g.GintPsiBeta(plan, proj, ang, rq)
+        Apot = gi.vector_potential(13, 0.05)
+        Qbuf = torch.empty((pb.nproj, plan.norb), dtype=torch.complex128, device=dev)
 
     def step():
+        if args.only == "psibeta":
+            pb.overlap(Apot, out=Qbuf)
+            return
         if args.only == "DK":
             plan.build_DK(V, out=DKbuf)
             return
@@ -358,6 +475,20 @@ def main():
              "rho_force": 2 * s2 + 8 * s1, "H_rho_force": 4 * s2 + 8 * s1, "HR": 2 * s2,
              # three non-symmetric products phi (d_c phi)^T over the supported orbitals
              "DK": 6 * s2}
+    if args.only == "psibeta":
+        # the contraction over quadrature points of every projector against
+        # every orbital of the atoms whose cutoff reaches the projector sphere
+        # (complex: 4 flops per multiply-add)
+        rb = max(r.rc for r in proj[0].radials)
+        rcJ = max(r.rc for r in w.species[0].radials)
+        pos = w.positions
+        shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]) @ w.lattice
+        near = 0
+        for I in range(w.natom):
+            d = pos[I][None, None, :] - pos[None, :, :] - shifts[:, None, :]
+            near += int(np.any(np.linalg.norm(d, axis=2) < rb + rcJ, axis=0).sum())
+        flops["psibeta"] = 4.0 * len(ang) * len(rq) * proj[0].norb * near * w.species[0].norb
+        work["psibeta_pairs"] = near
     # the H reduction moves every block partial once and writes H's blocks
     hbytes = {"H_reduce": work["nblock"] * work["mno"] ** 2 * work["partial_bytes"],
               "H_fill": 8 * plan.norb ** 2 * (len(R_list) if args.only == "HR" else 1)}
@@ -449,6 +580,13 @@ def main():
             "force_rel_max": float((F - F64).abs().max() / F64.abs().max()),
         }
         ref.close()
+    if args.precision == "fp64" and args.only is None and not args.no_mixed and not args.serial \
+            and not args.separate:
+        _progress("mixed-precision leg (fp16x3)")
+        H64, rho64, F64 = H.clone(), rho.clone(), F.clone()
+        plan.close()
+        out["mixed_fp16x3"] = mixed_leg(args, w, V, D, H64, rho64, F64, torch, g, dev, ms_step)
+        del H64, rho64, F64
     if args.only is not None:
         out["only"] = args.only
     if args.only == "HR":
@@ -456,6 +594,12 @@ def main():
                                      f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the lattice-vector "
                                      f"blocks H(R) of {len(R_list)} lattice vectors (gint_build_HR)")
         out["config"]["n_R"] = len(R_list)
+    if args.only == "psibeta":
+        out["config"]["workload"] = (f"{w.name}: {w.natom} atoms x 9 synthetic projectors (l = 0, 1, 2), "
+                                     f"{plan.norb} orbitals, one step = <phi_mu|e^{{-iA.r}}|beta_p> on the "
+                                     "110-point Lebedev x 140-point Gauss-Legendre grid of every atom "
+                                     "(gint_psibeta_overlap)")
+        out["config"]["projector_atom_pairs"] = work["psibeta_pairs"]
     if args.only == "DK":
         out["config"]["workload"] = (f"{w.name}: {w.natom} atoms, {plan.norb} orbitals, mesh "
                                      f"{'x'.join(map(str, w.grid))}, DZP rc=8 bohr, one step = the moving-basis "

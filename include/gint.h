@@ -314,6 +314,55 @@ gint_status gint_HR_to_Hk_noalloc(gint_plan plan, int nR, const int *R, const do
  * stream once. */
 gint_status gint_HR_lattice(gint_plan plan, int cap, int *nR, int *R);
 
+/* ---------------------------------------------------------------------
+ * Spherical-grid projector overlaps of the velocity-gauge nonlocal
+ * pseudopotential (Sec. 3.3.2, "Spherical Grid Integration for Nonlocal
+ * Potentials"; the phase-modulated projector overlap of Sec. 2.2):
+ *
+ *   Q[p][mu] = < phit_mu | e^{-i A.r} | beta_p >
+ *            = sum_{i,j} W_ij phit_mu(tau_I + x_ij) e^{-i A.(tau_I + x_ij)} beta_p(x_ij),
+ *
+ * evaluated on the product grid centred on the projector's atom I:
+ * x_ij = r_i u_j with r_i = rb x_i and W_ij = rb q_i r_i^2 w_j, where
+ * (u_j, w_j) is the caller's angular rule on the unit sphere (the paper uses
+ * the 110-point Lebedev-Laikov rule), (x_i, q_i) its radial rule on [0, 1]
+ * (the paper: 140-point Gauss-Legendre) and rb the largest projector cutoff
+ * of I's species.  beta_p(x) = b(|x|) Y_lm(x/|x|) with b the clamped cubic
+ * spline of the projector table (strict cutoff, the r = 0 limits of the
+ * orbitals); phit the orbital folded over lattice images; tau_I the position
+ * as given to the plan (gint_plan_set_positions), so moving an atom by a
+ * lattice vector L multiplies its rows by e^{-i A.L}.
+ * --------------------------------------------------------------------- */
+typedef struct gint_psibeta_s *gint_psibeta;
+
+/* Projector tables and quadrature for a plan (the plan must outlive it):
+ *   nspecies  must equal the plan's species count
+ *   proj      host, nspecies entries: the projector radials of each species
+ *             (nradial may be 0: no projectors; l <= 2, at most 16
+ *             projectors per species); projectors are ordered like the
+ *             orbitals (atoms in input order; radials by l, stable; m)
+ *   ang       host, nang*4 doubles: (x, y, z, w) per angular node, unit x
+ *   rq        host, nrq*2 doubles: (x, q) per radial node on [0, 1]
+ * The neighbour lists (atoms whose orbitals reach each projector sphere) are
+ * built on the GPU now and again after the plan's atoms move.  Synchronises
+ * the plan's stream. */
+gint_status gint_psibeta_create(gint_plan plan, int nspecies, const gint_species *proj, int nang, const double *ang,
+                                int nrq, const double *rq, gint_psibeta *out);
+
+/* Rows of Q (projectors over all atoms), or -1. */
+int gint_psibeta_nproj(gint_psibeta pb);
+
+/* Q for the vector potential A (host, 3 doubles, bohr^-1):
+ *   Q_dev  device, nproj*norb complex values as (re, im) double pairs,
+ *          row-major, overwritten.
+ * One workgroup per projector atom contracts its projector table against
+ * the orbitals of every neighbouring atom over the quadrature points on the
+ * FP64 matrix cores; each block is written once (repeatable bits).  FP64 in
+ * every plan precision. */
+gint_status gint_psibeta_overlap(gint_psibeta pb, const double A[3], double *Q_dev);
+
+void gint_psibeta_destroy(gint_psibeta pb);
+
 /* Kernel classes reported by gint_plan_timing. */
 enum {
     GINT_K_BIN = 0,       /* binning kernels of plan creation / set_positions / tune */
@@ -328,7 +377,8 @@ enum {
     GINT_K_H_RHO_FORCE = 9, /* H blocks, rho and force in one pass (gint_H_rho_force) */
     GINT_K_HR = 10,       /* lattice-vector blocks H(R) (gint_build_HR)            */
     GINT_K_DK = 11,       /* moving-basis matrix (gint_build_DK)                    */
-    GINT_NKERNEL = 12
+    GINT_K_PSIBETA = 12,  /* spherical-grid projector overlaps (gint_psibeta_overlap) */
+    GINT_NKERNEL = 13
 };
 
 /* Enable (1) or disable (0) timing: each kernel launch of later calls is

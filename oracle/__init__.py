@@ -82,6 +82,7 @@ def _load():
     lib.oracle_set_positions.argtypes = [P, dp]
     lib.oracle_support_stats.argtypes = [P, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -115,6 +116,11 @@ def Hk_from_HR(R, HR, kfrac) -> np.ndarray:
         for q in range(R.shape[0]):
             out[i] += np.exp(2j * np.pi * float(k @ R[q])) * HR[q]
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    _load().oracle_set_threads(int(n))
 
 
 def num_threads() -> int:

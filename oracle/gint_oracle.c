@@ -1167,6 +1167,17 @@ void oracle_set_positions(void *p, const double *pos)
     memcpy(c->pos, pos, sizeof(double) * 3 * c->natom);
 }
 
+/* Threads used by the parallel loops from now on (for timing). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -34,10 +34,11 @@ EXPORTS = (
     "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk", "gint_forceR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
-    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_build_DK", "gint_HR_to_Hk_noalloc",
+    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_build_DK",
+    "gint_psibeta_create", "gint_psibeta_nproj", "gint_psibeta_overlap", "gint_psibeta_destroy", "gint_HR_to_Hk_noalloc",
 )
 KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
-           "H_rho_force", "HR", "DK")
+           "H_rho_force", "HR", "DK", "psibeta")
 
 
 class GintError(RuntimeError):
@@ -135,6 +136,15 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_timing.argtypes = [P, dp, ip]
     lib.gint_plan_destroy.restype = None
     lib.gint_plan_destroy.argtypes = [P]
+    lib.gint_psibeta_create.restype = st
+    lib.gint_psibeta_create.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Species), ctypes.c_int, dp, ctypes.c_int,
+                                        dp, ctypes.POINTER(P)]
+    lib.gint_psibeta_nproj.restype = ctypes.c_int
+    lib.gint_psibeta_nproj.argtypes = [P]
+    lib.gint_psibeta_overlap.restype = st
+    lib.gint_psibeta_overlap.argtypes = [P, dp, P]
+    lib.gint_psibeta_destroy.restype = None
+    lib.gint_psibeta_destroy.argtypes = [P]
     lib.gint_plan_atom_order.restype = st
     lib.gint_plan_atom_order.argtypes = [P, ip]
     lib.gint_test_fail_rebuilds.restype = st
@@ -487,6 +497,52 @@ class GintPlan:
         op = _dev_ptr(out, self.natom * 3, "dEdR")
         _check(self._lib.gint_H_rho_force(self._handle(), vp, dp, hp, rp, op))
         return H, rho, out
+
+
+class GintPsiBeta:
+    """Spherical-grid projector overlaps Q[p, mu] = <phit_mu|e^{-iA.r}|beta_p>
+    of one plan (gint_psibeta_*): ``proj_species`` holds one Species of
+    projector radials per orbital species (may be empty), ``ang`` the
+    angular rule rows (x, y, z, w), ``rq`` the radial rule rows (x, q) on
+    [0, 1]."""
+
+    def __init__(self, plan: GintPlan, proj_species, ang, rq):
+        self._lib = plan._lib
+        self.plan = plan
+        self._keep = []
+        sp_arr = _species_array(proj_species, self._keep)
+        self._ang = np.ascontiguousarray(ang, dtype=np.float64).reshape(-1, 4)
+        self._rq = np.ascontiguousarray(rq, dtype=np.float64).reshape(-1, 2)
+        h = ctypes.c_void_p()
+        _check(self._lib.gint_psibeta_create(plan._handle(), len(proj_species), sp_arr, self._ang.shape[0],
+                                             _dptr(self._ang), self._rq.shape[0], _dptr(self._rq), ctypes.byref(h)))
+        self._h = h
+        self.nproj = int(self._lib.gint_psibeta_nproj(h))
+
+    def overlap(self, A, out=None):
+        """Q for the vector potential A (3 floats): complex128 (nproj, norb)."""
+        import torch
+
+        a = np.ascontiguousarray(A, dtype=np.float64).reshape(3)
+        n = self.plan.norb
+        if out is None:
+            out = torch.empty((self.nproj, n), dtype=torch.complex128,
+                              device=torch.device("cuda", torch.cuda.current_device()))
+        if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() != self.nproj * n:
+            raise TypeError("out must be a contiguous complex128 tensor of nproj*norb elements")
+        _check(self._lib.gint_psibeta_overlap(self._h, _dptr(a), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.gint_psibeta_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build_H(plan: GintPlan, V, out=None):

@@ -14,7 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgint.so")
-SOURCES = ["gint_api.hip", "gint_kernels.hip", "gint_contract.hip", "gint_hr.hip", "gint_dphi.hip"]
+SOURCES = ["gint_api.hip", "gint_kernels.hip", "gint_contract.hip", "gint_hr.hip", "gint_dphi.hip",
+           "gint_sphere.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -125,6 +125,9 @@ struct gint_plan_s {
     DevBuf Hpart, S2pk, Fent, sums, readback;
     DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist, lcnt, lptr, blist;
     DevBuf pown, lsl, slabq;  // owner of each owned pair; slab ranges of its block list
+    DevBuf dk_desc;           // per block-list entry: batch and the two entries (gint_build_DK)
+    long long nlist = 0;      // entries of the pairs' block lists
+    long long dk_gen = -1;    // list generation of dk_desc
     DevBuf scan_tmp;          // tile sums of the list scans
     // H(R) blocks: internal atom of each image, wrap shift of each atom,
     // the caller's R list as a box map (rebuilt when the lists or the list
@@ -538,6 +541,7 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     HIPCHK(hipStreamSynchronize(s));
     if (tlist < 0)
         return fail(GINT_EUNSUPPORTED, "pair block lists exceed 2^31 entries");
+    p->nlist = tlist;
     STCHK(p->blist.ensure(sizeof(int) * ((size_t)tlist + 1)));
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_pair_blocks(s, na, tpart, p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>(),
@@ -990,10 +994,18 @@ gint_status gint_build_DK(gint_plan p, const double *W_dev, double *DK_dev)
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_H_FILL,
                 [&] { return launch_fill_f64(p->stream, DK_dev, 3LL * p->norb * p->norb, 0.0); }));
+    if (p->dk_gen != p->gen) {
+        // per list entry: its batch and the two atoms' entries (once per geometry)
+        STCHK(p->dk_desc.ensure(sizeof(int4) * (size_t)std::max(p->nlist, 1LL)));
+        STCHK(timed(p, GINT_K_BIN, [&] {
+            return launch_DK_desc(p->stream, p->nlist, p->geo.nbatch, p->blist.as<int>(), p->boff.as<int>(),
+                                  p->bptr.as<int>(), p->dk_desc.as<int4>());
+        }));
+        p->dk_gen = p->gen;
+    }
     STCHK(timed(p, GINT_K_DK, [&] {
         return launch_DK_pairs(p->stream, p->geo, bn, B, W_dev, p->dV, p->npair_owned, p->pown.as<int>(),
-                               p->plist.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), p->boff.as<int>(), p->norb,
-                               DK_dev);
+                               p->plist.as<int>(), p->lptr.as<int>(), p->dk_desc.as<int4>(), p->norb, DK_dev);
     }));
     return GINT_OK;
 }
@@ -1523,6 +1535,316 @@ void gint_plan_destroy(gint_plan p)
 
 }  // extern "C"
 
+
+// ===========================================================================
+// Spherical-grid projector overlaps (Sec. 3.3.2): per-plan projector tables,
+// quadrature rules and per-geometry neighbour lists; the kernels are in
+// gint_sphere.hip.
+
+namespace {
+constexpr unsigned kPBMagic = 0x47505342u;  // "GPSB"
+}  // namespace
+
+struct gint_psibeta_s {
+    unsigned magic = kPBMagic;
+    gint_plan plan = nullptr;
+    long long gen = -1;  // list generation of the plan the neighbour lists were built for
+    int nprad = 0, npa = 0, nproj = 0, nang = 0, nrq = 0;
+    int max_entries = 0;  // most neighbour entries of one projector atom
+    double rb_max = 0.0;
+    std::vector<int> pin_h, prow_h;  // projector atoms (input order) and their first rows
+    std::vector<double> prb_h;       // projector cutoff of each projector atom
+    std::vector<int> sp_nproj;       // projectors per species
+    DevBuf prad, psp, pknots, ps0, psn, pcoef, pscratch, ang, rq;
+    DevBuf pint, pin, prow, prb, cnt, ioff, eptr, ent, img;
+};
+
+namespace {
+
+gint_status check_psibeta(gint_psibeta b)
+{
+    if (!b)
+        return fail(GINT_EINVAL, "psibeta is NULL");
+    if (b->magic != kPBMagic)
+        return fail(GINT_ESTATE, "psibeta is destroyed or corrupted");
+    return check_plan(b->plan);
+}
+
+// neighbour lists of the projector atoms for the plan's current positions
+gint_status psibeta_lists(gint_psibeta b)
+{
+    gint_plan p = b->plan;
+    if (b->gen == p->gen)
+        return GINT_OK;
+    const hipStream_t s = p->stream;
+    const int natom = p->natom, npa = b->npa;
+    if (npa == 0) {
+        b->gen = p->gen;
+        return GINT_OK;
+    }
+    std::vector<int> inv(natom);
+    HIPCHK(hipMemcpyAsync(inv.data(), p->inv_perm.p, sizeof(int) * natom, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> pint(npa);
+    for (int a = 0; a < npa; ++a)
+        pint[a] = inv[b->pin_h[a]];
+    const Geo &g = p->geo;
+    int m[3];
+    for (int i = 0; i < 3; ++i) {
+        const double bn = std::sqrt(g.rec[3 * i] * g.rec[3 * i] + g.rec[3 * i + 1] * g.rec[3 * i + 1] +
+                                    g.rec[3 * i + 2] * g.rec[3 * i + 2]);
+        m[i] = (int)std::ceil((b->rb_max + p->rc_max) * bn) + 1;
+        if (m[i] > 125)
+            return fail(GINT_EUNSUPPORTED, "projector and orbital cutoffs span more than 125 cells");
+    }
+    const size_t nn = (size_t)npa * natom;
+    STCHK(b->pint.ensure(sizeof(int) * npa));
+    HIPCHK(hipMemcpyAsync(b->pint.p, pint.data(), sizeof(int) * npa, hipMemcpyHostToDevice, s));
+    STCHK(b->cnt.ensure(sizeof(int) * nn));
+    const Basis B = p->basis();
+    HIPCHK(launch_pb_images(s, g, B, npa, b->pint.as<int>(), b->prb.as<double>(), m, b->cnt.as<int>(), nullptr,
+                            nullptr));
+    std::vector<int> cnt(nn);
+    HIPCHK(hipMemcpyAsync(cnt.data(), b->cnt.p, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // image offsets of every (projector atom, atom) pair; entries of the
+    // pairs with images, per projector atom in atom (internal) order
+    std::vector<int> ioff(nn), ent, eptr(npa + 1);
+    long long tot = 0;
+    for (int a = 0; a < npa; ++a) {
+        eptr[a] = (int)(ent.size() / 3);
+        for (int J = 0; J < natom; ++J) {
+            const size_t t = (size_t)a * natom + J;
+            ioff[t] = (int)tot;
+            if (cnt[t] > 0) {
+                ent.push_back(J);
+                ent.push_back((int)tot);
+                ent.push_back(cnt[t]);
+            }
+            tot += cnt[t];
+            if (tot >= 0x7fffffffLL)
+                return fail(GINT_EUNSUPPORTED, "projector neighbour lists exceed 2^31 images");
+        }
+    }
+    eptr[npa] = (int)(ent.size() / 3);
+    b->max_entries = 0;
+    for (int a = 0; a < npa; ++a)
+        b->max_entries = std::max(b->max_entries, eptr[a + 1] - eptr[a]);
+    STCHK(b->ioff.ensure(sizeof(int) * nn));
+    STCHK(b->img.ensure(sizeof(int) * (size_t)std::max(tot, 1LL)));
+    STCHK(b->ent.ensure(sizeof(int) * std::max(ent.size(), (size_t)3)));
+    STCHK(b->eptr.ensure(sizeof(int) * (npa + 1)));
+    HIPCHK(hipMemcpyAsync(b->ioff.p, ioff.data(), sizeof(int) * nn, hipMemcpyHostToDevice, s));
+    if (!ent.empty())
+        HIPCHK(hipMemcpyAsync(b->ent.p, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(b->eptr.p, eptr.data(), sizeof(int) * (npa + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_pb_images(s, g, B, npa, b->pint.as<int>(), b->prb.as<double>(), m, b->cnt.as<int>(),
+                            b->ioff.as<int>(), b->img.as<int>()));
+    HIPCHK(hipStreamSynchronize(s));  // the host tables outlive the copies
+    b->gen = p->gen;
+    return GINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gint_status gint_psibeta_create(gint_plan p, int nspecies, const gint_species *proj, int nang, const double *ang,
+                                int nrq, const double *rq, gint_psibeta *out)
+{
+    STCHK(check_plan(p));
+    if (!out)
+        return fail(GINT_EINVAL, "out is NULL");
+    if (nspecies != p->nspecies || !proj)
+        return fail(GINT_EINVAL, "projectors must be given for each of the plan's %d species", p->nspecies);
+    if (nang < 1 || nang > 65536 || !ang || nrq < 1 || nrq > 65536 || !rq)
+        return fail(GINT_EINVAL, "need 1..65536 angular and radial quadrature nodes (non-NULL)");
+    if ((long long)nang * nrq >= 0x7fffffffLL)
+        return fail(GINT_EINVAL, "quadrature grid of %lld points is too large", (long long)nang * nrq);
+    if (!finite3(ang, 4LL * nang) || !finite3(rq, 2LL * nrq))
+        return fail(GINT_EINVAL, "quadrature rules have non-finite entries");
+    for (int i = 0; i < nrq; ++i)
+        if (rq[2 * i] < 0.0 || rq[2 * i] > 1.0)
+            return fail(GINT_EINVAL, "radial node %d = %g is outside [0, 1]", i, rq[2 * i]);
+    int nrad_total = 0;
+    for (int s = 0; s < nspecies; ++s) {
+        const gint_species &S = proj[s];
+        if (S.nradial < 0 || (S.nradial > 0 && !S.radial))
+            return fail(GINT_EINVAL, "projector species %d: bad radial list", s);
+        nrad_total += S.nradial;
+        int np = 0;
+        for (int k = 0; k < S.nradial; ++k) {
+            const gint_radial &R = S.radial[k];
+            if (R.l < 0 || R.l > 2)
+                return fail(R.l < 0 ? GINT_EINVAL : GINT_EUNSUPPORTED, "projector %d of species %d: l = %d", k, s,
+                            R.l);
+            if (R.nr < 4 || !(R.dr > 0.0) || !std::isfinite(R.dr) || !R.f)
+                return fail(GINT_EINVAL, "projector %d of species %d: bad table", k, s);
+            if (!finite3(R.f, R.nr) || !std::isfinite(R.dfdr_0) || !std::isfinite(R.dfdr_rc))
+                return fail(GINT_EINVAL, "projector %d of species %d: non-finite table", k, s);
+            np += 2 * R.l + 1;
+        }
+        if (np > kMaxOrb)
+            return fail(GINT_EUNSUPPORTED, "species %d has %d projectors (max %d)", s, np, kMaxOrb);
+    }
+    if (nrad_total > kMaxRadTotal)
+        return fail(GINT_EUNSUPPORTED, "%d projector radials (max %d)", nrad_total, kMaxRadTotal);
+    HIPCHK(hipSetDevice(p->device));
+    gint_psibeta b = new (std::nothrow) gint_psibeta_s;
+    if (!b)
+        return fail(GINT_ENOMEM, "host allocation failed");
+    b->plan = p;
+    b->nang = nang;
+    b->nrq = nrq;
+    // projector tables, ordered like the orbitals (l ascending, stable; m)
+    std::vector<DevRadial> rad;
+    std::vector<DevSpecies> sp(nspecies);
+    std::vector<double> knots, s0, sn;
+    int coef_off = 0;
+    b->sp_nproj.assign(nspecies, 0);
+    for (int s = 0; s < nspecies; ++s) {
+        const gint_species &S = proj[s];
+        sp[s].rad0 = (int)rad.size();
+        sp[s].nrad = S.nradial;
+        sp[s].rc = 0.0;
+        for (int o = 0; o < kMaxOrb; ++o)
+            sp[s].orb_rad[o] = sp[s].orb_m[o] = 0;
+        int orb = 0;
+        for (int l = 0; l <= 2; ++l)
+            for (int k = 0; k < S.nradial; ++k) {
+                const gint_radial &R = S.radial[k];
+                if (R.l != l)
+                    continue;
+                DevRadial d;
+                for (int m = 0; m < 2 * l + 1; ++m) {
+                    sp[s].orb_rad[orb + m] = (signed char)rad.size();
+                    sp[s].orb_m[orb + m] = (signed char)(m - l);
+                }
+                d.dr = R.dr;
+                d.inv_dr = 1.0 / R.dr;
+                d.rc = (R.nr - 1) * R.dr;
+                d.l = R.l;
+                d.nr = R.nr;
+                d.orb0 = orb;
+                d.coef_off = coef_off;
+                d.knot_off = (int)knots.size();
+                coef_off += 4 * (R.nr - 1);
+                knots.insert(knots.end(), R.f, R.f + R.nr);
+                s0.push_back(R.dfdr_0);
+                sn.push_back(R.dfdr_rc);
+                rad.push_back(d);
+                orb += 2 * l + 1;
+                sp[s].rc = std::max(sp[s].rc, d.rc);
+            }
+        sp[s].norb = orb;
+        b->sp_nproj[s] = orb;
+        b->rb_max = std::max(b->rb_max, sp[s].rc);
+    }
+    b->nprad = (int)rad.size();
+    // projector atoms (input order) and their rows
+    std::vector<int> spc_h(p->natom);
+    gint_status st = GINT_OK;
+    do {
+        hipError_t e = hipMemcpyAsync(spc_h.data(), p->spc_in.p, sizeof(int) * p->natom, hipMemcpyDeviceToHost,
+                                      p->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) {
+            st = fail(GINT_EDEVICE, "reading the species failed: %s", hipGetErrorString(e));
+            break;
+        }
+        int row = 0;
+        for (int i = 0; i < p->natom; ++i) {
+            const int np = b->sp_nproj[spc_h[i]];
+            if (np == 0)
+                continue;
+            b->pin_h.push_back(i);
+            b->prow_h.push_back(row);
+            b->prb_h.push_back(sp[spc_h[i]].rc);
+            row += np;
+        }
+        b->npa = (int)b->pin_h.size();
+        b->nproj = row;
+        auto upload = [&](DevBuf &d, const void *h, size_t bytes) -> gint_status {
+            STCHK(d.ensure(bytes));
+            if (bytes)
+                HIPCHK(hipMemcpyAsync(d.p, h, bytes, hipMemcpyHostToDevice, p->stream));
+            return GINT_OK;
+        };
+        if ((st = upload(b->psp, sp.data(), sizeof(DevSpecies) * sp.size())) != GINT_OK) break;
+        if ((st = upload(b->ang, ang, sizeof(double) * 4 * nang)) != GINT_OK) break;
+        if ((st = upload(b->rq, rq, sizeof(double) * 2 * nrq)) != GINT_OK) break;
+        if ((st = upload(b->pin, b->pin_h.data(), sizeof(int) * b->npa)) != GINT_OK) break;
+        if ((st = upload(b->prow, b->prow_h.data(), sizeof(int) * b->npa)) != GINT_OK) break;
+        if ((st = upload(b->prb, b->prb_h.data(), sizeof(double) * b->npa)) != GINT_OK) break;
+        if (b->nprad > 0) {
+            if ((st = upload(b->prad, rad.data(), sizeof(DevRadial) * rad.size())) != GINT_OK) break;
+            if ((st = upload(b->pknots, knots.data(), sizeof(double) * knots.size())) != GINT_OK) break;
+            if ((st = upload(b->ps0, s0.data(), sizeof(double) * s0.size())) != GINT_OK) break;
+            if ((st = upload(b->psn, sn.data(), sizeof(double) * sn.size())) != GINT_OK) break;
+            if ((st = b->pcoef.ensure(sizeof(double) * coef_off)) != GINT_OK) break;
+            if ((st = b->pscratch.ensure(sizeof(double) * 3 * knots.size())) != GINT_OK) break;
+            e = launch_spline(p->stream, b->nprad, b->prad.as<DevRadial>(), b->pknots.as<double>(),
+                              b->ps0.as<double>(), b->psn.as<double>(), b->pcoef.as<double>(),
+                              b->pscratch.as<double>());
+            if (e != hipSuccess) {
+                st = fail(GINT_EDEVICE, "projector spline launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+        }
+        e = hipStreamSynchronize(p->stream);  // the host tables outlive the copies
+        if (e != hipSuccess) {
+            st = fail(GINT_EDEVICE, "projector setup failed on the device: %s", hipGetErrorString(e));
+            break;
+        }
+        st = psibeta_lists(b);
+    } while (0);
+    if (st != GINT_OK) {
+        b->magic = 0;
+        delete b;
+        return st;
+    }
+    *out = b;
+    return GINT_OK;
+}
+
+int gint_psibeta_nproj(gint_psibeta b) { return (b && b->magic == kPBMagic) ? b->nproj : -1; }
+
+gint_status gint_psibeta_overlap(gint_psibeta b, const double A[3], double *Q_dev)
+{
+    STCHK(check_psibeta(b));
+    if (!A || !Q_dev)
+        return fail(GINT_EINVAL, "A (host) and Q (device) must be non-NULL");
+    if (!finite3(A, 3))
+        return fail(GINT_EINVAL, "A has non-finite entries");
+    gint_plan p = b->plan;
+    HIPCHK(hipSetDevice(p->device));
+    STCHK(psibeta_lists(b));
+    STCHK(timed(p, GINT_K_H_FILL,
+                [&] { return launch_fill_f64(p->stream, Q_dev, 2LL * b->nproj * p->norb, 0.0); }));
+    STCHK(timed(p, GINT_K_PSIBETA, [&] {
+        return launch_psibeta(p->stream, p->geo, p->basis(), b->prad.as<DevRadial>(), b->psp.as<DevSpecies>(),
+                              b->pcoef.as<double>(), b->nprad, b->npa, b->pint.as<int>(), b->pin.as<int>(),
+                              b->prow.as<int>(), b->eptr.as<int>(), b->ent.as<int>(), b->img.as<int>(),
+                              p->pos_in.as<double>(), b->nang, b->ang.as<double>(), b->nrq, b->rq.as<double>(), A,
+                              p->norb, b->max_entries, Q_dev);
+    }));
+    return GINT_OK;
+}
+
+void gint_psibeta_destroy(gint_psibeta b)
+{
+    if (!b || b->magic != kPBMagic)
+        return;
+    if (b->plan && b->plan->magic == kMagic) {
+        (void)hipSetDevice(b->plan->device);
+        (void)hipStreamSynchronize(b->plan->stream);
+    }
+    b->magic = 0;
+    delete b;
+}
+
+}  // extern "C"
 
 // ===========================================================================
 // Batched cells: one plan per cell; every call on the batch is captured once

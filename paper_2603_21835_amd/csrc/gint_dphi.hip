@@ -136,21 +136,61 @@ __device__ __forceinline__ void eval_phi_grad(const Geo &g, const DevRadial *__r
 
 }  // namespace
 
+// Entry descriptors of the pairs' block lists, once per geometry: list
+// entry k holds, in batch order for its pair, the index q of the pair's
+// block among the H block partials (boff[b] <= q < boff[b+1], block
+// (lo, hi) of batch b's slot triangle), negated as -(q + 1) when the owner
+// sits in the higher slot; desc[k] = (b, entry of the owner, entry of the
+// partner, 0).
+__global__ __launch_bounds__(256) void k_DK_desc(long long n, int nbatch, const int *__restrict__ list,
+                                                 const int *__restrict__ boff, const int *__restrict__ bptr,
+                                                 int4 *__restrict__ desc)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n)
+        return;
+    const int code = list[k];
+    const int q = code >= 0 ? code : -code - 1;
+    int lo = 0, hi = nbatch;  // last b with boff[b] <= q
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (boff[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int b = lo;
+    const int e0 = bptr[b], nb = bptr[b + 1] - e0;
+    int t = q - boff[b], slo = 0;
+    while (t >= nb - slo) {  // row slo of the triangle holds nb - slo blocks
+        t -= nb - slo;
+        ++slo;
+    }
+    const int shi = slo + t;
+    desc[k] = int4{b, e0 + (code >= 0 ? slo : shi), e0 + (code >= 0 ? shi : slo), 0};
+}
+
+hipError_t launch_DK_desc(hipStream_t s, long long n, int nbatch, const int *list, const int *boff, const int *bptr,
+                          int4 *desc)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_DK_desc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nbatch, list, boff, bptr,
+                       desc);
+    return hipGetLastError();
+}
+
 // One workgroup (kDKWaves waves) per owned pair p = (pown[p], plist[p])
-// (internal atoms); list[lptr[p] .. lptr[p+1]) holds, in batch order, one
-// code per shared batch: the index q of the pair's block among the H block
-// partials of that batch (boff[b] <= q < boff[b+1], block (lo, hi) of the
-// batch's slot triangle), negated as -(q + 1) when the owner sits in the
-// higher slot.  DK (3 x norb x norb, input orbital order) must be zero
-// outside the blocks of the owned pairs; each owned pair's blocks are
-// written once (rows of I, columns of J, and rows of J, columns of I).
+// (internal atoms) over its list entries desc[lptr[p] .. lptr[p+1]).  DK
+// (3 x norb x norb, input orbital order) must be zero outside the blocks of
+// the owned pairs; each owned pair's blocks are written once (rows of I,
+// columns of J, and rows of J, columns of I).
 template <int P>
 __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
                                                            double wscale, int npair, const int *__restrict__ pown,
                                                            const int *__restrict__ plist,
                                                            const int *__restrict__ lptr,
-                                                           const int *__restrict__ list,
-                                                           const int *__restrict__ boff, int norb,
+                                                           const int4 *__restrict__ desc, int norb,
                                                            double *__restrict__ DK)
 {
     constexpr int NV = kDKVals;
@@ -181,27 +221,13 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
         cIJ[c] = cJI[c] = MM<double>::zero();
 
     const int l0 = lptr[p], l1 = lptr[p + 1];
+    // the wave's next descriptor is loaded one entry ahead
+    int4 dn = l0 + wave < l1 ? desc[l0 + wave] : int4{0, 0, 0, 0};
     for (int k = l0 + wave; k < l1; k += kDKWaves) {
-        // the batch and the two atoms' slots in it (wave-uniform)
-        const int code = list[k];
-        const int q = code >= 0 ? code : -code - 1;
-        int lo = 0, hi = g.nbatch;  // last b with boff[b] <= q
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (boff[mid] <= q)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const int b = lo;
-        const int e0 = bn.bptr[b], nb = bn.bptr[b + 1] - e0;
-        int t = q - boff[b], slo = 0;
-        while (t >= nb - slo) {  // row slo of the triangle holds nb - slo blocks
-            t -= nb - slo;
-            ++slo;
-        }
-        const int shi = slo + t;
-        const int sI = code >= 0 ? slo : shi, sJ = code >= 0 ? shi : slo;
+        const int4 dc = dn;
+        if (k + kDKWaves < l1)
+            dn = desc[k + kDKWaves];
+        const int b = dc.x;  // the batch and the two atoms' entries in it (wave-uniform)
         int ib[3];
         batch_coords(g, b, ib);
 
@@ -210,8 +236,8 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
         {
             const int s = lane / P, qp = lane % P;
             if (s < 2 && !(self && s == 1)) {
-                const int e = e0 + (s == 0 ? sI : sJ);
-                const int atom = bn.ent_atom[e];
+                const int e = s == 0 ? dc.y : dc.z;
+                const int atom = s == 0 ? I : J;
                 const DevSpecies &S = s_sp[bs.spc[atom]];
                 int n[3];
                 const bool valid = batch_point(g, ib, qp, n);
@@ -289,8 +315,8 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
 size_t DK_pairs_lds(int P) { return sizeof(double) * (size_t)kDKWaves * kDKVals * 2 * P * kMaxOrb; }
 
 hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *W, double wscale,
-                           int npair, const int *pown, const int *plist, const int *lptr, const int *list,
-                           const int *boff, int norb, double *DK)
+                           int npair, const int *pown, const int *plist, const int *lptr, const int4 *desc, int norb,
+                           double *DK)
 {
     if (npair <= 0)
         return hipSuccess;
@@ -302,13 +328,13 @@ hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Ba
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_DK_pairs<32>, dim3(nblk), dim3(64 * kDKWaves), lds, s, g, bn, b, W, wscale, npair, pown,
-                           plist, lptr, list, boff, norb, DK);
+                           plist, lptr, desc, norb, DK);
     } else if (g.P == 16) {
         e = hipFuncSetAttribute((const void *)k_DK_pairs<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_DK_pairs<16>, dim3(nblk), dim3(64 * kDKWaves), lds, s, g, bn, b, W, wscale, npair, pown,
-                           plist, lptr, list, boff, norb, DK);
+                           plist, lptr, desc, norb, DK);
     } else {
         return hipErrorInvalidValue;
     }

@@ -159,12 +159,22 @@ hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, c
                              const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
                              const double *DR, double *rho);
 hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double *ph, const double *HR, double *Hk);
+// spherical-grid projector overlaps (gint_sphere.hip)
+hipError_t launch_pb_images(hipStream_t s, const Geo &g, const Basis &b, int npa, const int *pint, const double *prb,
+                            const int *m, int *cnt, const int *off, int *img);
+hipError_t launch_psibeta(hipStream_t s, const Geo &g, const Basis &b, const DevRadial *prad, const DevSpecies *psp,
+                          const double *pcoef, int nprad, int npa, const int *pint, const int *pin, const int *prow,
+                          const int *eptr, const int *ent, const int *img, const double *pos, int nang,
+                          const double *ang, int nrq, const double *rq, const double *A, int norb, int max_entries,
+                          double *Q);
 // moving-basis matrix DK (gint_dphi.hip): one workgroup per owned atom pair
 // over the pair's block list; DK must be zero beforehand
 size_t DK_pairs_lds(int P);
+hipError_t launch_DK_desc(hipStream_t s, long long n, int nbatch, const int *list, const int *boff, const int *bptr,
+                          int4 *desc);
 hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *W, double wscale,
-                           int npair, const int *pown, const int *plist, const int *lptr, const int *list,
-                           const int *boff, int norb, double *DK);
+                           int npair, const int *pown, const int *plist, const int *lptr, const int4 *desc, int norb,
+                           double *DK);
 // limits of the allocation-free H(k) (its workspace is a fixed device array)
 constexpr int kHkNaMaxPhase = 65536, kHkNaMaxK = 8192, kHkNaMaxR = 8192;
 // H(k) with the phases and staged inputs in the device array of gint_hr.hip
