@@ -269,15 +269,21 @@ def run_batched(args, torch, gi, g, dev):
     F = [torch.empty((n, 3), dtype=torch.float64, device=dev) for n in b.natom]
 
     def step():
-        b.build_H(V, out=H)
-        b.build_rho(D, out=rho)
-        b.force(V, D, out=F)
+        if args.separate:
+            b.build_H(V, out=H)
+            b.build_rho(D, out=rho)
+            b.force(V, D, out=F)
+        else:
+            b.H_rho_force(V, D, H=H, rho=rho, out=F)  # one graph replay for all three
 
     def seq_step():
         for i, p in enumerate(b.cells):
-            p.build_H(V[i], out=H[i])
-            p.build_rho(D[i], out=rho[i])
-            p.force(V[i], D[i], out=F[i])
+            if args.separate:
+                p.build_H(V[i], out=H[i])
+                p.build_rho(D[i], out=rho[i])
+                p.force(V[i], D[i], out=F[i])
+            else:
+                p.H_rho_force(V[i], D[i], H=H[i], rho=rho[i], out=F[i])
 
     _progress(f"warmup {args.warmup}")
     for _ in range(max(args.warmup, 1)):
@@ -316,8 +322,10 @@ def run_batched(args, torch, gi, g, dev):
         "data": "synthetic",
         "config": {
             "workload": (f"{args.cells} independent Si cells (8/16/32/64 atoms: {kinds.tolist()}), DZP rc=8 bohr, "
-                         f"{ngrid} mesh points in total; one step = H + rho + dE/dR of every cell, one graph "
-                         "replay each, fixed geometry"),
+                         f"{ngrid} mesh points in total; one step = H + rho + dE/dR of every cell, "
+                         + ("one graph replay each" if args.separate else
+                            "one graph replay of gint_H_rho_force over every cell")
+                         + ", fixed geometry"),
             "sequential_ms_per_step": seq_ms,
             "graph_speedup_vs_sequential": seq_ms / ms_step,
             "alg_tflops_whole_step": alg / (ms_step * 1e-3) / 1e12,

@@ -430,6 +430,12 @@ gint_status gint_batch_build_rho(gint_batch batch, const double *const *D_dev, d
 gint_status gint_batch_force(gint_batch batch, const double *const *W_dev, const double *const *D_dev,
                              double *const *dEdR_dev);
 
+/* H, rho and dE/dR of every cell in one graph replay (gint_H_rho_force per
+ * cell, on the cells' chains; the same bits as the single-cell call).  The
+ * arrays hold ncell device pointers each. */
+gint_status gint_batch_H_rho_force(gint_batch batch, const double *const *V_dev, const double *const *D_dev,
+                                   double *const *H_dev, double *const *rho_dev, double *const *dEdR_dev);
+
 /* Choose each cell's batch shape by timing: for every class of cells with
  * the same mesh and atom count, time `reps` rounds of H + rho + dE/dR of
  * the class's first cell on the batch stream for each candidate shape

@@ -35,7 +35,8 @@ EXPORTS = (
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
     "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_build_DK",
-    "gint_psibeta_create", "gint_psibeta_nproj", "gint_psibeta_overlap", "gint_psibeta_destroy", "gint_HR_to_Hk_noalloc",
+    "gint_psibeta_create", "gint_psibeta_nproj", "gint_psibeta_overlap", "gint_psibeta_destroy",
+    "gint_batch_H_rho_force", "gint_HR_to_Hk_noalloc",
 )
 KERNELS = ("bin", "H_blocks", "H_reduce", "rho", "pack_D", "force", "force_reduce", "H_fill", "rho_force",
            "H_rho_force", "HR", "DK", "psibeta")
@@ -158,6 +159,8 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).argtypes = [P, PP, PP]
     lib.gint_batch_force.restype = st
     lib.gint_batch_force.argtypes = [P, PP, PP, PP]
+    lib.gint_batch_H_rho_force.restype = st
+    lib.gint_batch_H_rho_force.argtypes = [P, PP, PP, PP, PP, PP]
     lib.gint_batch_autotune.restype = st
     lib.gint_batch_autotune.argtypes = [P, PP, PP, PP, PP, PP, ctypes.c_int, ip]
     lib.gint_batch_sync.restype = st
@@ -660,6 +663,18 @@ class GintBatch:
         _check(self._lib.gint_batch_build_rho(self._handle(), self._ptrs(D, nn, "D"),
                                               self._ptrs(out, self.ngrid, "rho")))
         return out
+
+    def H_rho_force(self, V, D, H=None, rho=None, out=None):
+        """H, rho and dE/dR of every cell in one graph replay."""
+        nn = [n * n for n in self.norb]
+        H = self._outs(H, [(n, n) for n in self.norb], V[0])
+        rho = self._outs(rho, [(g,) for g in self.ngrid], V[0])
+        out = self._outs(out, [(a, 3) for a in self.natom], V[0])
+        _check(self._lib.gint_batch_H_rho_force(self._handle(), self._ptrs(V, self.ngrid, "V"),
+                                                self._ptrs(D, nn, "D"), self._ptrs(H, nn, "H"),
+                                                self._ptrs(rho, self.ngrid, "rho"),
+                                                self._ptrs(out, [3 * a for a in self.natom], "dEdR")))
+        return H, rho, out
 
     def force(self, W, D, out=None):
         nn = [n * n for n in self.norb]

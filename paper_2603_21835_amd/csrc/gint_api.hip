@@ -1070,13 +1070,15 @@ gint_status gint_rho_force(gint_plan p, const double *W_dev, const double *D_dev
     return force_impl(p, W_dev, p->dV, D_dev, dEdR_dev, rho_dev);
 }
 
-gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_dev, double *H_dev, double *rho_dev,
-                             double *dEdR_dev)
+}  // extern "C"
+
+namespace {
+// H, rho and the force of one cell: the fused pass when a batch fits it;
+// otherwise H and the rho + force pass on a second stream of the plan
+// (two_streams) or one after the other on the plan's stream.
+gint_status H_rho_force_impl(gint_plan p, const double *V_dev, const double *D_dev, double *H_dev, double *rho_dev,
+                             double *dEdR_dev, bool two_streams)
 {
-    STCHK(check_plan(p));
-    if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
-        return fail(GINT_EINVAL, "V, D, H, rho and dEdR must be non-NULL device pointers");
-    HIPCHK(hipSetDevice(p->device));
     if (H_rho_force_fits((int)p->prec, p->geo.P, p->nbmax, p->mno)) {
         // one pass per H slab evaluates each batch's orbital tiles once for
         // the H blocks, rho and the force partials
@@ -1104,6 +1106,10 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
                     [&] { return launch_force_reduce(st, p->geo, bn, B, p->Fent.as<double>(), dEdR_dev); }));
         return GINT_OK;
     }
+    if (!two_streams) {
+        STCHK(build_H_impl(p, V_dev, p->dV, H_dev));
+        return force_impl(p, V_dev, p->dV, D_dev, dEdR_dev, rho_dev);
+    }
     // batches too large for the fused pass: H beside the rho + force pass on
     // a second stream
     if (!p->aux) {
@@ -1121,6 +1127,19 @@ gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_d
     HIPCHK(hipEventRecord(p->ev_join, p->aux));
     HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join, 0));
     return GINT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gint_status gint_H_rho_force(gint_plan p, const double *V_dev, const double *D_dev, double *H_dev, double *rho_dev,
+                             double *dEdR_dev)
+{
+    STCHK(check_plan(p));
+    if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
+        return fail(GINT_EINVAL, "V, D, H, rho and dEdR must be non-NULL device pointers");
+    HIPCHK(hipSetDevice(p->device));
+    return H_rho_force_impl(p, V_dev, D_dev, H_dev, rho_dev, dEdR_dev, true);
 }
 
 }  // extern "C"
@@ -1550,13 +1569,15 @@ struct gint_psibeta_s {
     gint_plan plan = nullptr;
     long long gen = -1;  // list generation of the plan the neighbour lists were built for
     int nprad = 0, npa = 0, nproj = 0, nang = 0, nrq = 0;
-    int max_entries = 0;  // most neighbour entries of one projector atom
+    int nent = 0;  // neighbour entries over all projector atoms
+    int nps = 0;   // most projectors of one species (row stride of the table)
     double rb_max = 0.0;
     std::vector<int> pin_h, prow_h;  // projector atoms (input order) and their first rows
     std::vector<double> prb_h;       // projector cutoff of each projector atom
     std::vector<int> sp_nproj;       // projectors per species
     DevBuf prad, psp, pknots, ps0, psn, pcoef, pscratch, ang, rq;
     DevBuf pint, pin, prow, prb, cnt, ioff, eptr, ent, img;
+    DevBuf tab;  // W e^{-iA.r} beta_p at every grid point of every projector atom (per call)
 };
 
 namespace {
@@ -1612,7 +1633,7 @@ gint_status psibeta_lists(gint_psibeta b)
     std::vector<int> ioff(nn), ent, eptr(npa + 1);
     long long tot = 0;
     for (int a = 0; a < npa; ++a) {
-        eptr[a] = (int)(ent.size() / 3);
+        eptr[a] = (int)(ent.size() / 4);
         for (int J = 0; J < natom; ++J) {
             const size_t t = (size_t)a * natom + J;
             ioff[t] = (int)tot;
@@ -1620,19 +1641,18 @@ gint_status psibeta_lists(gint_psibeta b)
                 ent.push_back(J);
                 ent.push_back((int)tot);
                 ent.push_back(cnt[t]);
+                ent.push_back(a);
             }
             tot += cnt[t];
             if (tot >= 0x7fffffffLL)
                 return fail(GINT_EUNSUPPORTED, "projector neighbour lists exceed 2^31 images");
         }
     }
-    eptr[npa] = (int)(ent.size() / 3);
-    b->max_entries = 0;
-    for (int a = 0; a < npa; ++a)
-        b->max_entries = std::max(b->max_entries, eptr[a + 1] - eptr[a]);
+    eptr[npa] = (int)(ent.size() / 4);
+    b->nent = eptr[npa];
     STCHK(b->ioff.ensure(sizeof(int) * nn));
     STCHK(b->img.ensure(sizeof(int) * (size_t)std::max(tot, 1LL)));
-    STCHK(b->ent.ensure(sizeof(int) * std::max(ent.size(), (size_t)3)));
+    STCHK(b->ent.ensure(sizeof(int) * std::max(ent.size(), (size_t)4)));
     STCHK(b->eptr.ensure(sizeof(int) * (npa + 1)));
     HIPCHK(hipMemcpyAsync(b->ioff.p, ioff.data(), sizeof(int) * nn, hipMemcpyHostToDevice, s));
     if (!ent.empty())
@@ -1738,6 +1758,7 @@ gint_status gint_psibeta_create(gint_plan p, int nspecies, const gint_species *p
             }
         sp[s].norb = orb;
         b->sp_nproj[s] = orb;
+        b->nps = std::max(b->nps, orb);
         b->rb_max = std::max(b->rb_max, sp[s].rc);
     }
     b->nprad = (int)rad.size();
@@ -1777,6 +1798,9 @@ gint_status gint_psibeta_create(gint_plan p, int nspecies, const gint_species *p
         if ((st = upload(b->pin, b->pin_h.data(), sizeof(int) * b->npa)) != GINT_OK) break;
         if ((st = upload(b->prow, b->prow_h.data(), sizeof(int) * b->npa)) != GINT_OK) break;
         if ((st = upload(b->prb, b->prb_h.data(), sizeof(double) * b->npa)) != GINT_OK) break;
+        if ((st = b->tab.ensure(2 * sizeof(double) * (size_t)b->npa * nang * nrq * (size_t)std::max(b->nps, 1))) !=
+            GINT_OK)
+            break;
         if (b->nprad > 0) {
             if ((st = upload(b->prad, rad.data(), sizeof(DevRadial) * rad.size())) != GINT_OK) break;
             if ((st = upload(b->pknots, knots.data(), sizeof(double) * knots.size())) != GINT_OK) break;
@@ -1825,9 +1849,9 @@ gint_status gint_psibeta_overlap(gint_psibeta b, const double A[3], double *Q_de
     STCHK(timed(p, GINT_K_PSIBETA, [&] {
         return launch_psibeta(p->stream, p->geo, p->basis(), b->prad.as<DevRadial>(), b->psp.as<DevSpecies>(),
                               b->pcoef.as<double>(), b->nprad, b->npa, b->pint.as<int>(), b->pin.as<int>(),
-                              b->prow.as<int>(), b->eptr.as<int>(), b->ent.as<int>(), b->img.as<int>(),
+                              b->prow.as<int>(), b->ent.as<int4>(), b->nent, b->img.as<int>(),
                               p->pos_in.as<double>(), b->nang, b->ang.as<double>(), b->nrq, b->rq.as<double>(), A,
-                              p->norb, b->max_entries, Q_dev);
+                              b->nps, b->tab.p, p->norb, Q_dev);
     }));
     return GINT_OK;
 }
@@ -1875,11 +1899,11 @@ struct gint_batch_s {
     hipStream_t chains[kChains] = {};
     hipEvent_t fork = nullptr, join[kChains] = {};
     DevBuf hpart[kChains];
-    GraphSlot gH, gR, gF;
+    GraphSlot gH, gR, gF, gHRF;
 
     ~gint_batch_s()
     {
-        for (GraphSlot *g : {&gH, &gR, &gF})
+        for (GraphSlot *g : {&gH, &gR, &gF, &gHRF})
             if (g->exec)
                 (void)hipGraphExecDestroy(g->exec);
         for (auto p : plans)
@@ -2131,6 +2155,29 @@ gint_status gint_batch_force(gint_batch b, const double *const *W_dev, const dou
     return run_graph(b, b->gF, sig, [&]() -> gint_status {
         for (int i : b->order)
             STCHK(force_impl(b->plans[i], W_dev[i], b->plans[i]->dV, D_dev[i], dEdR_dev[i]));
+        return GINT_OK;
+    });
+}
+
+gint_status gint_batch_H_rho_force(gint_batch b, const double *const *V_dev, const double *const *D_dev,
+                                   double *const *H_dev, double *const *rho_dev, double *const *dEdR_dev)
+{
+    STCHK(check_batch(b));
+    if (!V_dev || !D_dev || !H_dev || !rho_dev || !dEdR_dev)
+        return fail(GINT_EINVAL, "pointer arrays must be non-NULL");
+    const int n = (int)b->plans.size();
+    std::vector<const void *> sig;
+    for (int i = 0; i < n; ++i) {
+        if (!V_dev[i] || !D_dev[i] || !H_dev[i] || !rho_dev[i] || !dEdR_dev[i])
+            return fail(GINT_EINVAL, "cell %d: NULL device pointer", i);
+        for (const void *q : {(const void *)V_dev[i], (const void *)D_dev[i], (const void *)H_dev[i],
+                              (const void *)rho_dev[i], (const void *)dEdR_dev[i]})
+            sig.push_back(q);
+    }
+    HIPCHK(hipSetDevice(b->device));
+    return run_graph(b, b->gHRF, sig, [&]() -> gint_status {
+        for (int i : b->order)
+            STCHK(H_rho_force_impl(b->plans[i], V_dev[i], D_dev[i], H_dev[i], rho_dev[i], dEdR_dev[i], false));
         return GINT_OK;
     });
 }

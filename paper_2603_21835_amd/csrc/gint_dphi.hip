@@ -23,6 +23,8 @@
 // partials in HBM, no atomics, repeatable bits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gint_device.h"
 
 namespace gint {
@@ -194,7 +196,10 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
                                                            double *__restrict__ DK)
 {
     constexpr int NV = kDKVals;
-    constexpr int REG = NV * 2 * P * kMaxOrb;  // doubles of one wave's LDS region
+    // the batch's points in passes of HP (16 KB of LDS per wave, so that two
+    // workgroups share a compute unit)
+    constexpr int HP = P < 16 ? P : 16;
+    constexpr int REG = NV * 2 * HP * kMaxOrb;  // doubles of one wave's LDS region
     extern __shared__ __align__(16) double s_dyn[];
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
     const bool self = I == J;
     double *reg = s_dyn + (size_t)wave * REG;
     // element (value v, slot s, point q, orbital o) of this wave's region
-    auto at = [&](int v, int s, int q) { return reg + ((size_t)(v * 2 + s) * P + q) * kMaxOrb; };
+    auto at = [&](int v, int s, int q) { return reg + ((size_t)(v * 2 + s) * HP + q) * kMaxOrb; };
 
     typedef MM<double>::acc acc_t;
     acc_t cIJ[3], cJI[3];
@@ -231,19 +236,21 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
         int ib[3];
         batch_coords(g, b, ib);
 
+#pragma unroll 1
+        for (int h = 0; h < P / HP; ++h) {
         // ---- phit, grad phit of (atom slot s, point qp): one lane each ----
-        wave_lds_sync();  // the previous batch's operand reads are done
+        wave_lds_sync();  // the previous pass's operand reads are done
         {
-            const int s = lane / P, qp = lane % P;
+            const int s = lane / HP, ql = lane % HP, qp = h * HP + ql;
             if (s < 2 && !(self && s == 1)) {
                 const int e = s == 0 ? dc.y : dc.z;
                 const int atom = s == 0 ? I : J;
                 const DevSpecies &S = s_sp[bs.spc[atom]];
                 int n[3];
                 const bool valid = batch_point(g, ib, qp, n);
-                const int swz = qp & 15;
-                double *row = at(0, s, qp);
-                const int vs = 2 * P * kMaxOrb;  // stride between values
+                const int swz = ql & 15;
+                double *row = at(0, s, ql);
+                const int vs = 2 * HP * kMaxOrb;  // stride between values
                 for (int o = valid ? S.norb : 0; o < kMaxOrb; ++o)
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
@@ -265,17 +272,18 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
         // ---- the six (three for I == J) blocks on the matrix cores ----
         const int sj = self ? 0 : 1;
 #pragma unroll
-        for (int kk = 0; kk < P / 4; ++kk) {
-            const int qp = 4 * kk + lk;
-            const int o = li ^ (qp & 15);
-            const double aI = at(0, 0, qp)[o];
-            const double aJ = at(0, sj, qp)[o];
+        for (int kk = 0; kk < HP / 4; ++kk) {
+            const int ql = 4 * kk + lk;
+            const int o = li ^ (ql & 15);
+            const double aI = at(0, 0, ql)[o];
+            const double aJ = at(0, sj, ql)[o];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                cIJ[c] = MM<double>::mma(aI, at(1 + c, sj, qp)[o], cIJ[c]);
+                cIJ[c] = MM<double>::mma(aI, at(1 + c, sj, ql)[o], cIJ[c]);
                 if (!self)
-                    cJI[c] = MM<double>::mma(aJ, at(1 + c, 0, qp)[o], cJI[c]);
+                    cJI[c] = MM<double>::mma(aJ, at(1 + c, 0, ql)[o], cJI[c]);
             }
+        }
         }
     }
 
@@ -312,7 +320,13 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
     }
 }
 
-size_t DK_pairs_lds(int P) { return sizeof(double) * (size_t)kDKWaves * kDKVals * 2 * P * kMaxOrb; }
+size_t DK_pairs_lds(int P)
+{
+    const int HP = P < 16 ? P : 16;
+    // the phi / grad phi rows, and after the list the waves' six blocks
+    return std::max(sizeof(double) * (size_t)kDKWaves * kDKVals * 2 * HP * kMaxOrb,
+                    sizeof(double) * (size_t)kDKWaves * 6 * 256);
+}
 
 hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *W, double wscale,
                            int npair, const int *pown, const int *plist, const int *lptr, const int4 *desc, int norb,

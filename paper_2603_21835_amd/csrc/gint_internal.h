@@ -164,9 +164,8 @@ hipError_t launch_pb_images(hipStream_t s, const Geo &g, const Basis &b, int npa
                             const int *m, int *cnt, const int *off, int *img);
 hipError_t launch_psibeta(hipStream_t s, const Geo &g, const Basis &b, const DevRadial *prad, const DevSpecies *psp,
                           const double *pcoef, int nprad, int npa, const int *pint, const int *pin, const int *prow,
-                          const int *eptr, const int *ent, const int *img, const double *pos, int nang,
-                          const double *ang, int nrq, const double *rq, const double *A, int norb, int max_entries,
-                          double *Q);
+                          const int4 *ent, int nent, const int *img, const double *pos, int nang, const double *ang,
+                          int nrq, const double *rq, const double *A, int nps, void *tab, int norb, double *Q);
 // moving-basis matrix DK (gint_dphi.hip): one workgroup per owned atom pair
 // over the pair's block list; DK must be zero beforehand
 size_t DK_pairs_lds(int P);

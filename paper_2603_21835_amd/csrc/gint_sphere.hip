@@ -11,15 +11,13 @@
 // I's species), beta_p(x) = b(|x|) Y_lm(x/|x|), phit the orbital folded over
 // lattice images.
 //
-// One workgroup per projector atom, as in the paper's atom-level batching,
-// but the sum over quadrature points is a dense contraction and runs on the
-// FP64 matrix cores: points are taken 64 at a time (one per lane); the workgroup first
-// tabulates W e^{-iA.r} beta_p at the chunk's points in LDS (the A operands,
-// real and imaginary parts), then each wave evaluates phit of its
-// neighbouring atoms at the same points (one lane per point, one spline
-// evaluation per radial) and accumulates Q_re, Q_im of every (projector,
-// orbital) block in registers across all chunks.  Each (I, J) block is
-// written once: no atomics, repeatable bits.
+// The paper batches per projector atom and reduces over quadrature points
+// with wave and shared-memory reductions.  Here the sum over quadrature
+// points is a dense contraction and runs on the FP64 matrix cores: a table
+// pass writes W e^{-iA.r} beta_p at every grid point of every projector atom,
+// then one wave per (projector atom, neighbouring atom) pair streams the
+// table and the neighbour's orbitals at the same points, 64 at a time, into
+// two 16 x 16 accumulators (real and imaginary parts).
 #include <hip/hip_runtime.h>
 
 #include "gint_device.h"
@@ -28,10 +26,8 @@ namespace gint {
 
 namespace {
 
-constexpr int kPBWaves = 8;
-constexpr int kPBChunk = 64;                    // quadrature points per chunk (one per lane)
-constexpr int kPBPerWave = 2;                   // neighbour entries per wave
-constexpr int kPBGroup = kPBWaves * kPBPerWave;  // entries per workgroup
+constexpr int kPBWaves = 4;   // one neighbour entry per wave
+constexpr int kPBChunk = 64;  // quadrature points per chunk (one per lane)
 
 }  // namespace
 
@@ -118,171 +114,170 @@ hipError_t launch_pb_entries(hipStream_t s, int npa, int natom, const int *cnt, 
 }
 
 // ---------------------------------------------------------------------------
-// The overlaps.  Workgroup (a, gi) takes the gi-th group of kPBGroup
-// neighbour entries of projector atom a (ngrp groups per atom, the last
-// ones possibly empty), so that each atom's work spreads over several
-// compute units.  Projector atom a: internal index pint[a], input index
-// pin[a], first row prow[a] of Q, entries eptr[a] .. eptr[a+1] of ent
-// (orbital atom J internal, first image, image count).  prad / psp: the
-// projector radials and per-species projector tables (DevSpecies of the
-// projectors: rad0, nrad, norb = projectors, rc = rb); pcoef their spline
-// coefficients.  pos: positions as given (input order) for the phase.
-// Q: nproj x norb complex (re, im), zero outside the written blocks.
-__global__ __launch_bounds__(64 * kPBWaves) void k_psibeta(
-    Geo g, Basis bs, const DevRadial *__restrict__ prad, const DevSpecies *__restrict__ psp,
-    const double *__restrict__ pcoef, int nprad, int npa, const int *__restrict__ pint, const int *__restrict__ pin,
-    const int *__restrict__ prow, const int *__restrict__ eptr, const int *__restrict__ ent,
-    const int *__restrict__ img, const double *__restrict__ pos, int nang, const double *__restrict__ ang, int nrq,
-    const double *__restrict__ rq, double A0, double A1, double A2, int norb, int ngrp, double *__restrict__ Q)
+// The overlaps, in two kernels.
+//
+// k_pb_table: one thread per (projector atom a, quadrature point q) writes
+// W_q e^{-i A.(tau_I + x_q)} beta_p(x_q) for the atom's projectors p as
+// (re, im) pairs: tab[(a npts + q) nps + p].  prad / psp: the projector
+// radials and per-species tables (DevSpecies of the projectors: rad0, nrad,
+// norb = projectors, rc = rb); pcoef their spline coefficients; pos the
+// positions as given (input order, for the phase).
+//
+// k_psibeta: one wave per neighbour entry e = (projector atom a, orbital
+// atom J with its images), four waves per workgroup, consecutive entries
+// (the same projector atom) on one XCD.  Per chunk of 64 points the wave
+// evaluates phit_J at the points (one lane per point, one spline
+// evaluation per radial) into its own LDS rows and contracts them with the
+// table's rows on the FP64 matrix cores (A: the table, real and imaginary
+// parts; B: phit), keeping the two 16 x 16 accumulators for the whole
+// quadrature grid; waves never wait for each other.  Each (a, J) block is
+// written once: no atomics, repeatable bits.
+__global__ __launch_bounds__(256) void k_pb_table(Geo g, Basis bs, const DevRadial *__restrict__ prad,
+                                                  const DevSpecies *__restrict__ psp,
+                                                  const double *__restrict__ pcoef, int nprad, int npa,
+                                                  const int *__restrict__ pint, const int *__restrict__ pin,
+                                                  const double *__restrict__ pos, int nang,
+                                                  const double *__restrict__ ang, int nrq,
+                                                  const double *__restrict__ rq, double A0, double A1, double A2,
+                                                  int nps, double2 *__restrict__ tab)
+{
+    __shared__ DevRadial s_prad[kMaxRadTotal];
+    __shared__ double s_row[256][kMaxOrb];
+    for (int k = threadIdx.x; k < nprad; k += 256)
+        s_prad[k] = prad[k];
+    __syncthreads();
+    const int npts = nang * nrq;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)npa * npts)
+        return;
+    const int a = (int)(t / npts), q = (int)(t - (long long)a * npts);
+    const DevSpecies P = psp[bs.spc[pint[a]]];
+    const double rb = P.rc;
+    const int i = q / nang, j = q - i * nang;
+    const double r = rb * rq[2 * i];
+    const double W = rb * rq[2 * i + 1] * r * r * ang[4 * j + 3];
+    const double x[3] = {r * ang[4 * j], r * ang[4 * j + 1], r * ang[4 * j + 2]};
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double *row = s_row[threadIdx.x];
+    for (int o = 0; o < kMaxOrb; ++o)
+        row[o] = 0.0;
+    // beta at x: one image at the centre
+    eval_orbitals<double, 1>(g, s_prad, P.rad0, P.rad0 + P.nrad, rb, pcoef, zero, 1, 0, 0, nullptr, x, row, 0);
+    const int Iin = pin[a];
+    const double th = -(A0 * (pos[3 * Iin] + x[0]) + A1 * (pos[3 * Iin + 1] + x[1]) + A2 * (pos[3 * Iin + 2] + x[2]));
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    double2 *o = tab + (size_t)t * nps;
+    for (int p = 0; p < nps; ++p)
+        o[p] = p < P.norb ? double2{W * cs * row[p], W * sn * row[p]} : double2{0.0, 0.0};
+}
+
+__global__ __launch_bounds__(64 * kPBWaves) void k_psibeta(Geo g, Basis bs, const DevSpecies *__restrict__ psp,
+                                                          int nent, const int *__restrict__ pint,
+                                                          const int *__restrict__ prow, const int4 *__restrict__ ent,
+                                                          const int *__restrict__ img, int nang,
+                                                          const double *__restrict__ ang, int nrq,
+                                                          const double *__restrict__ rq, int nps,
+                                                          const double2 *__restrict__ tab, int norb,
+                                                          double *__restrict__ Q)
 {
     constexpr int CH = kPBChunk;
-    __shared__ DevRadial s_rad[kMaxRadTotal], s_prad[kMaxRadTotal];
+    __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
-    // dynamic LDS: [re, im][CH][16] W e^{-iA.r} beta at the chunk's points,
-    // then [wave][CH][16] phit of one neighbour per wave
-    extern __shared__ __align__(16) double s_dyn[];
-    double(*s_B)[CH][kMaxOrb] = reinterpret_cast<double(*)[CH][kMaxOrb]>(s_dyn);
-    double(*s_phi)[CH][kMaxOrb] = reinterpret_cast<double(*)[CH][kMaxOrb]>(s_dyn + 2 * CH * kMaxOrb);
+    __shared__ double s_phi[kPBWaves][CH][kMaxOrb];  // phit of the wave's neighbour at the chunk's points
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
-    const int t = xcd_batch(blockIdx.x, 0, npa * ngrp);  // consecutive groups of one atom share an XCD
-    const int a = t < 0 ? -1 : t / ngrp, gi = t < 0 ? 0 : t - a * ngrp;
     for (int k = tid; k < g.nrad; k += 64 * kPBWaves)
         s_rad[k] = bs.rad[k];
-    for (int k = tid; k < nprad; k += 64 * kPBWaves)
-        s_prad[k] = prad[k];
     for (int k = tid; k < g.nspecies; k += 64 * kPBWaves)
         s_sp[k] = bs.sp[k];
     __syncthreads();
-    if (a < 0)
+    const int nwg = (nent + kPBWaves - 1) / kPBWaves;
+    const int wg = xcd_batch(blockIdx.x, 0, nwg);
+    const int e = wg * kPBWaves + wave;
+    if (wg < 0 || e >= nent)
         return;
+    const int4 en = ent[e];  // (orbital atom J, first image, image count, projector atom a)
+    const int J = en.x, io = en.y, cnt = en.z, a = en.w;
     const int I = pint[a];
     const DevSpecies P = psp[bs.spc[I]];
     const double rb = P.rc;
     const double X[3] = {bs.xw[3 * I], bs.xw[3 * I + 1], bs.xw[3 * I + 2]};
-    const int Iin = pin[a];
-    const double T[3] = {pos[3 * Iin], pos[3 * Iin + 1], pos[3 * Iin + 2]};
+    const double XJ[3] = {bs.xw[3 * J], bs.xw[3 * J + 1], bs.xw[3 * J + 2]};
+    const DevSpecies &S = s_sp[bs.spc[J]];
     const int npts = nang * nrq;
     const int nchunk = (npts + CH - 1) / CH;
-    const int e0 = eptr[a] + gi * kPBGroup, e1 = min(eptr[a + 1], e0 + kPBGroup);
-    if (e0 >= e1)
-        return;
+    const int pk0 = img[io];
+    const double2 *ta = tab + (size_t)a * npts * nps;
     double(*phw)[kMaxOrb] = s_phi[wave];
-
-    {
-        const int g0 = e0;
-        typedef MM<double>::acc acc_t;
-        acc_t cre[kPBPerWave], cim[kPBPerWave];
+    const bool prow_ok = li < P.norb;  // this lane's table row (projector li) exists
+    typedef MM<double>::acc acc_t;
+    acc_t cre = MM<double>::zero(), cim = MM<double>::zero();
+    for (int c = 0; c < nchunk; ++c) {
+        // the chunk's table values of this lane (in flight during the evaluation)
+        double2 av[CH / 4];
 #pragma unroll
-        for (int u = 0; u < kPBPerWave; ++u)
-            cre[u] = cim[u] = MM<double>::zero();
-        for (int c = 0; c < nchunk; ++c) {
-            __syncthreads();  // every wave is done with the previous chunk's table
-            if (wave == 0) {
-                const int qg = c * CH + lane;
-                double *row = s_B[0][lane];
-                const int swz = lane & 15;
-                for (int o = 0; o < kMaxOrb; ++o)
-                    row[o] = 0.0;
-                if (qg < npts) {
-                    const int i = qg / nang, j = qg - i * nang;
-                    const double r = rb * rq[2 * i];
-                    const double W = rb * rq[2 * i + 1] * r * r * ang[4 * j + 3];
-                    const double x[3] = {r * ang[4 * j], r * ang[4 * j + 1], r * ang[4 * j + 2]};
-                    const double zero[3] = {0.0, 0.0, 0.0};
-                    // beta at x: one image at the centre
-                    eval_orbitals<double, 1>(g, s_prad, P.rad0, P.rad0 + P.nrad, rb, pcoef, zero, 1, 0, 0, img, x,
-                                             row, swz);
-                    const double th = -(A0 * (T[0] + x[0]) + A1 * (T[1] + x[1]) + A2 * (T[2] + x[2]));
-                    double sn, cs;
-                    sincos(th, &sn, &cs);
-                    for (int o = 0; o < kMaxOrb; ++o) {
-                        const double b = row[o];
-                        row[o] = W * cs * b;
-                        s_B[1][lane][o] = W * sn * b;
-                    }
-                } else {
-                    for (int o = 0; o < kMaxOrb; ++o)
-                        s_B[1][lane][o] = 0.0;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kPBPerWave; ++u) {
-                const int e = g0 + wave + kPBWaves * u;
-                if (e < e1) {  // (no early exit: keeps the accumulators in registers)
-                const int J = ent[3 * e], io = ent[3 * e + 1], cnt = ent[3 * e + 2];
-                const DevSpecies &S = s_sp[bs.spc[J]];
-                // phit_J at this lane's point (the point relative to the
-                // wrapped position of I; phit is periodic)
-                wave_lds_sync();  // the previous neighbour's operand reads are done
-                {
-                    const int qg = c * CH + lane;
-                    double *row = phw[lane];
-                    const int swz = lane & 15;
-                    for (int o = qg < npts ? S.norb : 0; o < kMaxOrb; ++o)
-                        row[o ^ swz] = 0.0;
-                    if (qg < npts) {
-                        const int i = qg / nang, j = qg - i * nang;
-                        const double r = rb * rq[2 * i];
-                        const double pt[3] = {X[0] + r * ang[4 * j], X[1] + r * ang[4 * j + 1],
-                                              X[2] + r * ang[4 * j + 2]};
-                        const double XJ[3] = {bs.xw[3 * J], bs.xw[3 * J + 1], bs.xw[3 * J + 2]};
-                        eval_orbitals<double, 1>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, XJ, cnt, img[io],
-                                                 io, img, pt, row, swz);
-                    }
-                }
-                wave_lds_sync();
-#pragma unroll
-                for (int kk = 0; kk < CH / 4; ++kk) {
-                    const int q = 4 * kk + lk;
-                    const int o = li ^ (q & 15);
-                    const double bv = phw[q][o];
-                    cre[u] = MM<double>::mma(s_B[0][q][o], bv, cre[u]);
-                    cim[u] = MM<double>::mma(s_B[1][q][o], bv, cim[u]);
-                }
-                }
+        for (int kk = 0; kk < CH / 4; ++kk) {
+            const int q = c * CH + 4 * kk + lk;
+            av[kk] = (prow_ok && q < npts) ? ta[(size_t)q * nps + li] : double2{0.0, 0.0};
+        }
+        // phit_J at this lane's point (relative to the wrapped position of
+        // the projector atom; phit is periodic)
+        wave_lds_sync();  // the previous chunk's operand reads are done
+        {
+            const int qg = c * CH + lane;
+            double *row = phw[lane];
+            const int swz = lane & 15;
+            for (int o = qg < npts ? S.norb : 0; o < kMaxOrb; ++o)
+                row[o ^ swz] = 0.0;
+            if (qg < npts) {
+                const int i = qg / nang, j = qg - i * nang;
+                const double r = rb * rq[2 * i];
+                const double pt[3] = {X[0] + r * ang[4 * j], X[1] + r * ang[4 * j + 1], X[2] + r * ang[4 * j + 2]};
+                eval_orbitals<double, 1>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, XJ, cnt, pk0, io, img, pt,
+                                         row, swz);
             }
         }
-        // this pass's blocks: rows of the projectors of I, columns of J
+        wave_lds_sync();
 #pragma unroll
-        for (int u = 0; u < kPBPerWave; ++u) {
-            const int e = g0 + wave + kPBWaves * u;
-            if (e >= e1)
-                continue;
-            const int J = ent[3 * e];
-            const int Jin = bs.perm[J];
-            const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
+        for (int kk = 0; kk < CH / 4; ++kk) {
+            const int q = 4 * kk + lk;
+            const double bv = phw[q][li ^ (q & 15)];
+            cre = MM<double>::mma(av[kk].x, bv, cre);
+            cim = MM<double>::mma(av[kk].y, bv, cim);
+        }
+    }
+    // rows of the projectors of I, columns of the orbitals of J
+    const int Jin = bs.perm[J];
+    const int nu0 = bs.orb0[Jin], nJ = bs.orb0[Jin + 1] - nu0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int p = MM<double>::row(lk, v);
-                if (p < P.norb && li < nJ) {
-                    double2 *o = reinterpret_cast<double2 *>(Q) + (size_t)(prow[a] + p) * norb + nu0 + li;
-                    *o = double2{cre[u][v], cim[u][v]};
-                }
-            }
+    for (int v = 0; v < 4; ++v) {
+        const int p = MM<double>::row(lk, v);
+        if (p < P.norb && li < nJ) {
+            double2 *o = reinterpret_cast<double2 *>(Q) + (size_t)(prow[a] + p) * norb + nu0 + li;
+            *o = double2{cre[v], cim[v]};
         }
     }
 }
 
 hipError_t launch_psibeta(hipStream_t s, const Geo &g, const Basis &b, const DevRadial *prad, const DevSpecies *psp,
                           const double *pcoef, int nprad, int npa, const int *pint, const int *pin, const int *prow,
-                          const int *eptr, const int *ent, const int *img, const double *pos, int nang,
-                          const double *ang, int nrq, const double *rq, const double *A, int norb, int max_entries,
-                          double *Q)
+                          const int4 *ent, int nent, const int *img, const double *pos, int nang, const double *ang,
+                          int nrq, const double *rq, const double *A, int nps, void *tab, int norb, double *Q)
 {
-    if (npa <= 0 || max_entries <= 0)
+    if (npa <= 0 || nent <= 0)
         return hipSuccess;
-    const int ngrp = (max_entries + kPBGroup - 1) / kPBGroup;
-    const long long nw = (long long)npa * ngrp;
-    const unsigned nblk = (unsigned)(kXcd * ((nw + kXcd - 1) / kXcd));
-    const size_t lds = sizeof(double) * (2 + kPBWaves) * kPBChunk * kMaxOrb;
-    const hipError_t e =
-        hipFuncSetAttribute((const void *)k_psibeta, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const long long nt = (long long)npa * nang * nrq;
+    hipLaunchKernelGGL(k_pb_table, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g, b, prad, psp, pcoef, nprad,
+                       npa, pint, pin, pos, nang, ang, nrq, rq, A[0], A[1], A[2], nps,
+                       static_cast<double2 *>(tab));
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_psibeta, dim3(nblk), dim3(64 * kPBWaves), lds, s, g, b, prad, psp, pcoef, nprad, npa, pint,
-                       pin, prow, eptr, ent, img, pos, nang, ang, nrq, rq, A[0], A[1], A[2], norb, ngrp, Q);
+    const int nwg = (nent + kPBWaves - 1) / kPBWaves;
+    const unsigned nblk = (unsigned)(kXcd * ((nwg + kXcd - 1) / kXcd));
+    hipLaunchKernelGGL(k_psibeta, dim3(nblk), dim3(64 * kPBWaves), 0, s, g, b, psp, nent, pint, prow, ent, img, nang,
+                       ang, nrq, rq, nps, static_cast<const double2 *>(tab), norb, Q);
     return hipGetLastError();
 }
 

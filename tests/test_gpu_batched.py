@@ -149,3 +149,39 @@ def test_autotune_keeps_results(tdev, cells, oracle_mod):
     Ho = o.H(c.V)
     assert np.abs(res[0][0] - Ho).max() / np.abs(Ho).max() <= 1e-10
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x3"])
+def test_batched_H_rho_force_matches_single_cells(tdev, cells, oracle_mod, precision):
+    # one graph replay for H, rho and dE/dR of every cell: bit for bit the
+    # single-cell gint_H_rho_force of each cell (twice: capture, then replay),
+    # and the FP64 oracle within 1e-10 (FP64) or 1e-6 Ha / 1e-6 (mixed)
+    torch, dev = tdev
+    import paper_2603_21835_amd as g
+
+    _say(f"case batched H_rho_force {precision}: {len(cells)} cells")
+    b = g.GintBatch(cells, cells[0].species, precision=precision)
+    V, D = _inputs(torch, dev, cells)
+    for rep in range(2):
+        H, rho, F = b.H_rho_force(V, D)
+        torch.cuda.synchronize()
+        for i, c in enumerate(cells):
+            p = g.GintPlan.from_workload(c, precision=precision)
+            Hs, rs, Fs = (t.cpu().numpy() for t in p.H_rho_force(V[i], D[i]))
+            assert np.array_equal(H[i].cpu().numpy(), Hs), (rep, i)
+            assert np.array_equal(rho[i].cpu().numpy(), rs), (rep, i)
+            assert np.array_equal(F[i].cpu().numpy(), Fs), (rep, i)
+            p.close()
+    i = 0  # the first cell against the oracle
+    o = oracle_mod.Oracle.from_workload(cells[i])
+    Ho, ro, Fo = o.H(cells[i].V), o.rho(cells[i].D), o.force(cells[i].V, cells[i].D)
+    Hn, rn, Fn = H[i].cpu().numpy(), rho[i].cpu().numpy(), F[i].cpu().numpy()
+    eH = np.abs(Hn - Ho).max()
+    er = np.linalg.norm(rn - ro) / np.linalg.norm(ro)
+    eF = np.abs(Fn - Fo).max() / np.abs(Fo).max()
+    _say(f"  cell 0 vs oracle: max|dH| {eH:.2e}  rho {er:.2e}  F {eF:.2e}")
+    if precision == "fp64":
+        assert eH <= 1e-10 * np.abs(Ho).max() and er <= 1e-10 and eF <= 1e-10
+    else:
+        assert eH <= 1e-6 and er <= 1e-6 and eF <= 1e-6
+    b.close()
