@@ -305,7 +305,10 @@ def run_batched(args, torch, gi, g, dev):
     seq_ms = (time.perf_counter() - t2) * 1e3
     s1 = sum(p.work()["sum_ng"] for p in b.cells)
     s2 = sum(p.work()["sum_ng2"] for p in b.cells)
-    alg = 3 * 2 * s2 + 2 * s1 + 6 * s1
+    # H, rho and dE/dR: with the fused call rho and the force share one
+    # contraction T = (D + D^T) phi (4 sum n^2 + 8 sum n); as three calls,
+    # three contractions
+    alg = (6 * s2 + 8 * s1) if args.separate else (4 * s2 + 8 * s1)
     kinds = np.bincount(gi.batched_kinds(args.cells), minlength=4)
     out = {
         "metric": "gint grid pts/s + MFMA util: FP64 vs mixed precision at stated |dH| (Si-512)",
