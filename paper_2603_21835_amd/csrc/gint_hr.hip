@@ -520,7 +520,10 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
 // c (c = a included), held in the MFMA result registers; then each lane
 // dots the gradients of its four orbitals at its point with w T_a
 // (grad4_dot) and the wave sums the lanes.  One partial per (batch, image),
-// summed per atom in batch order by k_forceR_reduce.
+// summed per atom in batch order by k_forceR_reduce.  The list indices of
+// both lattice vectors of every image pair (a, c) are looked up once per
+// batch into LDS, and each lane's D(R) elements of image c + 2 are loaded
+// while the products of image c run (three register sets in rotation).
 constexpr int kFRWaves = 8;  // (T_a of a whole image stays in registers)
 
 template <typename T, int P>
@@ -529,10 +532,12 @@ __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int
                                                        const int *__restrict__ img, Basis bs,
                                                        const int *__restrict__ wsh, HRMap m, int norb,
                                                        const double *__restrict__ DR, const double *__restrict__ W,
-                                                       double wscale, double *__restrict__ Fimg)
+                                                       double wscale, int nbmax, double *__restrict__ Fimg)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
+    // then per image pair (a, c), a * nb + c: list indices of R = T_c - T_a and of -R
+    int2 *s_q = reinterpret_cast<int2 *>(s_dyn + sizeof(T) * (size_t)nbmax * P * kRow);
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms], s_mu0[kMaxBatchAtoms];
@@ -588,6 +593,11 @@ __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int
                              row, swz);
         }
     }
+    for (int k = tid; k < nb * nb; k += blockDim.x) {
+        const int a = k / nb, c = k - a * nb;
+        const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
+        s_q[k] = int2{hr_lookup(m, Rx, Ry, Rz), hr_lookup(m, -Rx, -Ry, -Rz)};
+    }
     __syncthreads();
 
     constexpr int NT = P / 16;
@@ -598,35 +608,49 @@ __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int
 #pragma unroll
         for (int t = 0; t < NT; ++t)
             acc[t] = MM<T>::zero();
-        for (int c = 0; c < nb; ++c) {
-            const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
-            const int qp = hr_lookup(m, Rx, Ry, Rz);
-            const int qn = hr_lookup(m, -Rx, -Ry, -Rz);
-            if (qp < 0 && qn < 0)
-                continue;
+        // this lane's D(R) elements of image pair (a, c): both terms loaded
+        // (zero outside the blocks or for unlisted R), summed at use
+        auto load = [&](double (&xp)[4], double (&xn)[4], int c) {
+            const int2 q = s_q[a * nb + c];
             const int nJ = s_nor[c], mJ = s_mu0[c];
-            T aS[4];
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const int kc = lk + 4 * st;
-                double x = 0.0;
-                if (li < nI && kc < nJ) {
-                    if (qp >= 0)
-                        x += DR[qp * nn + (size_t)(mI + li) * norb + mJ + kc];
-                    if (qn >= 0)
-                        x += DR[qn * nn + (size_t)(mJ + kc) * norb + mI + li];
-                }
-                aS[st] = (T)x;
+                const bool in = li < nI && kc < nJ;
+                xp[st] = (in && q.x >= 0) ? DR[q.x * nn + (size_t)(mI + li) * norb + mJ + kc] : 0.0;
+                xn[st] = (in && q.y >= 0) ? DR[q.y * nn + (size_t)(mJ + kc) * norb + mI + li] : 0.0;
             }
+        };
+        auto block = [&](const double (&xp)[4], const double (&xn)[4], int c) {
+            const int2 q = s_q[a * nb + c];
+            if (q.x < 0 && q.y < 0)
+                return;
             const T *pC = s_phi + (size_t)(c * P) * kRow;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int p = 16 * t + li;
 #pragma unroll
                 for (int st = 0; st < 4; ++st)
-                    acc[t] = MM<T>::mma(aS[st], pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
+                    acc[t] = MM<T>::mma((T)(xp[st] + xn[st]), pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
             }
+        };
+        auto cl = [&](int c) { return c < nb ? c : nb - 1; };
+        double p0[4], n0[4], p1[4], n1[4], p2[4], n2[4];
+        load(p0, n0, 0);
+        load(p1, n1, cl(1));
+        int c = 0;
+        for (; c + 2 < nb; c += 3) {
+            load(p2, n2, c + 2);
+            block(p0, n0, c);
+            load(p0, n0, cl(c + 3));
+            block(p1, n1, c + 1);
+            load(p1, n1, cl(c + 4));
+            block(p2, n2, c + 2);
         }
+        if (c < nb)
+            block(p0, n0, c);
+        if (c + 1 < nb)
+            block(p1, n1, c + 1);
         // gradients of this lane's four orbitals of image a at its point
         const int atom = s_atom[a];
         const DevSpecies &S = s_sp[bs.spc[atom]];
@@ -692,13 +716,14 @@ static hipError_t launch_forceR_p(hipStream_t s, const Geo &g, int nbmax, const 
                                   const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
                                   const double *DR, const double *W, double wscale, double *Fimg)
 {
-    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow;
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow + sizeof(int2) * (size_t)nbmax * nbmax;
     hipError_t e =
         hipFuncSetAttribute((const void *)k_forceR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((k_forceR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
-                       dim3(64 * kFRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, Fimg);
+                       dim3(64 * kFRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, nbmax,
+                       Fimg);
     return hipGetLastError();
 }
 
