@@ -349,15 +349,19 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_HR_batch(Geo g, const int *__
 // D blocks of unlisted R being zero.  Per block, S_ac phi_c on the matrix
 // cores (16 points per product) is added to T_a in the result registers,
 // which is dotted with phi_a once per row of blocks; lanes and waves are
-// summed in a fixed order.  Each point is written once.
+// summed in a fixed order.  Each point is written once.  The list indices
+// of both lattice vectors of every image pair are looked up once per batch
+// into LDS, and each lane's D(R) elements are loaded two blocks ahead.
 template <typename T, int P>
 __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *__restrict__ iptr,
                                                      const int *__restrict__ img_atom, const int *__restrict__ img,
                                                      Basis bs, const int *__restrict__ wsh, HRMap m, int norb,
-                                                     const double *__restrict__ DR, double *__restrict__ rho)
+                                                     const double *__restrict__ DR, int nbmax, double *__restrict__ rho)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
+    // then per image pair (a, c), a * nb + c: list indices of R = T_c - T_a and of -R
+    int2 *s_q = reinterpret_cast<int2 *>(s_dyn + sizeof(T) * (size_t)nbmax * P * kRow);
     __shared__ DevRadial s_rad[kMaxRadTotal];
     __shared__ DevSpecies s_sp[kMaxSpecies];
     __shared__ int s_atom[kMaxBatchAtoms], s_nor[kMaxBatchAtoms], s_mu0[kMaxBatchAtoms];
@@ -409,6 +413,11 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
                              row, swz);
         }
     }
+    for (int k = tid; k < nb * nb; k += blockDim.x) {
+        const int a = k / nb, c = k - a * nb;
+        const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
+        s_q[k] = int2{hr_lookup(m, Rx, Ry, Rz), a != c ? hr_lookup(m, -Rx, -Ry, -Rz) : -1};
+    }
     __syncthreads();
 
     constexpr int NT = P / 16;  // 16-point tiles
@@ -452,44 +461,73 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
             acc[t] = MM<T>::zero();
         }
     };
-    for (int k = k0; k < k1; ++k) {
-        if (ia != cur) {
+    // this lane's D(R) elements of image pair (a, c): both terms loaded
+    // (zero outside the blocks, for unlisted R or past the wave's range),
+    // summed at use
+    auto load = [&](double (&xp)[4], double (&xn)[4], int a, int c, bool ok) {
+        const int2 q = ok ? s_q[a * nb + c] : int2{-1, -1};
+        const int nI = ok ? s_nor[a] : 0, nJ = ok ? s_nor[c] : 0;
+        const int mI = ok ? s_mu0[a] : 0, mJ = ok ? s_mu0[c] : 0;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int kc = lk + 4 * st;
+            const bool in = li < nI && kc < nJ;
+            xp[st] = (in && q.x >= 0) ? DR[q.x * nn + (size_t)(mI + li) * norb + mJ + kc] : 0.0;
+            xn[st] = (in && q.y >= 0) ? DR[q.y * nn + (size_t)(mJ + kc) * norb + mI + li] : 0.0;
+        }
+    };
+    auto block = [&](const double (&xp)[4], const double (&xn)[4], int a, int c) {
+        if (a != cur) {
             flush(cur);
-            cur = ia;
+            cur = a;
         }
-        const int Rx = s_T[ja][0] - s_T[ia][0], Ry = s_T[ja][1] - s_T[ia][1], Rz = s_T[ja][2] - s_T[ia][2];
-        const int qp = hr_lookup(m, Rx, Ry, Rz);
-        const int qn = ia != ja ? hr_lookup(m, -Rx, -Ry, -Rz) : -1;
-        if (qp >= 0 || qn >= 0) {
-            const int nI = s_nor[ia], nJ = s_nor[ja], mI = s_mu0[ia], mJ = s_mu0[ja];
-            // A operand: S[i = li][k = lk + 4 s]
-            T aS[4];
+        const int2 q = s_q[a * nb + c];
+        if (q.x < 0 && q.y < 0)
+            return;
+        const T *pC = s_phi + (size_t)(c * P) * kRow;
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const int kc = lk + 4 * st;
-                double x = 0.0;
-                if (li < nI && kc < nJ) {
-                    if (qp >= 0)
-                        x += DR[qp * nn + (size_t)(mI + li) * norb + mJ + kc];
-                    if (qn >= 0)
-                        x += DR[qn * nn + (size_t)(mJ + kc) * norb + mI + li];
-                }
-                aS[st] = (T)x;
-            }
-            const T *pC = s_phi + (size_t)(ja * P) * kRow;
+        for (int t = 0; t < NT; ++t) {
+            const int p = 16 * t + li;  // this lane's point (B and result column)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int p = 16 * t + li;  // this lane's point (B and result column)
-#pragma unroll
-                for (int st = 0; st < 4; ++st)
-                    acc[t] = MM<T>::mma(aS[st], pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
-            }
+            for (int st = 0; st < 4; ++st)
+                acc[t] = MM<T>::mma((T)(xp[st] + xn[st]), pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
         }
-        if (++ja == nb) {
-            ++ia;
-            ja = ia;
+    };
+    auto next = [&](int &x, int &y) {
+        if (++y == nb) {
+            ++x;
+            y = x;
         }
+    };
+    // blocks k, k + 1 and k + 2 of the wave's range in three register sets:
+    // the D(R) elements of block k + 2 are in flight while block k runs
+    double p0[4], n0[4], p1[4], n1[4], p2[4], n2[4];
+    int a0 = ia, c0 = ja, a1 = ia, c1 = ja, a2, c2;
+    next(a1, c1);
+    load(p0, n0, a0, c0, k0 < k1);
+    load(p1, n1, a1, c1, k0 + 1 < k1);
+    int k = k0;
+    for (; k + 2 < k1; k += 3) {
+        a2 = a1;
+        c2 = c1;
+        next(a2, c2);
+        load(p2, n2, a2, c2, true);
+        block(p0, n0, a0, c0);
+        a0 = a2;
+        c0 = c2;
+        next(a0, c0);
+        load(p0, n0, a0, c0, k + 3 < k1);
+        block(p1, n1, a1, c1);
+        a1 = a0;
+        c1 = c0;
+        next(a1, c1);
+        load(p1, n1, a1, c1, k + 4 < k1);
+        block(p2, n2, a2, c2);
     }
+    if (k < k1)
+        block(p0, n0, a0, c0);
+    if (k + 1 < k1)
+        block(p1, n1, a1, c1);
     if (k0 < k1)
         flush(cur);
     // lanes li, li + 16, li + 32, li + 48 hold the same point
@@ -754,13 +792,13 @@ static hipError_t launch_rhoR_p(hipStream_t s, const Geo &g, int nbmax, const in
                                 const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
                                 const double *DR, double *rho)
 {
-    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow;
+    const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow + sizeof(int2) * (size_t)nbmax * nbmax;
     hipError_t e =
         hipFuncSetAttribute((const void *)k_rhoR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((k_rhoR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
-                       dim3(64 * kHRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, rho);
+                       dim3(64 * kHRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, nbmax, rho);
     return hipGetLastError();
 }
 
