@@ -32,6 +32,8 @@ DTYPES = {"fp64": "f64", "fp32": "f32 (f64 sums)", "bf16": "bf16 H, f32 rho/forc
           "fp16": "f16 H, f32 rho/force (f64 sums)", "bf16x3": "bf16 hi/lo H, f32 rho/force (f64 sums)",
           "fp16x3": "f16 hi/lo H, f32 rho/force (f64 sums)"}
 PEAK_HBM_GBS = 8000.0
+N_XCD = 8  # MI355X: accelerator complex dies (GRBM_GUI_ACTIVE is summed over them)
+N_SIMD = 1024  # 256 compute units x 4 SIMDs
 
 
 def _kernel_sha() -> str:
@@ -102,6 +104,42 @@ def write_traffic(args):
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out), flush=True)
+
+
+def write_mfma(args):
+    """Issued FP64 matrix work of one kernel per launch from a rocprofv3 --pmc
+    run with SQ_INSTS_VALU_MFMA_MOPS_F64 (one MOP = 512 flops),
+    SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (summed over the 8 XCDs)."""
+    d = args.mfma_from
+    sym = KERNEL_SYMBOLS[args.kernel]
+    vals = {}
+    for counter in ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"):
+        v = [x for k, x in _counter_csv(d, counter) if re.search(sym, k)]
+        if not v:
+            raise SystemExit(f"no {sym} dispatch with {counter} in {d}")
+        vals[counter] = sum(v) / len(v)
+    grbm_xcd = vals["GRBM_GUI_ACTIVE"] / N_XCD
+    out = {"kernel": args.kernel, "symbol": sym, "workload": args.workload, "precision": args.precision,
+           "kernel_sha": _kernel_sha(), "counters": vals,
+           "issued_flops_per_launch": vals["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512.0,
+           "mfma_busy": vals["SQ_VALU_MFMA_BUSY_CYCLES"] / (grbm_xcd * N_SIMD)}
+    path = os.path.join(ROOT, "profiles", f"mfma_{args.kernel}_{args.workload}_{args.precision}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+def _mfma(kernel: str, workload: str, precision: str):
+    """Issued matrix flops per launch and the matrix-pipe busy fraction from
+    committed counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"mfma_{kernel}_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sha") != _kernel_sha():
+        return None
+    return t
 
 
 def _progress(msg):
@@ -367,10 +405,18 @@ def main():
     ap.add_argument("--traffic-from", default=None, metavar="DIR",
                     help="write profiles/traffic_<kernel>_<workload>_<precision>.json from the rocprofv3 "
                          "counter CSVs under DIR (fetch/, write/, copy_fetch/, copy_write/) and exit")
-    ap.add_argument("--kernel", default="rho_force", help="timing kind whose traffic --traffic-from records")
+    ap.add_argument("--mfma-from", default=None, metavar="DIR",
+                    help="write profiles/mfma_<kernel>_<workload>_<precision>.json from a rocprofv3 counter CSV "
+                         "directory with SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE "
+                         "and exit")
+    ap.add_argument("--kernel", default="rho_force",
+                    help="timing kind whose traffic (--traffic-from) or matrix work (--mfma-from) is recorded")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args)
+        return
+    if args.mfma_from:
+        write_mfma(args)
         return
 
     if args.gpus != 1:
@@ -543,6 +589,15 @@ def main():
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(ach / PEAK_HBM_GBS, 4), "kernel": dom, "alg_bytes_per_launch": per_launch}
         roof["traffic"] = _traffic(dom, args.workload, args.precision)
+        mf = _mfma(dom, args.workload, args.precision) if args.precision == "fp64" else None
+        if mf is not None:
+            # matrix work as issued (padded tiles included) over the live launch time
+            iss = mf["issued_flops_per_launch"] / avg_s / 1e12
+            roof["issued"] = {"achieved": round(iss, 3), "frac": round(iss / PEAK_FP64_TFLOPS, 4),
+                              "flops_per_launch": mf["issued_flops_per_launch"],
+                              "mfma_busy_counter": round(mf["mfma_busy"], 4)}
+        else:
+            roof["issued"] = None
 
     # full-size consistency check: dV sum V rho == Tr(D H)  (adjoint identity)
     check = None
