@@ -476,6 +476,13 @@ gint_status gint_plan_atom_order(gint_plan plan, int *order);
  * releases it. */
 gint_status gint_test_fail_rebuilds(int n);
 
+/* Test switch of gint_build_rhoR and gint_forceR: with on != 0 every lane
+ * gathers its D(R) and D(-R)^T elements one by one, as the calls do when an
+ * image pair spans more than 31 cells (no packed blocks); on = 0 (the
+ * default) restores the packed blocks.  Results agree to rounding.  Process
+ * wide, not thread-safe. */
+gint_status gint_test_DR_gather(int on);
+
 int gint_norb(gint_plan plan);   /* total orbitals, or -1 for an invalid plan */
 int gint_natom(gint_plan plan);  /* atoms, or -1                               */
 double gint_dV(gint_plan plan);  /* mesh volume element, or -1                 */

@@ -34,7 +34,7 @@ EXPORTS = (
     "gint_build_HR", "gint_HR_lattice", "gint_build_rhoR", "gint_HR_to_Hk", "gint_forceR",
     "gint_batch_create", "gint_batch_build_H", "gint_batch_build_rho", "gint_batch_force",
     "gint_batch_sync", "gint_batch_ncell", "gint_batch_cell", "gint_batch_destroy", "gint_batch_autotune",
-    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_build_DK",
+    "gint_plan_atom_order", "gint_test_fail_rebuilds", "gint_test_DR_gather", "gint_build_DK",
     "gint_psibeta_create", "gint_psibeta_nproj", "gint_psibeta_overlap", "gint_psibeta_destroy",
     "gint_batch_H_rho_force", "gint_HR_to_Hk_noalloc",
 )
@@ -150,6 +150,8 @@ def load_library(path: str = LIB_PATH):
     lib.gint_plan_atom_order.argtypes = [P, ip]
     lib.gint_test_fail_rebuilds.restype = st
     lib.gint_test_fail_rebuilds.argtypes = [ctypes.c_int]
+    lib.gint_test_DR_gather.restype = st
+    lib.gint_test_DR_gather.argtypes = [ctypes.c_int]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.gint_batch_create.restype = st
     lib.gint_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_Cell), ctypes.c_int, ctypes.POINTER(_Species),

@@ -24,6 +24,9 @@ thread_local std::string g_last_error;
 // failure injection for tests of the error paths: the next n list rebuilds
 // fail with GINT_ENOMEM before touching the device (gint_test_fail_rebuilds)
 int g_fail_rebuilds = 0;
+// rho and the force from D(R) gather their D(R) elements instead of reading
+// packed blocks (gint_test_DR_gather)
+int g_dr_gather = 0;
 
 gint_status fail(gint_status s, const char *fmt, ...)
 {
@@ -144,6 +147,13 @@ struct gint_plan_s {
     DevBuf img_id, cnt_u, boff_u, hkey, hkey2, hcode, hcode2, hflag, hfscan, tstart, tkey, sort_tmp, hbad;
     long long nblock_u = 0;
     int ntri = 0;
+    long long hblk_gen = -1;   // list generation of img_id / boff_u / nblock_u
+    long long htri_gen = -1;   // list generation of the sorted triples (or of their failure)
+    bool htri_bad = false;     // an image pair spans more than kHRBox cells: no triples
+    // packed D(R) blocks of gint_build_rhoR / gint_forceR: triple of every
+    // block entry (per geometry), packed S and its nonzero flags (per call)
+    DevBuf etri, spk, snz;
+    long long etri_gen = -1;
     bool hr_fixed = false;  // the partials fit the budget: sorted-triple path
     size_t hbudget_eff = 0;  // partial-buffer budget of the last list build
     int npair_owned = 0;          // owned atom pairs (entries of plist)
@@ -1171,15 +1181,14 @@ gint_status hr_images(gint_plan p)
 // when the block partials of the unfolded images fit the partial-buffer
 // budget, the sorted canonical triples of the fixed-order H(R) reduction,
 // once per list generation
-gint_status hr_prepare(gint_plan p)
+// per-batch block offsets of the unfolded images (once per geometry)
+gint_status hr_blocks(gint_plan p)
 {
     STCHK(hr_images(p));
-    if (p->hrfix_gen == p->gen)
+    if (p->hblk_gen == p->gen)
         return GINT_OK;
     const hipStream_t st = p->stream;
     const long long nb = p->geo.nbatch;
-
-    // block offsets of the unfolded images
     STCHK(p->img_id.ensure(sizeof(int) * (size_t)(p->nimg + 1)));
     HIPCHK(launch_iota(st, p->nimg + 1, p->img_id.as<int>()));
     STCHK(p->cnt_u.ensure(sizeof(int) * nb));
@@ -1191,11 +1200,27 @@ gint_status hr_prepare(gint_plan p)
     if (nbu < 0)
         return fail(GINT_EUNSUPPORTED, "H(R) block lists exceed 2^31 entries");
     p->nblock_u = nbu;
-    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
-    const size_t blk_bytes = esz * (size_t)block_pitch(p->mno, (int)esz);
-    p->hr_fixed = !p->ext_hpart && blk_bytes * (size_t)std::max(nbu, 1) <= std::max(p->hbudget_eff, p->Hpart.bytes);
+    p->hblk_gen = p->gen;
+    return GINT_OK;
+}
+
+// canonical (I, J, R) triple of every unfolded block, sorted, and the runs
+// of equal triples (once per geometry); GINT_EUNSUPPORTED when an image
+// pair spans more than kHRBox cells along an axis
+gint_status hr_triples(gint_plan p)
+{
+    STCHK(hr_blocks(p));
+    if (p->htri_gen == p->gen) {
+        if (p->htri_bad)
+            return fail(GINT_EUNSUPPORTED, "an atom-image pair spans more than %d cells along an axis", kHRBox);
+        return GINT_OK;
+    }
+    const hipStream_t st = p->stream;
+    const long long nb = p->geo.nbatch;
+    const int nbu = (int)p->nblock_u;
     p->ntri = 0;
-    if (p->hr_fixed && nbu > 0) {
+    p->htri_bad = false;
+    if (nbu > 0) {
         const size_t n = (size_t)nbu;
         STCHK(p->hkey.ensure(sizeof(unsigned long long) * n));
         STCHK(p->hkey2.ensure(sizeof(unsigned long long) * n));
@@ -1208,8 +1233,11 @@ gint_status hr_prepare(gint_plan p)
                               p->hkey.as<unsigned long long>(), p->hcode.as<int>(), p->hbad.as<int>()));
         int bad = 0;
         STCHK(read_scalar(p, p->hbad.as<int>(), &bad));
-        if (bad)
+        if (bad) {
+            p->htri_bad = true;
+            p->htri_gen = p->gen;
             return fail(GINT_EUNSUPPORTED, "an atom-image pair spans more than %d cells along an axis", kHRBox);
+        }
         int end_bit = 18;
         while (end_bit < 64 && ((unsigned long long)p->natom * p->natom) >> (end_bit - 18))
             ++end_bit;
@@ -1232,9 +1260,62 @@ gint_status hr_prepare(gint_plan p)
         HIPCHK(launch_seg(st, nbu, p->hkey2.as<unsigned long long>(), nullptr, p->hfscan.as<int>(),
                           p->tstart.as<int>(), p->tkey.as<unsigned long long>(), true));
         p->ntri = ntri;
-        STCHK(p->Hpart.ensure(blk_bytes * n));
+    }
+    p->htri_gen = p->gen;
+    return GINT_OK;
+}
+
+gint_status hr_prepare(gint_plan p)
+{
+    STCHK(hr_images(p));
+    if (p->hrfix_gen == p->gen)
+        return GINT_OK;
+    STCHK(hr_blocks(p));
+    const long long nbu = p->nblock_u;
+    const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
+    const size_t blk_bytes = esz * (size_t)block_pitch(p->mno, (int)esz);
+    p->hr_fixed = !p->ext_hpart &&
+                  blk_bytes * (size_t)std::max(nbu, 1LL) <= std::max(p->hbudget_eff, p->Hpart.bytes);
+    if (p->hr_fixed && nbu > 0) {
+        STCHK(hr_triples(p));
+        STCHK(p->Hpart.ensure(blk_bytes * (size_t)nbu));
     }
     p->hrfix_gen = p->gen;
+    return GINT_OK;
+}
+
+// D(R) blocks of the rho / force contractions packed per triple (the
+// triples and the triple of every block entry once per geometry, the blocks
+// per call).  *ps stays NULL, and the kernels gather D(R) elements instead,
+// when the triples are unavailable or gathering is forced.
+gint_status hr_pack(gint_plan p, const HRMap &m, const double *DR, PackedS *buf, const PackedS **ps)
+{
+    *ps = nullptr;
+    if (g_dr_gather)
+        return GINT_OK;
+    const gint_status tst = hr_triples(p);
+    if (tst == GINT_EUNSUPPORTED) {
+        g_last_error.clear();
+        return GINT_OK;
+    }
+    STCHK(tst);
+    if (p->ntri == 0)
+        return GINT_OK;
+    const hipStream_t st = p->stream;
+    if (p->etri_gen != p->gen) {
+        STCHK(p->etri.ensure(sizeof(int) * (size_t)p->nblock_u));
+        HIPCHK(launch_entry_tri(st, p->nblock_u, p->hcode2.as<int>(), p->hfscan.as<int>(), p->etri.as<int>()));
+        p->etri_gen = p->gen;
+    }
+    STCHK(p->spk.ensure(sizeof(double) * 512 * (size_t)p->ntri));
+    STCHK(p->snz.ensure(sizeof(int) * (size_t)p->ntri));
+    const Basis B = p->basis();
+    STCHK(timed(p, GINT_K_PACK, [&] {
+        return launch_S_pack(st, p->ntri, p->tkey.as<unsigned long long>(), p->natom, B.orb0, m, p->norb, DR,
+                             p->spk.as<double>(), p->snz.as<int>());
+    }));
+    *buf = PackedS{p->etri.as<int>(), p->boff_u.as<int>(), p->snz.as<int>(), p->spk.as<double>()};
+    *ps = buf;
     return GINT_OK;
 }
 
@@ -1363,10 +1444,13 @@ gint_status gint_build_rhoR(gint_plan p, int nR, const int *R, const double *DR_
         return fail(GINT_EINVAL, "nR = %d must be >= 1", nR);
     HRMap m;
     STCHK(hr_map(p, nR, R, &m));
+    PackedS buf;
+    const PackedS *ps = nullptr;
+    STCHK(hr_pack(p, m, DR_dev, &buf, &ps));
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_RHO, [&] {
         return launch_rhoR_batch(p->stream, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(), p->img_atom.as<int>(),
-                                 p->img.as<int>(), B, p->wsh.as<int>(), m, p->norb, DR_dev, rho_dev);
+                                 p->img.as<int>(), B, p->wsh.as<int>(), m, p->norb, DR_dev, ps, rho_dev);
     }));
     return GINT_OK;
 }
@@ -1437,11 +1521,14 @@ gint_status gint_forceR(gint_plan p, const double *V_dev, int nR, const int *R, 
     HRMap m;
     STCHK(hr_map(p, nR, R, &m));
     STCHK(p->Fimg.ensure(sizeof(double) * 3 * (size_t)(p->nimg + 1)));
+    PackedS buf;
+    const PackedS *ps = nullptr;
+    STCHK(hr_pack(p, m, DR_dev, &buf, &ps));
     const Basis B = p->basis();
     STCHK(timed(p, GINT_K_FORCE, [&] {
         return launch_forceR_batch(p->stream, p->f32(), p->geo, p->nbmax_img, p->iptr.as<int>(),
                                    p->img_atom.as<int>(), p->img.as<int>(), B, p->wsh.as<int>(), m, p->norb, DR_dev,
-                                   V_dev, p->dV, p->Fimg.as<double>());
+                                   ps, V_dev, p->dV, p->Fimg.as<double>());
     }));
     STCHK(timed(p, GINT_K_F_REDUCE, [&] {
         return launch_forceR_reduce(p->stream, p->natom, p->aptr.as<int>(), p->aent.as<int>(), p->ent_img.as<int>(),
@@ -1535,6 +1622,12 @@ gint_status gint_test_fail_rebuilds(int n)
     if (n < 0)
         return fail(GINT_EINVAL, "n = %d must be >= 0", n);
     g_fail_rebuilds = n;
+    return GINT_OK;
+}
+
+gint_status gint_test_DR_gather(int on)
+{
+    g_dr_gather = on ? 1 : 0;
     return GINT_OK;
 }
 

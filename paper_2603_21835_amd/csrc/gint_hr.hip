@@ -217,6 +217,111 @@ hipError_t sort_HR_keys(hipStream_t s, void *tmp, size_t &tmp_bytes, const unsig
     return hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, code_in, code_out, n, 0, end_bit, s);
 }
 
+// Per unfolded block entry (batch block of image pair a <= c, in the order
+// of k_HR_keys): 2 t + o, t = its canonical (I, J, R) triple (the run of equal
+// sorted keys it falls in), o = 1 where the canonical orientation swaps the
+// pair, so that the entry's block is the transpose of the triple's.
+__global__ void k_entry_tri(long long n, const int *__restrict__ code, const int *__restrict__ fscan,
+                            int *__restrict__ etri)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    const int c = code[s];
+    const int e = c >= 0 ? c : -c - 1;
+    etri[e] = 2 * (fscan[s + 1] - 1) + (c < 0 ? 1 : 0);
+}
+
+hipError_t launch_entry_tri(hipStream_t s, long long n, const int *code, const int *fscan, int *etri)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_entry_tri, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, code, fscan, etri);
+    return hipGetLastError();
+}
+
+// The density-matrix block of a canonical triple (I, J, R) as the rho and
+// force contractions use it (Sec. 3.3.1, rho(r_g) equation with its sums
+// over R and R'):
+//     S_IJ(R) = D_IJ(R) + D_JI(-R)^T,
+// each term zero where its lattice vector is not in the caller's list,
+// zero-padded to 16 x 16, in both orientations (o = 0: S, o = 1: S^T), laid
+// out in the lane order of the FP64 MFMA A operand: lane (i, k0) of 64
+// holds elements (i, k0 + 4 s), s = 0..3, as 4 consecutive doubles, so that
+// a wave reads one block with two 16-byte loads per lane.  One wave per
+// triple; nz[t] = 0 when neither R nor -R is listed.
+constexpr int kPackWaves = 4;
+__global__ __launch_bounds__(64 * kPackWaves) void k_S_pack(int ntri, const unsigned long long *__restrict__ tkey,
+                                                            int natom, const int *__restrict__ orb0, HRMap m,
+                                                            int norb, const double *__restrict__ DR,
+                                                            double *__restrict__ spk, int *__restrict__ nz)
+{
+    const int t = blockIdx.x * kPackWaves + (threadIdx.x >> 6);
+    if (t >= ntri)
+        return;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const unsigned long long key = tkey[t];
+    const unsigned long long ij = key >> 18;
+    const int ridx = (int)(key & ((1ULL << 18) - 1));
+    const int I = (int)(ij / (unsigned long long)natom), J = (int)(ij % (unsigned long long)natom);
+    constexpr int M = kHRBox, w = 2 * kHRBox + 1;
+    const int R0 = ridx / (w * w) - M, R1 = (ridx / w) % w - M, R2 = ridx % w - M;
+    const int qR = hr_lookup(m, R0, R1, R2), qN = hr_lookup(m, -R0, -R1, -R2);
+    if (lane == 0)
+        nz[t] = (qR >= 0 || qN >= 0) ? 1 : 0;
+    const int mI = orb0[I], nI = orb0[I + 1] - mI, mJ = orb0[J], nJ = orb0[J + 1] - mJ;
+    const size_t nn = (size_t)norb * norb;
+    double v0[4], v1[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const int kc = lk + 4 * st;
+        // o = 0: S[li][kc]; o = 1: S^T[li][kc] = S[kc][li]
+        const bool in0 = li < nI && kc < nJ, in1 = kc < nI && li < nJ;
+        const double a0 = (in0 && qR >= 0) ? DR[qR * nn + (size_t)(mI + li) * norb + mJ + kc] : 0.0;
+        const double b0 = (in0 && qN >= 0) ? DR[qN * nn + (size_t)(mJ + kc) * norb + mI + li] : 0.0;
+        const double a1 = (in1 && qR >= 0) ? DR[qR * nn + (size_t)(mI + kc) * norb + mJ + li] : 0.0;
+        const double b1 = (in1 && qN >= 0) ? DR[qN * nn + (size_t)(mJ + li) * norb + mI + kc] : 0.0;
+        v0[st] = a0 + b0;
+        v1[st] = a1 + b1;
+    }
+    double4 *o = reinterpret_cast<double4 *>(spk) + (size_t)2 * t * 64;
+    o[lane] = double4{v0[0], v0[1], v0[2], v0[3]};
+    o[64 + lane] = double4{v1[0], v1[1], v1[2], v1[3]};
+}
+
+hipError_t launch_S_pack(hipStream_t s, int ntri, const unsigned long long *tkey, int natom, const int *orb0,
+                         const HRMap &m, int norb, const double *DR, double *spk, int *nz)
+{
+    if (ntri > 0)
+        hipLaunchKernelGGL(k_S_pack, dim3((unsigned)((ntri + kPackWaves - 1) / kPackWaves)), dim3(64 * kPackWaves),
+                           0, s, ntri, tkey, natom, orb0, m, norb, DR, spk, nz);
+    return hipGetLastError();
+}
+
+// Packed index (2 t + o) of image pair (a, c) of batch b, or -1 when its
+// triple has no listed lattice vector; c < a takes the transpose of (c, a).
+__device__ __forceinline__ int packed_block(const PackedS &ps, int b, int nb, int a, int c)
+{
+    const int lo = a < c ? a : c, hi = a < c ? c : a;
+    const int v = ps.etri[ps.boff[b] + lo * nb - lo * (lo - 1) / 2 + (hi - lo)];
+    if (!ps.nz[v >> 1])
+        return -1;
+    return a <= c ? v : v ^ 1;
+}
+
+// this lane's four elements of a packed block (zeros for v < 0), times f
+__device__ __forceinline__ void load_packed(const PackedS &ps, int v, int lane, double f, double (&x)[4])
+{
+    if (v < 0) {
+        x[0] = x[1] = x[2] = x[3] = 0.0;
+        return;
+    }
+    const double4 d = reinterpret_cast<const double4 *>(ps.spk)[(size_t)v * 64 + lane];
+    x[0] = f * d.x;
+    x[1] = f * d.y;
+    x[2] = f * d.z;
+    x[3] = f * d.w;
+}
+
 constexpr int kHRWaves = 16;
 
 template <typename T, int P>
@@ -352,11 +457,12 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_HR_batch(Geo g, const int *__
 // summed in a fixed order.  Each point is written once.  The list indices
 // of both lattice vectors of every image pair are looked up once per batch
 // into LDS, and each lane's D(R) elements are loaded two blocks ahead.
-template <typename T, int P>
+template <typename T, int P, bool PK>
 __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *__restrict__ iptr,
                                                      const int *__restrict__ img_atom, const int *__restrict__ img,
                                                      Basis bs, const int *__restrict__ wsh, HRMap m, int norb,
-                                                     const double *__restrict__ DR, int nbmax, double *__restrict__ rho)
+                                                     const double *__restrict__ DR, PackedS ps, int nbmax,
+                                                     double *__restrict__ rho)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
@@ -415,8 +521,13 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
     }
     for (int k = tid; k < nb * nb; k += blockDim.x) {
         const int a = k / nb, c = k - a * nb;
-        const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
-        s_q[k] = int2{hr_lookup(m, Rx, Ry, Rz), a != c ? hr_lookup(m, -Rx, -Ry, -Rz) : -1};
+        if (PK) {
+            if (a <= c)
+                s_q[k] = int2{packed_block(ps, b, nb, a, c), -1};
+        } else {
+            const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
+            s_q[k] = int2{hr_lookup(m, Rx, Ry, Rz), a != c ? hr_lookup(m, -Rx, -Ry, -Rz) : -1};
+        }
     }
     __syncthreads();
 
@@ -466,6 +577,11 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
     // summed at use
     auto load = [&](double (&xp)[4], double (&xn)[4], int a, int c, bool ok) {
         const int2 q = ok ? s_q[a * nb + c] : int2{-1, -1};
+        if (PK) {
+            // the packed S_ac (S_aa = D_II(0) + D_II(0)^T: half of it on the diagonal)
+            load_packed(ps, q.x, lane, a == c ? 0.5 : 1.0, xp);
+            return;
+        }
         const int nI = ok ? s_nor[a] : 0, nJ = ok ? s_nor[c] : 0;
         const int mI = ok ? s_mu0[a] : 0, mJ = ok ? s_mu0[c] : 0;
 #pragma unroll
@@ -490,7 +606,8 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
             const int p = 16 * t + li;  // this lane's point (B and result column)
 #pragma unroll
             for (int st = 0; st < 4; ++st)
-                acc[t] = MM<T>::mma((T)(xp[st] + xn[st]), pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
+                acc[t] = MM<T>::mma((T)(PK ? xp[st] : xp[st] + xn[st]), pC[p * kRow + ((lk + 4 * st) ^ (p & 15))],
+                                    acc[t]);
         }
     };
     auto next = [&](int &x, int &y) {
@@ -564,13 +681,14 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
 // while the products of image c run (three register sets in rotation).
 constexpr int kFRWaves = 8;  // (T_a of a whole image stays in registers)
 
-template <typename T, int P>
+template <typename T, int P, bool PK>
 __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int *__restrict__ iptr,
                                                        const int *__restrict__ img_atom,
                                                        const int *__restrict__ img, Basis bs,
                                                        const int *__restrict__ wsh, HRMap m, int norb,
                                                        const double *__restrict__ DR, const double *__restrict__ W,
-                                                       double wscale, int nbmax, double *__restrict__ Fimg)
+                                                       double wscale, PackedS ps, int nbmax,
+                                                       double *__restrict__ Fimg)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T *s_phi = reinterpret_cast<T *>(s_dyn);  // [nbmax][P][kRow]
@@ -633,8 +751,12 @@ __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int
     }
     for (int k = tid; k < nb * nb; k += blockDim.x) {
         const int a = k / nb, c = k - a * nb;
-        const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
-        s_q[k] = int2{hr_lookup(m, Rx, Ry, Rz), hr_lookup(m, -Rx, -Ry, -Rz)};
+        if (PK) {
+            s_q[k] = int2{packed_block(ps, b, nb, a, c), -1};
+        } else {
+            const int Rx = s_T[c][0] - s_T[a][0], Ry = s_T[c][1] - s_T[a][1], Rz = s_T[c][2] - s_T[a][2];
+            s_q[k] = int2{hr_lookup(m, Rx, Ry, Rz), hr_lookup(m, -Rx, -Ry, -Rz)};
+        }
     }
     __syncthreads();
 
@@ -650,6 +772,10 @@ __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int
         // (zero outside the blocks or for unlisted R), summed at use
         auto load = [&](double (&xp)[4], double (&xn)[4], int c) {
             const int2 q = s_q[a * nb + c];
+            if (PK) {
+                load_packed(ps, q.x, lane, 1.0, xp);
+                return;
+            }
             const int nJ = s_nor[c], mJ = s_mu0[c];
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
@@ -669,7 +795,8 @@ __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int
                 const int p = 16 * t + li;
 #pragma unroll
                 for (int st = 0; st < 4; ++st)
-                    acc[t] = MM<T>::mma((T)(xp[st] + xn[st]), pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
+                    acc[t] = MM<T>::mma((T)(PK ? xp[st] : xp[st] + xn[st]),
+                                        pC[p * kRow + ((lk + 4 * st) ^ (p & 15))], acc[t]);
             }
         };
         auto cl = [&](int c) { return c < nb ? c : nb - 1; };
@@ -749,34 +876,49 @@ __global__ __launch_bounds__(256) void k_forceR_reduce(const int *__restrict__ a
         dEdR[3 * perm[a] + threadIdx.x] = red[threadIdx.x][0];
 }
 
-template <typename T, int P>
+template <typename T, int P, bool PK>
 static hipError_t launch_forceR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                                   const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
-                                  const double *DR, const double *W, double wscale, double *Fimg)
+                                  const double *DR, const PackedS &ps, const double *W, double wscale, double *Fimg)
 {
     const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow + sizeof(int2) * (size_t)nbmax * nbmax;
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_forceR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_forceR_batch<T, P, PK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_forceR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
-                       dim3(64 * kFRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, nbmax,
+    hipLaunchKernelGGL((k_forceR_batch<T, P, PK>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
+                       dim3(64 * kFRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, ps, nbmax,
                        Fimg);
     return hipGetLastError();
 }
 
+template <typename T, int P>
+static hipError_t launch_forceR_pk(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                                   const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
+                                   const double *DR, const PackedS *ps, const double *W, double wscale, double *Fimg)
+{
+    if (ps)
+        return launch_forceR_p<T, P, true>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, *ps, W, wscale,
+                                           Fimg);
+    return launch_forceR_p<T, P, false>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, PackedS{}, W, wscale,
+                                        Fimg);
+}
+
 hipError_t launch_forceR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr,
                                const int *img_atom, const int *img, const Basis &b, const int *wsh, const HRMap &m,
-                               int norb, const double *DR, const double *W, double wscale, double *Fimg)
+                               int norb, const double *DR, const PackedS *ps, const double *W, double wscale,
+                               double *Fimg)
 {
     if (g.P == 32)
-        return f32 ? launch_forceR_p<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, Fimg)
-                   : launch_forceR_p<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale,
-                                                 Fimg);
+        return f32 ? launch_forceR_pk<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, W, wscale,
+                                                 Fimg)
+                   : launch_forceR_pk<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, W,
+                                                  wscale, Fimg);
     if (g.P == 16)
-        return f32 ? launch_forceR_p<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale, Fimg)
-                   : launch_forceR_p<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, W, wscale,
-                                                 Fimg);
+        return f32 ? launch_forceR_pk<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, W, wscale,
+                                                 Fimg)
+                   : launch_forceR_pk<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, W,
+                                                  wscale, Fimg);
     return hipErrorInvalidValue;
 }
 
@@ -787,31 +929,41 @@ hipError_t launch_forceR_reduce(hipStream_t s, int natom, const int *aptr, const
     return hipGetLastError();
 }
 
-template <typename T, int P>
+template <typename T, int P, bool PK>
 static hipError_t launch_rhoR_p(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                                 const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
-                                const double *DR, double *rho)
+                                const double *DR, const PackedS &ps, double *rho)
 {
     const size_t lds = sizeof(T) * (size_t)nbmax * P * kRow + sizeof(int2) * (size_t)nbmax * nbmax;
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_rhoR_batch<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_rhoR_batch<T, P, PK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_rhoR_batch<T, P>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
-                       dim3(64 * kHRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, nbmax, rho);
+    hipLaunchKernelGGL((k_rhoR_batch<T, P, PK>), dim3((unsigned)(kXcd * ((g.nbatch + kXcd - 1) / kXcd))),
+                       dim3(64 * kHRWaves), lds, s, g, iptr, img_atom, img, b, wsh, m, norb, DR, ps, nbmax, rho);
     return hipGetLastError();
+}
+
+template <typename T, int P>
+static hipError_t launch_rhoR_pk(hipStream_t s, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
+                                 const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
+                                 const double *DR, const PackedS *ps, double *rho)
+{
+    if (ps)
+        return launch_rhoR_p<T, P, true>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, *ps, rho);
+    return launch_rhoR_p<T, P, false>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, PackedS{}, rho);
 }
 
 hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                              const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
-                             const double *DR, double *rho)
+                             const double *DR, const PackedS *ps, double *rho)
 {
     if (g.P == 32)
-        return f32 ? launch_rhoR_p<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho)
-                   : launch_rhoR_p<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho);
+        return f32 ? launch_rhoR_pk<float, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, rho)
+                   : launch_rhoR_pk<double, 32>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, rho);
     if (g.P == 16)
-        return f32 ? launch_rhoR_p<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho)
-                   : launch_rhoR_p<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, rho);
+        return f32 ? launch_rhoR_pk<float, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, rho)
+                   : launch_rhoR_pk<double, 16>(s, g, nbmax, iptr, img_atom, img, b, wsh, m, norb, DR, ps, rho);
     return hipErrorInvalidValue;
 }
 

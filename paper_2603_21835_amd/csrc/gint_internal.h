@@ -155,9 +155,25 @@ hipError_t sort_HR_keys(hipStream_t s, void *tmp, size_t &tmp_bytes, const unsig
 hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const unsigned long long *tkey, const int *tstart,
                             const int *list, int natom, const HRMap &m, const Basis &b, int mno, int norb,
                             const void *part, double *HR);
+// D(R) blocks of the rho and force contractions packed per canonical (I, J, R)
+// triple: etri[entry] = 2 t + o for every unfolded block entry (batch b's
+// entries from boff[b], image pairs a <= c in row-major order), nz[t] = 0
+// where neither R nor -R is listed, spk[2 t + o] = 16 x 16 doubles of S_IJ(R)
+// = D_IJ(R) + D_JI(-R)^T (o = 0) or its transpose (o = 1) in MFMA A-operand
+// lane order
+struct PackedS {
+    const int *etri;
+    const int *boff;
+    const int *nz;
+    const double *spk;
+};
+hipError_t launch_entry_tri(hipStream_t s, long long n, const int *code, const int *fscan, int *etri);
+hipError_t launch_S_pack(hipStream_t s, int ntri, const unsigned long long *tkey, int natom, const int *orb0,
+                         const HRMap &m, int norb, const double *DR, double *spk, int *nz);
+// ps == nullptr: each lane gathers its D(R) elements instead
 hipError_t launch_rhoR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr, const int *img_atom,
                              const int *img, const Basis &b, const int *wsh, const HRMap &m, int norb,
-                             const double *DR, double *rho);
+                             const double *DR, const PackedS *ps, double *rho);
 hipError_t launch_Hk(hipStream_t s, long long nel, int nR, int nk, const double *ph, const double *HR, double *Hk);
 // spherical-grid projector overlaps (gint_sphere.hip)
 hipError_t launch_pb_images(hipStream_t s, const Geo &g, const Basis &b, int npa, const int *pint, const double *prb,
@@ -183,7 +199,8 @@ hipError_t Hk_noalloc(hipStream_t s, int device, long long nel, int nR, const in
                       const double *HR, double *Hk);
 hipError_t launch_forceR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, const int *iptr,
                                const int *img_atom, const int *img, const Basis &b, const int *wsh, const HRMap &m,
-                               int norb, const double *DR, const double *W, double wscale, double *Fimg);
+                               int norb, const double *DR, const PackedS *ps, const double *W, double wscale,
+                               double *Fimg);
 hipError_t launch_forceR_reduce(hipStream_t s, int natom, const int *aptr, const int *aent, const int *ent_img,
                                 const int *perm, const double *Fimg, double *dEdR);
 hipError_t launch_HR_mark(hipStream_t s, const Geo &g, const int *iptr, const int *img_atom, const int *img,

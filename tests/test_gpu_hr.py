@@ -449,3 +449,39 @@ def test_rhoR_fp32_si64_sampled(oracle_mod, torch_dev):
     e = _rel_l2(rho[idx], oracle_mod.Oracle.from_workload(w).rhoR(R, DR, idx))
     _say(f"  fp32 si64 rhoR sampled: rel-L2 {e:.2e}")
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("make", [gi.si8_sz, _triclinic_two_species, _long_range_tiny])
+def test_rhoR_forceR_packed_and_gathered(oracle_mod, torch_dev, make):
+    # the default path reads D(R) blocks packed per (I, J, R) triple; the
+    # element gathers (taken when no triples can be formed) stay covered here.
+    # dE/dR sums the same operands in the same order on both paths (equal
+    # bits); rho's diagonal blocks use (D + D^T)/2 when packed, so rho agrees
+    # to rounding
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = make()
+    plan = g.GintPlan.from_workload(w)
+    R = plan.HR_lattice()
+    DR = _dev(torch, dev, _random_DR(len(R), plan.norb, 31))
+    V = _dev(torch, dev, w.V)
+    o = oracle_mod.Oracle.from_workload(w)
+    DRh = DR.cpu().numpy()
+    ref_rho, ref_F = o.rhoR(R, DRh), o.forceR(w.V, R, DRh)
+    out = {}
+    lib = g.load_library()
+    try:
+        for gather in (0, 1):
+            assert lib.gint_test_DR_gather(gather) == 0
+            _say(f"case rhoR/forceR {w.name} gather={gather}")
+            rho = plan.build_rhoR(R, DR).cpu().numpy()
+            F = plan.forceR(V, R, DR).cpu().numpy()
+            er, eF = _rel_l2(rho, ref_rho), _rel_max(F, ref_F)
+            _say(f"  rho rel-L2 {er:.2e}  dE/dR rel {eF:.2e}")
+            assert er <= TOL and eF <= TOL
+            out[gather] = (rho, F)
+    finally:
+        lib.gint_test_DR_gather(0)
+    assert np.array_equal(out[0][1], out[1][1])
+    assert _rel_l2(out[0][0], out[1][0]) <= 1e-13
