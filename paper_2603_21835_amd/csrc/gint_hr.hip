@@ -679,7 +679,7 @@ __global__ __launch_bounds__(64 * kHRWaves) void k_rhoR_batch(Geo g, const int *
 // both lattice vectors of every image pair (a, c) are looked up once per
 // batch into LDS, and each lane's D(R) elements of image c + 2 are loaded
 // while the products of image c run (three register sets in rotation).
-constexpr int kFRWaves = 8;  // (T_a of a whole image stays in registers)
+constexpr int kFRWaves = 12;  // three waves per SIMD (147 VGPRs in FP64)
 
 template <typename T, int P, bool PK>
 __global__ __launch_bounds__(64 * kFRWaves) void k_forceR_batch(Geo g, const int *__restrict__ iptr,
