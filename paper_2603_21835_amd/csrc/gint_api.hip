@@ -157,6 +157,10 @@ struct gint_plan_s {
     bool hr_fixed = false;  // the partials fit the budget: sorted-triple path
     size_t hbudget_eff = 0;  // partial-buffer budget of the last list build
     int npair_owned = 0;          // owned atom pairs (entries of plist)
+    // owned pairs heaviest first (block count over all slabs): launch order of
+    // the per-pair reductions and of D_K; pord holds [idx | order], pcost
+    // [cost | sorted cost]
+    DevBuf pcost, pord, psort_tmp;
     std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
 
@@ -191,6 +195,7 @@ struct gint_plan_s {
 
     bool f32() const { return prec != GINT_FP64; }  // FP32 tiles for all but FP64
     void *hpart() const { return ext_hpart ? ext_hpart : Hpart.p; }
+    const int *porder() const { return npair_owned > 0 ? pord.as<int>() + npair_owned + 1 : nullptr; }
     AtomLists atom_lists() const
     {
         AtomLists a;
@@ -598,6 +603,16 @@ gint_status rebuild_lists(gint_plan p, bool resort)
             return launch_pair_slabs(s, na, tpart, p->pptr.as<int>(), p->lptr.as<int>(), p->blist.as<int>(), ns,
                                      p->slabq.as<int>(), p->pown.as<int>(), p->lsl.as<int>());
         }));
+        STCHK(p->pcost.ensure(sizeof(int) * 2 * ((size_t)tpart + 1)));
+        STCHK(p->pord.ensure(sizeof(int) * 2 * ((size_t)tpart + 1)));
+        size_t tb = 0;
+        HIPCHK(launch_pair_order(s, nullptr, tb, tpart, ns, nullptr, nullptr, nullptr, nullptr, nullptr));
+        STCHK(p->psort_tmp.ensure(tb));
+        STCHK(timed(p, GINT_K_BIN, [&] {
+            return launch_pair_order(s, p->psort_tmp.p, tb, tpart, ns, p->lsl.as<int>(), p->pcost.as<int>(),
+                                     p->pcost.as<int>() + tpart + 1, p->pord.as<int>(),
+                                     p->pord.as<int>() + tpart + 1);
+        }));
         HIPCHK(hipStreamSynchronize(s));  // slab_q (host) outlives the copy
     }
     if (p->ext_hpart) {
@@ -973,9 +988,10 @@ static gint_status build_H_impl(gint_plan p, const double *W, double wscale, dou
                                   p->mno, p->hpart());
         }));
         STCHK(timed(p, GINT_K_H_REDUCE, [&] {
-            return launch_H_pairreduce(p->stream, p->f32(), p->npair_owned, p->pown.as<int>(), p->plist.as<int>(),
-                                       p->lsl.as<int>(), (int)p->slab.size() - 1, (int)i, p->blist.as<int>(), B,
-                                       p->mno, p->norb, p->hpart(), p->slab_q[i], i > 0 ? 1 : 0, H);
+            return launch_H_pairreduce(p->stream, p->f32(), p->npair_owned, p->porder(), p->pown.as<int>(),
+                                       p->plist.as<int>(), p->lsl.as<int>(), (int)p->slab.size() - 1, (int)i,
+                                       p->blist.as<int>(), B, p->mno, p->norb, p->hpart(), p->slab_q[i],
+                                       i > 0 ? 1 : 0, H);
         }));
     }
     return GINT_OK;
@@ -1014,8 +1030,9 @@ gint_status gint_build_DK(gint_plan p, const double *W_dev, double *DK_dev)
         p->dk_gen = p->gen;
     }
     STCHK(timed(p, GINT_K_DK, [&] {
-        return launch_DK_pairs(p->stream, p->geo, bn, B, W_dev, p->dV, p->npair_owned, p->pown.as<int>(),
-                               p->plist.as<int>(), p->lptr.as<int>(), p->dk_desc.as<int4>(), p->norb, DK_dev);
+        return launch_DK_pairs(p->stream, p->geo, bn, B, W_dev, p->dV, p->npair_owned, p->porder(),
+                               p->pown.as<int>(), p->plist.as<int>(), p->lptr.as<int>(), p->dk_desc.as<int4>(),
+                               p->norb, DK_dev);
     }));
     return GINT_OK;
 }
@@ -1107,9 +1124,10 @@ gint_status H_rho_force_impl(gint_plan p, const double *V_dev, const double *D_d
                                           p->Fent.as<double>(), rho_dev, b0, b1, p->boff.as<int>(), p->hpart());
             }));
             STCHK(timed(p, GINT_K_H_REDUCE, [&] {
-                return launch_H_pairreduce(st, p->f32(), p->npair_owned, p->pown.as<int>(), p->plist.as<int>(),
-                                           p->lsl.as<int>(), (int)p->slab.size() - 1, (int)i, p->blist.as<int>(), B,
-                                           p->mno, p->norb, p->hpart(), p->slab_q[i], i > 0 ? 1 : 0, H_dev);
+                return launch_H_pairreduce(st, p->f32(), p->npair_owned, p->porder(), p->pown.as<int>(),
+                                           p->plist.as<int>(), p->lsl.as<int>(), (int)p->slab.size() - 1, (int)i,
+                                           p->blist.as<int>(), B, p->mno, p->norb, p->hpart(), p->slab_q[i],
+                                           i > 0 ? 1 : 0, H_dev);
             }));
         }
         STCHK(timed(p, GINT_K_F_REDUCE,

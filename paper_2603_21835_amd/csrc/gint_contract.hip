@@ -469,7 +469,8 @@ struct Vec16<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__restrict__ pown,
+__global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__restrict__ order,
+                                                      const int *__restrict__ pown,
                                                       const int *__restrict__ plist, const int *__restrict__ lsl,
                                                       int nslab1, int si, const int *__restrict__ list, Basis bs,
                                                       int mno, int norb, const T *__restrict__ part, int q0,
@@ -480,9 +481,10 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__re
     constexpr int M = (kMaxOrb * kMaxOrb + 64 * V - 1) / (64 * V);  // vectors per lane
     __shared__ double s_sum[4][2][kMaxOrb * kMaxOrb];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int p = blockIdx.x * 4 + wv;
-    if (p >= npair)
+    const int w = blockIdx.x * 4 + wv;
+    if (w >= npair)
         return;
+    const int p = order ? order[w] : w;
     auto qof = [](int c) { return c >= 0 ? c : -c - 1; };
     const int l0 = lsl[(size_t)p * nslab1 + si], l1 = lsl[(size_t)p * nslab1 + si + 1];
     if (accumulate && l0 == l1)
@@ -565,19 +567,19 @@ __global__ __launch_bounds__(256) void k_H_pairreduce(int npair, const int *__re
     }
 }
 
-hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *pown, const int *plist, const int *lsl,
-                               int nslab, int si, const int *list, const Basis &b, int mno, int norb,
-                               const void *part, int q0, int accumulate, double *H)
+hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *order, const int *pown,
+                               const int *plist, const int *lsl, int nslab, int si, const int *list, const Basis &b,
+                               int mno, int norb, const void *part, int q0, int accumulate, double *H)
 {
     if (npair <= 0)
         return hipSuccess;
     const unsigned nblk = (unsigned)((npair + 3) / 4);
     if (f32)
-        hipLaunchKernelGGL(k_H_pairreduce<float>, dim3(nblk), dim3(256), 0, s, npair, pown, plist, lsl, nslab + 1, si,
-                           list, b, mno, norb, static_cast<const float *>(part), q0, accumulate, H);
+        hipLaunchKernelGGL(k_H_pairreduce<float>, dim3(nblk), dim3(256), 0, s, npair, order, pown, plist, lsl,
+                           nslab + 1, si, list, b, mno, norb, static_cast<const float *>(part), q0, accumulate, H);
     else
-        hipLaunchKernelGGL(k_H_pairreduce<double>, dim3(nblk), dim3(256), 0, s, npair, pown, plist, lsl, nslab + 1,
-                           si, list, b, mno, norb, static_cast<const double *>(part), q0, accumulate, H);
+        hipLaunchKernelGGL(k_H_pairreduce<double>, dim3(nblk), dim3(256), 0, s, npair, order, pown, plist, lsl,
+                           nslab + 1, si, list, b, mno, norb, static_cast<const double *>(part), q0, accumulate, H);
     return hipGetLastError();
 }
 

@@ -189,7 +189,8 @@ hipError_t launch_DK_desc(hipStream_t s, long long n, int nbatch, const int *lis
 // columns of J, and rows of J, columns of I).
 template <int P>
 __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basis bs, const double *__restrict__ W,
-                                                           double wscale, int npair, const int *__restrict__ pown,
+                                                           double wscale, int npair, const int *__restrict__ order,
+                                                           const int *__restrict__ pown,
                                                            const int *__restrict__ plist,
                                                            const int *__restrict__ lptr,
                                                            const int4 *__restrict__ desc, int norb,
@@ -205,14 +206,19 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
     __shared__ DevSpecies s_sp[kMaxSpecies];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
-    const int p = xcd_batch(blockIdx.x, 0, npair);
+    // with a heaviest-first order, consecutive workgroups take consecutive
+    // pairs (the hardware deals them round-robin over the XCDs, so every XCD
+    // gets heavy and light pairs); without one, each XCD takes a contiguous
+    // range of pairs (their batches overlap in its L2)
+    const int w = order ? ((int)blockIdx.x < npair ? (int)blockIdx.x : -1) : xcd_batch(blockIdx.x, 0, npair);
     for (int k = tid; k < g.nrad; k += 64 * kDKWaves)
         s_rad[k] = bs.rad[k];
     for (int k = tid; k < g.nspecies; k += 64 * kDKWaves)
         s_sp[k] = bs.sp[k];
     __syncthreads();
-    if (p < 0)
+    if (w < 0)
         return;
+    const int p = order ? order[w] : w;
     const int I = pown[p], J = plist[p];
     const bool self = I == J;
     double *reg = s_dyn + (size_t)wave * REG;
@@ -329,8 +335,8 @@ size_t DK_pairs_lds(int P)
 }
 
 hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *W, double wscale,
-                           int npair, const int *pown, const int *plist, const int *lptr, const int4 *desc, int norb,
-                           double *DK)
+                           int npair, const int *order, const int *pown, const int *plist, const int *lptr,
+                           const int4 *desc, int norb, double *DK)
 {
     if (npair <= 0)
         return hipSuccess;
@@ -341,14 +347,14 @@ hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Ba
         e = hipFuncSetAttribute((const void *)k_DK_pairs<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_DK_pairs<32>, dim3(nblk), dim3(64 * kDKWaves), lds, s, g, bn, b, W, wscale, npair, pown,
-                           plist, lptr, desc, norb, DK);
+        hipLaunchKernelGGL(k_DK_pairs<32>, dim3(nblk), dim3(64 * kDKWaves), lds, s, g, bn, b, W, wscale, npair, order,
+                           pown, plist, lptr, desc, norb, DK);
     } else if (g.P == 16) {
         e = hipFuncSetAttribute((const void *)k_DK_pairs<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_DK_pairs<16>, dim3(nblk), dim3(64 * kDKWaves), lds, s, g, bn, b, W, wscale, npair, pown,
-                           plist, lptr, desc, norb, DK);
+        hipLaunchKernelGGL(k_DK_pairs<16>, dim3(nblk), dim3(64 * kDKWaves), lds, s, g, bn, b, W, wscale, npair, order,
+                           pown, plist, lptr, desc, norb, DK);
     } else {
         return hipErrorInvalidValue;
     }

@@ -188,8 +188,8 @@ size_t DK_pairs_lds(int P);
 hipError_t launch_DK_desc(hipStream_t s, long long n, int nbatch, const int *list, const int *boff, const int *bptr,
                           int4 *desc);
 hipError_t launch_DK_pairs(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *W, double wscale,
-                           int npair, const int *pown, const int *plist, const int *lptr, const int4 *desc, int norb,
-                           double *DK);
+                           int npair, const int *order, const int *pown, const int *plist, const int *lptr,
+                           const int4 *desc, int norb, double *DK);
 // limits of the allocation-free H(k) (its workspace is a fixed device array)
 constexpr int kHkNaMaxPhase = 65536, kHkNaMaxK = 8192, kHkNaMaxR = 8192;
 // H(k) with the phases and staged inputs in the device array of gint_hr.hip
@@ -211,13 +211,18 @@ hipError_t launch_HR_batch(hipStream_t s, bool f32, const Geo &g, int nbmax, con
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                           int b1, const double *W, double wscale, const int *boff, int mno, void *part);
 // H block partials of slab si summed per owned pair (I = pown[p], J = plist[p])
-// over its list entries lsl[p (nslab + 1) + si] .. lsl[... + si + 1]
-hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *pown, const int *plist, const int *lsl,
-                               int nslab, int si, const int *list, const Basis &b, int mno, int norb,
-                               const void *part, int q0, int accumulate, double *H);
+// over its list entries lsl[p (nslab + 1) + si] .. lsl[... + si + 1]; pairs
+// launched in the order order[] (nullptr: index order)
+hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *order, const int *pown,
+                               const int *plist, const int *lsl, int nslab, int si, const int *list, const Basis &b,
+                               int mno, int norb, const void *part, int q0, int accumulate, double *H);
 hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
                               const int *abat, const int *bptr, const int *boff, const int *pptr, const int *plist,
                               int *lcnt, const int *lptr, int *list);
+// owned pairs sorted by their block count, heaviest first (stable), into
+// order[npair]; tmp == nullptr: tmp_bytes receives the scratch size
+hipError_t launch_pair_order(hipStream_t s, void *tmp, size_t &tmp_bytes, int npair, int nslab, const int *lsl,
+                             int *cost, int *cost2, int *idx, int *order);
 hipError_t launch_pair_slabs(hipStream_t s, int natom, int npair, const int *pptr, const int *lptr, const int *list,
                              int nslab, const int *slab_q, int *pown, int *lsl);
 hipError_t launch_fill_f64(hipStream_t s, double *p, long long n, double v);

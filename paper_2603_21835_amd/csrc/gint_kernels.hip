@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <hipcub/hipcub.hpp>
 
 #include "gint_device.h"
 
@@ -1023,6 +1024,34 @@ hipError_t launch_pair_slabs(hipStream_t s, int natom, int npair, const int *ppt
     hipLaunchKernelGGL(k_pair_slabs, dim3((npair + 255) / 256), dim3(256), 0, s, natom, npair, pptr, lptr, list, nslab,
                        slab_q, pown, lsl);
     return hipGetLastError();
+}
+
+// Blocks of every owned pair over all slabs (cost of its reduction), with
+// the pair index as the value, for a heaviest-first launch order
+__global__ void k_pair_cost(int npair, int nslab, const int *__restrict__ lsl, int *__restrict__ cost,
+                            int *__restrict__ idx)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair)
+        return;
+    cost[p] = lsl[(size_t)p * (nslab + 1) + nslab] - lsl[(size_t)p * (nslab + 1)];
+    idx[p] = p;
+}
+
+hipError_t launch_pair_order(hipStream_t s, void *tmp, size_t &tmp_bytes, int npair, int nslab, const int *lsl,
+                             int *cost, int *cost2, int *idx, int *order)
+{
+    if (!tmp)
+        return hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp_bytes, cost, cost2, idx, order,
+                                                            npair > 0 ? npair : 1, 0, 32, s);
+    if (npair <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pair_cost, dim3((npair + 255) / 256), dim3(256), 0, s, npair, nslab, lsl, cost, idx);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    // stable: pairs of equal cost keep their index order
+    return hipcub::DeviceRadixSort::SortPairsDescending(tmp, tmp_bytes, cost, cost2, idx, order, npair, 0, 32, s);
 }
 
 }  // namespace gint
