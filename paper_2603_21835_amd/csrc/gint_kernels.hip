@@ -17,6 +17,7 @@
 //                dense output layouts (conversion to the target format)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <hipcub/hipcub.hpp>
 
@@ -629,11 +630,14 @@ __device__ __forceinline__ void mesh_point(const Geo &g, int b, int q, double *r
 }
 
 // Maximum of an int array (one workgroup).
+// max of n non-negative ints: per-workgroup maxima combined with an integer
+// atomic max into *out, zeroed first (the result does not depend on the
+// order of the atomics)
 __global__ __launch_bounds__(256) void k_max_i32(const int *__restrict__ a, long long n, int *__restrict__ out)
 {
     __shared__ int red[256];
     int m = 0;
-    for (long long i = threadIdx.x; i < n; i += 256)
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
         m = a[i] > m ? a[i] : m;
     red[threadIdx.x] = m;
     __syncthreads();
@@ -643,12 +647,16 @@ __global__ __launch_bounds__(256) void k_max_i32(const int *__restrict__ a, long
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        *out = red[0];
+        atomicMax(out, red[0]);
 }
 
 hipError_t launch_max_i32(hipStream_t s, const int *a, long long n, int *out)
 {
-    hipLaunchKernelGGL(k_max_i32, dim3(1), dim3(256), 0, s, a, n, out);
+    const hipError_t e = launch_fill_i32(s, out, 1, 0);
+    if (e != hipSuccess)
+        return e;
+    const long long nblk = std::min<long long>(256, std::max<long long>(1, (n + 1023) / 1024));
+    hipLaunchKernelGGL(k_max_i32, dim3((unsigned)nblk), dim3(256), 0, s, a, n, out);
     return hipGetLastError();
 }
 
