@@ -161,6 +161,8 @@ struct gint_plan_s {
     // the per-pair reductions and of D_K; pord holds [idx | order], pcost
     // [cost | sorted cost]
     DevBuf pcost, pord, psort_tmp;
+    // canonical H(R) triples heaviest first, laid out like pcost / pord
+    DevBuf tcost, tord, tsort_tmp;
     std::vector<int> slab_q;      // first block partial of each slab (+ end)
     int nbmax = 0, ngbmax = 0;  // most atoms / atom groups reaching one batch
 
@@ -606,10 +608,10 @@ gint_status rebuild_lists(gint_plan p, bool resort)
         STCHK(p->pcost.ensure(sizeof(int) * 2 * ((size_t)tpart + 1)));
         STCHK(p->pord.ensure(sizeof(int) * 2 * ((size_t)tpart + 1)));
         size_t tb = 0;
-        HIPCHK(launch_pair_order(s, nullptr, tb, tpart, ns, nullptr, nullptr, nullptr, nullptr, nullptr));
+        HIPCHK(launch_item_order(s, nullptr, tb, tpart, ns + 1, ns, nullptr, nullptr, nullptr, nullptr, nullptr));
         STCHK(p->psort_tmp.ensure(tb));
         STCHK(timed(p, GINT_K_BIN, [&] {
-            return launch_pair_order(s, p->psort_tmp.p, tb, tpart, ns, p->lsl.as<int>(), p->pcost.as<int>(),
+            return launch_item_order(s, p->psort_tmp.p, tb, tpart, ns + 1, ns, p->lsl.as<int>(), p->pcost.as<int>(),
                                      p->pcost.as<int>() + tpart + 1, p->pord.as<int>(),
                                      p->pord.as<int>() + tpart + 1);
         }));
@@ -1278,6 +1280,14 @@ gint_status hr_triples(gint_plan p)
         HIPCHK(launch_seg(st, nbu, p->hkey2.as<unsigned long long>(), nullptr, p->hfscan.as<int>(),
                           p->tstart.as<int>(), p->tkey.as<unsigned long long>(), true));
         p->ntri = ntri;
+        // the triples' reductions heaviest first (block count)
+        STCHK(p->tcost.ensure(sizeof(int) * 2 * ((size_t)ntri + 1)));
+        STCHK(p->tord.ensure(sizeof(int) * 2 * ((size_t)ntri + 1)));
+        size_t tb2 = 0;
+        HIPCHK(launch_item_order(st, nullptr, tb2, ntri, 1, 1, nullptr, nullptr, nullptr, nullptr, nullptr));
+        STCHK(p->tsort_tmp.ensure(tb2));
+        HIPCHK(launch_item_order(st, p->tsort_tmp.p, tb2, ntri, 1, 1, p->tstart.as<int>(), p->tcost.as<int>(),
+                                 p->tcost.as<int>() + ntri + 1, p->tord.as<int>(), p->tord.as<int>() + ntri + 1));
     }
     p->htri_gen = p->gen;
     return GINT_OK;
@@ -1441,7 +1451,8 @@ gint_status gint_build_HR(gint_plan p, const double *V_dev, int nR, const int *R
                                   p->boff_u.as<int>(), p->mno, p->Hpart.p);
         }));
         STCHK(timed(p, GINT_K_HR, [&] {
-            return launch_HR_reduce(st, p->f32(), p->ntri, p->tkey.as<unsigned long long>(), p->tstart.as<int>(),
+            return launch_HR_reduce(st, p->f32(), p->ntri, p->ntri > 0 ? p->tord.as<int>() + p->ntri + 1 : nullptr,
+                                    p->tkey.as<unsigned long long>(), p->tstart.as<int>(),
                                     p->hcode2.as<int>(), p->natom, m, B, p->mno, p->norb, p->Hpart.p, HR_dev);
         }));
         return GINT_OK;

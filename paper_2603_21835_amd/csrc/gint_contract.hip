@@ -589,7 +589,8 @@ hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *or
 // H_JI(-R) for the listed R (for I = J and R = 0 the upper triangle,
 // mirrored).
 template <typename T>
-__global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long long *__restrict__ tkey,
+__global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const int *__restrict__ order,
+                                                   const unsigned long long *__restrict__ tkey,
                                                    const int *__restrict__ tstart, const int *__restrict__ list,
                                                    int natom, HRMap hm, Basis bs, int mno, int norb,
                                                    const T *__restrict__ part, double *__restrict__ HR)
@@ -600,9 +601,10 @@ __global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long
     constexpr int B = kHRBox, w = 2 * kHRBox + 1;
     __shared__ double s_sum[4][2][kMaxOrb * kMaxOrb];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int t = blockIdx.x * 4 + wv;
-    if (t >= ntri)
+    const int slot = blockIdx.x * 4 + wv;
+    if (slot >= ntri)
         return;
+    const int t = order ? order[slot] : slot;
     const unsigned long long key = tkey[t];
     const int ridx = (int)(key & 0x3ffffULL);
     const long long ij = (long long)(key >> 18);
@@ -688,19 +690,19 @@ __global__ __launch_bounds__(256) void k_HR_reduce(int ntri, const unsigned long
     }
 }
 
-hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const unsigned long long *tkey, const int *tstart,
-                            const int *list, int natom, const HRMap &m, const Basis &b, int mno, int norb,
-                            const void *part, double *HR)
+hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const int *order, const unsigned long long *tkey,
+                            const int *tstart, const int *list, int natom, const HRMap &m, const Basis &b, int mno,
+                            int norb, const void *part, double *HR)
 {
     if (ntri <= 0)
         return hipSuccess;
     const unsigned nblk = (unsigned)((ntri + 3) / 4);
     if (f32)
-        hipLaunchKernelGGL(k_HR_reduce<float>, dim3(nblk), dim3(256), 0, s, ntri, tkey, tstart, list, natom, m, b, mno,
-                           norb, static_cast<const float *>(part), HR);
+        hipLaunchKernelGGL(k_HR_reduce<float>, dim3(nblk), dim3(256), 0, s, ntri, order, tkey, tstart, list, natom, m,
+                           b, mno, norb, static_cast<const float *>(part), HR);
     else
-        hipLaunchKernelGGL(k_HR_reduce<double>, dim3(nblk), dim3(256), 0, s, ntri, tkey, tstart, list, natom, m, b,
-                           mno, norb, static_cast<const double *>(part), HR);
+        hipLaunchKernelGGL(k_HR_reduce<double>, dim3(nblk), dim3(256), 0, s, ntri, order, tkey, tstart, list, natom,
+                           m, b, mno, norb, static_cast<const double *>(part), HR);
     return hipGetLastError();
 }
 

@@ -152,9 +152,9 @@ hipError_t launch_seg(hipStream_t s, long long n, const unsigned long long *key,
 hipError_t sort_HR_keys(hipStream_t s, void *tmp, size_t &tmp_bytes, const unsigned long long *key_in,
                         unsigned long long *key_out, const int *code_in, int *code_out, int n, int end_bit);
 // fixed-order sums of the H(R) block partials, one wave per canonical triple
-hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const unsigned long long *tkey, const int *tstart,
-                            const int *list, int natom, const HRMap &m, const Basis &b, int mno, int norb,
-                            const void *part, double *HR);
+hipError_t launch_HR_reduce(hipStream_t s, bool f32, int ntri, const int *order, const unsigned long long *tkey,
+                            const int *tstart, const int *list, int natom, const HRMap &m, const Basis &b, int mno,
+                            int norb, const void *part, double *HR);
 // D(R) blocks of the rho and force contractions packed per canonical (I, J, R)
 // triple: etri[entry] = 2 t + o for every unfolded block entry (batch b's
 // entries from boff[b], image pairs a <= c in row-major order), nz[t] = 0
@@ -219,9 +219,10 @@ hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *or
 hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
                               const int *abat, const int *bptr, const int *boff, const int *pptr, const int *plist,
                               int *lcnt, const int *lptr, int *list);
-// owned pairs sorted by their block count, heaviest first (stable), into
-// order[npair]; tmp == nullptr: tmp_bytes receives the scratch size
-hipError_t launch_pair_order(hipStream_t s, void *tmp, size_t &tmp_bytes, int npair, int nslab, const int *lsl,
+// items (owned pairs, H(R) triples) sorted by the length of their list
+// range ptr[i stride] .. ptr[i stride + span], heaviest first (stable), into
+// order[n]; tmp == nullptr: tmp_bytes receives the scratch size
+hipError_t launch_item_order(hipStream_t s, void *tmp, size_t &tmp_bytes, int n, int stride, int span, const int *ptr,
                              int *cost, int *cost2, int *idx, int *order);
 hipError_t launch_pair_slabs(hipStream_t s, int natom, int npair, const int *pptr, const int *lptr, const int *list,
                              int nslab, const int *slab_q, int *pown, int *lsl);

@@ -1034,32 +1034,33 @@ hipError_t launch_pair_slabs(hipStream_t s, int natom, int npair, const int *ppt
     return hipGetLastError();
 }
 
-// Blocks of every owned pair over all slabs (cost of its reduction), with
-// the pair index as the value, for a heaviest-first launch order
-__global__ void k_pair_cost(int npair, int nslab, const int *__restrict__ lsl, int *__restrict__ cost,
+// Cost of every item (list entries of its reduction: ptr[i stride + span] -
+// ptr[i stride]), with the item index as the value, for a heaviest-first
+// launch order
+__global__ void k_item_cost(int n, int stride, int span, const int *__restrict__ ptr, int *__restrict__ cost,
                             int *__restrict__ idx)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npair)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
         return;
-    cost[p] = lsl[(size_t)p * (nslab + 1) + nslab] - lsl[(size_t)p * (nslab + 1)];
-    idx[p] = p;
+    cost[i] = ptr[(size_t)i * stride + span] - ptr[(size_t)i * stride];
+    idx[i] = i;
 }
 
-hipError_t launch_pair_order(hipStream_t s, void *tmp, size_t &tmp_bytes, int npair, int nslab, const int *lsl,
+hipError_t launch_item_order(hipStream_t s, void *tmp, size_t &tmp_bytes, int n, int stride, int span, const int *ptr,
                              int *cost, int *cost2, int *idx, int *order)
 {
     if (!tmp)
         return hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp_bytes, cost, cost2, idx, order,
-                                                            npair > 0 ? npair : 1, 0, 32, s);
-    if (npair <= 0)
+                                                            n > 0 ? n : 1, 0, 32, s);
+    if (n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_pair_cost, dim3((npair + 255) / 256), dim3(256), 0, s, npair, nslab, lsl, cost, idx);
+    hipLaunchKernelGGL(k_item_cost, dim3((n + 255) / 256), dim3(256), 0, s, n, stride, span, ptr, cost, idx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     // stable: pairs of equal cost keep their index order
-    return hipcub::DeviceRadixSort::SortPairsDescending(tmp, tmp_bytes, cost, cost2, idx, order, npair, 0, 32, s);
+    return hipcub::DeviceRadixSort::SortPairsDescending(tmp, tmp_bytes, cost, cost2, idx, order, n, 0, 32, s);
 }
 
 }  // namespace gint
