@@ -244,10 +244,12 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
 
 #pragma unroll 1
         for (int h = 0; h < P / HP; ++h) {
-        // ---- phit, grad phit of (atom slot s, point qp): one lane each ----
+        // ---- phit, grad phit of (atom slot s, point qp): two lanes each,
+        // the first half of the atom's radials on one, the rest on the other ----
         wave_lds_sync();  // the previous pass's operand reads are done
         {
-            const int s = lane / HP, ql = lane % HP, qp = h * HP + ql;
+            const int it = lane % (2 * HP), part = lane / (2 * HP);
+            const int s = it / HP, ql = it % HP, qp = h * HP + ql;
             if (s < 2 && !(self && s == 1)) {
                 const int e = s == 0 ? dc.y : dc.z;
                 const int atom = s == 0 ? I : J;
@@ -257,19 +259,22 @@ __global__ __launch_bounds__(64 * kDKWaves) void k_DK_pairs(Geo g, Bins bn, Basi
                 const int swz = ql & 15;
                 double *row = at(0, s, ql);
                 const int vs = 2 * HP * kMaxOrb;  // stride between values
-                for (int o = valid ? S.norb : 0; o < kMaxOrb; ++o)
+                if (part == 0)
+                    for (int o = valid ? S.norb : 0; o < kMaxOrb; ++o)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        row[v * vs + (o ^ swz)] = 0.0;
-                if (valid) {
+                        for (int v = 0; v < NV; ++v)
+                            row[v * vs + (o ^ swz)] = 0.0;
+                const int kmid = S.rad0 + (S.nrad + 1) / 2;
+                const int k0 = part == 0 ? S.rad0 : kmid, k1 = part == 0 ? kmid : S.rad0 + S.nrad;
+                if (valid && k0 < k1) {
                     const double wp = wscale * (W ? W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 1.0);
                     const int io = bn.ent_img[e];
                     const int cnt = bn.ent_img[e + 1] - io;
                     const double X[3] = {bs.xw[3 * atom], bs.xw[3 * atom + 1], bs.xw[3 * atom + 2]};
                     double r[3];
                     mesh_cart(g, n, r);
-                    eval_phi_grad(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img,
-                                  r, wp, row, vs, swz);
+                    eval_phi_grad(g, s_rad, k0, k1, S.rc, bs.coef, X, cnt, bn.img[io], io, bn.img, r, wp, row, vs,
+                                  swz);
                 }
             }
         }
