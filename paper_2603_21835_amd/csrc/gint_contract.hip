@@ -1352,19 +1352,23 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             wl[kk] = (T)s_w[p];
             po[kk] = (p >> 4) * kTile + (p & 15);
         }
-        // operand row li of tile t: phi of packed row 16 t + li (zero past the last row)
+        // operand row li of tile t: phi of packed row 16 t + li.  Rows past
+        // the last orbital read row (0, 0): the products of such rows and
+        // columns are never stored, and no select waits for the loads
         auto oprow = [&](int t, T (&v8)[P / 4], bool weighted) {
-            const int c = s_row[16 * t + li];
-            const T *pr = tile(c >= 0 ? c >> 16 : 0, 0) + kPitch * (c & 15);
+            const int c = max(s_row[16 * t + li], 0);
+            const T *pr = tile(c >> 16, 0) + kPitch * (c & 15);
 #pragma unroll
             for (int kk = 0; kk < P / 4; ++kk) {
-                const T f = c >= 0 ? pr[po[kk]] : (T)0;
+                const T f = pr[po[kk]];
                 v8[kk] = weighted ? wl[kk] * f : f;
             }
         };
         int cur = -1;
         T aw[P / 4];
-        int rkey[4], rb[4];  // per output row of this lane: 16 x + ox (or -1), partial offset
+        // per output row of this lane: key 16 x + ox (larger than every
+        // column key past the last orbital), partial offset
+        int rkey[4], rb[4];
         for (int k = k0; k < k1; ++k) {
             if (ti != cur) {
                 oprow(ti, aw, true);
@@ -1372,7 +1376,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
                 for (int v = 0; v < 4; ++v) {
                     const int c = s_row[16 * ti + MM<T>::row(lk, v)];
                     const int x = c >> 16, ox = c & 15;
-                    rkey[v] = c >= 0 ? 16 * x + ox : -1;
+                    rkey[v] = c >= 0 ? 16 * x + ox : 0x7fffffff;
                     // block (x, y) is number x nb - x (x - 1) / 2 + (y - x) of the triangle
                     rb[v] = (x * nb - x * (x - 1) / 2 - x) * mm + ox * mno;
                 }
@@ -1387,9 +1391,11 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             const int cc = s_row[16 * tj + li];
             const int ckey = cc >= 0 ? 16 * (cc >> 16) + (cc & 15) : -1;
             const int cb = (cc >> 16) * mm + (cc & 15);
+            // stored when both rows are orbitals (a padding column's key is
+            // -1) and the element lies in the blocks' upper triangle
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (rkey[v] >= 0 && ckey >= 0 && rkey[v] <= ckey)
+                if (rkey[v] <= ckey)
                     store_partial(pb + rb[v] + cb, hc[v]);
             if (++tj == ntile) {
                 ++ti;
