@@ -1075,8 +1075,10 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
         return launch_force_batch(st, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, W, wscale,
                                   p->Fent.as<double>(), rho);
     }));
-    STCHK(timed_on(p, st, GINT_K_F_REDUCE,
-                   [&] { return launch_force_reduce(st, p->geo, bn, B, p->Fent.as<double>(), dEdR); }));
+    STCHK(timed_on(p, st, GINT_K_F_REDUCE, [&] {
+        return launch_force_reduce(st, p->natom, p->aptr.as<int>(), p->aent.as<int>(), p->perm.as<int>(),
+                                   p->Fent.as<double>(), dEdR);
+    }));
     return GINT_OK;
 }
 
@@ -1132,8 +1134,10 @@ gint_status H_rho_force_impl(gint_plan p, const double *V_dev, const double *D_d
                                            i > 0 ? 1 : 0, H_dev);
             }));
         }
-        STCHK(timed(p, GINT_K_F_REDUCE,
-                    [&] { return launch_force_reduce(st, p->geo, bn, B, p->Fent.as<double>(), dEdR_dev); }));
+        STCHK(timed(p, GINT_K_F_REDUCE, [&] {
+            return launch_force_reduce(st, p->natom, p->aptr.as<int>(), p->aent.as<int>(), p->perm.as<int>(),
+                                       p->Fent.as<double>(), dEdR_dev);
+        }));
         return GINT_OK;
     }
     if (!two_streams) {

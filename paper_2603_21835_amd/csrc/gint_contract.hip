@@ -1690,20 +1690,18 @@ hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins 
 
 // dE/dR per atom: fixed-order sum of its per-(batch, atom) partials over the
 // batches of its group's list.
-__global__ __launch_bounds__(256) void k_force_reduce(Geo g, Bins bn, Basis bs, const double *__restrict__ Fent,
+__global__ __launch_bounds__(256) void k_force_reduce(const int *__restrict__ aptr, const int *__restrict__ aent,
+                                                      const int *__restrict__ perm, const double *__restrict__ Fent,
                                                       double *__restrict__ dEdR)
 {
     __shared__ double red[3][256];
     const int ii = blockIdx.x;
-    const int grp = ii / kGroup;
+    // the atom's entries in batch order (its list of the pair-block build)
     double v[3] = {0.0, 0.0, 0.0};
-    for (int k = bn.gptr[grp] + threadIdx.x; k < bn.gptr[grp + 1]; k += 256) {
-        const int b = bn.gbatch[k];
-        const int lo = bn.bptr[b], hi = bn.bptr[b + 1];
-        const int e = lower_bound_i(bn.ent_atom, lo, hi, ii);
-        if (e < hi && bn.ent_atom[e] == ii)
-            for (int x = 0; x < 3; ++x)
-                v[x] += Fent[(size_t)e * 3 + x];
+    for (int k = aptr[ii] + threadIdx.x; k < aptr[ii + 1]; k += 256) {
+        const int e = aent[k];
+        for (int x = 0; x < 3; ++x)
+            v[x] += Fent[(size_t)e * 3 + x];
     }
     for (int x = 0; x < 3; ++x)
         red[x][threadIdx.x] = v[x];
@@ -1715,13 +1713,15 @@ __global__ __launch_bounds__(256) void k_force_reduce(Geo g, Bins bn, Basis bs, 
         __syncthreads();
     }
     if (threadIdx.x < 3)
-        dEdR[3 * bs.perm[ii] + threadIdx.x] = red[threadIdx.x][0];
+        dEdR[3 * perm[ii] + threadIdx.x] = red[threadIdx.x][0];
 }
 
-hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, const double *Fent,
-                               double *dEdR)
+hipError_t launch_force_reduce(hipStream_t s, int natom, const int *aptr, const int *aent, const int *perm,
+                               const double *Fent, double *dEdR)
 {
-    hipLaunchKernelGGL(k_force_reduce, dim3(g.natom), dim3(256), 0, s, g, bn, b, Fent, dEdR);
+    if (natom <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_force_reduce, dim3(natom), dim3(256), 0, s, aptr, aent, perm, Fent, dEdR);
     return hipGetLastError();
 }
 

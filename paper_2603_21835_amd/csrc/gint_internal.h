@@ -250,7 +250,9 @@ bool H_rho_force_fits(int mode, int P, int nbmax, int mno);
 hipError_t launch_H_rho_force(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                               int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho,
                               int b0, int b1, const int *boff, void *part);
-hipError_t launch_force_reduce(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b,
+// dE/dR of every atom: its entry partials Fent summed in batch order (its
+// atom list aptr / aent), written at the atom's input index
+hipError_t launch_force_reduce(hipStream_t s, int natom, const int *aptr, const int *aent, const int *perm,
                                const double *Fent, double *dEdR);
 hipError_t launch_max_i32(hipStream_t s, const int *a, long long n, int *out);
 
