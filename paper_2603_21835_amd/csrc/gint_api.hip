@@ -127,6 +127,7 @@ struct gint_plan_s {
     // work buffers
     DevBuf Hpart, S2pk, Fent, sums, readback;
     DevBuf cnt_blk, boff, acnt, aptr, aent, abat, pcnt, pptr, plist, lcnt, lptr, blist;
+    DevBuf ucnt, uptr, blist_ub;  // per-pair list bounds, their offsets, the lists at those offsets
     DevBuf pown, lsl, slabq;  // owner of each owned pair; slab ranges of its block list
     DevBuf dk_desc;           // per block-list entry: batch and the two entries (gint_build_DK)
     long long nlist = 0;      // entries of the pairs' block lists
@@ -543,14 +544,30 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_partners(s, g, B2, p->brad, p->pptr.as<int>(), p->pcnt.as<int>(), p->plist.as<int>());
     }));
-    // block lists of the owned pairs (batch order) for the H reduction
+    // block lists of the owned pairs (batch order) for the H reduction: one
+    // intersection pass writes each list at the offset of its bound (the
+    // smaller of the two atoms' entry counts) and its length; the lists are
+    // then compacted
     p->npair_owned = tpart;
     STCHK(p->lcnt.ensure(sizeof(int) * (tpart + 1)));
     STCHK(p->lptr.ensure(sizeof(int) * (tpart + 1)));
+    STCHK(p->ucnt.ensure(sizeof(int) * (tpart + 1)));
+    STCHK(p->uptr.ensure(sizeof(int) * (tpart + 1)));
+    STCHK(timed(p, GINT_K_BIN, [&] {
+        return launch_pair_ub(s, na, tpart, p->aptr.as<int>(), p->pptr.as<int>(), p->plist.as<int>(),
+                              p->ucnt.as<int>());
+    }));
+    STCHK(scan_i32(p, s, p->ucnt.as<int>(), tpart, p->uptr.as<int>()));
+    int tub = 0;
+    HIPCHK(hipMemcpyAsync(&tub, p->uptr.as<int>() + tpart, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (tub < 0)
+        return fail(GINT_EUNSUPPORTED, "pair block lists exceed 2^31 entries");
+    STCHK(p->blist_ub.ensure(sizeof(int) * ((size_t)tub + 1)));
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_pair_blocks(s, na, tpart, p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>(),
                                   p->bptr.as<int>(), p->boff.as<int>(), p->pptr.as<int>(), p->plist.as<int>(),
-                                  p->lcnt.as<int>(), nullptr, nullptr);
+                                  p->lcnt.as<int>(), p->uptr.as<int>(), p->blist_ub.as<int>());
     }));
     STCHK(scan_i32(p, s, p->lcnt.as<int>(), tpart, p->lptr.as<int>()));
     int tlist = 0;
@@ -561,9 +578,8 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     p->nlist = tlist;
     STCHK(p->blist.ensure(sizeof(int) * ((size_t)tlist + 1)));
     STCHK(timed(p, GINT_K_BIN, [&] {
-        return launch_pair_blocks(s, na, tpart, p->aptr.as<int>(), p->aent.as<int>(), p->abat.as<int>(),
-                                  p->bptr.as<int>(), p->boff.as<int>(), p->pptr.as<int>(), p->plist.as<int>(),
-                                  p->lcnt.as<int>(), p->lptr.as<int>(), p->blist.as<int>());
+        return launch_list_compact(s, tpart, p->uptr.as<int>(), p->lptr.as<int>(), p->lcnt.as<int>(),
+                                   p->blist_ub.as<int>(), p->blist.as<int>());
     }));
     const size_t esz = p->f32() ? sizeof(float) : sizeof(double);
     const size_t blk_bytes = esz * (size_t)block_pitch(p->mno, (int)esz);

@@ -216,6 +216,12 @@ hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn,
 hipError_t launch_H_pairreduce(hipStream_t s, bool f32, int npair, const int *order, const int *pown,
                                const int *plist, const int *lsl, int nslab, int si, const int *list, const Basis &b,
                                int mno, int norb, const void *part, int q0, int accumulate, double *H);
+// the smaller entry count of each owned pair's two atoms (a bound on its
+// block list), and the compaction of lists written at those bounds' offsets
+hipError_t launch_pair_ub(hipStream_t s, int natom, int npair, const int *aptr, const int *pptr, const int *plist,
+                          int *ub);
+hipError_t launch_list_compact(hipStream_t s, int npair, const int *uptr, const int *lptr, const int *cnt,
+                               const int *src, int *dst);
 hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
                               const int *abat, const int *bptr, const int *boff, const int *pptr, const int *plist,
                               int *lcnt, const int *lptr, int *list);

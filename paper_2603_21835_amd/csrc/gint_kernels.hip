@@ -898,7 +898,8 @@ namespace gint {
 // per pair intersects the two atoms' batch-sorted entry lists 64 at a time:
 // each lane looks its batch up in the other window (a binary search over
 // lanes), and both windows then advance past the smaller window maximum, so
-// every common batch is met exactly once.
+// every common batch is met exactly once.  Both forms write the list's
+// length to lcnt; the filling form writes the list at lptr[p].
 
 namespace {
 __device__ __forceinline__ int upper_bound_i(const int *__restrict__ a, int lo, int hi, int key)
@@ -966,8 +967,56 @@ __global__ __launch_bounds__(256) void k_pair_blocks(int natom, int npair, const
         ia0 += __popcll(__ballot(av <= m));
         ib0 += __popcll(__ballot(bv <= m));
     }
-    if (!FILL && lane == 0)
+    if (lane == 0)
         lcnt[p] = run;
+}
+
+// Upper bound of every owned pair's block count (the smaller of the two
+// atoms' entry counts): the fill pass writes each list at its bound's offset
+__global__ __launch_bounds__(256) void k_pair_ub(int natom, int npair, const int *__restrict__ aptr,
+                                                 const int *__restrict__ pptr, const int *__restrict__ plist,
+                                                 int *__restrict__ ub)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair)
+        return;
+    const int I = upper_bound_i(pptr, 0, natom + 1, p) - 1;
+    const int J = plist[p];
+    ub[p] = min(aptr[I + 1] - aptr[I], aptr[J + 1] - aptr[J]);
+}
+
+// Each pair's list (cnt[p] entries from src + uptr[p]) to dst + lptr[p], one
+// wave per pair
+__global__ __launch_bounds__(256) void k_list_compact(int npair, const int *__restrict__ uptr,
+                                                      const int *__restrict__ lptr, const int *__restrict__ cnt,
+                                                      const int *__restrict__ src, int *__restrict__ dst)
+{
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= npair)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int *a = src + uptr[p];
+    int *b = dst + lptr[p];
+    for (int k = lane; k < cnt[p]; k += 64)
+        b[k] = a[k];
+}
+
+hipError_t launch_pair_ub(hipStream_t s, int natom, int npair, const int *aptr, const int *pptr, const int *plist,
+                          int *ub)
+{
+    if (npair <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pair_ub, dim3((npair + 255) / 256), dim3(256), 0, s, natom, npair, aptr, pptr, plist, ub);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_compact(hipStream_t s, int npair, const int *uptr, const int *lptr, const int *cnt,
+                               const int *src, int *dst)
+{
+    if (npair <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_list_compact, dim3((npair + 3) / 4), dim3(256), 0, s, npair, uptr, lptr, cnt, src, dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_blocks(hipStream_t s, int natom, int npair, const int *aptr, const int *aent,
