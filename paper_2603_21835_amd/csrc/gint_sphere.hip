@@ -71,21 +71,6 @@ __global__ __launch_bounds__(256) void k_pb_images(Geo g, Basis bs, int npa, con
         cnt[t] = n;
 }
 
-// entries with at least one image: atom, first image, image count; per
-// projector atom its entry range (ecnt[a] counts)
-__global__ __launch_bounds__(256) void k_pb_entries(int npa, int natom, const int *__restrict__ cnt,
-                                                    const int *__restrict__ ioff, const int *__restrict__ eoff,
-                                                    int *__restrict__ ent)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)npa * natom || cnt[t] == 0)
-        return;
-    const int e = eoff[t];
-    ent[3 * e] = (int)(t % natom);
-    ent[3 * e + 1] = ioff[t];
-    ent[3 * e + 2] = cnt[t];
-}
-
 hipError_t launch_pb_images(hipStream_t s, const Geo &g, const Basis &b, int npa, const int *pint, const double *prb,
                             const int *m, int *cnt, const int *off, int *img)
 {
@@ -99,17 +84,6 @@ hipError_t launch_pb_images(hipStream_t s, const Geo &g, const Basis &b, int npa
     else
         hipLaunchKernelGGL(k_pb_images<false>, dim3(nblk), dim3(256), 0, s, g, b, npa, pint, prb, m[0], m[1], m[2],
                            cnt, off, img);
-    return hipGetLastError();
-}
-
-hipError_t launch_pb_entries(hipStream_t s, int npa, int natom, const int *cnt, const int *ioff, const int *eoff,
-                             int *ent)
-{
-    const long long n = (long long)npa * natom;
-    if (n <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_pb_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, npa, natom, cnt, ioff, eoff,
-                       ent);
     return hipGetLastError();
 }
 
