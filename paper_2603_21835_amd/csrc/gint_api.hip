@@ -1084,12 +1084,15 @@ static gint_status force_impl(gint_plan p, const double *W, double wscale, const
         st = p->stream;
     const Bins bn = p->bins();
     const Basis B = p->basis();
+    // FP16 hi/lo: T on FP16 matrix cores, as in the fused pass (the same bits)
+    const bool h16 = p->prec == GINT_FP16_SPLIT && force_h16_fits(p->geo.P, p->nbmax, p->mno);
     STCHK(timed_on(p, st, GINT_K_PACK, [&] {
-        return launch_pack_S2(st, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
+        return h16 ? launch_pack_S2_h16(st, p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p)
+                   : launch_pack_S2(st, p->f32(), p->geo, bn, B, (int)p->npair, D, p->norb, p->S2pk.p);
     }));
     STCHK(timed_on(p, st, rho ? GINT_K_RHO_FORCE : GINT_K_FORCE, [&] {
         return launch_force_batch(st, p->f32(), p->geo, bn, B, p->nbmax, p->mno, p->S2pk.p, W, wscale,
-                                  p->Fent.as<double>(), rho);
+                                  p->Fent.as<double>(), rho, h16);
     }));
     STCHK(timed_on(p, st, GINT_K_F_REDUCE, [&] {
         return launch_force_reduce(st, p->natom, p->aptr.as<int>(), p->aent.as<int>(), p->perm.as<int>(),
@@ -1134,8 +1137,11 @@ gint_status H_rho_force_impl(gint_plan p, const double *V_dev, const double *D_d
         const hipStream_t st = p->stream;
         STCHK(timed(p, GINT_K_H_FILL,
                     [&] { return launch_fill_f64(st, H_dev, (long long)p->norb * p->norb, 0.0); }));
+        // FP16 hi/lo: the fused pass's T runs on FP16 matrix cores as well
         STCHK(timed(p, GINT_K_PACK, [&] {
-            return launch_pack_S2(st, p->f32(), p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.p);
+            return p->prec == GINT_FP16_SPLIT
+                       ? launch_pack_S2_h16(st, p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.p)
+                       : launch_pack_S2(st, p->f32(), p->geo, bn, B, (int)p->npair, D_dev, p->norb, p->S2pk.p);
         }));
         for (size_t i = 0; i + 1 < p->slab.size(); ++i) {
             const int b0 = p->slab[i], b1 = p->slab[i + 1];

@@ -235,6 +235,31 @@ __device__ __forceinline__ void split16(float x, unsigned &hi, unsigned &lo)
     }
 }
 
+// v_mfma_f32_16x16x16_f16 on two 4-half operands held as 2 x 32 bits each
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f4 mma16k16(u2v a, u2v b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4v, a), __builtin_bit_cast(h4v, b), c, 0, 0,
+                                                 0);
+}
+
+// FP16 hi/lo planes of four values (scaled by 2^8): {hi 0|1, hi 2|3, lo 0|1,
+// lo 2|3}
+__device__ __forceinline__ u4v split4_f16(float x0, float x1, float x2, float x3)
+{
+    unsigned h[4], l[4];
+    const float x[4] = {x0, x1, x2, x3};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const _Float16 hv = (_Float16)(x[m] * 256.0f);
+        const _Float16 lv = (_Float16)(x[m] * 256.0f - (float)hv);
+        h[m] = __builtin_bit_cast(unsigned short, hv);
+        l[m] = __builtin_bit_cast(unsigned short, lv);
+    }
+    return u4v{h[0] | (h[1] << 16), h[2] | (h[3] << 16), l[0] | (l[1] << 16), l[2] | (l[3] << 16)};
+}
+
 template <bool F16>
 __device__ __forceinline__ f4 mma16(u4v a, u4v b, f4 c)
 {
@@ -755,6 +780,44 @@ __global__ __launch_bounds__(256) void k_pack_S2(Geo g, Bins bn, Basis bs, const
     pk[base + 256 + t] = (T)v1;
 }
 
+// The same fragments as FP16 hi/lo planes for the 16-bit T of the FP16 hi/lo
+// mode: per (block, orientation) 64 lanes of 16 bytes, lane (i, k0) holding
+// the four values (i, k0 + 4 m), m = 0..3, of the FP32 form's lane (i, k0)
+__global__ __launch_bounds__(128) void k_pack_S2_h16(Geo g, Bins bn, Basis bs, const double *__restrict__ D,
+                                                     int norb, u4v *__restrict__ pk)
+{
+    const int pair = blockIdx.x >> 4, blk = blockIdx.x & 15;
+    const int A = bn.pairA[pair], B = bn.pairB[pair];
+    const int sX = blk >> 2, sY = blk & 3;
+    const int X = A * kGroup + sX, Y = B * kGroup + sY;
+    const int o = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const bool ok = X < g.natom && Y < g.natom && !(A == B && sX > sY);
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (ok) {
+        const int Xin = bs.perm[X], Yin = bs.perm[Y];
+        const int mx = bs.orb0[Xin], nx = bs.orb0[Xin + 1] - mx;
+        const int my = bs.orb0[Yin], ny = bs.orb0[Yin + 1] - my;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int kb = lk + 4 * m;
+            if (o == 0 && li < nx && kb < ny)
+                v[m] = (float)(D[(size_t)(mx + li) * norb + my + kb] + D[(size_t)(my + kb) * norb + mx + li]);
+            if (o == 1 && kb < nx && li < ny)
+                v[m] = (float)(D[(size_t)(mx + kb) * norb + my + li] + D[(size_t)(my + li) * norb + mx + kb]);
+        }
+    }
+    pk[((size_t)blockIdx.x * 2 + o) * 64 + lane] = split4_f16(v[0], v[1], v[2], v[3]);
+}
+
+hipError_t launch_pack_S2_h16(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                              const double *D, int norb, void *pk)
+{
+    if (npair <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pack_S2_h16, dim3(npair * 16), dim3(128), 0, s, g, bn, b, D, norb, static_cast<u4v *>(pk));
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int npair,
                           const double *D, int norb, void *pk)
 {
@@ -1136,7 +1199,10 @@ __host__ __device__ inline size_t h16_plane_offset(size_t esz, int nbmax, int P)
 // slab), from the same orbital tiles, before phase A; the same operands and
 // order as k_H_batch / k_H_batch16 (the same bits), written to part at block
 // offset boff[b] - boff[b0] + k.
-template <bool RHO, typename T, int P, int KU, int HB>
+// T16 (the FP16 hi/lo mode; FP32 tiles, 32-point batches): T = S2 phi on
+// FP16 matrix cores as well, from packed blocks in the 16-bit form
+// (three products of FP16 hi/lo planes, FP32 accumulation).
+template <bool RHO, typename T, int P, int KU, int HB, bool T16 = HB == kModeF16x3 + 1>
 __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, int nbmax,
                                                                   const T *__restrict__ pk,
                                                                   const double *__restrict__ W, double wscale,
@@ -1165,6 +1231,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     const int li = lane & 15, lk = lane >> 4;
     constexpr int HMODE = HB - 1;  // arithmetic mode of the H blocks
     constexpr bool H16 = HB > kModeF32 + 1;
+    static_assert(!T16 || (P == 32 && sizeof(T) == 4), "16-bit T: FP32 tiles of 32-point batches");
     const int b = HB ? xcd_batch(blockIdx.x, b0, b1 - b0) : xcd_batch(blockIdx.x, 0, g.nbatch);
     if (b < 0)
         return;
@@ -1404,6 +1471,21 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         }
     }
 
+    if constexpr (T16) {
+        // phase A's right operands as FP16 hi/lo planes over the H planes
+        // (every wave is past them): lane (j, k0) of point tile s2 of atom y
+        // holds phi_y at point 16 s2 + j of slots k0 + 4 m, m = 0..3
+        __syncthreads();
+        u4v *s_tp = reinterpret_cast<u4v *>(s_dyn + h16_plane_offset(sizeof(T), nbmax, P));  // [atom][tile][lane]
+        for (int k = tid; k < nb * NS * 64; k += NT) {
+            const int ln = k & 63, y = k / (NS * 64), s2 = (k >> 6) % NS;
+            const T *tp = tile(y, s2) + (ln & 15);
+            const int k0 = ln >> 4;
+            s_tp[k] = split4_f16(tp[kPitch * k0], tp[kPitch * (k0 + 4)], tp[kPitch * (k0 + 8)], tp[kPitch * (k0 + 12)]);
+        }
+        __syncthreads();
+    }
+
     // ---- phase A ----
     const int ntile = nrp >> 4;
     double rp[NS];
@@ -1447,22 +1529,62 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         // three register sets in rotation: an atom's D values are loaded two
         // atoms ahead of their use (past the end, the last atom is reloaded)
         auto at = [&](int y) { return y < nb ? y : nb - 1; };
-        T fa[4], fb[4], fc[4];
-        load(fa, 0);
-        load(fb, at(1));
-        int ja = 0;
-        for (; ja + 2 < nb; ja += 3) {
-            load(fc, ja + 2);
-            mblock(fa, ja);
-            load(fa, at(ja + 3));
-            mblock(fb, ja + 1);
-            load(fb, at(ja + 4));
-            mblock(fc, ja + 2);
+        if constexpr (T16) {
+            // the 16-byte hi/lo form of the same packed values (lane
+            // 16 lk + ox of the block), right operands from the planes; K
+            // order k0 + 4 m on both operands
+            const u4v *pk16 = reinterpret_cast<const u4v *>(pk);
+            const u4v *s_tp = reinterpret_cast<const u4v *>(s_dyn + h16_plane_offset(sizeof(T), nbmax, P));
+            auto load16 = [&](u4v &a, int y) { a = pk16[(size_t)s_bb[x * nb + y] * 64 + 16 * lk + ox]; };
+            auto mblock16 = [&](const u4v &a, int y) {
+                const u2v aH = u2v{a.x, a.y}, aL = u2v{a.z, a.w};
+#pragma unroll
+                for (int s2 = 0; s2 < NS; ++s2) {
+                    const u4v b = s_tp[(y * NS + s2) * 64 + lane];
+                    const u2v bH = u2v{b.x, b.y}, bL = u2v{b.z, b.w};
+                    acc[u][s2] = mma16k16(aH, bH, acc[u][s2]);
+                    acc[u][s2] = mma16k16(aH, bL, acc[u][s2]);
+                    acc[u][s2] = mma16k16(aL, bH, acc[u][s2]);
+                }
+            };
+            u4v fa, fb, fc;
+            load16(fa, 0);
+            load16(fb, at(1));
+            int ja = 0;
+            for (; ja + 2 < nb; ja += 3) {
+                load16(fc, ja + 2);
+                mblock16(fa, ja);
+                load16(fa, at(ja + 3));
+                mblock16(fb, ja + 1);
+                load16(fb, at(ja + 4));
+                mblock16(fc, ja + 2);
+            }
+            if (ja < nb)
+                mblock16(fa, ja);
+            if (ja + 1 < nb)
+                mblock16(fb, ja + 1);
+            // both operands carried a 2^8 scale
+#pragma unroll
+            for (int s2 = 0; s2 < NS; ++s2)
+                acc[u][s2] *= 1.0f / 65536.0f;
+        } else {
+            T fa[4], fb[4], fc[4];
+            load(fa, 0);
+            load(fb, at(1));
+            int ja = 0;
+            for (; ja + 2 < nb; ja += 3) {
+                load(fc, ja + 2);
+                mblock(fa, ja);
+                load(fa, at(ja + 3));
+                mblock(fb, ja + 1);
+                load(fb, at(ja + 4));
+                mblock(fc, ja + 2);
+            }
+            if (ja < nb)
+                mblock(fa, ja);
+            if (ja + 1 < nb)
+                mblock(fb, ja + 1);
         }
-        if (ja < nb)
-            mblock(fa, ja);
-        if (ja + 1 < nb)
-            mblock(fb, ja + 1);
         if (RHO) {
             // phi at the output rows of this lane (zero for padding rows)
 #pragma unroll
@@ -1554,18 +1676,18 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         }
 }
 
-template <bool RHO, typename T, int P, int KU, int HB = 0>
+template <bool RHO, typename T, int P, int KU, int HB = 0, bool T16 = HB == kModeF16x3 + 1>
 static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                   size_t lds, const void *pk, const double *W, double wscale, double *out,
                                   double *rho2, int b0 = 0, int b1 = 0, const int *boff = nullptr, int mno = 0,
                                   void *part = nullptr)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU, HB>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU, HB, T16>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
     const int nbat = HB ? b1 - b0 : g.nbatch;
-    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU, HB>), dim3(xcd_grid(nbat)), dim3(64 * kForceWaves), lds, s,
+    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU, HB, T16>), dim3(xcd_grid(nbat)), dim3(64 * kForceWaves), lds, s,
                        g, bn, b, nbmax, static_cast<const T *>(pk), W, wscale, out, rho2, b0, b1, boff, mno,
                        static_cast<T *>(part));
     return hipGetLastError();
@@ -1678,9 +1800,35 @@ hipError_t launch_H_rho_force(hipStream_t s, int mode, const Geo &g, const Bins 
     return hipErrorNotSupported;
 }
 
-hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
-                              int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho)
+bool force_h16_fits(int P, int nbmax, int mno)
 {
+    size_t lds = 0;
+    return P == 32 && packed_ku<float, 32>(nbmax, mno, kModeF16x3, &lds) > 0;
+}
+
+// the packed form with the 16-bit T (no H: the H planes' LDS holds the T planes)
+template <bool RHO>
+static hipError_t launch_force_h16(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int mno,
+                                   const void *pk, const double *W, double wscale, double *out, double *rho2)
+{
+    size_t lds = 0;
+    if (g.P != 32)
+        return hipErrorNotSupported;
+    switch (packed_ku<float, 32>(nbmax, mno, kModeF16x3, &lds)) {
+    case 1: return launch_packed_k<RHO, float, 32, 1, 0, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, out, rho2);
+    case 2: return launch_packed_k<RHO, float, 32, 2, 0, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, out, rho2);
+    case 3: return launch_packed_k<RHO, float, 32, 3, 0, true>(s, g, bn, b, nbmax, lds, pk, W, wscale, out, rho2);
+    default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                              int mno, const void *pk, const double *W, double wscale, double *Fent, double *rho,
+                              bool h16)
+{
+    if (h16)
+        return rho ? launch_force_h16<true>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho)
+                   : launch_force_h16<false>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, nullptr);
     if (rho)
         return f32 ? launch_force_t<true, float>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho)
                    : launch_force_t<true, double>(s, g, bn, b, nbmax, mno, pk, W, wscale, Fent, rho);

@@ -242,12 +242,19 @@ hipError_t launch_partners(hipStream_t s, const Geo &g, const Basis &b, double b
                            int *pcnt, int *plist);
 hipError_t launch_pack_S2(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int npair,
                           const double *D, int norb, void *pk);
+// the same fragments as FP16 hi/lo planes (each value scaled by 2^8): per
+// block and orientation 64 lanes of 16 bytes, lane (i, k0) holding (i, k0 + 4 m)
+hipError_t launch_pack_S2_h16(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int npair,
+                              const double *D, int norb, void *pk);
 size_t batch_lds_bytes(int nbmax, int P, bool f32);
 hipError_t launch_rho_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                             const void *pk, double *rho);
+// h16: T on FP16 hi/lo matrix cores from the 16-bit packed form
+// (launch_pack_S2_h16), possible where force_h16_fits says so
+bool force_h16_fits(int P, int nbmax, int mno);
 hipError_t launch_force_batch(hipStream_t s, bool f32, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                               int mno, const void *pk, const double *W, double wscale, double *Fent,
-                              double *rho /* NULL, or rho as well */);
+                              double *rho /* NULL, or rho as well */, bool h16 = false);
 // H blocks of batches b0 .. b1 - 1 (into part, as launch_H_batch) together
 // with rho and the force partials of the same batches, from one evaluation of
 // the orbital tiles (mode: the H arithmetic, kModeF64 .. kModeF16x3);
