@@ -30,10 +30,25 @@ PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
 # arithmetic type of the path per mode: H operands (+ rho/force operands) and accumulation
 DTYPES = {"fp64": "f64", "fp32": "f32 (f64 sums)", "bf16": "bf16 H, f32 rho/force (f64 sums)",
           "fp16": "f16 H, f32 rho/force (f64 sums)", "bf16x3": "bf16 hi/lo H, f32 rho/force (f64 sums)",
-          "fp16x3": "f16 hi/lo H, f32 rho/force (f64 sums)"}
+          "fp16x3": "f16 hi/lo H and rho/force contraction, f32 accumulation (f64 sums)"}
 PEAK_HBM_GBS = 8000.0
+
 N_XCD = 8  # MI355X: accelerator complex dies (GRBM_GUI_ACTIVE is summed over them)
 N_SIMD = 1024  # 256 compute units x 4 SIMDs
+
+
+def fused_peak(prec: str, kernel: str):
+    """The matrix peak a contraction kernel is priced at, and why."""
+    if prec == "fp64":
+        return PEAK_FP64_TFLOPS, "FP64 matrix cores"
+    if prec == "fp16x3" and kernel in ("H_rho_force", "rho_force", "force", "H_blocks"):
+        # every multiply-add of the n_g^2 work runs as three FP16 products
+        return PEAK_16BIT_TFLOPS / 3, ("H and T = (D + D^T) phi on FP16 matrix cores, three hi/lo products "
+                                       "per multiply-add: the 16-bit peak / 3")
+    if kernel == "H_blocks" and prec != "fp32":
+        return PEAK_16BIT_TFLOPS, "16-bit matrix cores"
+    return PEAK_FP32_TFLOPS, ("T = (D + D^T) phi on FP32 matrix cores (the larger share), H on the mode's; "
+                              "priced at the FP32 peak")
 
 
 def _kernel_sha() -> str:
@@ -58,7 +73,8 @@ def _traffic(kernel: str, workload: str, precision: str):
 
 
 # device kernel (symbol prefix) behind each timing kind whose traffic is recorded
-KERNEL_SYMBOLS = {"rho_force": r"k_force_packed<[^>]*, 0>", "H_rho_force": r"k_force_packed<[^>]*, [1-6]>",
+KERNEL_SYMBOLS = {"rho_force": r"k_force_packed<[^>]*, 0, (?:true|false)>",
+                  "H_rho_force": r"k_force_packed<[^>]*, [1-6], (?:true|false)>",
                   "H_blocks": r"k_H_batch<", "H_reduce": r"k_H_pairreduce<"}
 
 
@@ -234,8 +250,8 @@ def cpu_baseline(w):
 
 def mixed_leg(args, w, V, D, H64, rho64, F64, torch, g, dev, ms_fp64):
     """The same step (re-binning + gint_H_rho_force) in the FP16 hi/lo mode
-    (H on FP16 matrix cores with 3 products, rho and the force on FP32
-    tiles, FP64 sums across batches), timed like the FP64 step, with its
+    (H and the rho / force contraction on FP16 matrix cores with 3 products,
+    FP32 orbital tiles, FP64 sums across batches), timed like the FP64 step, with its
     error against the FP64 GPU outputs of the same inputs."""
     prec = "fp16x3"
     plan = g.GintPlan.from_workload(w, precision=prec)
@@ -268,10 +284,9 @@ def mixed_leg(args, w, V, D, H64, rho64, F64, torch, g, dev, ms_fp64):
     if dom == "H_rho_force":
         per = (4 * s2 + 8 * s1) / (timing[dom][1] / args.steps)
         ach = per / (kernels[dom]["avg_ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                "note": "fused pass: T = (D + D^T) phi on FP32 matrix cores (the larger share), H on FP16 ones; "
-                        "priced at the FP32 peak"}
+        peak, why = fused_peak(prec, dom)
+        roof = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3), "peak": round(peak, 1),
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "note": "fused pass: " + why}
     out = {
         "precision": prec,
         "dtype": DTYPES[prec],
@@ -573,15 +588,10 @@ def main():
         lps = timing[dom][1] / args.steps
         avg_s = kernels[dom]["avg_ms"] * 1e-3
         if dom in flops:
-            if args.precision == "fp64":
-                peak = PEAK_FP64_TFLOPS
-            elif dom == "H_blocks" and args.precision != "fp32":
-                peak = PEAK_16BIT_TFLOPS
-            else:
-                peak = PEAK_FP32_TFLOPS
+            peak, _ = fused_peak(args.precision, dom)
             per_launch = flops[dom] / lps
             ach = per_launch / avg_s / 1e12
-            roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
                     "frac": round(ach / peak, 4), "kernel": dom, "alg_flops_per_launch": per_launch}
         else:
             per_launch = hbytes[dom] / lps
