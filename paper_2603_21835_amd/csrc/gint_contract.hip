@@ -1370,26 +1370,46 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         const int k0 = wave * nblk / NW, k1 = (wave + 1) * nblk / NW;
         int ia = 0, ja = 0;
         tri_advance(ia, ja, k0, nb);
-        const size_t mm = (size_t)block_pitch(mno, sizeof(float));
+        const int mm = block_pitch(mno, sizeof(float));
+        // this wave's block in LDS (row-major, pitch mno), streamed out as
+        // one contiguous run of 16-byte stores
+        float *s_hb = reinterpret_cast<float *>(s_dyn + h16_plane_offset(sizeof(T), nbmax, P) +
+                                                2 * 64 * 16 * (size_t)nbmax) +
+                      kMaxOrb * kMaxOrb * wave;
+        // the left operands stay in registers while the blocks share atom ia
+        int cur = -1, nI = 0;
+        u4v aH = u4v{0u, 0u, 0u, 0u}, aL = aH;
         for (int k = k0; k < k1; ++k) {
-            const u4v aH = s_pl[(2 * ia) * 64 + lane] ^ neg;
+            if (ia != cur) {
+                aH = s_pl[(2 * ia) * 64 + lane] ^ neg;
+                if (SPLIT)
+                    aL = s_pl[(2 * ia + 1) * 64 + lane] ^ neg;
+                nI = s_sp[s_spc[ia]].norb;
+                cur = ia;
+            }
             const u4v bH = s_pl[(2 * ja) * 64 + lane];
             f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
             acc = mma16<F16>(aH, bH, acc);
             if (SPLIT) {
-                const u4v aL = s_pl[(2 * ia + 1) * 64 + lane] ^ neg;
                 const u4v bL = s_pl[(2 * ja + 1) * 64 + lane];
                 acc = mma16<F16>(aH, bL, acc);
                 acc = mma16<F16>(aL, bH, acc);
             }
-            const int nI = s_sp[s_spc[ia]].norb, nJ = s_sp[s_spc[ja]].norb;
-            float *o = reinterpret_cast<float *>(part) + (size_t)(boff[b] - boff[b0] + k) * mm;
+            const int nJ = s_sp[s_spc[ja]].norb;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 4 * lk + v;
                 if (row < nI && li < nJ)
-                    o[row * mno + li] = acc[v] * kUnscale;
+                    s_hb[row * mno + li] = acc[v] * kUnscale;
             }
+            // LDS operations of one wave complete in order: the reads below
+            // see the writes above, and the next block's writes follow them
+            __builtin_amdgcn_wave_barrier();
+            if (4 * lane < mm) {
+                f4 *o = reinterpret_cast<f4 *>(part) + ((size_t)(boff[b] - boff[b0] + k) * mm >> 2);
+                __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(s_hb + 4 * lane), o + lane);
+            }
+            __builtin_amdgcn_wave_barrier();
             if (++ja == nb) {
                 ++ia;
                 ja = ia;
@@ -1742,7 +1762,9 @@ static int packed_ku(int nbmax, int mno, int mode, size_t *lds)
     if (mode > kModeF32) {
         if (P != 32)
             return 0;
-        *lds = h16_plane_offset(sizeof(T), nbmax, P) + 2 * 64 * 16 * (size_t)nbmax;
+        // the hi/lo planes (later phase A's), then one block per wave
+        *lds = h16_plane_offset(sizeof(T), nbmax, P) + 2 * 64 * 16 * (size_t)nbmax +
+               sizeof(float) * kMaxOrb * kMaxOrb * kForceWaves;
     }
     return (*lds + 24576 > 163840 || ku > 3) ? 0 : (ku < 1 ? 1 : ku);
 }
