@@ -373,9 +373,12 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
     const int nblk = nb * (nb + 1) / 2;
     int ia = 0, ja = 0;
     tri_advance(ia, ja, wave, nb);
-    const size_t mm = (size_t)block_pitch(mno, sizeof(float));
+    const int mm = block_pitch(mno, sizeof(float));
     const u4v *pl = reinterpret_cast<const u4v *>(s_phi);
     const int apitch = P * kRow / 4;  // u4v per atom region
+    // this wave's block in LDS (row-major, pitch mno) past the batch's
+    // planes, streamed out as one contiguous run of 16-byte stores
+    float *s_hb = s_phi + (size_t)nb * P * kRow + kMaxOrb * kMaxOrb * wave;
     for (int k = wave; k < nblk; k += nw) {
         const u4v aH = pl[ia * apitch + lane] ^ neg;
         const u4v bH = pl[ja * apitch + lane];
@@ -388,13 +391,20 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
             acc = mma16<F16>(aL, bH, acc);
         }
         const int nI = s_nor[ia], nJ = s_nor[ja];
-        float *o = part + (size_t)(boff[b] - boff[b0] + k) * mm;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * lk + v;
             if (row < nI && li < nJ)
-                o[row * mno + li] = acc[v] * kUnscale;
+                s_hb[row * mno + li] = acc[v] * kUnscale;
         }
+        // LDS operations of one wave complete in order: the reads below see
+        // the writes above, and the next block's writes follow them
+        __builtin_amdgcn_wave_barrier();
+        if (4 * lane < mm) {
+            f4 *o = reinterpret_cast<f4 *>(part) + ((size_t)(boff[b] - boff[b0] + k) * mm >> 2);
+            __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(s_hb + 4 * lane), o + lane);
+        }
+        __builtin_amdgcn_wave_barrier();
         tri_advance(ia, ja, nw, nb);
     }
 }
@@ -403,7 +413,8 @@ template <bool F16, bool SPLIT>
 static hipError_t launch_H16_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0, int b1,
                                const double *W, double wscale, const int *boff, int mno, void *part)
 {
-    const size_t lds = sizeof(float) * (size_t)nbmax * g.P * kRow;
+    // the batch's tiles (then its planes), then one block per wave
+    const size_t lds = sizeof(float) * ((size_t)nbmax * g.P * kRow + kMaxOrb * kMaxOrb * kHWaves);
     hipError_t e = hipFuncSetAttribute((const void *)k_H_batch16<F16, SPLIT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
