@@ -78,17 +78,36 @@ __device__ __forceinline__ void eval_phi_grad(const Geo &g, const DevRadial *__r
                 q[3 * vstride] = gz;
             }
         };
-        for (int k = k0; k < k1; ++k) {
-            const DevRadial R = rads[k];
-            double f = 0.0, fp = 0.0;
-            if (inside && rr < R.rc) {
-                double t;
-                const int iv = spline_interval(R, rr, &t);
-                const double2 c01 = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
-                const double2 c23 = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
-                f = c01.x + t * (c01.y + t * (c23.x + t * c23.y));
-                fp = c01.y + t * (2.0 * c23.x + t * 3.0 * c23.y);
+        // the spline coefficients of U radials are loaded together, then
+        // the radials are evaluated one by one
+        constexpr int U = 3;
+        for (int kb = k0; kb < k1; kb += U) {
+        double2 c01[U], c23[U];
+        double tt[U];
+#pragma unroll
+        for (int iu = 0; iu < U; ++iu) {
+            const int k = kb + iu;
+            c01[iu] = double2{0.0, 0.0};
+            c23[iu] = double2{0.0, 0.0};
+            tt[iu] = 0.0;
+            if (k < k1) {
+                const DevRadial R = rads[k];
+                if (inside && rr < R.rc) {
+                    const int iv = spline_interval(R, rr, &tt[iu]);
+                    c01[iu] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv);
+                    c23[iu] = *reinterpret_cast<const double2 *>(coef + R.coef_off + 4 * iv + 2);
+                }
             }
+        }
+#pragma unroll
+        for (int iu = 0; iu < U; ++iu) {
+            const int k = kb + iu;
+            if (k >= k1)
+                break;
+            const DevRadial R = rads[k];
+            const double t = tt[iu];
+            const double f = c01[iu].x + t * (c01[iu].y + t * (c23[iu].x + t * c23[iu].y));
+            const double fp = c01[iu].y + t * (2.0 * c23[iu].x + t * 3.0 * c23[iu].y);
             const int o = R.orb0;
             const double fr = f * ir;
             if (R.l == 0) {
@@ -132,6 +151,7 @@ __device__ __forceinline__ void eval_phi_grad(const Geo &g, const DevRadial *__r
                     put(o + m, f * Y[m], gv[0], gv[1], gv[2]);
                 }
             }
+        }
         }
     }
 }
