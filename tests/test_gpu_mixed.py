@@ -1,9 +1,11 @@
 """Mixed-precision modes against the FP64 oracle.
 
-FP32 mode (and rho and the force in the 16-bit modes): orbital tiles, packed
-D and per-batch H block partials in FP32 on v_mfma_f32_16x16x4; every
+FP32 mode (and rho and the force in the other 16-bit modes): orbital tiles,
+packed D and per-batch H block partials in FP32 on v_mfma_f32_16x16x4; every
 cross-batch sum and every dot product stays FP64.  16-bit modes: H operands
-in BF16 or FP16 (single or hi/lo split) on v_mfma_f32_16x16x32.
+in BF16 or FP16 (single or hi/lo split) on v_mfma_f32_16x16x32; in the FP16
+hi/lo mode the rho / force contraction T = (D + D^T) phi runs as three FP16
+hi/lo products on v_mfma_f32_16x16x16f16 as well.
 The accuracy target for the mixed path is max|dH| <= 1e-6 Ha (absolute);
 the rho relative-L2 and force errors are reported beside it.
 """
@@ -101,9 +103,12 @@ def test_16bit_H_si64_sampled(tdev, oracle_mod, prec):
     idx = np.random.default_rng(0).choice(w.ngrid, 20000, replace=False)
     ro = o.rho(w.D, idx)
     er = np.linalg.norm(rho[idx] - ro) / np.linalg.norm(ro)
-    _say(f"  {prec} si64: max|dH| {dH:.2e} Ha  rho rel-L2 {er:.2e}")
+    # gint_force of the mode (FP16 hi/lo: T on FP16 matrix cores as well)
+    Fo = o.force(w.V, w.D, [5, 60])
+    eF = np.abs(F[[5, 60]] - Fo).max() / np.abs(Fo).max()
+    _say(f"  {prec} si64: max|dH| {dH:.2e} Ha  rho rel-L2 {er:.2e}  F rel {eF:.2e}")
     assert np.array_equal(H, H.T)
-    assert dH <= MODES16[prec] and er <= 1e-5
+    assert dH <= MODES16[prec] and er <= 1e-5 and eF <= 1e-4
 
 
 def test_16bit_modes_need_32_point_batches(tdev):

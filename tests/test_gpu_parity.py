@@ -281,6 +281,8 @@ def test_H_rho_force_one_call(oracle_mod, torch_dev, make, precision):
     rs, Fs = (t.cpu().numpy() for t in plan.rho_force(V, D))
     for a, b2, c in ((H1, H2, Hs), (rho1, rho2, rs), (F1, F2, Fs)):
         assert np.array_equal(a, b2) and np.array_equal(a, c)
+    # the force-only pass (no rho) gives the same dE/dR bits
+    assert np.array_equal(F1, plan.force(V, D).cpu().numpy())
     o = oracle_mod.Oracle.from_workload(w)
     idx = np.random.default_rng(3).choice(w.ngrid, min(w.ngrid, 4000), replace=False)
     er = _rel_l2(rho1[idx], o.rho(w.D, idx))
