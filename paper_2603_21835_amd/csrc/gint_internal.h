@@ -131,10 +131,11 @@ hipError_t launch_support_count(hipStream_t s, const Geo &g, const Bins &bn, con
 // Contractions (gint_contract.hip).
 // f32 selects FP32 orbital tiles, packed D and H partials (else FP64).
 // Elements between consecutive H block partials: mno * mno rounded up to
-// 16 bytes, so that every block starts 16-byte aligned.
+// whole 128-byte lines, so that every block starts on a line of its own and
+// its stores and loads never share a line with a neighbouring block.
 __host__ __device__ inline int block_pitch(int mno, int esz)
 {
-    const int v = 16 / esz;
+    const int v = 128 / esz;
     return (mno * mno + v - 1) / v * v;
 }
 // arithmetic modes of the H kernel (values of gint_precision)
