@@ -532,14 +532,15 @@ gint_status rebuild_lists(gint_plan p, bool resort)
     const Basis B2 = p->basis();
     STCHK(timed(p, GINT_K_BIN, [&] { return launch_partners(s, g, B2, p->brad, nullptr, p->pcnt.as<int>(), nullptr); }));
     STCHK(scan_i32(p, s, p->pcnt.as<int>(), na, p->pptr.as<int>()));
-    std::vector<int> hboff(nb + 1);
-    int tpart = 0;
-    HIPCHK(hipMemcpyAsync(hboff.data(), p->boff.p, sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, s));
+    // the block total and the owned-pair count (the per-batch block offsets
+    // come to the host only when H needs more than one slab, below)
+    int tblk = 0, tpart = 0;
+    HIPCHK(hipMemcpyAsync(&tblk, p->boff.as<int>() + nb, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&tpart, p->pptr.as<int>() + na, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hboff[nb] < 0 || tpart < 0)
+    if (tblk < 0 || tpart < 0)
         return fail(GINT_EUNSUPPORTED, "block lists exceed 2^31 entries");
-    p->nblock = hboff[nb];
+    p->nblock = tblk;
     STCHK(p->plist.ensure(sizeof(int) * (tpart + 1)));
     STCHK(timed(p, GINT_K_BIN, [&] {
         return launch_partners(s, g, B2, p->brad, p->pptr.as<int>(), p->pcnt.as<int>(), p->plist.as<int>());
@@ -592,25 +593,34 @@ gint_status rebuild_lists(gint_plan p, bool resort)
             budget = fr / 3;
     }
     p->hbudget_eff = budget;
-    // a range holds at least one whole batch
-    long long per_slab = (long long)(budget / blk_bytes);
-    for (int b = 0; b < nb; ++b)
-        per_slab = std::max(per_slab, (long long)hboff[b + 1] - hboff[b]);
     p->slab.assign(1, 0);
+    p->slab_q.assign(1, 0);
     long long most = 0;
-    for (int b = 0; b < nb;) {
-        int e = b;
-        while (e < nb && (long long)hboff[e + 1] - hboff[b] <= per_slab)
-            ++e;
-        if (e == b)
-            ++e;
-        most = std::max(most, (long long)hboff[e] - hboff[b]);
-        p->slab.push_back(e);
-        b = e;
+    if (nb > 0 && (long long)(budget / blk_bytes) >= (long long)tblk) {
+        // every partial fits: one slab
+        p->slab.push_back((int)nb);
+        p->slab_q.push_back(tblk);
+        most = tblk;
+    } else {
+        std::vector<int> hboff(nb + 1);
+        HIPCHK(hipMemcpyAsync(hboff.data(), p->boff.p, sizeof(int) * (nb + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        // a range holds at least one whole batch
+        long long per_slab = (long long)(budget / blk_bytes);
+        for (int b = 0; b < nb; ++b)
+            per_slab = std::max(per_slab, (long long)hboff[b + 1] - hboff[b]);
+        for (int b = 0; b < nb;) {
+            int e = b;
+            while (e < nb && (long long)hboff[e + 1] - hboff[b] <= per_slab)
+                ++e;
+            if (e == b)
+                ++e;
+            most = std::max(most, (long long)hboff[e] - hboff[b]);
+            p->slab.push_back(e);
+            p->slab_q.push_back(hboff[e]);
+            b = e;
+        }
     }
-    p->slab_q.clear();
-    for (int b : p->slab)
-        p->slab_q.push_back(hboff[b]);
     {
         const int ns = (int)p->slab.size() - 1;
         STCHK(p->slabq.ensure(sizeof(int) * (ns + 1)));
