@@ -66,15 +66,21 @@ typedef enum {
 /* Arithmetic of the contractions.  Inputs/outputs stay FP64 in all modes;
    the cross-batch reductions and the final dot products are FP64 in all
    modes.  The 16-bit modes apply to H; rho and the force then run as in
-   GINT_FP32.  Split modes write each H operand as hi + lo (both 16-bit) and
-   sum hi.hi + hi.lo + lo.hi on the matrix cores (3 products). */
+   GINT_FP32, except in GINT_FP16_SPLIT, where gint_rho_force, gint_force and
+   gint_H_rho_force also contract T = (D + D^T) phi as FP16 hi/lo products
+   (gint_build_rho keeps FP32).  Split modes write each operand as hi + lo
+   (both 16-bit) and sum hi.hi + hi.lo + lo.hi on the matrix cores (3
+   products).  FP16 operands are scaled by 2^8, so the scaled values must stay
+   inside the FP16 range: |D_mu,nu + D_nu,mu|, |phi| and |w|^(1/2) |phi| below
+   255; larger values overflow to infinity (practical density matrices and
+   normalised orbitals are of order one). */
 typedef enum {
     GINT_FP64 = 0,       /* FP64 orbitals, FP64 MFMA                          */
     GINT_FP32 = 1,       /* FP32 orbitals, FP32 MFMA (FP32 within a batch)     */
     GINT_BF16 = 2,       /* H: BF16 operands, FP32 accumulation, one product   */
     GINT_FP16 = 3,       /* H: FP16 operands (scaled), FP32 accumulation       */
     GINT_BF16_SPLIT = 4, /* H: BF16 hi/lo operands, 3 products                 */
-    GINT_FP16_SPLIT = 5  /* H: FP16 hi/lo operands (scaled), 3 products        */
+    GINT_FP16_SPLIT = 5  /* H and T: FP16 hi/lo operands (scaled), 3 products  */
 } gint_precision;
 
 /* One radial function, tabulated on the host at r_i = i*dr, i < nr; its
