@@ -131,7 +131,10 @@ typedef struct gint_plan_s *gint_plan;
  *   prec             arithmetic of the contractions
  *   hip_stream       hipStream_t to enqueue on (NULL = default stream)
  *   out              receives the plan (unchanged on error)
- * Synchronises the stream once (list sizes are read back). */
+ * Batches start as 4x4x2 mesh points; an FP64 or FP32 plan whose atoms are
+ * too many for the LDS of a 32-point batch starts with 2x2x4 instead
+ * (gint_work reports the shape).  Synchronises the stream (list sizes are
+ * read back). */
 gint_status gint_plan_create(const double lattice[9], const int grid[3], int nspecies,
                              const gint_species *species, int natom, const int *species_of_atom,
                              const double *positions, gint_precision prec, void *hip_stream,

@@ -919,7 +919,21 @@ static gint_status plan_create(const double lattice[9], const int grid[3], int n
             st = fail(GINT_EDEVICE, "spline kernel launch failed: %s", hipGetErrorString(e));
             break;
         }
-        if ((st = rebuild_lists(p, true)) != GINT_OK) break;
+        if ((st = rebuild_lists(p, true)) != GINT_OK) {
+            // so many atoms reach a 32-point batch that its tiles exceed the
+            // LDS: FP64 and FP32 plans start with 16-point batches instead
+            if (st != GINT_EUNSUPPORTED || (prec != GINT_FP64 && prec != GINT_FP32))
+                break;
+            const int bs1[3] = {2, 2, 4};
+            Geo g1 = p->geo;
+            set_batch(g1, bs1);
+            if (max_image_index(g1, rc_max) >= 126.0)
+                break;
+            p->geo = g1;
+            p->brad = batch_radius(g1);
+            if ((st = rebuild_lists(p, true)) != GINT_OK)
+                break;
+        }
         e = hipStreamSynchronize(p->stream);
         if (e != hipSuccess) {
             st = fail(GINT_EDEVICE, "plan construction failed on the device: %s", hipGetErrorString(e));

@@ -370,3 +370,51 @@ def test_failed_retune_keeps_plan_usable(oracle_mod, torch_dev):
     H = plan.build_H(V).cpu().numpy()
     o = oracle_mod.Oracle.from_workload(w)
     assert _rel_max(H, o.H(w.V)) <= TOL
+
+
+def _dense_si64():
+    # Si-64 compressed to 0.75 of its lattice constant: about 50 atoms reach
+    # each 16-point batch, more than one fused pass holds (row tiles per wave)
+    lat, pos = gi.si_supercell((2, 2, 2))
+    s = 0.75
+    return gi.small_cell(pos * s, lat * s, (48, 48, 48), [gi.dzp_species()], n_waves=8, nocc=64, seed=21)
+
+
+def test_H_rho_force_split_when_batches_are_large(oracle_mod, torch_dev):
+    # gint_H_rho_force where a batch's atoms do not fit the fused pass: H on
+    # the plan's stream beside the rho + force pass (per-atom form) on the
+    # second stream; the same bits as the separate calls, and H rows, rho
+    # points and dE/dR against the oracle
+    torch, dev = torch_dev
+    import paper_2603_21835_amd as g
+
+    w = _dense_si64()
+    # too many atoms for the LDS of a 32-point batch: the plan starts with
+    # 16-point batches by itself
+    plan = g.GintPlan.from_workload(w)
+    assert plan.work()["batch"] == (2, 2, 4)
+    _say(f"case H_rho_force with large batches: {w.natom} atoms, grid {w.grid}")
+    V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
+    plan.set_timing(True)
+    H1, rho1, F1 = (t.cpu().numpy() for t in plan.H_rho_force(V, D))
+    t = plan.timing()
+    plan.set_timing(False)
+    ran = {k for k, (ms, n) in t.items() if n}
+    _say(f"  kernels: {sorted(ran)}")
+    assert "H_rho_force" not in ran and "H_blocks" in ran and "rho_force" in ran
+    Hs = plan.build_H(V).cpu().numpy()
+    rs, Fs = (x.cpu().numpy() for x in plan.rho_force(V, D))
+    assert np.array_equal(H1, Hs) and np.array_equal(rho1, rs) and np.array_equal(F1, Fs)
+    o = oracle_mod.Oracle.from_workload(w)
+    for I in (0, w.natom - 1):
+        rows = o.H_rows(w.V, I, I + 1)
+        r0 = o.atom_orb0[I]
+        e = _rel_max(H1[r0:r0 + rows.shape[0]], rows)
+        _say(f"  H rows of atom {I}: rel {e:.2e}")
+        assert e <= TOL
+    idx = np.random.default_rng(5).choice(w.ngrid, 4000, replace=False)
+    er = _rel_l2(rho1[idx], o.rho(w.D, idx))
+    atoms = [3, 40]
+    eF = _rel_max(F1[atoms], o.force(w.V, w.D, atoms))
+    _say(f"  rho sampled {er:.2e}  dE/dR rel {eF:.2e}")
+    assert er <= TOL and eF <= TOL
