@@ -173,9 +173,9 @@ __device__ __forceinline__ int spline_interval(const DevRadial &R, double rr, do
 // the first listed image, accumulation for further images (several images
 // of one atom reach a point only in cells smaller than the cutoff sphere).
 // pk0 is the first packed image; further ones are read from img[ioff + i].
-// The radial loop is unrolled by 8 so that all spline-coefficient loads of
-// an image are in flight together.  Orbital o goes to row[(o ^ swz) * ST].
-template <typename T, int ST = 1>
+// The radial loop is unrolled by U (8: all spline-coefficient loads of an
+// image in flight together).  Orbital o goes to row[(o ^ swz) * ST].
+template <typename T, int ST = 1, int U = 8>
 __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__restrict__ rads, int k0, int k1,
                                               double rc, const double *__restrict__ coef, const double *X,
                                               int icnt, int pk0, int ioff, const int *__restrict__ img,
@@ -200,11 +200,11 @@ __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__r
         }
         const double ux = d[0] * ir, uy = d[1] * ir, uz = d[2] * ir;
         const bool add = i > 0;
-        for (int kb = k0; kb < k1; kb += 8) {
-            double2 c01[8], c23[8];
-            double tt[8];
+        for (int kb = k0; kb < k1; kb += U) {
+            double2 c01[U], c23[U];
+            double tt[U];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int k = kb + u;
                 c01[u] = double2{0.0, 0.0};
                 c23[u] = double2{0.0, 0.0};
@@ -219,7 +219,7 @@ __device__ __forceinline__ void eval_orbitals(const Geo &g, const DevRadial *__r
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int k = kb + u;
                 if (k >= k1)
                     break;

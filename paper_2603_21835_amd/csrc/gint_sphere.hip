@@ -188,13 +188,6 @@ __global__ __launch_bounds__(64 * kPBWaves) void k_psibeta(Geo g, Basis bs, cons
     typedef MM<double>::acc acc_t;
     acc_t cre = MM<double>::zero(), cim = MM<double>::zero();
     for (int c = 0; c < nchunk; ++c) {
-        // the chunk's table values of this lane (in flight during the evaluation)
-        double2 av[CH / 4];
-#pragma unroll
-        for (int kk = 0; kk < CH / 4; ++kk) {
-            const int q = c * CH + 4 * kk + lk;
-            av[kk] = (prow_ok && q < npts) ? ta[(size_t)q * nps + li] : double2{0.0, 0.0};
-        }
         // phit_J at this lane's point (relative to the wrapped position of
         // the projector atom; phit is periodic)
         wave_lds_sync();  // the previous chunk's operand reads are done
@@ -208,9 +201,17 @@ __global__ __launch_bounds__(64 * kPBWaves) void k_psibeta(Geo g, Basis bs, cons
                 const int i = qg / nang, j = qg - i * nang;
                 const double r = rb * rq[2 * i];
                 const double pt[3] = {X[0] + r * ang[4 * j], X[1] + r * ang[4 * j + 1], X[2] + r * ang[4 * j + 2]};
-                eval_orbitals<double, 1>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, XJ, cnt, pk0, io, img, pt,
-                                         row, swz);
+                eval_orbitals<double, 1, 4>(g, s_rad, S.rad0, S.rad0 + S.nrad, S.rc, bs.coef, XJ, cnt, pk0, io,
+                                            img, pt, row, swz);
             }
+        }
+        // the chunk's table values of this lane (loaded after the evaluation:
+        // fewer live registers, three waves per SIMD)
+        double2 av[CH / 4];
+#pragma unroll
+        for (int kk = 0; kk < CH / 4; ++kk) {
+            const int q = c * CH + 4 * kk + lk;
+            av[kk] = (prow_ok && q < npts) ? ta[(size_t)q * nps + li] : double2{0.0, 0.0};
         }
         wave_lds_sync();
 #pragma unroll
