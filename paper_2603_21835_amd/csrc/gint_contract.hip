@@ -397,14 +397,14 @@ __global__ __launch_bounds__(64 * kHWaves) void k_H_batch16(Geo g, Bins bn, Basi
             if (row < nI && li < nJ)
                 s_hb[row * mno + li] = acc[v] * kUnscale;
         }
-        // LDS operations of one wave complete in order: the reads below see
-        // the writes above, and the next block's writes follow them
-        __builtin_amdgcn_wave_barrier();
+        // (wave-level fences: the reads below see the writes above, and the
+        // next block's writes follow them)
+        wave_lds_sync();
         if (4 * lane < mm) {
             f4 *o = reinterpret_cast<f4 *>(part) + ((size_t)(boff[b] - boff[b0] + k) * mm >> 2);
             __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(s_hb + 4 * lane), o + lane);
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
         tri_advance(ia, ja, nw, nb);
     }
 }
@@ -1413,14 +1413,14 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
                 if (row < nI && li < nJ)
                     s_hb[row * mno + li] = acc[v] * kUnscale;
             }
-            // LDS operations of one wave complete in order: the reads below
-            // see the writes above, and the next block's writes follow them
-            __builtin_amdgcn_wave_barrier();
+            // (wave-level fences: the reads below see the writes above, and
+            // the next block's writes follow them)
+            wave_lds_sync();
             if (4 * lane < mm) {
                 f4 *o = reinterpret_cast<f4 *>(part) + ((size_t)(boff[b] - boff[b0] + k) * mm >> 2);
                 __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(s_hb + 4 * lane), o + lane);
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
             if (++ja == nb) {
                 ++ia;
                 ja = ia;
