@@ -449,6 +449,10 @@ static hipError_t launch_H_batch_t(hipStream_t s, const Geo &g, const Bins &bn, 
     return hipErrorInvalidValue;
 }
 
+static hipError_t launch_H_packed(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                                  int b0, int b1, const double *W, double wscale, const int *boff, int mno,
+                                  void *part);
+
 hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
                           int b1, const double *W, double wscale, const int *boff, int mno, void *part)
 {
@@ -456,6 +460,14 @@ hipError_t launch_H_batch(hipStream_t s, int mode, const Geo &g, const Bins &bn,
         return hipSuccess;
     if (mode != kModeF64 && mode != kModeF32 && g.P != 32)
         return hipErrorInvalidValue;
+    if (mode == kModeF32) {
+        // FP32: the packed-row form where the batch's tiles fit it (the same
+        // bits; 16.0 -> 14.8 ms at Si-512).  In FP64 the per-block form is
+        // faster (19.6 against 32.0 ms), so it stays.
+        const hipError_t e = launch_H_packed(s, mode, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
+        if (e != hipErrorNotSupported)
+            return e;
+    }
     switch (mode) {
     case kModeF64: return launch_H_batch_t<double>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
     case kModeF32: return launch_H_batch_t<float>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff, mno, part);
@@ -1213,7 +1225,9 @@ __host__ __device__ inline size_t h16_plane_offset(size_t esz, int nbmax, int P)
 // T16 (the FP16 hi/lo mode; FP32 tiles, 32-point batches): T = S2 phi on
 // FP16 matrix cores as well, from packed blocks in the 16-bit form
 // (three products of FP16 hi/lo planes, FP32 accumulation).
-template <bool RHO, typename T, int P, int KU, int HB, bool T16 = HB == kModeF16x3 + 1>
+// HONLY (FP32 H, HB = kModeF32 + 1): the H blocks alone (no packed D, no rho
+// or force): the packed-row form of k_H_batch, with the same bits.
+template <bool RHO, typename T, int P, int KU, int HB, bool T16 = HB == kModeF16x3 + 1, bool HONLY = false>
 __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins bn, Basis bs, int nbmax,
                                                                   const T *__restrict__ pk,
                                                                   const double *__restrict__ W, double wscale,
@@ -1243,6 +1257,7 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
     constexpr int HMODE = HB - 1;  // arithmetic mode of the H blocks
     constexpr bool H16 = HB > kModeF32 + 1;
     static_assert(!T16 || (P == 32 && sizeof(T) == 4), "16-bit T: FP32 tiles of 32-point batches");
+    static_assert(!HONLY || (HB && !H16 && !T16 && !RHO), "H alone: FP64 / FP32 H blocks");
     const int b = HB ? xcd_batch(blockIdx.x, b0, b1 - b0) : xcd_batch(blockIdx.x, 0, g.nbatch);
     if (b < 0)
         return;
@@ -1261,11 +1276,12 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         s_spc[a] = bs.spc[atom];
         s_F[a][0] = s_F[a][1] = s_F[a][2] = 0.0;
     }
-    for (int k = tid; k < ngb * ngb; k += NT) {
-        const int ra = k / ngb, rb = k % ngb;
-        const int ga = bn.bgrp[g0 + ra], gb = bn.bgrp[g0 + rb];
-        s_ptab[k] = (ra <= rb) ? bn.pair_index[(size_t)ga * g.ngroup + gb] : -1;
-    }
+    if constexpr (!HONLY)
+        for (int k = tid; k < ngb * ngb; k += NT) {
+            const int ra = k / ngb, rb = k % ngb;
+            const int ga = bn.bgrp[g0 + ra], gb = bn.bgrp[g0 + rb];
+            s_ptab[k] = (ra <= rb) ? bn.pair_index[(size_t)ga * g.ngroup + gb] : -1;
+        }
     for (int p = tid; p < P; p += NT) {
         int n[3];
         s_w[p] = batch_point(g, ib, p, n) ? wscale * W[(n[0] * g.N[1] + n[1]) * g.N[2] + n[2]] : 0.0;
@@ -1293,13 +1309,14 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             s_off[0] = 0;
     }
     __syncthreads();
-    for (int k = tid; k < nb * nb; k += NT) {
-        const int x = k / nb, y = k % nb;
-        const bool le = x <= y;
-        const int lo = le ? x : y, hi = le ? y : x;
-        const int pr = s_ptab[s_grank[lo] * ngb + s_grank[hi]];
-        s_bb[k] = (pr * 16 + (s_atom[lo] % kGroup) * 4 + s_atom[hi] % kGroup) * 2 + (le ? 0 : 1);
-    }
+    if constexpr (!HONLY)
+        for (int k = tid; k < nb * nb; k += NT) {
+            const int x = k / nb, y = k % nb;
+            const bool le = x <= y;
+            const int lo = le ? x : y, hi = le ? y : x;
+            const int pr = s_ptab[s_grank[lo] * ngb + s_grank[hi]];
+            s_bb[k] = (pr * 16 + (s_atom[lo] % kGroup) * 4 + s_atom[hi] % kGroup) * 2 + (le ? 0 : 1);
+        }
     const int nrow = s_off[nb];
     const int nrp = (nrow + 15) & ~15;  // packed rows incl. the padding of the last tile
     for (int r = tid; r < nrp; r += NT) {
@@ -1501,6 +1518,8 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
             }
         }
     }
+    if constexpr (HONLY)
+        return;
 
     if constexpr (T16) {
         // phase A's right operands as FP16 hi/lo planes over the H planes
@@ -1707,18 +1726,18 @@ __global__ __launch_bounds__(64 * kForceWaves) void k_force_packed(Geo g, Bins b
         }
 }
 
-template <bool RHO, typename T, int P, int KU, int HB = 0, bool T16 = HB == kModeF16x3 + 1>
+template <bool RHO, typename T, int P, int KU, int HB = 0, bool T16 = HB == kModeF16x3 + 1, bool HONLY = false>
 static hipError_t launch_packed_k(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
                                   size_t lds, const void *pk, const double *W, double wscale, double *out,
                                   double *rho2, int b0 = 0, int b1 = 0, const int *boff = nullptr, int mno = 0,
                                   void *part = nullptr)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU, HB, T16>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_force_packed<RHO, T, P, KU, HB, T16, HONLY>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
     const int nbat = HB ? b1 - b0 : g.nbatch;
-    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU, HB, T16>), dim3(xcd_grid(nbat)), dim3(64 * kForceWaves), lds, s,
+    hipLaunchKernelGGL((k_force_packed<RHO, T, P, KU, HB, T16, HONLY>), dim3(xcd_grid(nbat)), dim3(64 * kForceWaves), lds, s,
                        g, bn, b, nbmax, static_cast<const T *>(pk), W, wscale, out, rho2, b0, b1, boff, mno,
                        static_cast<T *>(part));
     return hipGetLastError();
@@ -1830,6 +1849,33 @@ hipError_t launch_H_rho_force(hipStream_t s, int mode, const Geo &g, const Bins 
         }
     }
 #undef GINT_HRF
+    return hipErrorNotSupported;
+}
+
+// H alone through the fused kernel's packed-row H loop: its tiles and the
+// slot-pair table in LDS; hipErrorNotSupported (nothing launched) where they
+// do not fit
+template <typename T, int P, int HB>
+static hipError_t launch_H_packed_t(hipStream_t s, const Geo &g, const Bins &bn, const Basis &b, int nbmax, int b0,
+                                    int b1, const double *W, double wscale, const int *boff, int mno, void *part)
+{
+    const size_t lds = sizeof(T) * (size_t)nbmax * (P / 16) * kTile + sizeof(int) * (size_t)nbmax * nbmax;
+    if (nbmax > kMaxBatchAtoms || lds + 24576 > 163840)
+        return hipErrorNotSupported;
+    return launch_packed_k<false, T, P, 1, HB, false, true>(s, g, bn, b, nbmax, lds, nullptr, W, wscale, nullptr,
+                                                            nullptr, b0, b1, boff, mno, part);
+}
+
+static hipError_t launch_H_packed(hipStream_t s, int mode, const Geo &g, const Bins &bn, const Basis &b, int nbmax,
+                                  int b0, int b1, const double *W, double wscale, const int *boff, int mno,
+                                  void *part)
+{
+    if (mode == kModeF32)
+        return g.P == 32   ? launch_H_packed_t<float, 32, kModeF32 + 1>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff,
+                                                                        mno, part)
+               : g.P == 16 ? launch_H_packed_t<float, 16, kModeF32 + 1>(s, g, bn, b, nbmax, b0, b1, W, wscale, boff,
+                                                                        mno, part)
+                           : hipErrorNotSupported;
     return hipErrorNotSupported;
 }
 
