@@ -380,21 +380,25 @@ def _dense_si64():
     return gi.small_cell(pos * s, lat * s, (48, 48, 48), [gi.dzp_species()], n_waves=8, nocc=64, seed=21)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x3"])
 def test_H_rho_force_split_when_batches_are_large(oracle_mod, torch_dev, precision):
     # gint_H_rho_force where a batch's atoms do not fit the fused pass: H on
     # the plan's stream beside the rho + force pass (per-atom form) on the
     # second stream; the same bits as the separate calls, and H rows, rho
-    # points and dE/dR against the oracle (FP16 hi/lo: 16-bit H blocks and an
-    # FP32 T, within 1e-6)
+    # points and dE/dR against the oracle (FP32: the H-only packed-row pass on
+    # 16-point batches; FP16 hi/lo: 16-bit H blocks and an FP32 T; H within
+    # 1e-6 Ha, rho and dE/dR within 1e-5)
     torch, dev = torch_dev
     import paper_2603_21835_amd as g
 
     w = _dense_si64()
     plan = g.GintPlan.from_workload(w, precision=precision)
     # FP64: too many atoms for the LDS of a 32-point batch, so the plan starts
-    # with 16-point batches by itself; the 16-bit modes keep 32 points
+    # with 16-point batches by itself; FP32 tiles fit 32 points (tuned to 16
+    # here, the H-only pass on 16-point batches); FP16 hi/lo keeps 32 points
     assert plan.work()["batch"] == ((2, 2, 4) if precision == "fp64" else (4, 4, 2))
+    if precision == "fp32":
+        plan.tune((2, 2, 4))
     _say(f"case H_rho_force with large batches: {w.natom} atoms, grid {w.grid}, {precision}")
     V, D = _dev(torch, dev, w.V), _dev(torch, dev, w.D)
     plan.set_timing(True)
@@ -409,6 +413,7 @@ def test_H_rho_force_split_when_batches_are_large(oracle_mod, torch_dev, precisi
     assert np.array_equal(H1, Hs) and np.array_equal(rho1, rs) and np.array_equal(F1, Fs)
     o = oracle_mod.Oracle.from_workload(w)
     tol = TOL if precision == "fp64" else 1e-6
+    tol_rf = TOL if precision == "fp64" else 1e-5
     for I in (0, w.natom - 1):
         rows = o.H_rows(w.V, I, I + 1)
         r0 = o.atom_orb0[I]
@@ -421,4 +426,4 @@ def test_H_rho_force_split_when_batches_are_large(oracle_mod, torch_dev, precisi
     atoms = [3, 40]
     eF = _rel_max(F1[atoms], o.force(w.V, w.D, atoms))
     _say(f"  rho sampled {er:.2e}  dE/dR rel {eF:.2e}")
-    assert er <= tol and eF <= tol
+    assert er <= tol_rf and eF <= tol_rf
